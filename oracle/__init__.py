@@ -1,0 +1,293 @@
+"""FP64 CPU oracle for the granular contact step -- TEST INFRASTRUCTURE ONLY.
+
+Python view of ``liboracle.so`` (built from ``oracle.cpp`` by ``oracle.build``).
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg use
+it; the product path never imports this package.
+
+Every function cites the part of arXiv 2306.01369 it follows; the C++ source
+states the readings taken where the paper is silent or garbled.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import math
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+SHAPES = {"plane": 0, "box": 1, "capsule": 2}
+
+
+class Body(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("env", C.c_int32), ("params", C.c_float * 4),
+                ("R", C.c_double * 9), ("t", C.c_double * 3), ("nu", C.c_double * 3),
+                ("omega", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
+                ("relax", C.c_double), ("density", C.c_double), ("g", C.c_double * 3),
+                ("n_iters", C.c_int32), ("mass_split", C.c_int32), ("inv_c", C.c_float),
+                ("pad", C.c_int32), ("n_h", C.c_int64)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        P = C.POINTER
+        L.ggo_hash.restype = C.c_int64
+        L.ggo_hash.argtypes = [C.c_int64] * 4
+        L.ggo_cell_index.argtypes = [C.c_int64, C.c_void_p, C.c_float, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ggo_pair_touch.restype = C.c_int32
+        L.ggo_pair_touch.argtypes = [C.c_void_p, C.c_void_p, C.c_float, C.c_float]
+        L.ggo_sdf_f32.restype = C.c_float
+        L.ggo_sdf_f32.argtypes = [P(Body), C.c_void_p]
+        L.ggo_sdf_f64.restype = C.c_double
+        L.ggo_sdf_f64.argtypes = [P(Body), C.c_void_p, C.c_void_p]
+        L.ggo_pp_bruteforce.restype = C.c_int64
+        L.ggo_pp_bruteforce.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_void_p]
+        L.ggo_pp_hashgrid.restype = C.c_int64
+        L.ggo_pp_hashgrid.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                      C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]
+        L.ggo_pb_contacts.restype = C.c_int64
+        L.ggo_pb_contacts.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                      P(Body), C.c_int64, C.c_void_p]
+        L.ggo_advance_bodies.argtypes = [C.c_int32, P(Body), C.c_double]
+        L.ggo_step.restype = C.c_int64
+        L.ggo_step.argtypes = [P(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_int32, P(Body), C.c_int32, C.c_int64,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_int32, C.c_void_p, C.c_void_p]
+        L.ggo_num_threads.restype = C.c_int32
+        L.ggo_sizeof_body.restype = C.c_int32
+        L.ggo_sizeof_params.restype = C.c_int32
+        assert L.ggo_sizeof_body() == C.sizeof(Body), "Body layout mismatch"
+        assert L.ggo_sizeof_params() == C.sizeof(Params), "Params layout mismatch"
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def default_cell(radius):
+    """Cell size c = max(r_i + r_j) * (1 + 2^-10) and its binary32 reciprocal."""
+    r = np.asarray(radius, dtype=np.float32)
+    c = float(np.float32(2.0 * float(r.max()) * (1.0 + 2.0 ** -10))) if r.size else 1.0
+    return c, float(np.float32(1.0) / np.float32(c))
+
+
+def make_bodies(body_dicts):
+    arr = (Body * max(1, len(body_dicts)))()
+    for k, b in enumerate(body_dicts):
+        B = arr[k]
+        B.shape = SHAPES[b["shape"]]
+        B.env = int(b.get("env", 0))
+        for q in range(4):
+            B.params[q] = float(np.float32(b["params"][q]))
+        R = np.asarray(b["R"], dtype=np.float64).reshape(9)
+        for q in range(9):
+            B.R[q] = float(R[q])
+        for q in range(3):
+            B.t[q] = float(b["t"][q])
+            B.nu[q] = float(b["nu"][q])
+            B.omega[q] = float(b["omega"][q])
+    return arr
+
+
+def bodies_to_f32_pose(arr, nb):
+    """Round the FP64 poses to binary32 (the pose both sides see)."""
+    for k in range(nb):
+        for q in range(9):
+            arr[k].R[q] = float(np.float32(arr[k].R[q]))
+        for q in range(3):
+            arr[k].t[q] = float(np.float32(arr[k].t[q]))
+            arr[k].nu[q] = float(np.float32(arr[k].nu[q]))
+            arr[k].omega[q] = float(np.float32(arr[k].omega[q]))
+    return arr
+
+
+# ---------------------------------------------------------------- Eq. (6)
+
+def spatial_hash(kappa, n_h):
+    """Bucket of one cell: XOR of p_a*(kappa_a - q), floored mod n_h (Eq. (6))."""
+    return int(lib().ggo_hash(int(kappa[0]), int(kappa[1]), int(kappa[2]), int(n_h)))
+
+
+def cell_index(x, inv_c, n_h, bucket_offset=None, env_n_h=None):
+    """(kappa (n,3) int64, h (n,) int64): kappa = rne(fl32(x * inv_c)) and h by Eq. (6)."""
+    x = _f32(x, (-1, 3))
+    n = x.shape[0]
+    kappa = np.zeros((n, 3), np.int64)
+    h = np.zeros(n, np.int64)
+    bo = None if bucket_offset is None else np.ascontiguousarray(bucket_offset, np.int64)
+    en = None if env_n_h is None else np.ascontiguousarray(env_n_h, np.int64)
+    lib().ggo_cell_index(n, _ptr(x), C.c_float(inv_c), int(n_h), _ptr(bo), _ptr(en), _ptr(kappa), _ptr(h))
+    return kappa, h
+
+
+# ---------------------------------------------------------------- contacts
+
+def pair_touch(xi, xj, ri, rj):
+    a, b = _f32(xi), _f32(xj)
+    return bool(lib().ggo_pair_touch(_ptr(a), _ptr(b), C.c_float(ri), C.c_float(rj)))
+
+
+def pp_bruteforce(x, r, env=None):
+    """O(n^2) contact set {(i, j): i < j, ||xi-xj||^2 <= (ri+rj)^2} (Sec. II-C)."""
+    x, r = _f32(x, (-1, 3)), _f32(r)
+    e = None if env is None else np.ascontiguousarray(env, np.int32)
+    n = x.shape[0]
+    cnt = lib().ggo_pp_bruteforce(n, _ptr(x), _ptr(r), _ptr(e), 0, None)
+    out = np.zeros((max(cnt, 1), 2), np.int32)
+    lib().ggo_pp_bruteforce(n, _ptr(x), _ptr(r), _ptr(e), cnt, _ptr(out))
+    return out[:cnt]
+
+
+def pp_hashgrid(x, r, inv_c, n_h, env=None):
+    """Contact set through the linked hashmap of Alg. 2 and the 27-cell query
+    (Sec. II-B).  Returns (pairs (C,2) sorted, candidates)."""
+    x, r = _f32(x, (-1, 3)), _f32(r)
+    e = None if env is None else np.ascontiguousarray(env, np.int32)
+    n = x.shape[0]
+    cand = np.zeros(1, np.int64)
+    cnt = lib().ggo_pp_hashgrid(n, _ptr(x), _ptr(r), _ptr(e), C.c_float(inv_c), int(n_h), 0, None, _ptr(cand))
+    out = np.zeros((max(cnt, 1), 2), np.int32)
+    lib().ggo_pp_hashgrid(n, _ptr(x), _ptr(r), _ptr(e), C.c_float(inv_c), int(n_h), cnt, _ptr(out), _ptr(cand))
+    return out[:cnt], int(cand[0])
+
+
+def pb_contacts(x, r, body_dicts, env=None):
+    """Particle-body contacts {(i, b): f32 SDF_b(x_i) - r_i <= 0} (Eq. (7))."""
+    x, r = _f32(x, (-1, 3)), _f32(r)
+    e = None if env is None else np.ascontiguousarray(env, np.int32)
+    B = bodies_to_f32_pose(make_bodies(body_dicts), len(body_dicts))
+    n = x.shape[0]
+    cnt = lib().ggo_pb_contacts(n, _ptr(x), _ptr(r), _ptr(e), len(body_dicts), B, 0, None)
+    out = np.zeros((max(cnt, 1), 2), np.int32)
+    lib().ggo_pb_contacts(n, _ptr(x), _ptr(r), _ptr(e), len(body_dicts), B, cnt, _ptr(out))
+    return out[:cnt]
+
+
+def sdf32(body, x):
+    B = bodies_to_f32_pose(make_bodies([body]), 1)
+    return float(lib().ggo_sdf_f32(B, _ptr(_f32(x))))
+
+
+def sdf64_body_frame(body, p):
+    """FP64 SDF and unit gradient at body-frame point p (Sec. II-C)."""
+    B = make_bodies([body])
+    p = np.ascontiguousarray(p, np.float64)
+    g = np.zeros(3)
+    f = lib().ggo_sdf_f64(B, _ptr(p), _ptr(g))
+    return float(f), g
+
+
+# ---------------------------------------------------------------- the step
+
+class Oracle:
+    """FP64 simulation state stepped by the oracle (Alg. 1, Eqs. (1)-(7)).
+
+    Positions/velocities are held in FP64; contact decisions use their
+    binary32 rounding.  Body poses are FP64, advanced after each step."""
+
+    def __init__(self, x, v, radius, bodies=(), *, dt=1e-3, alpha=0.2, mu=0.5, n_iters=20,
+                 gravity=(0.0, 0.0, -9.81), relax=1.0, density=2500.0, mass_split=True,
+                 cell_size=None, hash_size=None, env=None):
+        self.x = np.array(x, dtype=np.float64, copy=True).reshape(-1, 3)
+        self.v = np.array(v, dtype=np.float64, copy=True).reshape(-1, 3)
+        self.r = _f32(radius)
+        self.n = self.x.shape[0]
+        self.body_dicts = list(bodies)
+        self.nb = len(self.body_dicts)
+        self.B = bodies_to_f32_pose(make_bodies(self.body_dicts), self.nb)
+        self.env = None if env is None else np.ascontiguousarray(env, np.int32)
+        P = Params()
+        P.dt, P.alpha, P.mu, P.relax, P.density = dt, alpha, mu, relax, density
+        for a in range(3):
+            P.g[a] = gravity[a]
+        P.n_iters = n_iters
+        P.mass_split = 1 if mass_split else 0
+        if cell_size is None:
+            cell_size, inv_c = default_cell(self.r)
+        else:
+            inv_c = float(np.float32(1.0) / np.float32(cell_size))
+        P.inv_c = inv_c
+        P.n_h = int(hash_size) if hash_size else max(1, 2 * self.n)
+        self.P = P
+        self.cell_size = cell_size
+        self.stats = np.zeros(4, np.int64)
+
+    def set_twists(self, tw):
+        """tw: (n_bodies, 6) (nu, omega) for the next step."""
+        for b in range(self.nb):
+            for q in range(3):
+                self.B[b].nu[q] = float(np.float32(tw[b][q]))
+                self.B[b].omega[q] = float(np.float32(tw[b][3 + q]))
+
+    def step(self, detail=False, n_hist=0, advance_bodies=True):
+        n = self.n
+        cap = 0
+        if detail:
+            # count first (dry detection) to size the outputs
+            xf = self.x.astype(np.float32)
+            pp, _ = pp_hashgrid(xf, self.r, self.P.inv_c, self.P.n_h, self.env)
+            pbc = lib().ggo_pb_contacts(n, _ptr(_f32(xf)), _ptr(self.r), _ptr(self.env), self.nb, self.B, 0, None)
+            cap = len(pp) + int(pbc)
+        capm = max(cap, 1)
+        pairs = np.zeros((capm, 2), np.int32) if detail else None
+        imp = np.zeros((capm, 3)) if detail else None
+        psi = np.zeros(capm) if detail else None
+        nrm = np.zeros((capm, 3)) if detail else None
+        dv = np.zeros((n, 3)) if detail else None
+        hist = np.zeros((max(n_hist, 1), capm, 3)) if (detail and n_hist) else None
+        Cn = lib().ggo_step(C.byref(self.P), n, _ptr(self.x), _ptr(self.v), _ptr(self.r), _ptr(self.env),
+                            self.nb, self.B, 1 if advance_bodies else 0, cap, _ptr(pairs), _ptr(imp),
+                            _ptr(psi), _ptr(nrm), _ptr(dv), int(n_hist), _ptr(hist), _ptr(self.stats))
+        if not detail:
+            return None
+        assert Cn == cap
+        out = {"pairs": pairs[:cap], "impulses": imp[:cap], "psi": psi[:cap], "normals": nrm[:cap],
+               "dv": dv, "n_pp": int(self.stats[1]), "n_pb": int(self.stats[2]),
+               "candidates": int(self.stats[0])}
+        if hist is not None:
+            out["history"] = hist[:, :cap]
+        return out
+
+    def body_pose(self, b):
+        R = np.array(self.B[b].R[:]).reshape(3, 3)
+        t = np.array(self.B[b].t[:])
+        return R, t
+
+
+def num_threads():
+    return int(lib().ggo_num_threads())
+
+
+def scene_oracle(scene, **kw):
+    """Oracle initialised from a scenes.Scene."""
+    env = None
+    if scene.env_offsets is not None:
+        env = np.repeat(np.arange(len(scene.env_offsets) - 1, dtype=np.int32), np.diff(scene.env_offsets))
+    args = dict(dt=scene.dt, alpha=scene.alpha, mu=scene.mu, n_iters=scene.n_iters,
+                gravity=scene.gravity, env=env)
+    args.update(kw)
+    return Oracle(scene.x, scene.v, scene.radius, scene.bodies, **args)

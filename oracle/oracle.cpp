@@ -1,0 +1,564 @@
+// Reference oracle for the granular contact step -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, FP64 CPU implementation of one timestep of the method of
+// "GranularGym" (arXiv 2306.01369), Sec. II:
+//   * cell coordinates and the spatial hash of Eq. (6)                (Sec. II-B)
+//   * the parallel linked hashmap of Alg. 2, built here sequentially
+//     (push-front into table[h] / next[i])                             (Sec. II-B)
+//   * the 3^3 neighbour-cell query and the sphere test ||xi-xj||^2 <= (ri+rj)^2
+//                                                                      (Sec. II-B, II-C)
+//   * particle-body contact through closed-form SDFs, psi = f_G(x) - r,
+//     evaluated at the inverse body pose                               (Eq. (7), Sec. II-C)
+//   * contact frame (e1 = normal, e2/e3 any tangent basis)             (Fig. contact-frame)
+//   * projected Jacobi over the stored contact list (Alg. 1) for the NCP of
+//     Eqs. (1)-(3), with Baumgarte bias alpha*psi/dt                  (Sec. II-A)
+//   * symplectic Euler: velocity first, then position                 (Eqs. (4)-(5))
+//
+// Only tests/, the smoke check and the benchmark's CPU-baseline leg may load
+// this library.  It shares no code, header or constant table with the GPU path.
+//
+// Readings taken where the paper is silent or garbled (all documented in the
+// design notes):
+//   - the impulse opposes the velocity residual: y = lam - mt*(u + bias*e1),
+//     normal n points from j to i, psi <= 0 for touching pairs;
+//   - relative velocity of a pair is w_i - w_j (gamma = 1), both sides carry
+//     gravity and all impulses accumulated so far (symmetric Jacobi);
+//   - each contact carries its own accumulated impulse lam_c, and the total is
+//     projected (clamp normal at 0, then scale the tangential part radially to
+//     radius mu*lam_n, as the listing of Alg. 1 does);
+//   - per-contact effective mass by mass splitting, mt = 1/(n_i/m_i + n_j/m_j)
+//     (n_i = contacts touching i), or mt = m_i/n_i for a body contact;
+//   - integrator v' = v + dt*g + dv, x' = x + dt*v';
+//   - cell size c is a parameter (c >= max(ri+rj)); cells kappa = rne(fl32(x*inv_c));
+//     hash products in 64-bit integers, floored (non-negative) modulus;
+//   - the contact decision is taken in binary32 with a fixed operation order
+//     (no fused multiply-add), everything downstream is FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------- Eq. (6)
+const int64_t kP1 = 73856093, kP2 = 19349663, kP3 = 83492791, kQ = 100;
+
+int64_t floor_mod(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+int64_t hash_cell(int64_t k0, int64_t k1, int64_t k2, int64_t n_h) {
+  int64_t v = (kP1 * (k0 - kQ)) ^ (kP2 * (k1 - kQ)) ^ (kP3 * (k2 - kQ));
+  return floor_mod(v, n_h);
+}
+
+// round(x / c): the product is rounded once to binary32, then to the nearest
+// integer with ties to even (the IEEE default rounding mode).
+int64_t cell_coord(float x, float inv_c) {
+  volatile float s = x * inv_c;
+  return (int64_t)std::nearbyint((float)s);
+}
+
+// ---------------------------------------------------------------- bodies
+enum Shape { PLANE = 0, BOX = 1, CAPSULE = 2 };
+
+struct Body {          // mirrored by the Python wrapper (ctypes)
+  int32_t shape;
+  int32_t env;
+  float params[4];     // box: half extents; capsule: radius, half length
+  double R[9];         // world <- body rotation, row major
+  double t[3];         // body origin in world
+  double nu[3];        // linear velocity of the body origin (world)
+  double omega[3];     // angular velocity (world)
+};
+
+struct Params {
+  double dt, alpha, mu, relax, density;
+  double g[3];
+  int32_t n_iters, mass_split;
+  float inv_c;
+  int32_t pad;
+  int64_t n_h;
+};
+
+// binary32 SDF with a fixed operation order (the contact decision).
+float sdf_f32(const Body& b, const float x[3]) {
+  float R[9], t[3];
+  for (int k = 0; k < 9; ++k) R[k] = (float)b.R[k];
+  for (int k = 0; k < 3; ++k) t[k] = (float)b.t[k];
+  float d0 = x[0] - t[0], d1 = x[1] - t[1], d2 = x[2] - t[2];
+  float p[3];
+  for (int c = 0; c < 3; ++c) {
+    float a0 = R[0 * 3 + c] * d0;
+    float a1 = R[1 * 3 + c] * d1;
+    float a2 = R[2 * 3 + c] * d2;
+    float s = a0 + a1;
+    p[c] = s + a2;
+  }
+  if (b.shape == PLANE) return p[2];
+  if (b.shape == BOX) {
+    float q[3], m[3];
+    for (int c = 0; c < 3; ++c) {
+      q[c] = std::fabs(p[c]) - b.params[c];
+      m[c] = q[c] > 0.0f ? q[c] : 0.0f;
+    }
+    float s0 = m[0] * m[0];
+    float s1 = m[1] * m[1];
+    float s2 = m[2] * m[2];
+    float ss = s0 + s1;
+    ss = ss + s2;
+    float outside = std::sqrt(ss);
+    float inside = std::max(q[0], std::max(q[1], q[2]));
+    inside = inside < 0.0f ? inside : 0.0f;
+    return outside + inside;
+  }
+  // capsule
+  float h = b.params[1];
+  float cz = std::min(std::max(p[2], -h), h);
+  float dz = p[2] - cz;
+  float s0 = p[0] * p[0];
+  float s1 = p[1] * p[1];
+  float s2 = dz * dz;
+  float ss = s0 + s1;
+  ss = ss + s2;
+  return std::sqrt(ss) - b.params[0];
+}
+
+bool body_touch_f32(const Body& b, const float x[3], float r) {
+  float f = sdf_f32(b, x);
+  float psi = f - r;
+  return psi <= 0.0f;
+}
+
+// binary32 sphere-sphere decision ||xi - xj||^2 <= (ri + rj)^2 (Sec. II-C).
+bool pair_touch_f32(const float xi[3], const float xj[3], float ri, float rj) {
+  float dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
+  float a = dx * dx, b = dy * dy, c = dz * dz;
+  float D = a + b;
+  D = D + c;
+  float s = ri + rj;
+  float S = s * s;
+  return D <= S;
+}
+
+// FP64 SDF in the body frame and its unit gradient.  Ties at non-smooth points
+// go to the lowest axis index; sign(0) = +1.
+double sdf_f64(const Body& b, const double p[3], double grad[3]) {
+  if (b.shape == PLANE) {
+    grad[0] = 0; grad[1] = 0; grad[2] = 1;
+    return p[2];
+  }
+  if (b.shape == BOX) {
+    double q[3], m[3];
+    bool outside = false;
+    for (int c = 0; c < 3; ++c) {
+      q[c] = std::fabs(p[c]) - (double)b.params[c];
+      m[c] = q[c] > 0 ? q[c] : 0.0;
+      if (q[c] > 0) outside = true;
+    }
+    if (outside) {
+      double L = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      for (int c = 0; c < 3; ++c) grad[c] = (p[c] < 0 ? -1.0 : 1.0) * m[c] / L;
+      return L;
+    }
+    int a = 0;
+    for (int c = 1; c < 3; ++c)
+      if (q[c] > q[a]) a = c;
+    grad[0] = grad[1] = grad[2] = 0;
+    grad[a] = p[a] < 0 ? -1.0 : 1.0;
+    return q[a];
+  }
+  double h = b.params[1];
+  double cz = std::min(std::max(p[2], -h), h);
+  double e[3] = {p[0], p[1], p[2] - cz};
+  double L = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  if (L > 0) {
+    for (int c = 0; c < 3; ++c) grad[c] = e[c] / L;
+  } else {
+    grad[0] = 1; grad[1] = 0; grad[2] = 0;
+  }
+  return L - (double)b.params[0];
+}
+
+// Any orthonormal tangent pair for the unit normal n (Frisvad's construction
+// as revised by Duff et al., "Building an Orthonormal Basis, Revisited").
+void tangent_basis(const double n[3], double t1[3], double t2[3]) {
+  double sgn = n[2] >= 0 ? 1.0 : -1.0;
+  double a = -1.0 / (sgn + n[2]);
+  double b = n[0] * n[1] * a;
+  t1[0] = 1.0 + sgn * n[0] * n[0] * a; t1[1] = sgn * b; t1[2] = -sgn * n[0];
+  t2[0] = b; t2[1] = sgn + n[1] * n[1] * a; t2[2] = -n[1];
+}
+
+double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+struct Contact {
+  int32_t i, j;      // j >= 0: particle, j < 0: body (-1 - body index)
+  double n[3], t1[3], t2[3];
+  double psi;
+  double vel[3];     // body point velocity (body contacts)
+};
+
+// Sequential linked hashmap of Alg. 2: table[h] holds the most recently
+// inserted particle of bucket h, next[i] the one inserted before i.
+struct LinkedHashmap {
+  std::vector<int64_t> table, next, kappa;
+  void build(int64_t n, const float* x, float inv_c, int64_t n_h) {
+    table.assign(n_h, -1);
+    next.assign(n, -1);
+    kappa.resize(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int a = 0; a < 3; ++a) kappa[3 * i + a] = cell_coord(x[3 * i + a], inv_c);
+      int64_t h = hash_cell(kappa[3 * i], kappa[3 * i + 1], kappa[3 * i + 2], n_h);
+      next[i] = table[h];
+      table[h] = i;
+    }
+  }
+};
+
+// Particle-particle contact set through the hashmap: for each particle, the
+// lists of its own cell and its 26 neighbours; a candidate counts only if it
+// really lies in the queried cell (buckets may alias).  Pairs come out as
+// (i, j), i < j, sorted.
+void pp_contacts_grid(int64_t n, const float* x, const float* r, const int32_t* env,
+                      float inv_c, int64_t n_h, std::vector<std::pair<int32_t, int32_t>>& out,
+                      int64_t* candidates) {
+  LinkedHashmap hm;
+  hm.build(n, x, inv_c, n_h);
+  std::vector<std::vector<int32_t>> partners(n);
+  int64_t cand_total = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : cand_total)
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t* ki = &hm.kappa[3 * i];
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          int64_t c0 = ki[0] + dx, c1 = ki[1] + dy, c2 = ki[2] + dz;
+          int64_t h = hash_cell(c0, c1, c2, n_h);
+          for (int64_t j = hm.table[h]; j >= 0; j = hm.next[j]) {
+            if (j == i) continue;
+            const int64_t* kj = &hm.kappa[3 * j];
+            if (kj[0] != c0 || kj[1] != c1 || kj[2] != c2) continue;
+            if (env && env[i] != env[j]) continue;
+            ++cand_total;
+            if (j > i && pair_touch_f32(&x[3 * i], &x[3 * j], r[i], r[j]))
+              partners[i].push_back((int32_t)j);
+          }
+        }
+    std::sort(partners[i].begin(), partners[i].end());
+  }
+  out.clear();
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t j : partners[i]) out.emplace_back((int32_t)i, j);
+  if (candidates) *candidates = cand_total;
+}
+
+void pb_contacts(int64_t n, const float* x, const float* r, const int32_t* env, int nb,
+                 const Body* bodies, std::vector<std::pair<int32_t, int32_t>>& out) {
+  out.clear();
+  for (int64_t i = 0; i < n; ++i)
+    for (int b = 0; b < nb; ++b) {
+      if (env && bodies[b].env != env[i]) continue;
+      if (body_touch_f32(bodies[b], &x[3 * i], r[i])) out.emplace_back((int32_t)i, (int32_t)b);
+    }
+}
+
+double particle_mass(double radius, double density) {
+  return density * (4.0 / 3.0) * M_PI * radius * radius * radius;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Eq. (6) for single cells (tests evaluate it against other sources).
+int64_t ggo_hash(int64_t k0, int64_t k1, int64_t k2, int64_t n_h) { return hash_cell(k0, k1, k2, n_h); }
+
+// Cell coordinates and bucket of every particle; env_bucket_offset/env_n_h
+// (may be NULL) give per-particle bucket offsets and table sizes for
+// segmented (multi-environment) tables.
+void ggo_cell_index(int64_t n, const float* x, float inv_c, int64_t n_h, const int64_t* bucket_offset,
+                    const int64_t* env_n_h, int64_t* kappa, int64_t* h) {
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t k[3];
+    for (int a = 0; a < 3; ++a) k[a] = cell_coord(x[3 * i + a], inv_c);
+    if (kappa)
+      for (int a = 0; a < 3; ++a) kappa[3 * i + a] = k[a];
+    int64_t nh = env_n_h ? env_n_h[i] : n_h;
+    h[i] = hash_cell(k[0], k[1], k[2], nh) + (bucket_offset ? bucket_offset[i] : 0);
+  }
+}
+
+// Decisions in binary32, exposed for tests.
+int32_t ggo_pair_touch(const float* xi, const float* xj, float ri, float rj) {
+  return pair_touch_f32(xi, xj, ri, rj) ? 1 : 0;
+}
+float ggo_sdf_f32(const Body* b, const float* x) { return sdf_f32(*b, x); }
+double ggo_sdf_f64(const Body* b, const double* p_body, double* grad) { return sdf_f64(*b, p_body, grad); }
+
+// O(n^2) particle-particle contact set: every pair i < j tested directly.
+int64_t ggo_pp_bruteforce(int64_t n, const float* x, const float* r, const int32_t* env, int64_t cap,
+                          int32_t* pairs) {
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = i + 1; j < n; ++j) {
+      if (env && env[i] != env[j]) continue;
+      if (pair_touch_f32(&x[3 * i], &x[3 * j], r[i], r[j])) {
+        if (k < cap) {
+          pairs[2 * k] = (int32_t)i;
+          pairs[2 * k + 1] = (int32_t)j;
+        }
+        ++k;
+      }
+    }
+  return k;
+}
+
+// Particle-particle contact set through the linked hashmap (Alg. 2 + 27-cell query).
+int64_t ggo_pp_hashgrid(int64_t n, const float* x, const float* r, const int32_t* env, float inv_c,
+                        int64_t n_h, int64_t cap, int32_t* pairs, int64_t* candidates) {
+  std::vector<std::pair<int32_t, int32_t>> out;
+  pp_contacts_grid(n, x, r, env, inv_c, n_h, out, candidates);
+  for (int64_t k = 0; k < (int64_t)out.size() && k < cap; ++k) {
+    pairs[2 * k] = out[k].first;
+    pairs[2 * k + 1] = out[k].second;
+  }
+  return (int64_t)out.size();
+}
+
+int64_t ggo_pb_contacts(int64_t n, const float* x, const float* r, const int32_t* env, int32_t nb,
+                        const Body* bodies, int64_t cap, int32_t* pairs) {
+  std::vector<std::pair<int32_t, int32_t>> out;
+  pb_contacts(n, x, r, env, nb, bodies, out);
+  for (int64_t k = 0; k < (int64_t)out.size() && k < cap; ++k) {
+    pairs[2 * k] = out[k].first;
+    pairs[2 * k + 1] = out[k].second;
+  }
+  return (int64_t)out.size();
+}
+
+// Advance kinematic body poses by one step: t += dt*nu, R = Exp(dt*[omega]x) R.
+void ggo_advance_bodies(int32_t nb, Body* bodies, double dt) {
+  for (int b = 0; b < nb; ++b) {
+    Body& B = bodies[b];
+    for (int a = 0; a < 3; ++a) B.t[a] += dt * B.nu[a];
+    double w[3] = {B.omega[0] * dt, B.omega[1] * dt, B.omega[2] * dt};
+    double th = std::sqrt(dot3(w, w));
+    if (th == 0) continue;
+    double k[3] = {w[0] / th, w[1] / th, w[2] / th};
+    double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+    double K2[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int m = 0; m < 3; ++m) s += K[3 * r + m] * K[3 * m + c];
+        K2[3 * r + c] = s;
+      }
+    double E[9];
+    for (int q = 0; q < 9; ++q) E[q] = (q % 4 == 0 ? 1.0 : 0.0) + std::sin(th) * K[q] + (1 - std::cos(th)) * K2[q];
+    double Rn[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int m = 0; m < 3; ++m) s += E[3 * r + m] * B.R[3 * m + c];
+        Rn[3 * r + c] = s;
+      }
+    std::memcpy(B.R, Rn, sizeof(Rn));
+  }
+}
+
+// One timestep.  State x, v (n x 3, FP64) is updated in place; contact
+// decisions use the binary32 rounding of x and of the body poses.
+// Outputs (each may be NULL):
+//   pairs      [cap x 2]  canonical list: pp (i<j) by (i,j), then pb (i, body) by (i, body)
+//   impulses   [cap x 3]  world impulse on the first member, R_c * lam_c
+//   psi        [cap]      signed gap of each contact
+//   normals    [cap x 3]  unit contact normal e1 (from the second member to the first)
+//   dv         [n x 3]    w - w0 after the last iteration (velocity change by impulses)
+//   lam_hist   [n_hist x cap x 3] world impulses after iterations 1..n_hist (n_hist <= n_iters)
+//   stats      [4]        candidates, pp count, pb count, 0
+// Returns the number of contacts (which may exceed cap; arrays then hold the
+// first cap entries and the state is still advanced).
+int64_t ggo_step(const Params* P, int64_t n, double* x, double* v, const float* radius,
+                 const int32_t* env, int32_t nb, Body* bodies, int32_t advance_bodies, int64_t cap,
+                 int32_t* pairs, double* impulses, double* psi_out, double* normals, double* dv, int32_t n_hist,
+                 double* lam_hist, int64_t* stats) {
+  // ---- detection on binary32 positions
+  std::vector<float> xf(3 * n);
+  for (int64_t q = 0; q < 3 * n; ++q) xf[q] = (float)x[q];
+  std::vector<std::pair<int32_t, int32_t>> pp, pb;
+  int64_t cand = 0;
+  pp_contacts_grid(n, xf.data(), radius, env, P->inv_c, P->n_h, pp, &cand);
+  pb_contacts(n, xf.data(), radius, env, nb, bodies, pb);
+  const int64_t C = (int64_t)(pp.size() + pb.size());
+  if (stats) {
+    stats[0] = cand;
+    stats[1] = (int64_t)pp.size();
+    stats[2] = (int64_t)pb.size();
+    stats[3] = 0;
+  }
+
+  // ---- contact geometry (FP64)
+  std::vector<Contact> cs(C);
+  std::vector<int32_t> count(n, 0);
+  for (int64_t c = 0; c < (int64_t)pp.size(); ++c) {
+    Contact& K = cs[c];
+    K.i = pp[c].first;
+    K.j = pp[c].second;
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = x[3 * K.i + a] - x[3 * K.j + a];
+    double L = std::sqrt(dot3(d, d));
+    double rs = (double)radius[K.i] + (double)radius[K.j];
+    if (L > 0) {
+      for (int a = 0; a < 3; ++a) K.n[a] = d[a] / L;
+    } else {
+      K.n[0] = 0; K.n[1] = 0; K.n[2] = 1;
+    }
+    K.psi = L - rs;
+    K.vel[0] = K.vel[1] = K.vel[2] = 0;
+    count[K.i]++;
+    count[K.j]++;
+  }
+  for (int64_t q = 0; q < (int64_t)pb.size(); ++q) {
+    Contact& K = cs[pp.size() + q];
+    K.i = pb[q].first;
+    int b = pb[q].second;
+    K.j = -1 - b;
+    const Body& B = bodies[b];
+    double d[3], p[3], g[3];
+    for (int a = 0; a < 3; ++a) d[a] = x[3 * K.i + a] - B.t[a];
+    for (int c = 0; c < 3; ++c) p[c] = B.R[0 * 3 + c] * d[0] + B.R[1 * 3 + c] * d[1] + B.R[2 * 3 + c] * d[2];
+    double f = sdf_f64(B, p, g);
+    for (int a = 0; a < 3; ++a) K.n[a] = B.R[3 * a + 0] * g[0] + B.R[3 * a + 1] * g[1] + B.R[3 * a + 2] * g[2];
+    double nn = std::sqrt(dot3(K.n, K.n));
+    for (int a = 0; a < 3; ++a) K.n[a] /= nn;
+    K.psi = f - (double)radius[K.i];
+    double pc[3], arm[3];
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = x[3 * K.i + a] - f * K.n[a];
+      arm[a] = pc[a] - B.t[a];
+    }
+    K.vel[0] = B.nu[0] + B.omega[1] * arm[2] - B.omega[2] * arm[1];
+    K.vel[1] = B.nu[1] + B.omega[2] * arm[0] - B.omega[0] * arm[2];
+    K.vel[2] = B.nu[2] + B.omega[0] * arm[1] - B.omega[1] * arm[0];
+    count[K.i]++;
+  }
+  for (auto& K : cs) tangent_basis(K.n, K.t1, K.t2);
+
+  // ---- masses and split masses
+  std::vector<double> mass(n), mt(C);
+  for (int64_t i = 0; i < n; ++i) mass[i] = particle_mass((double)radius[i], P->density);
+  for (int64_t c = 0; c < C; ++c) {
+    const Contact& K = cs[c];
+    double ni = P->mass_split ? (double)count[K.i] : 1.0;
+    if (K.j >= 0) {
+      double nj = P->mass_split ? (double)count[K.j] : 1.0;
+      mt[c] = 1.0 / (ni / mass[K.i] + nj / mass[K.j]);
+    } else {
+      mt[c] = mass[K.i] / ni;
+    }
+  }
+
+  // ---- projected Jacobi (Alg. 1): every contact reads iterate l-1
+  std::vector<double> w0(3 * n), w(3 * n), lam(3 * C, 0.0), lam_new(3 * C);
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) w0[3 * i + a] = v[3 * i + a] + P->dt * P->g[a];
+  w = w0;
+  // incident contacts of each particle, in contact-list order
+  std::vector<int64_t> start(n + 1, 0), inc;
+  for (int64_t c = 0; c < C; ++c) {
+    start[cs[c].i + 1]++;
+    if (cs[c].j >= 0) start[cs[c].j + 1]++;
+  }
+  for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+  inc.resize(start[n]);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t c = 0; c < C; ++c) {
+      inc[fill[cs[c].i]++] = c;
+      if (cs[c].j >= 0) inc[fill[cs[c].j]++] = c;
+    }
+  }
+  const double mu = P->mu, om = P->relax;
+  for (int32_t l = 1; l <= P->n_iters; ++l) {
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < C; ++c) {
+      const Contact& K = cs[c];
+      double u[3];
+      for (int a = 0; a < 3; ++a)
+        u[a] = w[3 * K.i + a] - (K.j >= 0 ? w[3 * K.j + a] : K.vel[a]);
+      const double* L = &lam[3 * c];
+      double ln = dot3(K.n, L), l1 = dot3(K.t1, L), l2 = dot3(K.t2, L);
+      double yn = ln - mt[c] * (dot3(K.n, u) + P->alpha * K.psi / P->dt);
+      double y1 = l1 - mt[c] * dot3(K.t1, u);
+      double y2 = l2 - mt[c] * dot3(K.t2, u);
+      yn = yn > 0 ? yn : 0.0;
+      double s = std::sqrt(y1 * y1 + y2 * y2);
+      if (s > mu * yn) {
+        double f = mu * yn / s;
+        y1 *= f;
+        y2 *= f;
+      }
+      for (int a = 0; a < 3; ++a) {
+        double yw = yn * K.n[a] + y1 * K.t1[a] + y2 * K.t2[a];
+        lam_new[3 * c + a] = (1.0 - om) * L[a] + om * yw;
+      }
+    }
+    lam.swap(lam_new);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      double acc[3] = {0, 0, 0};
+      for (int64_t q = start[i]; q < start[i + 1]; ++q) {
+        int64_t c = inc[q];
+        double sg = (cs[c].i == i) ? 1.0 : -1.0;
+        for (int a = 0; a < 3; ++a) acc[a] += sg * lam[3 * c + a];
+      }
+      for (int a = 0; a < 3; ++a) w[3 * i + a] = w0[3 * i + a] + acc[a] / mass[i];
+    }
+    if (lam_hist && l <= n_hist)
+      for (int64_t c = 0; c < C && c < cap; ++c)
+        for (int a = 0; a < 3; ++a) lam_hist[((int64_t)(l - 1) * cap + c) * 3 + a] = lam[3 * c + a];
+  }
+
+  // ---- outputs
+  for (int64_t c = 0; c < C && c < cap; ++c) {
+    if (pairs) {
+      pairs[2 * c] = cs[c].i;
+      pairs[2 * c + 1] = cs[c].j >= 0 ? cs[c].j : -1 - cs[c].j;
+    }
+    if (impulses)
+      for (int a = 0; a < 3; ++a) impulses[3 * c + a] = lam[3 * c + a];
+    if (psi_out) psi_out[c] = cs[c].psi;
+    if (normals)
+      for (int a = 0; a < 3; ++a) normals[3 * c + a] = cs[c].n[a];
+  }
+  if (dv)
+    for (int64_t q = 0; q < 3 * n; ++q) dv[q] = w[q] - w0[q];
+
+  // ---- symplectic Euler (Eqs. (4)-(5)): velocity first, then position
+  for (int64_t q = 0; q < 3 * n; ++q) {
+    v[q] = w[q];
+    x[q] = x[q] + P->dt * v[q];
+  }
+  if (advance_bodies) ggo_advance_bodies(nb, bodies, P->dt);
+  return C;
+}
+
+int32_t ggo_num_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int32_t ggo_sizeof_body() { return (int32_t)sizeof(Body); }
+int32_t ggo_sizeof_params() { return (int32_t)sizeof(Params); }
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+"""Seeded synthetic scenes: particle beds, containers and tool trajectories.
+
+This module builds inputs only.  It places spheres on jittered lattices, draws
+radii and tool twists from seeded NumPy generators (PCG64 via
+``numpy.random.default_rng``) and writes kinematic body descriptions.  It holds
+none of the simulation arithmetic (no hashing, contact tests, impulses or
+integration), so both the GPU path and the CPU oracle can take their inputs
+from it.
+
+Body records are plain dicts::
+
+    {"shape": "plane"|"box"|"capsule", "params": [4 floats],
+     "R": 3x3 world<-body rotation, "t": 3-vector, "nu": 3, "omega": 3, "env": int}
+
+Shapes follow the closed-form primitives of Sec. II-C (signed distance
+functions): a plane is the body-frame half space z <= 0 with outward normal +z;
+a box has half extents ``params[0:3]``; a capsule is the set within
+``params[0]`` of the body-frame segment from (0,0,-params[1]) to (0,0,+params[1]).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+DENSITY = 2500.0          # kg/m^3, grain density used for m_i = rho*4/3*pi*r_i^3
+GRAVITY = (0.0, 0.0, -9.81)
+
+
+@dataclass
+class Scene:
+    """A complete simulation input.  Arrays are float32 as handed to both sides."""
+    name: str
+    x: np.ndarray                 # (n, 3) float32 positions [m]
+    v: np.ndarray                 # (n, 3) float32 velocities [m/s]
+    radius: np.ndarray            # (n,) float32 radii [m]
+    bodies: list = field(default_factory=list)
+    dt: float = 1e-3
+    n_iters: int = 20
+    mu: float = 0.5
+    alpha: float = 0.2
+    gravity: tuple = GRAVITY
+    n_steps: int = 100
+    env_offsets: np.ndarray | None = None   # (n_envs+1,) int64, None = one env
+    # per-step twists (n_steps, n_bodies, 6) or None for constant twists
+    twists: np.ndarray | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# bodies
+# ----------------------------------------------------------------------------
+
+def _rot_z_to(nrm):
+    """Rotation whose third column is the unit vector ``nrm`` (body +z -> nrm).
+
+    Only used for axis-aligned container walls, so the result is exact in
+    float32 (entries are 0 and +-1)."""
+    nrm = np.asarray(nrm, dtype=np.float64)
+    table = {
+        (0, 0, 1): np.eye(3),
+        (1, 0, 0): np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], float),
+        (-1, 0, 0): np.array([[0, 0, -1], [0, 1, 0], [1, 0, 0]], float),
+        (0, 1, 0): np.array([[1, 0, 0], [0, 0, 1], [0, -1, 0]], float),
+        (0, -1, 0): np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], float),
+    }
+    return table[tuple(int(round(c)) for c in nrm)]
+
+
+def plane(point, normal, env=0):
+    """Half-space container wall through ``point`` whose outward normal (pointing
+    into the free region) is ``normal``."""
+    return {"shape": "plane", "params": [0.0, 0.0, 0.0, 0.0],
+            "R": _rot_z_to(normal), "t": np.asarray(point, float),
+            "nu": np.zeros(3), "omega": np.zeros(3), "env": env}
+
+
+def box_tool(center, half_extents, nu=(0, 0, 0), omega=(0, 0, 0), R=None, env=0):
+    return {"shape": "box", "params": [*map(float, half_extents), 0.0],
+            "R": np.eye(3) if R is None else np.asarray(R, float),
+            "t": np.asarray(center, float), "nu": np.asarray(nu, float),
+            "omega": np.asarray(omega, float), "env": env}
+
+
+def capsule_tool(center, radius, half_length, nu=(0, 0, 0), omega=(0, 0, 0), R=None, env=0):
+    return {"shape": "capsule", "params": [float(radius), float(half_length), 0.0, 0.0],
+            "R": np.eye(3) if R is None else np.asarray(R, float),
+            "t": np.asarray(center, float), "nu": np.asarray(nu, float),
+            "omega": np.asarray(omega, float), "env": env}
+
+
+def walled_box(x0, x1, y0, y1, env=0, ground_z=0.0):
+    """Ground plane plus four side walls of an open-top container."""
+    return [
+        plane((0, 0, ground_z), (0, 0, 1), env),
+        plane((x0, 0, 0), (1, 0, 0), env),
+        plane((x1, 0, 0), (-1, 0, 0), env),
+        plane((0, y0, 0), (0, 1, 0), env),
+        plane((0, y1, 0), (0, -1, 0), env),
+    ]
+
+
+def random_rotation(rng):
+    """Uniform random rotation from a unit quaternion (Shoemake's method)."""
+    u1, u2, u3 = rng.random(3)
+    a, b = math.sqrt(1 - u1), math.sqrt(u1)
+    qx, qy = a * math.sin(2 * math.pi * u2), a * math.cos(2 * math.pi * u2)
+    qz, qw = b * math.sin(2 * math.pi * u3), b * math.cos(2 * math.pi * u3)
+    return np.array([
+        [1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw), 2 * (qx * qz + qy * qw)],
+        [2 * (qx * qy + qz * qw), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw)],
+        [2 * (qx * qz - qy * qw), 2 * (qy * qz + qx * qw), 1 - 2 * (qx * qx + qy * qy)],
+    ])
+
+
+def uniform_ball(rng, radius):
+    """Point uniform in the 3-ball of the given radius."""
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    return d * radius * rng.random() ** (1.0 / 3.0)
+
+
+# ----------------------------------------------------------------------------
+# particle beds
+# ----------------------------------------------------------------------------
+
+def jittered_lattice(counts, spacing, origin, jitter, rng):
+    """Cubic lattice, index i = (a*counts[1] + b)*counts[2] + c at
+    origin + spacing*(a, b, c) + U(-jitter, jitter)^3 (one (n, 3) draw)."""
+    na, nb, nc = counts
+    a, b, c = np.meshgrid(np.arange(na), np.arange(nb), np.arange(nc), indexing="ij")
+    idx = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1).astype(np.float64)
+    pos = np.asarray(origin, float) + spacing * idx
+    pos += rng.uniform(-jitter, jitter, size=pos.shape)
+    return pos
+
+
+def packed_bed(n, r, x0, x1, y0, y1, rng, overlap=1e-3, jitter_frac=0.1):
+    """A dense resting bed of ``n`` equal spheres inside [x0,x1]x[y0,y1].
+
+    Simple-cubic layers filled bottom-up, row by row (index order is spatial
+    order).  Neighbour spacing is s = 2r(1 - overlap) so every face neighbour
+    touches (six contacts per interior grain, the coordination of a random
+    close packing); each coordinate gets an independent U(+-jitter_frac *
+    overlap * r) jitter, small enough that every face pair still overlaps and
+    no diagonal pair does.  The bottom layer rests on z = 0 with the same
+    overlap.  Returns float64 positions (n, 3)."""
+    s = 2.0 * r * (1.0 - overlap)
+    nx = int(math.floor(((x1 - x0) - 2 * r) / s)) + 1
+    ny = int(math.floor(((y1 - y0) - 2 * r) / s)) + 1
+    per_layer = nx * ny
+    layers = -(-n // per_layer)
+    ox = x0 + 0.5 * ((x1 - x0) - (nx - 1) * s)
+    oy = y0 + 0.5 * ((y1 - y0) - (ny - 1) * s)
+    oz = r * (1.0 - overlap)
+    k = np.arange(n)
+    layer, rem = np.divmod(k, per_layer)
+    row, col = np.divmod(rem, nx)
+    pos = np.stack([ox + s * col, oy + s * row, oz + s * layer], axis=1).astype(np.float64)
+    pos += rng.uniform(-1.0, 1.0, size=pos.shape) * (jitter_frac * overlap * r)
+    assert layers >= 1
+    return pos
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+# ----------------------------------------------------------------------------
+
+def drop_scene(seed=0):
+    """4,096 spheres, r = 5 mm, jittered 16^3 lattice (spacing 2.1r, jitter
+    +-0.05r) falling onto the floor of a 0.2 m box; dt = 1 ms, 20 iterations,
+    mu = 0.5, 100 steps."""
+    r = 0.005
+    rng = np.random.default_rng(seed)
+    pos = jittered_lattice((16, 16, 16), 2.1 * r, (0.02125, 0.02125, 1.1 * r), 0.05 * r, rng)
+    n = pos.shape[0]
+    return Scene("drop-4096", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), walled_box(0.0, 0.2, 0.0, 0.2),
+                 dt=1e-3, n_iters=20, mu=0.5, alpha=0.2, n_steps=100)
+
+
+def scoop_scene(seed=0, n=1 << 20, r=0.002):
+    """1,048,576 spheres, r = 2 mm, resting bed in a 1 x 1 m walled box, with a
+    0.05 x 0.1 x 0.2 m box tool whose bottom edge starts 1 cm above the bed at
+    x = 0.3 m and moves at 0.2 m/s along (cos 30deg, 0, -sin 30deg)."""
+    rng = np.random.default_rng(seed)
+    pos = packed_bed(n, r, 0.0, 1.0, 0.0, 1.0, rng)
+    s = 2.0 * r * (1.0 - 1e-3)
+    per_layer = int(math.floor((1.0 - 2 * r) / s) + 1) ** 2
+    full_layers = n // per_layer
+    surface = r * (1 - 1e-3) + s * (full_layers - 1) + r
+    half = (0.025, 0.05, 0.1)
+    center = (0.3, 0.5, surface + 0.01 + half[2])
+    speed = 0.2
+    a = math.radians(30.0)
+    tool = box_tool(center, half, nu=(speed * math.cos(a), 0.0, -speed * math.sin(a)))
+    bodies = walled_box(0.0, 1.0, 0.0, 1.0) + [tool]
+    return Scene(f"scoop-{n}", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), bodies, dt=1e-3, n_iters=20, mu=0.5,
+                 alpha=0.2, n_steps=200)
+
+
+def column_scene(n=4096, r=0.005, seed=0, overlap=1e-3):
+    """A resting column of equal spheres (the paper's 'particles at rest'
+    benchmark shape) on a 8 x 8 footprint per layer, walled box around it."""
+    rng = np.random.default_rng(seed)
+    side = 8 * 2 * r * (1 - overlap) + 2 * r * overlap
+    pos = packed_bed(n, r, 0.0, side, 0.0, side, rng, overlap=overlap)
+    return Scene(f"column-{n}", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), walled_box(0.0, side, 0.0, side),
+                 n_steps=100)
+
+
+def batched_scene(seed=0, n_envs=256, lo=8192, hi=65536, r=0.003, n_steps=100,
+                  resample_every=20):
+    """256 independent walled 0.3 x 0.3 m beds of U{8192..65536} spheres
+    (r = 3 mm), each with a capsule tool (radius 2 cm, 15 cm between cap
+    centres) in a random orientation starting 1 mm above its bed, driven by
+    piecewise-constant random twists (|nu| <= 0.3 m/s, |omega| <= 1 rad/s,
+    first segment moving down), resampled every 20 steps."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(lo, hi + 1, size=n_envs)
+    offsets = np.zeros(n_envs + 1, np.int64)
+    offsets[1:] = np.cumsum(counts)
+    xs, bodies = [], []
+    n_seg = -(-n_steps // resample_every)
+    tw = np.zeros((n_steps, 0, 6))
+    twist_cols = []
+    spacing_env = 0.5     # envs are laid out on a grid, 0.5 m apart (no overlap)
+    grid = int(math.ceil(math.sqrt(n_envs)))
+    for e in range(n_envs):
+        erng = np.random.default_rng(1000 + seed + e)
+        gx, gy = (e % grid) * spacing_env, (e // grid) * spacing_env
+        pos = packed_bed(int(counts[e]), r, gx, gx + 0.3, gy, gy + 0.3, erng)
+        xs.append(pos)
+        top = float(pos[:, 2].max()) + r
+        Rm = random_rotation(erng)
+        # lowest point of the capsule above the bed by 1 mm
+        axis = Rm[:, 2]
+        low = 0.075 * abs(axis[2]) + 0.02
+        center = (gx + 0.15, gy + 0.15, top + 0.001 + low)
+        for wb in walled_box(gx, gx + 0.3, gy, gy + 0.3, env=e):
+            bodies.append(wb)
+            twist_cols.append(np.zeros((n_steps, 6)))
+        cap = capsule_tool(center, 0.02, 0.075, R=Rm, env=e)
+        seq = np.zeros((n_steps, 6))
+        for sgi in range(n_seg):
+            nu = uniform_ball(erng, 0.3)
+            if sgi == 0 and nu[2] > 0:
+                nu[2] = -nu[2]
+            om = uniform_ball(erng, 1.0)
+            seq[sgi * resample_every:(sgi + 1) * resample_every, :3] = nu
+            seq[sgi * resample_every:(sgi + 1) * resample_every, 3:] = om
+        cap["nu"], cap["omega"] = seq[0, :3].copy(), seq[0, 3:].copy()
+        bodies.append(cap)
+        twist_cols.append(seq)
+    x = np.concatenate(xs, axis=0)
+    n = x.shape[0]
+    tw = np.stack(twist_cols, axis=1)   # (n_steps, n_bodies, 6)
+    return Scene(f"batched-{n_envs}x", _f32(x), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), bodies, dt=1e-3, n_iters=20, mu=0.5,
+                 alpha=0.2, n_steps=n_steps, env_offsets=offsets,
+                 twists=tw.astype(np.float32))
+
+
+def diff_scene(seed=0, n=32768, r=0.003):
+    """32,768 spheres (r = 3 mm) resting in a 0.3 x 0.3 m walled footprint
+    with a capsule tool 1 mm above the bed; 50 steps."""
+    rng = np.random.default_rng(seed)
+    pos = packed_bed(n, r, 0.0, 0.3, 0.0, 0.3, rng)
+    top = float(pos[:, 2].max()) + r
+    Rm = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], float)   # axis along world y
+    cap = capsule_tool((0.1, 0.15, top + 0.001 + 0.02), 0.02, 0.075, nu=(0.2, 0, -0.05), R=Rm)
+    bodies = walled_box(0.0, 0.3, 0.0, 0.3) + [cap]
+    return Scene(f"diff-{n}", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), bodies, n_steps=50)
+
+
+def polydisperse_radii(n, rng, median=0.002, sigma=0.25, lo=0.001, hi=0.004):
+    r = np.exp(math.log(median) + sigma * rng.normal(size=n))
+    return np.clip(r, lo, hi)
+
+
+def random_spheres(n, box, r, rng, r_jitter=0.0):
+    """Uniform random centres in ``box`` = ((x0,x1),(y0,y1),(z0,z1)); radii
+    r*(1+U(-r_jitter, r_jitter)).  Used for small brute-force tests."""
+    lo = np.array([b[0] for b in box])
+    hi = np.array([b[1] for b in box])
+    x = lo + (hi - lo) * rng.random((n, 3))
+    rad = r * (1.0 + r_jitter * rng.uniform(-1, 1, size=n))
+    return _f32(x), _f32(rad)
+
+
+def scaled(scene: Scene, n: int, seed=0):
+    """A smaller bed of the same structure as ``scene`` (same radius and
+    packing) for tests that need the full-size recipe at oracle-friendly size."""
+    r = float(scene.radius[0])
+    rng = np.random.default_rng(seed)
+    side = max(0.05, math.sqrt(n / 10.0) * 2 * r)
+    pos = packed_bed(n, r, 0.0, side, 0.0, side, rng)
+    return Scene(f"{scene.name}-scaled{n}", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), walled_box(0.0, side, 0.0, side),
+                 dt=scene.dt, n_iters=scene.n_iters, mu=scene.mu, alpha=scene.alpha,
+                 n_steps=scene.n_steps)
