@@ -1,0 +1,175 @@
+"""Throughput of the granular contact step on one MI355X.
+
+Workload: 1,048,576 spheres (r = 2 mm) in a resting bed of a 1 x 1 m walled
+box, a 0.05 x 0.1 x 0.2 m box tool moving at 0.2 m/s on a linear scoop path,
+dt = 1 ms, 20 projected-Jacobi sweeps per step, mu = 0.5.  A step is one pass
+of the whole hot path: cell keys, bucket sort, contact detection, 20 sweeps,
+position update.  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
+(one projected-Jacobi sweep) measured with HIP events on the library's stream,
+and the FP64 oracle timed on this host's cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (20 PJA iters) at 1M particles; batched & backward vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pja_traffic_scoop-1M.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pja_algorithmic_bytes(n, contacts):
+    """Bytes one projected-Jacobi sweep must move: per contact its impulse
+    read and written (12 + 12), both endpoint indices (8), normal (12),
+    effective mass and bias (8) and the two endpoint iterates (12); per
+    particle its iterate read and written (16 + 16)."""
+    return 64.0 * contacts + 32.0 * n
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_2306_01369_amd/csrc/kernels.hip.h", "paper_2306_01369_amd/csrc/gg.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by a copy
+    kernel's reading), if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, steps):
+    import oracle as O
+    orc = O.scene_oracle(scene)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        orc.step()
+    dt = time.perf_counter() - t0
+    return {"value": scene.n * steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same 1,048,576-sphere scoop bed from its initial state, FP64"}
+
+
+def copy_calibration(mib=512, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} copies of {mib} MiB")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the workload is a single bed on one device; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        copy_calibration()
+        return
+
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+
+    log("generating the scoop bed")
+    scene = scenes.scoop_scene()
+    n = scene.n
+    stream = torch.cuda.current_stream(0).cuda_stream
+    x = torch.from_numpy(scene.x).to("cuda:0")
+    v = torch.from_numpy(scene.v).to("cuda:0")
+    r = torch.from_numpy(scene.radius).to("cuda:0")
+    sim = gg.Sim(x, v, r, scene.bodies, dt=scene.dt, alpha=scene.alpha, mu=scene.mu, n_iters=scene.n_iters,
+                 gravity=scene.gravity, device=0, stream=stream, profile=True)
+    del x, v, r
+    log(f"n={n} warmup {args.warmup} steps")
+    if args.warmup:
+        sim.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = sim.stats()
+    log(f"done: {elapsed:.3f} s, stats {st}")
+
+    steps = args.steps
+    value = n * steps / elapsed
+    ms_step = 1e3 * elapsed / steps
+    launches = max(1, st["pja_launches"])
+    pja_ms = st["ms_pja"] / launches
+    contacts_avg = st["contacts_summed"] / max(1, st["steps_done"])
+    algo = pja_algorithmic_bytes(n, contacts_avg)
+    achieved = algo / (pja_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scoop bed: 1,048,576 spheres r=2mm, resting bed in a 1x1 m walled box, "
+                               "box tool 0.05x0.1x0.2 m at 0.2 m/s on a linear scoop path, dt=1 ms, "
+                               "20 PJA sweeps, mu=0.5",
+                   "n": n, "pja_iters": scene.n_iters, "contacts_per_step": contacts_avg,
+                   "hit_rate": 2.0 * st["n_pp"] / max(1, st["candidates"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_pja (one projected-Jacobi sweep)", "avg_launch_us": pja_ms * 1e3,
+                     "algorithmic_bytes_per_launch": algo},
+        "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
+                               "integrate": st["ms_integrate"] / steps},
+    }
+    sim.close()
+    if not args.skip_cpu_baseline:
+        log(f"oracle on the host cores: {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * gg.h -- C ABI of the MI355X granular contact step.
+ *
+ * One timestep of the method of "GranularGym: High Performance Simulation for
+ * Robotic Tasks with Granular Materials" (arXiv 2306.01369), Sec. II:
+ *   1. cell coordinates kappa_i = round(x_i / c) and the spatial hash of Eq. (6)
+ *      h_i = XOR_a p_a (kappa_ia - q)  mod n_h;
+ *   2. a table of particles per hash bucket (the role of the linked hashmap of
+ *      Alg. 2, built here by a counting sort instead of compare-and-swap);
+ *   3. particle-particle contacts from the particle's own cell and its 26
+ *      neighbour cells, ||x_i - x_j||^2 <= (r_i + r_j)^2 (Sec. II-B, II-C);
+ *   4. particle-body contacts psi = f_G(X^{-1} x) - r <= 0 through closed-form
+ *      signed distance functions (Eq. (7), Sec. II-C);
+ *   5. projected Jacobi sweeps over the stored contacts (Alg. 1) for the contact
+ *      NCP of Eqs. (1)-(3) with the Baumgarte term alpha*psi/dt;
+ *   6. symplectic Euler: velocities first, then positions (Eqs. (4)-(5)).
+ *
+ * Conventions shared by every call
+ *   - All calls return a gg_status and never throw.  Argument checks run on the
+ *     host before any device work; a failed HIP call leaves the handle in a
+ *     sticky failed state (every later call returns GG_ERR_HIP).
+ *   - gg_error_detail() returns a message for the last failure on this thread.
+ *   - gg_mem says where a caller buffer lives: GG_MEM_HOST (pageable or pinned
+ *     host memory) or GG_MEM_DEVICE (device memory on params.device).
+ *   - The library copies every input into buffers it owns and copies outputs
+ *     into caller memory; it never keeps or frees a caller pointer.
+ *   - Work is enqueued on params.stream (a hipStream_t; NULL makes the library
+ *     create its own non-blocking stream).  Calls return after the work they
+ *     enqueued has finished.
+ *   - Arrays of 3-vectors are dense row-major (n x 3, float32).
+ *   - Units are SI (m, s, kg).
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gg_sim gg_sim; /* opaque; owns every device buffer of one simulation */
+
+typedef enum {
+  GG_OK = 0,
+  GG_ERR_INVALID = 1,     /* bad argument; nothing was changed */
+  GG_ERR_OOM = 2,         /* device or host allocation failed */
+  GG_ERR_HIP = 3,         /* a HIP runtime call failed; the handle is unusable */
+  GG_ERR_CAPACITY = 4,    /* a particle exceeded its contact capacity; see gg_step */
+  GG_ERR_NONFINITE = 5,   /* non-finite or out-of-range position/velocity */
+  GG_ERR_NO_TAPE = 6,     /* gg_step_backward without a recorded forward */
+  GG_ERR_UNSUPPORTED = 7  /* valid request that this build does not implement */
+} gg_status;
+
+typedef enum { GG_PLANE = 0, GG_BOX = 1, GG_CAPSULE = 2 } gg_shape;
+typedef enum { GG_MEM_HOST = 0, GG_MEM_DEVICE = 1 } gg_mem;
+
+/* A kinematic rigid body (Sec. II: bodies are driven by time and receive no
+ * reaction).  Shapes are the closed-form SDF primitives of Sec. II-C:
+ *   GG_PLANE:   f(p) = p_z (the half space below the body-frame xy plane is solid)
+ *   GG_BOX:     half extents params[0..2]
+ *   GG_CAPSULE: radius params[0] around the body-frame segment
+ *               (0,0,-params[1]) .. (0,0,+params[1])
+ * pose = row-major [R | t] (3 x 4) mapping body to world, x_w = R p + t.
+ * twist = (nu, omega): velocity of the body origin and angular velocity, both
+ * in the world frame.  The pose given is the pose at the start of the next
+ * step; poses are advanced by the library after every step,
+ * t += dt nu, R = Exp(dt [omega]x) R, in double precision. */
+typedef struct {
+  int32_t env;       /* environment the body acts in (0 .. n_envs-1) */
+  int32_t shape;     /* gg_shape */
+  float params[4];
+  float pose[12];
+  float twist[6];
+} gg_body;
+
+/* Flags for gg_params.flags */
+#define GG_FLAG_PROFILE 1u     /* time detection and projected-Jacobi phases with HIP events */
+#define GG_FLAG_DIAGNOSTICS 2u /* keep the last step's velocity change (GG_FIELD_DV) */
+
+/* Simulation parameters.  Zero selects the stated default. */
+typedef struct {
+  float dt;          /* timestep (> 0) */
+  float alpha;       /* Baumgarte factor, Sec. II-A (>= 0) */
+  float mu;          /* Coulomb friction coefficient, Eq. (3) (>= 0) */
+  float gravity[3];  /* external acceleration (F_ext / m) */
+  int32_t n_iters;   /* projected-Jacobi sweeps per step, Alg. 1 (>= 1) */
+  float cell_size;   /* hash cell edge c; 0 -> 2 r_max (1 + 2^-10); must be >= 2 r_max */
+  int64_t hash_size; /* buckets n_h per environment; 0 -> 2 x (particles of the env),
+                        the heuristic of Sec. II-B */
+  float relax;       /* over-relaxation of the impulse update, 0 -> 1 */
+  int32_t mass_split;/* 1: per-contact mass m/n_i (mass splitting); 0: plain masses */
+  int32_t checkpoint_every;          /* backward pass: steps per checkpoint (0 -> 10) */
+  int32_t max_contacts_per_particle; /* 0 -> bound from the radius ratio + bodies */
+  int32_t precision; /* 0 = binary32 (only value supported) */
+  float density;     /* grain density for m = rho 4/3 pi r^3; 0 -> 2500 */
+  uint32_t flags;    /* GG_FLAG_* */
+  int32_t device;    /* HIP device ordinal */
+  void* stream;      /* hipStream_t or NULL */
+} gg_params;
+
+/* Create a simulation of n particles split into n_envs independent
+ * environments: particles env_offsets[e] .. env_offsets[e+1]-1 form
+ * environment e (env_offsets: n_envs+1 host int64 values, first 0, last n,
+ * non-decreasing; NULL means one environment).  Particles of different
+ * environments never touch.  x, v: n x 3; radius: n (> 0).  where applies to
+ * x, v and radius.  n may be 0.  On success *out owns a new handle.
+ * Errors: GG_ERR_INVALID (bad params, offsets, radius <= 0, cell smaller than
+ * 2 r_max, |x / c| >= 2^30), GG_ERR_NONFINITE (non-finite x or v),
+ * GG_ERR_OOM, GG_ERR_HIP. */
+gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_offsets, int64_t n,
+                    const float* x, const float* v, const float* radius, gg_mem where, gg_sim** out);
+
+/* Replace all bodies (n_bodies >= 0).  Each body's env must be < n_envs.
+ * Errors: GG_ERR_INVALID (unknown shape, bad env, non-positive extents,
+ * non-finite pose or twist). */
+gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg_mem where);
+
+/* Advance n_steps timesteps (>= 0).  twists: NULL keeps every body's current
+ * twist, else n_steps x n_bodies x 6 floats, the twist of each body during
+ * each step (where applies to twists).
+ * Capacity: if a particle has more contacts than its capacity (see
+ * GG_FIELD_STATS), the step is abandoned before any impulse is applied, the
+ * state stays that of the start of that step, later steps of the call are not
+ * run, and GG_ERR_CAPACITY is returned; GG_FIELD_STATS reports the steps
+ * completed.  GG_ERR_NONFINITE likewise if a position leaves the hashable
+ * range or becomes non-finite. */
+gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem where);
+
+/* Reverse-mode gradient of the last gg_step call (differentiable extension of
+ * the method; see the design notes).  dL_dx, dL_dv: n x 3 gradients with
+ * respect to the final positions and velocities; outputs dL_dx0, dL_dv0
+ * (n x 3) and dL_dtwists (n_steps x n_bodies x 6), any may be NULL.
+ * Returns GG_ERR_NO_TAPE when no differentiable forward was recorded;
+ * this build records none and returns GG_ERR_UNSUPPORTED. */
+gg_status gg_step_backward(gg_sim* sim, const float* dL_dx, const float* dL_dv, float* dL_dx0,
+                           float* dL_dv0, float* dL_dtwists, gg_mem where);
+
+/* Fields for gg_read */
+enum {
+  GG_FIELD_POS = 0,        /* n x 3 float32, caller's particle order */
+  GG_FIELD_VEL = 1,        /* n x 3 float32 */
+  GG_FIELD_CELL_INDEX = 2, /* n int64: bucket of each particle at the last detection
+                              (env bucket offset + Eq. (6) value) */
+  GG_FIELD_CONTACTS = 3,   /* C x 2 int32: particle pairs (i < j) sorted by (i, j), then
+                              particle-body pairs (i, body) sorted by (i, body) */
+  GG_FIELD_IMPULSES = 4,   /* C x 3 float32: world-frame impulse R_c lam_c on the first
+                              member of each contact, same order as GG_FIELD_CONTACTS */
+  GG_FIELD_STATS = 5,      /* one gg_stats */
+  GG_FIELD_DV = 6,         /* n x 3 float32: velocity change by impulses in the last
+                              step (needs GG_FLAG_DIAGNOSTICS) */
+  GG_FIELD_RADIUS = 7      /* n float32 */
+};
+
+typedef struct {
+  int64_t steps_done;     /* steps completed by the last gg_step call */
+  int64_t steps_total;    /* steps completed since creation */
+  int64_t n_pp;           /* particle-particle contacts at the last detection */
+  int64_t n_pb;           /* particle-body contacts at the last detection */
+  int64_t candidates;     /* ordered candidate pairs tested at the last detection */
+  int64_t max_contacts;   /* largest contact count of one particle at the last detection */
+  int64_t capacity;       /* contact capacity per particle */
+  int64_t last_status;    /* gg_status of the last gg_step call */
+  int64_t n;              /* particles */
+  int64_t n_buckets;      /* hash buckets over all environments */
+  double ms_detect;       /* profiled: cell keys + sort + detection, summed over the last call */
+  double ms_pja;          /* profiled: projected-Jacobi sweeps, summed */
+  double ms_integrate;    /* profiled: position update, summed */
+  int64_t pja_launches;   /* profiled: projected-Jacobi launches timed */
+  int64_t contacts_summed;/* contacts (pairs + body) summed over the steps of the last call */
+} gg_stats;
+
+/* Copy a field into dst (where says where dst lives).  If dst is NULL only
+ * *written is set, to the number of bytes the field needs.  Otherwise
+ * capacity_bytes must be at least that size (else GG_ERR_INVALID) and
+ * *written receives the bytes copied.  Contacts and impulses describe the last
+ * completed detection and projected-Jacobi solve. */
+gg_status gg_read(gg_sim* sim, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written,
+                  gg_mem where);
+
+/* Release every resource of the handle (NULL is ignored). */
+void gg_destroy(gg_sim* sim);
+
+/* Static description of a status code. */
+const char* gg_status_string(gg_status status);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* gg_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GG_H */

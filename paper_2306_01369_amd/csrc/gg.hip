@@ -1,0 +1,775 @@
+// Host side of libgg: the C ABI declared in include/gg.h, argument checks,
+// device buffers, kinematic body poses, and the per-step launch sequence.
+#include "gg.h"
+#include "kernels.hip.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_detail;
+
+gg_status fail(gg_status s, const std::string& msg) {
+  g_detail = msg;
+  return s;
+}
+
+struct HostBody {
+  int32_t env, shape;
+  float params[4];
+  double R[9], t[3], nu[3], om[3];
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool finite3(const float* a) { return std::isfinite(a[0]) && std::isfinite(a[1]) && std::isfinite(a[2]); }
+
+// Upper bound on how many spheres of radius >= r_min can touch one sphere of
+// radius r_max: caps of half-angle asin(r_min / (r_max + r_min)) cannot
+// overlap on the unit sphere, so N <= 2 / (1 - cos theta); 25% margin for
+// overlapping (compressed) neighbours.
+int contact_bound(double r_min, double r_max) {
+  double s = r_min / (r_max + r_min);
+  double c = std::sqrt(std::max(0.0, 1.0 - s * s));
+  double N = 2.0 / (1.0 - c);
+  return (int)std::ceil(1.25 * N);
+}
+
+// Exp(dt [om]x) R by Rodrigues' formula, t += dt nu (double precision).
+void advance_pose(HostBody& B, double dt) {
+  for (int a = 0; a < 3; ++a) B.t[a] += dt * B.nu[a];
+  double w[3] = {B.om[0] * dt, B.om[1] * dt, B.om[2] * dt};
+  double th = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  if (th == 0.0) return;
+  double k[3] = {w[0] / th, w[1] / th, w[2] / th};
+  double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+  double s = std::sin(th), c1 = 1.0 - std::cos(th);
+  double E[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double kk = 0;
+      for (int m = 0; m < 3; ++m) kk += K[3 * r + m] * K[3 * m + c];
+      E[3 * r + c] = (r == c ? 1.0 : 0.0) + s * K[3 * r + c] + c1 * kk;
+    }
+  double Rn[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0;
+      for (int m = 0; m < 3; ++m) acc += E[3 * r + m] * B.R[3 * m + c];
+      Rn[3 * r + c] = acc;
+    }
+  std::memcpy(B.R, Rn, sizeof(Rn));
+}
+
+ggk::DevBody to_dev(const HostBody& B) {
+  ggk::DevBody d;
+  d.shape = B.shape;
+  d.env = B.env;
+  for (int q = 0; q < 4; ++q) d.params[q] = B.params[q];
+  for (int q = 0; q < 9; ++q) d.R[q] = (float)B.R[q];
+  for (int q = 0; q < 3; ++q) {
+    d.t[q] = (float)B.t[q];
+    d.nu[q] = (float)B.nu[q];
+    d.om[q] = (float)B.om[q];
+  }
+  return d;
+}
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct gg_sim {
+  gg_params p{};
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool failed = false;
+
+  int64_t n = 0;
+  int32_t n_envs = 1;
+  std::vector<int64_t> env_off;
+  std::vector<int32_t> env_nh, env_boff;
+  int64_t n_buckets = 0;
+  float cell = 0, inv_c = 0, r_max = 0, r_min = 0;
+  int K = 0, K_pp = 0;
+  int64_t n_pad = 0;
+
+  std::vector<HostBody> bodies;
+  std::vector<int32_t> body_lo, body_hi;
+
+  // device buffers
+  float4 *x = nullptr, *v = nullptr, *wa = nullptr, *wb = nullptr, *dv = nullptr;
+  int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
+  int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
+  float *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
+  int32_t *env_of = nullptr, *d_env_nh = nullptr, *d_env_boff = nullptr, *d_body_lo = nullptr,
+          *d_body_hi = nullptr;
+  ggk::DevBody* d_bodies = nullptr;
+  int64_t d_bodies_cap = 0;
+  ggk::DevBody* h_bodies = nullptr;  // pinned staging
+  int64_t h_bodies_cap = 0;
+  ggk::Ctl* ctl = nullptr;
+  ggk::Ctl* h_ctl = nullptr;  // pinned
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  std::vector<hipEvent_t> events;
+
+  gg_stats stats{};
+  bool contacts_valid = false;
+  std::vector<HostBody> pose_hist;  // scratch for gg_step
+};
+
+namespace {
+
+gg_status hip_fail(gg_sim* s, hipError_t e, const char* what) {
+  if (s) s->failed = true;
+  return fail(GG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(sim, expr)                              \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return hip_fail(sim, _e, #expr); \
+  } while (0)
+
+gg_status check_params(const gg_params* p) {
+  if (!p) return fail(GG_ERR_INVALID, "params is NULL");
+  if (!(p->dt > 0.0f) || !std::isfinite(p->dt)) return fail(GG_ERR_INVALID, "dt must be finite and > 0");
+  if (!(p->alpha >= 0.0f) || !std::isfinite(p->alpha)) return fail(GG_ERR_INVALID, "alpha must be finite and >= 0");
+  if (!(p->mu >= 0.0f) || !std::isfinite(p->mu)) return fail(GG_ERR_INVALID, "mu must be finite and >= 0");
+  if (!finite3(p->gravity)) return fail(GG_ERR_INVALID, "gravity must be finite");
+  if (p->n_iters < 1 || p->n_iters > 100000) return fail(GG_ERR_INVALID, "n_iters must be in [1, 100000]");
+  if (!(p->cell_size >= 0.0f) || !std::isfinite(p->cell_size)) return fail(GG_ERR_INVALID, "cell_size must be finite and >= 0");
+  if (p->hash_size < 0 || p->hash_size > (int64_t)1 << 30) return fail(GG_ERR_INVALID, "hash_size must be in [0, 2^30]");
+  if (!(p->relax >= 0.0f && p->relax <= 2.0f)) return fail(GG_ERR_INVALID, "relax must be in [0, 2] (0 = default 1)");
+  if (p->mass_split != 0 && p->mass_split != 1) return fail(GG_ERR_INVALID, "mass_split must be 0 or 1");
+  if (p->checkpoint_every < 0) return fail(GG_ERR_INVALID, "checkpoint_every must be >= 0");
+  if (p->max_contacts_per_particle < 0 || p->max_contacts_per_particle > 256)
+    return fail(GG_ERR_INVALID, "max_contacts_per_particle must be in [0, 256]");
+  if (p->precision != 0) return fail(GG_ERR_UNSUPPORTED, "only precision 0 (binary32) is built");
+  if (!(p->density >= 0.0f) || !std::isfinite(p->density)) return fail(GG_ERR_INVALID, "density must be finite and >= 0");
+  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS)) return fail(GG_ERR_INVALID, "unknown flag bits");
+  if (p->device < 0) return fail(GG_ERR_INVALID, "device must be >= 0");
+  return GG_OK;
+}
+
+gg_status ensure_tmp(gg_sim* s, size_t bytes) {
+  if (bytes <= s->tmp_bytes) return GG_OK;
+  if (s->tmp) HIPCHK(s, hipFree(s->tmp));
+  s->tmp = nullptr;
+  s->tmp_bytes = 0;
+  hipError_t e = hipMalloc(&s->tmp, bytes);
+  if (e != hipSuccess) return fail(GG_ERR_OOM, "readout buffer allocation failed");
+  s->tmp_bytes = bytes;
+  return GG_OK;
+}
+
+// (Re)allocate the contact table for capacity K per particle.
+gg_status ensure_ell(gg_sim* s, int K) {
+  if (K == s->K && s->partner) return GG_OK;
+  (void)hipFree(s->partner); (void)hipFree(s->Px); (void)hipFree(s->Py); (void)hipFree(s->Pz);
+  (void)hipFree(s->Psi);
+  s->partner = nullptr; s->Px = s->Py = s->Pz = s->Psi = nullptr;
+  size_t slots = (size_t)s->n_pad * (size_t)K;
+  if (dev_alloc(&s->partner, slots) != hipSuccess || dev_alloc(&s->Px, slots) != hipSuccess ||
+      dev_alloc(&s->Py, slots) != hipSuccess || dev_alloc(&s->Pz, slots) != hipSuccess ||
+      dev_alloc(&s->Psi, slots) != hipSuccess)
+    return fail(GG_ERR_OOM, "contact table allocation failed");
+  s->K = K;
+  s->stats.capacity = K;
+  s->contacts_valid = false;
+  return GG_OK;
+}
+
+int compute_K(const gg_sim* s) {
+  if (s->p.max_contacts_per_particle > 0) return s->p.max_contacts_per_particle;
+  int nb_env = 0;
+  for (int e = 0; e < s->n_envs; ++e) nb_env = std::max(nb_env, s->body_hi[e] - s->body_lo[e]);
+  int K = s->K_pp + nb_env;
+  K = (K + 1) & ~1;
+  return std::min(K, 256);
+}
+
+ggk::EnvTables env_tables(const gg_sim* s) {
+  ggk::EnvTables t;
+  t.env_of = s->env_of;
+  t.nh = s->d_env_nh;
+  t.boff = s->d_env_boff;
+  t.body_lo = s->d_body_lo;
+  t.body_hi = s->d_body_hi;
+  return t;
+}
+
+void free_all(gg_sim* s) {
+  void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->h, s->rank, s->counts, s->bstart, s->bsum,
+                  s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
+                  s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (s->h_bodies) (void)hipHostFree(s->h_bodies);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  s->events.clear();
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+gg_status copy_in(const void* src, size_t bytes, gg_mem where, void* host_dst) {
+  if (bytes == 0) return GG_OK;
+  if (where == GG_MEM_HOST) {
+    std::memcpy(host_dst, src, bytes);
+    return GG_OK;
+  }
+  hipError_t e = hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("copy of device input: ") + hipGetErrorString(e));
+  return GG_OK;
+}
+
+gg_status upload_env_bodies(gg_sim* s) {
+  std::vector<int32_t> lo(s->n_envs, 0), hi(s->n_envs, 0);
+  for (int e = 0; e < s->n_envs; ++e) lo[e] = hi[e] = 0;
+  int nb = (int)s->bodies.size();
+  for (int e = 0, b = 0; e < s->n_envs; ++e) {
+    while (b < nb && s->bodies[b].env < e) ++b;
+    lo[e] = b;
+    while (b < nb && s->bodies[b].env == e) ++b;
+    hi[e] = b;
+  }
+  s->body_lo = lo;
+  s->body_hi = hi;
+  if (s->env_of) {
+    HIPCHK(s, hipMemcpy(s->d_body_lo, lo.data(), lo.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(s->d_body_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
+  }
+  return GG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gg_status_string(gg_status st) {
+  switch (st) {
+    case GG_OK: return "ok";
+    case GG_ERR_INVALID: return "invalid argument";
+    case GG_ERR_OOM: return "out of memory";
+    case GG_ERR_HIP: return "HIP runtime error";
+    case GG_ERR_CAPACITY: return "contact capacity exceeded";
+    case GG_ERR_NONFINITE: return "non-finite or out-of-range state";
+    case GG_ERR_NO_TAPE: return "no recorded forward pass";
+    case GG_ERR_UNSUPPORTED: return "unsupported in this build";
+  }
+  return "unknown status";
+}
+
+const char* gg_error_detail(void) { return g_detail.c_str(); }
+
+gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_offsets, int64_t n,
+                    const float* x, const float* v, const float* radius, gg_mem where, gg_sim** out) {
+  g_detail.clear();
+  if (!out) return fail(GG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  gg_status st = check_params(params);
+  if (st != GG_OK) return st;
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (n < 0 || n > ((int64_t)1 << 30)) return fail(GG_ERR_INVALID, "n must be in [0, 2^30]");
+  if (n_envs < 1) return fail(GG_ERR_INVALID, "n_envs must be >= 1");
+  std::vector<int64_t> off(n_envs + 1);
+  if (env_offsets) {
+    for (int e = 0; e <= n_envs; ++e) off[e] = env_offsets[e];
+    if (off[0] != 0 || off[n_envs] != n) return fail(GG_ERR_INVALID, "env_offsets must start at 0 and end at n");
+    for (int e = 0; e < n_envs; ++e)
+      if (off[e + 1] < off[e]) return fail(GG_ERR_INVALID, "env_offsets must be non-decreasing");
+  } else {
+    if (n_envs != 1) return fail(GG_ERR_INVALID, "env_offsets is required when n_envs > 1");
+    off[0] = 0;
+    off[1] = n;
+  }
+  if (n > 0 && (!x || !v || !radius)) return fail(GG_ERR_INVALID, "x, v and radius are required when n > 0");
+
+  // ---- inputs to the host, then checks
+  std::vector<float> hx(3 * n), hv(3 * n), hr(n);
+  if (where == GG_MEM_DEVICE) {
+    DeviceGuard g(params->device);
+    if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+    if ((st = copy_in(x, 12 * n, where, hx.data())) != GG_OK) return st;
+    if ((st = copy_in(v, 12 * n, where, hv.data())) != GG_OK) return st;
+    if ((st = copy_in(radius, 4 * n, where, hr.data())) != GG_OK) return st;
+  } else {
+    copy_in(x, 12 * n, where, hx.data());
+    copy_in(v, 12 * n, where, hv.data());
+    copy_in(radius, 4 * n, where, hr.data());
+  }
+  float rmax = 0.0f, rmin = INFINITY;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(hr[i] > 0.0f) || !std::isfinite(hr[i])) return fail(GG_ERR_INVALID, "radius must be finite and > 0");
+    rmax = std::max(rmax, hr[i]);
+    rmin = std::min(rmin, hr[i]);
+    if (!finite3(&hx[3 * i]) || !finite3(&hv[3 * i])) return fail(GG_ERR_NONFINITE, "non-finite position or velocity");
+  }
+  if (n == 0) rmin = rmax = 1.0f;
+  float cell = params->cell_size;
+  if (cell == 0.0f) cell = (float)(2.0 * (double)rmax * (1.0 + 1.0 / 1024.0));
+  if (n > 0 && !((double)cell >= 2.0 * (double)rmax))
+    return fail(GG_ERR_INVALID, "cell_size must be at least twice the largest radius");
+  const float inv_c = 1.0f / cell;
+  for (int64_t q = 0; q < 3 * n; ++q) {
+    float s = hx[q] * inv_c;
+    if (!(std::fabs(std::nearbyint(s)) < 1073741824.0f))
+      return fail(GG_ERR_INVALID, "position too far from the origin for the cell size (|x/c| >= 2^30)");
+  }
+  std::vector<int32_t> env_nh(n_envs), env_boff(n_envs);
+  int64_t total = 0;
+  for (int e = 0; e < n_envs; ++e) {
+    int64_t ne = off[e + 1] - off[e];
+    int64_t nh = params->hash_size > 0 ? params->hash_size : std::max<int64_t>(1, 2 * ne);
+    env_nh[e] = (int32_t)nh;
+    env_boff[e] = (int32_t)total;
+    total += nh;
+    if (total > ((int64_t)1 << 31) - 2) return fail(GG_ERR_INVALID, "total hash buckets exceed 2^31 - 2");
+  }
+
+  gg_sim* s = new (std::nothrow) gg_sim();
+  if (!s) return fail(GG_ERR_OOM, "host allocation failed");
+  s->p = *params;
+  if (s->p.relax == 0.0f) s->p.relax = 1.0f;
+  if (s->p.density == 0.0f) s->p.density = 2500.0f;
+  if (s->p.checkpoint_every == 0) s->p.checkpoint_every = 10;
+  s->dev = params->device;
+  s->n = n;
+  s->n_envs = n_envs;
+  s->env_off = off;
+  s->env_nh = env_nh;
+  s->env_boff = env_boff;
+  s->n_buckets = total;
+  s->cell = cell;
+  s->inv_c = inv_c;
+  s->r_max = rmax;
+  s->r_min = rmin;
+  s->K_pp = contact_bound(rmin, rmax);
+  s->n_pad = (n + 63) / 64 * 64;
+  s->body_lo.assign(n_envs, 0);
+  s->body_hi.assign(n_envs, 0);
+  s->stats.n = n;
+  s->stats.n_buckets = total;
+
+  DeviceGuard g(s->dev);
+  auto bail = [&](gg_status code) {
+    free_all(s);
+    delete s;
+    return code;
+  };
+  if (!g.ok) return bail(fail(GG_ERR_HIP, "hipSetDevice failed"));
+  if (params->stream) {
+    s->stream = (hipStream_t)params->stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hip_fail(nullptr, e, "hipStreamCreateWithFlags"));
+    s->own_stream = true;
+  }
+  const size_t N = (size_t)std::max<int64_t>(n, 1);
+  bool ok = dev_alloc(&s->x, N) == hipSuccess && dev_alloc(&s->v, N) == hipSuccess &&
+            dev_alloc(&s->wa, N) == hipSuccess && dev_alloc(&s->wb, N) == hipSuccess &&
+            dev_alloc(&s->h, N) == hipSuccess && dev_alloc(&s->rank, N) == hipSuccess &&
+            dev_alloc(&s->counts, (size_t)total) == hipSuccess &&
+            dev_alloc(&s->bstart, (size_t)total + 1) == hipSuccess &&
+            dev_alloc(&s->bsum, (size_t)(total + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
+            dev_alloc(&s->sidx, N) == hipSuccess && dev_alloc(&s->ncon, N) == hipSuccess &&
+            dev_alloc(&s->ctl, 1) == hipSuccess;
+  if (ok && (s->p.flags & GG_FLAG_DIAGNOSTICS)) ok = dev_alloc(&s->dv, N) == hipSuccess;
+  if (ok && n_envs > 1) {
+    ok = dev_alloc(&s->env_of, N) == hipSuccess && dev_alloc(&s->d_env_nh, (size_t)n_envs) == hipSuccess &&
+         dev_alloc(&s->d_env_boff, (size_t)n_envs) == hipSuccess &&
+         dev_alloc(&s->d_body_lo, (size_t)n_envs) == hipSuccess &&
+         dev_alloc(&s->d_body_hi, (size_t)n_envs) == hipSuccess;
+  }
+  if (!ok) return bail(fail(GG_ERR_OOM, "device allocation failed"));
+  if (hipHostMalloc((void**)&s->h_ctl, sizeof(ggk::Ctl), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(GG_ERR_OOM, "pinned allocation failed"));
+
+  // ---- upload state: x = (x, r), v = (v, 1/m)
+  std::vector<float4> hx4(N), hv4(N);
+  const double rho = (double)s->p.density;
+  for (int64_t i = 0; i < n; ++i) {
+    double r = hr[i];
+    double m = rho * (4.0 / 3.0) * M_PI * r * r * r;
+    hx4[i] = make_float4(hx[3 * i], hx[3 * i + 1], hx[3 * i + 2], hr[i]);
+    hv4[i] = make_float4(hv[3 * i], hv[3 * i + 1], hv[3 * i + 2], (float)(1.0 / m));
+  }
+  hipError_t e = hipSuccess;
+  if (n > 0) {
+    if (e == hipSuccess) e = hipMemcpy(s->x, hx4.data(), n * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->v, hv4.data(), n * sizeof(float4), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total * 4);
+  if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
+  if (e == hipSuccess && n_envs > 1) {
+    std::vector<int32_t> eo(N, 0);
+    for (int q = 0; q < n_envs; ++q)
+      for (int64_t i = off[q]; i < off[q + 1]; ++i) eo[i] = q;
+    e = hipMemcpy(s->env_of, eo.data(), N * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_env_nh, env_nh.data(), n_envs * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_env_boff, env_boff.data(), n_envs * 4, hipMemcpyHostToDevice);
+    std::vector<int32_t> zeros(n_envs, 0);
+    if (e == hipSuccess) e = hipMemcpy(s->d_body_lo, zeros.data(), n_envs * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_body_hi, zeros.data(), n_envs * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return bail(hip_fail(nullptr, e, "upload"));
+  st = ensure_ell(s, compute_K(s));
+  if (st != GG_OK) return bail(st);
+  *out = s;
+  return GG_OK;
+}
+
+gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (n_bodies < 0 || n_bodies > 65536) return fail(GG_ERR_INVALID, "n_bodies must be in [0, 65536]");
+  if (n_bodies > 0 && !bodies) return fail(GG_ERR_INVALID, "bodies is NULL");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  std::vector<gg_body> hb(n_bodies);
+  if (where == GG_MEM_DEVICE) {
+    DeviceGuard g(s->dev);
+    gg_status st = copy_in(bodies, sizeof(gg_body) * n_bodies, where, hb.data());
+    if (st != GG_OK) return st;
+  } else {
+    copy_in(bodies, sizeof(gg_body) * n_bodies, where, hb.data());
+  }
+  std::vector<HostBody> nb(n_bodies);
+  int prev_env = 0;
+  for (int b = 0; b < n_bodies; ++b) {
+    const gg_body& B = hb[b];
+    if (B.env < 0 || B.env >= s->n_envs) return fail(GG_ERR_INVALID, "body env out of range");
+    if (B.env < prev_env) return fail(GG_ERR_INVALID, "bodies must be grouped by env in non-decreasing order");
+    prev_env = B.env;
+    if (B.shape < GG_PLANE || B.shape > GG_CAPSULE) return fail(GG_ERR_INVALID, "unknown body shape");
+    for (int q = 0; q < 4; ++q)
+      if (!std::isfinite(B.params[q])) return fail(GG_ERR_INVALID, "non-finite body parameter");
+    if (B.shape == GG_BOX && !(B.params[0] > 0 && B.params[1] > 0 && B.params[2] > 0))
+      return fail(GG_ERR_INVALID, "box half extents must be > 0");
+    if (B.shape == GG_CAPSULE && !(B.params[0] > 0 && B.params[1] >= 0))
+      return fail(GG_ERR_INVALID, "capsule radius must be > 0 and half length >= 0");
+    for (int q = 0; q < 12; ++q)
+      if (!std::isfinite(B.pose[q])) return fail(GG_ERR_INVALID, "non-finite body pose");
+    for (int q = 0; q < 6; ++q)
+      if (!std::isfinite(B.twist[q])) return fail(GG_ERR_INVALID, "non-finite body twist");
+    HostBody& H = nb[b];
+    H.env = B.env;
+    H.shape = B.shape;
+    for (int q = 0; q < 4; ++q) H.params[q] = B.params[q];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) H.R[3 * r + c] = B.pose[4 * r + c];
+      H.t[r] = B.pose[4 * r + 3];
+    }
+    for (int q = 0; q < 3; ++q) {
+      H.nu[q] = B.twist[q];
+      H.om[q] = B.twist[3 + q];
+    }
+  }
+  DeviceGuard g(s->dev);
+  s->bodies = nb;
+  gg_status st = upload_env_bodies(s);
+  if (st != GG_OK) return st;
+  return ensure_ell(s, compute_K(s));
+}
+
+gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (n_steps < 0) return fail(GG_ERR_INVALID, "n_steps must be >= 0");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  const int nb = (int)s->bodies.size();
+  DeviceGuard g(s->dev);
+  if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+  std::vector<float> tw;
+  if (twists && nb > 0 && n_steps > 0) {
+    tw.resize((size_t)n_steps * nb * 6);
+    gg_status st = copy_in(twists, tw.size() * 4, where, tw.data());
+    if (st != GG_OK) return st;
+    for (float f : tw)
+      if (!std::isfinite(f)) return fail(GG_ERR_INVALID, "non-finite twist");
+  }
+  s->stats.steps_done = 0;
+  s->stats.last_status = GG_OK;
+  if (n_steps == 0) return GG_OK;
+
+  // ---- body poses for every step (double precision), staged for upload
+  const int64_t need = (int64_t)n_steps * std::max(nb, 1);
+  if (need > s->d_bodies_cap) {
+    if (s->d_bodies) HIPCHK(s, hipFree(s->d_bodies));
+    if (s->h_bodies) HIPCHK(s, hipHostFree(s->h_bodies));
+    s->d_bodies = nullptr;
+    s->h_bodies = nullptr;
+    s->d_bodies_cap = 0;
+    if (dev_alloc(&s->d_bodies, (size_t)need) != hipSuccess ||
+        hipHostMalloc((void**)&s->h_bodies, (size_t)need * sizeof(ggk::DevBody), hipHostMallocDefault) != hipSuccess)
+      return fail(GG_ERR_OOM, "body staging allocation failed");
+    s->d_bodies_cap = need;
+  }
+  s->pose_hist.resize((size_t)(n_steps + 1) * nb);
+  std::vector<HostBody> cur = s->bodies;
+  for (int st = 0; st < n_steps; ++st) {
+    for (int b = 0; b < nb; ++b) {
+      if (!tw.empty()) {
+        const float* t6 = &tw[((size_t)st * nb + b) * 6];
+        for (int q = 0; q < 3; ++q) {
+          cur[b].nu[q] = t6[q];
+          cur[b].om[q] = t6[3 + q];
+        }
+      }
+      s->h_bodies[(size_t)st * nb + b] = to_dev(cur[b]);
+      s->pose_hist[(size_t)st * nb + b] = cur[b];
+      advance_pose(cur[b], (double)s->p.dt);
+    }
+  }
+  for (int b = 0; b < nb; ++b) s->pose_hist[(size_t)n_steps * nb + b] = cur[b];
+  if (nb > 0)
+    HIPCHK(s, hipMemcpyAsync(s->d_bodies, s->h_bodies, (size_t)n_steps * nb * sizeof(ggk::DevBody),
+                             hipMemcpyHostToDevice, s->stream));
+
+  const bool prof = (s->p.flags & GG_FLAG_PROFILE) != 0;
+  if (prof) {
+    size_t ne = (size_t)n_steps * 4;
+    while (s->events.size() < ne) {
+      hipEvent_t ev;
+      HIPCHK(s, hipEventCreate(&ev));
+      s->events.push_back(ev);
+    }
+  }
+
+  const int n = (int)s->n;
+  const int K = s->K;
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  const int m = (int)s->n_buckets;
+  const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
+  int dblock = K <= 32 ? 256 : (K <= 64 ? 128 : 64);
+  const int dgrid = (n + dblock - 1) / dblock;
+  const size_t dlds = (size_t)dblock * K * sizeof(int);
+  const ggk::EnvTables et = env_tables(s);
+  const int nh1 = s->env_nh[0];
+  const float dt = s->p.dt, gx = s->p.gravity[0], gy = s->p.gravity[1], gz = s->p.gravity[2];
+  const float alpha_dt = s->p.alpha / s->p.dt;
+  hipStream_t S = s->stream;
+
+  ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
+  for (int st = 0; st < n_steps && n > 0; ++st) {
+    const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st], S));
+    ggk::k_key<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
+    ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum);
+    ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
+    ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
+    ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, s->sidx);
+    ggk::k_detect<<<dgrid, dblock, dlds, S>>>(n, K, s->x, s->v, s->inv_c, nh1, et, s->bstart, s->sidx, bod, nb,
+                                              gx, gy, gz, dt, s->p.mass_split, s->ncon, s->partner, s->Psi, s->wa,
+                                              s->ctl, st);
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
+    float4* win = s->wa;
+    float4* wout = s->wb;
+    for (int it = 0; it < s->p.n_iters; ++it) {
+      int mode = (it == 0 ? 1 : 0) | (it == s->p.n_iters - 1 ? 2 : 0);
+      ggk::k_pja<<<grid, ggk::kBlock, 0, S>>>(n, K, s->x, s->v, win, wout, s->ncon, s->partner, s->Psi, s->Px, s->Py,
+                                              s->Pz, bod, gx, gy, gz, dt, alpha_dt, s->p.mu, s->p.relax, mode,
+                                              s->dv, s->ctl);
+      std::swap(win, wout);
+    }
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
+    ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->v, dt, s->ctl);
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
+  }
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(ggk::Ctl), hipMemcpyDeviceToHost, S));
+  HIPCHK(s, hipStreamSynchronize(S));
+
+  const ggk::Ctl c = *s->h_ctl;
+  int done = n > 0 ? c.steps_done : n_steps;
+  if (done < 0) done = 0;
+  if (done > n_steps) done = n_steps;
+  for (int b = 0; b < nb; ++b) s->bodies[b] = s->pose_hist[(size_t)done * nb + b];
+  if (!tw.empty() && done > 0)
+    for (int b = 0; b < nb; ++b) {
+      const float* t6 = &tw[((size_t)(done - 1) * nb + b) * 6];
+      for (int q = 0; q < 3; ++q) {
+        s->bodies[b].nu[q] = t6[q];
+        s->bodies[b].om[q] = t6[3 + q];
+      }
+    }
+  s->stats.steps_done = done;
+  s->stats.steps_total += done;
+  if (n > 0) {
+    s->stats.n_pp = (int64_t)c.n_pp;
+    s->stats.n_pb = (int64_t)c.n_pb;
+    s->stats.candidates = (int64_t)c.cand;
+    s->stats.max_contacts = c.max_cnt;
+    s->stats.contacts_summed = (int64_t)c.summed;
+  }
+  s->stats.capacity = K;
+  if (prof && n > 0) {
+    double td = 0, tp = 0, ti = 0;
+    for (int st = 0; st < n_steps; ++st) {
+      float a = 0, b2 = 0, c3 = 0;
+      HIPCHK(s, hipEventElapsedTime(&a, s->events[4 * st], s->events[4 * st + 1]));
+      HIPCHK(s, hipEventElapsedTime(&b2, s->events[4 * st + 1], s->events[4 * st + 2]));
+      HIPCHK(s, hipEventElapsedTime(&c3, s->events[4 * st + 2], s->events[4 * st + 3]));
+      td += a;
+      tp += b2;
+      ti += c3;
+    }
+    s->stats.ms_detect = td;
+    s->stats.ms_pja = tp;
+    s->stats.ms_integrate = ti;
+    s->stats.pja_launches = (int64_t)n_steps * s->p.n_iters;
+  }
+  if (c.err != 0) {
+    s->stats.last_status = c.err;
+    s->contacts_valid = false;
+    if (c.err == GG_ERR_CAPACITY)
+      return fail(GG_ERR_CAPACITY, "a particle exceeded the contact capacity of " + std::to_string(K) +
+                                       " at step " + std::to_string(c.fail_step) + " of the call");
+    return fail((gg_status)c.err, "non-finite or out-of-range position at step " + std::to_string(c.fail_step));
+  }
+  s->contacts_valid = n > 0;
+  return GG_OK;
+}
+
+gg_status gg_step_backward(gg_sim* s, const float*, const float*, float*, float*, float*, gg_mem) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  return fail(GG_ERR_UNSUPPORTED, "the adjoint pass is not built in this version");
+}
+
+gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  const int64_t n = s->n;
+  int64_t need = 0;
+  const int64_t C = s->contacts_valid ? s->stats.n_pp + s->stats.n_pb : 0;
+  switch (field) {
+    case GG_FIELD_POS:
+    case GG_FIELD_VEL:
+    case GG_FIELD_DV: need = 12 * n; break;
+    case GG_FIELD_RADIUS: need = 4 * n; break;
+    case GG_FIELD_CELL_INDEX: need = 8 * n; break;
+    case GG_FIELD_CONTACTS: need = 8 * C; break;
+    case GG_FIELD_IMPULSES: need = 12 * C; break;
+    case GG_FIELD_STATS: need = sizeof(gg_stats); break;
+    default: return fail(GG_ERR_INVALID, "unknown field");
+  }
+  if (field == GG_FIELD_DV && !s->dv) return fail(GG_ERR_INVALID, "GG_FIELD_DV needs GG_FLAG_DIAGNOSTICS at creation");
+  if (written) *written = need;
+  if (!dst) return GG_OK;
+  if (capacity_bytes < need) return fail(GG_ERR_INVALID, "destination too small");
+  if (need == 0) return GG_OK;
+  DeviceGuard g(s->dev);
+  const hipMemcpyKind kind = where == GG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (field == GG_FIELD_STATS) {
+    if (where == GG_MEM_HOST) {
+      std::memcpy(dst, &s->stats, sizeof(gg_stats));
+    } else {
+      HIPCHK(s, hipMemcpy(dst, &s->stats, sizeof(gg_stats), hipMemcpyHostToDevice));
+    }
+    return GG_OK;
+  }
+  const int blocks = (int)((n + 255) / 256);
+  if (field == GG_FIELD_POS || field == GG_FIELD_VEL || field == GG_FIELD_DV || field == GG_FIELD_RADIUS ||
+      field == GG_FIELD_CELL_INDEX) {
+    gg_status st = ensure_tmp(s, (size_t)need);
+    if (st != GG_OK) return st;
+    if (field == GG_FIELD_POS) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->x, (float*)s->tmp);
+    if (field == GG_FIELD_VEL) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->v, (float*)s->tmp);
+    if (field == GG_FIELD_DV) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->dv, (float*)s->tmp);
+    if (field == GG_FIELD_RADIUS) ggk::k_pack_w<<<blocks, 256, 0, s->stream>>>((int)n, s->x, (float*)s->tmp);
+    if (field == GG_FIELD_CELL_INDEX) ggk::k_widen<<<blocks, 256, 0, s->stream>>>((int)n, s->h, (int64_t*)s->tmp);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(dst, s->tmp, (size_t)need, kind, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return GG_OK;
+  }
+  // contacts / impulses: gather the per-particle lists into the canonical order
+  const size_t slots = (size_t)s->n_pad * s->K;
+  std::vector<int32_t> cnt(n), part(slots);
+  std::vector<float> px, py, pz;
+  HIPCHK(s, hipMemcpyAsync(cnt.data(), s->ncon, n * 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(part.data(), s->partner, slots * 4, hipMemcpyDeviceToHost, s->stream));
+  if (field == GG_FIELD_IMPULSES) {
+    px.resize(slots); py.resize(slots); pz.resize(slots);
+    HIPCHK(s, hipMemcpyAsync(px.data(), s->Px, slots * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(py.data(), s->Py, slots * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(pz.data(), s->Pz, slots * 4, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  std::vector<int32_t> pairs;
+  std::vector<float> imp;
+  std::vector<int32_t> bpairs;
+  std::vector<float> bimp;
+  pairs.reserve(2 * (size_t)s->stats.n_pp);
+  const int K = s->K;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < cnt[i]; ++k) {
+      const size_t sl = (size_t)(i >> 6) * ((size_t)K << 6) + ((size_t)k << 6) + (size_t)(i & 63);
+      const int32_t j = part[sl];
+      if (j > i) {
+        pairs.push_back((int32_t)i);
+        pairs.push_back(j);
+        if (field == GG_FIELD_IMPULSES) {
+          imp.push_back(px[sl]); imp.push_back(py[sl]); imp.push_back(pz[sl]);
+        }
+      } else if (j < 0) {
+        bpairs.push_back((int32_t)i);
+        bpairs.push_back(-1 - j);
+        if (field == GG_FIELD_IMPULSES) {
+          bimp.push_back(px[sl]); bimp.push_back(py[sl]); bimp.push_back(pz[sl]);
+        }
+      }
+    }
+  }
+  pairs.insert(pairs.end(), bpairs.begin(), bpairs.end());
+  imp.insert(imp.end(), bimp.begin(), bimp.end());
+  const void* src = field == GG_FIELD_CONTACTS ? (const void*)pairs.data() : (const void*)imp.data();
+  const int64_t have = field == GG_FIELD_CONTACTS ? (int64_t)pairs.size() * 4 : (int64_t)imp.size() * 4;
+  if (have != need) return fail(GG_ERR_HIP, "contact list size disagrees with the detection counters");
+  if (where == GG_MEM_HOST) {
+    std::memcpy(dst, src, (size_t)need);
+  } else {
+    HIPCHK(s, hipMemcpy(dst, src, (size_t)need, hipMemcpyHostToDevice));
+  }
+  return GG_OK;
+}
+
+void gg_destroy(gg_sim* s) {
+  if (!s) return;
+  {
+    DeviceGuard g(s->dev);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_all(s);
+  }
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,635 @@
+// Device kernels of the granular contact step for gfx950 (CDNA4, wave64).
+//
+// Per timestep (arXiv 2306.01369, Sec. II):
+//   k_key      cell coordinates and spatial hash (Eq. (6)); bucket counters
+//   k_scan_*   exclusive prefix sum of the bucket counters -> bucket_start
+//   k_scatter  particles into hash-bucket order (stands in for Alg. 2's lists)
+//   k_detect   27-cell query, sphere test, SDF body tests (Sec. II-B, II-C, Eq. (7));
+//              writes each particle's sorted partner list
+//   k_pja      one projected-Jacobi sweep (Alg. 1) over all contacts, gathered
+//              per particle; the last sweep also writes the new velocity
+//   k_integrate  positions from the new velocities (Eq. (5))
+//
+// Layout.  Particle state is structure-of-arrays float4: x = (x, y, z, r),
+// v = (vx, vy, vz, 1/m), w = (wx, wy, wz, s) with s = n_i/m_i (the split inverse
+// mass).  Every contact is stored once per member ("half contacts") in an
+// ELL table of K slots per particle, laid out slot-major within groups of 64
+// particles: slot(i, k) = (i/64)*64K + 64k + i%64, so the k-th contact of the 64
+// lanes of a wavefront is one contiguous 256-byte row.  Each half contact holds
+// the partner (>= 0 particle, < 0 body -1-b) and the world-frame impulse on the
+// lower-indexed member; both halves compute it with identical arithmetic from
+// identical inputs, so the two copies agree bit for bit and no atomics or
+// second pass are needed.  Sums run in partner order, so results are
+// deterministic and independent of the launch shape.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ggk {
+
+constexpr int kBlock = 256;
+constexpr int kScanTile = 1024;  // elements per block of the bucket scan
+constexpr int kQ = 100;
+
+struct DevBody {  // one body at one step; 96 bytes
+  int32_t shape, env;
+  float params[4];
+  float R[9];  // world <- body, row major
+  float t[3];
+  float nu[3];
+  float om[3];
+};
+
+struct Ctl {                    // device control block, one per simulation
+  int32_t err;                  // first failure of the current call (gg_status), 0 = none
+  int32_t fail_step;            // step index of that failure
+  int32_t steps_done;           // steps completed in the current call
+  int32_t max_cnt;              // largest contact count (last detection)
+  unsigned long long n_pp;      // pair contacts (last detection)
+  unsigned long long n_pb;      // body contacts (last detection)
+  unsigned long long cand;      // ordered candidate pairs (last detection)
+  unsigned long long summed;    // contacts summed over the steps of the current call
+};
+
+struct EnvTables {   // per-environment hash tables (batched form)
+  const int32_t* env_of;       // particle -> env (nullptr: one env)
+  const int32_t* nh;           // buckets per env
+  const int32_t* boff;         // bucket offset per env
+  const int32_t* body_lo;      // first body of env (bodies sorted by env)
+  const int32_t* body_hi;      // one past last body of env
+};
+
+// Blocks are handed to the 8 XCDs round robin; remap so each XCD works on a
+// contiguous range of particles and keeps its neighbours in its own L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd * per + min(xcd, rem) + idx;
+}
+
+__device__ __forceinline__ int ell_slot(int i, int k, int K) {
+  return (i >> 6) * (K << 6) + (k << 6) + (i & 63);
+}
+
+// ------------------------------------------------------------------ Eq. (6)
+// round(x / c) as rne(fl32(x * inv_c)); ok = false when out of the hashable range.
+__device__ __forceinline__ int cell_coord(float x, float inv_c, bool& ok) {
+#pragma clang fp contract(off)
+  float s = x * inv_c;
+  float r = __builtin_rintf(s);
+  ok = ok && (fabsf(r) < 1073741824.0f);  // |kappa| < 2^30; false for NaN too
+  return ok ? (int)r : 0;
+}
+
+// Bucket of cell (k0, k1, k2) in a table of nh buckets: XOR of p_a*(k_a - q),
+// floored modulo nh.  64-bit products; for a power-of-two nh the low bits of
+// 32-bit wrap-around products are the same bits.
+__device__ __forceinline__ int hash_cell(int k0, int k1, int k2, int nh) {
+  if ((nh & (nh - 1)) == 0) {
+    uint32_t a = (uint32_t)(k0 - kQ) * 73856093u;
+    uint32_t b = (uint32_t)(k1 - kQ) * 19349663u;
+    uint32_t c = (uint32_t)(k2 - kQ) * 83492791u;
+    return (int)((a ^ b ^ c) & (uint32_t)(nh - 1));
+  }
+  long long a = (long long)(k0 - kQ) * 73856093LL;
+  long long b = (long long)(k1 - kQ) * 19349663LL;
+  long long c = (long long)(k2 - kQ) * 83492791LL;
+  long long v = (a ^ b ^ c) % (long long)nh;
+  return (int)(v < 0 ? v + nh : v);
+}
+
+// --------------------------------------------------------- contact decisions
+// ||xi - xj||^2 <= (ri + rj)^2 in binary32, each operation rounded as written.
+__device__ __forceinline__ bool pair_touch(const float4 a, const float4 b) {
+#pragma clang fp contract(off)
+  float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  float D = dx * dx + dy * dy;
+  D = D + dz * dz;
+  float s = a.w + b.w;
+  float S = s * s;
+  return D <= S;
+}
+
+// Body-frame point p = R^T (x - t), fixed summation order.
+__device__ __forceinline__ void to_body(const DevBody& B, float x0, float x1, float x2, float p[3]) {
+#pragma clang fp contract(off)
+  float d0 = x0 - B.t[0], d1 = x1 - B.t[1], d2 = x2 - B.t[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float a0 = B.R[0 * 3 + c] * d0;
+    float a1 = B.R[1 * 3 + c] * d1;
+    float a2 = B.R[2 * 3 + c] * d2;
+    float s = a0 + a1;
+    p[c] = s + a2;
+  }
+}
+
+// Closed-form SDFs (Sec. II-C) in binary32 with a fixed operation order: the
+// value that decides contact (psi = f - r <= 0, Eq. (7)).
+__device__ __forceinline__ float sdf_decide(const DevBody& B, float x0, float x1, float x2) {
+#pragma clang fp contract(off)
+  float p[3];
+  to_body(B, x0, x1, x2, p);
+  if (B.shape == 0) return p[2];
+  if (B.shape == 1) {
+    float q0 = fabsf(p[0]) - B.params[0];
+    float q1 = fabsf(p[1]) - B.params[1];
+    float q2 = fabsf(p[2]) - B.params[2];
+    float m0 = q0 > 0.0f ? q0 : 0.0f, m1 = q1 > 0.0f ? q1 : 0.0f, m2 = q2 > 0.0f ? q2 : 0.0f;
+    float s0 = m0 * m0, s1 = m1 * m1, s2 = m2 * m2;
+    float ss = s0 + s1;
+    ss = ss + s2;
+    float outside = __builtin_sqrtf(ss);
+    float in = fmaxf(q0, fmaxf(q1, q2));
+    in = in < 0.0f ? in : 0.0f;
+    return outside + in;
+  }
+  float h = B.params[1];
+  float cz = fminf(fmaxf(p[2], -h), h);
+  float dz = p[2] - cz;
+  float s0 = p[0] * p[0], s1 = p[1] * p[1], s2 = dz * dz;
+  float ss = s0 + s1;
+  ss = ss + s2;
+  return __builtin_sqrtf(ss) - B.params[0];
+}
+
+__device__ __forceinline__ bool body_touch(const DevBody& B, const float4 xi) {
+#pragma clang fp contract(off)
+  float f = sdf_decide(B, xi.x, xi.y, xi.z);
+  float psi = f - xi.w;
+  return psi <= 0.0f;
+}
+
+// Signed gap of a particle pair, psi = ||xi - xj|| - (ri + rj) (Eq. (7) for two
+// spheres), free of cancellation: differences and squares of binary32 inputs
+// are exact in double precision, and psi = (D - S) / (sqrt(D) + s).  The
+// expression is symmetric in (i, j), so both members of a pair store the same bits.
+__device__ __forceinline__ float pair_gap(const float4 a, const float4 b) {
+  const double d0 = (double)a.x - (double)b.x;
+  const double d1 = (double)a.y - (double)b.y;
+  const double d2 = (double)a.z - (double)b.z;
+  const double D = d0 * d0 + d1 * d1 + d2 * d2;
+  const double s = (double)a.w + (double)b.w;
+  return (float)((D - s * s) / (sqrt(D) + s));
+}
+
+// Signed gap f(X^-1 x) - r of a body contact in double precision (Eq. (7)).
+__device__ __forceinline__ float body_gap(const DevBody& B, const float4 xi) {
+  double d[3] = {(double)xi.x - B.t[0], (double)xi.y - B.t[1], (double)xi.z - B.t[2]};
+  double p[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[c] = (double)B.R[c] * d[0] + (double)B.R[3 + c] * d[1] + (double)B.R[6 + c] * d[2];
+  double f;
+  if (B.shape == 0) {
+    f = p[2];
+  } else if (B.shape == 1) {
+    double q0 = fabs(p[0]) - B.params[0], q1 = fabs(p[1]) - B.params[1], q2 = fabs(p[2]) - B.params[2];
+    double m0 = fmax(q0, 0.0), m1 = fmax(q1, 0.0), m2 = fmax(q2, 0.0);
+    f = sqrt(m0 * m0 + m1 * m1 + m2 * m2) + fmin(fmax(q0, fmax(q1, q2)), 0.0);
+  } else {
+    double h = B.params[1];
+    double cz = fmin(fmax(p[2], -h), h);
+    double e2 = p[2] - cz;
+    f = sqrt(p[0] * p[0] + p[1] * p[1] + e2 * e2) - (double)B.params[0];
+  }
+  return (float)(f - (double)xi.w);
+}
+
+// Contact geometry for a body contact with stored gap psi: world normal
+// n = R grad f / |R grad f| and the velocity of the body's material point at
+// the contact point pc = x - f n, V = nu + om x (pc - t).
+__device__ __forceinline__ void body_geometry(const DevBody& B, const float4 xi, float psi, float n[3],
+                                              float V[3]) {
+  float p[3];
+  to_body(B, xi.x, xi.y, xi.z, p);
+  float g[3], f;
+  if (B.shape == 0) {
+    g[0] = 0.f; g[1] = 0.f; g[2] = 1.f;
+    f = p[2];
+  } else if (B.shape == 1) {
+    float q[3], m[3];
+    bool outside = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[c] = fabsf(p[c]) - B.params[c];
+      m[c] = fmaxf(q[c], 0.0f);
+      outside = outside || (q[c] > 0.0f);
+    }
+    if (outside) {
+      float L = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      float il = 1.0f / L;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[c] = (p[c] < 0.0f ? -1.0f : 1.0f) * m[c] * il;
+      f = L;
+    } else {
+      int a = 0;
+      if (q[1] > q[a]) a = 1;
+      if (q[2] > q[a]) a = 2;
+      g[0] = g[1] = g[2] = 0.f;
+      g[a] = p[a] < 0.0f ? -1.0f : 1.0f;
+      f = q[a];
+    }
+  } else {
+    float h = B.params[1];
+    float cz = fminf(fmaxf(p[2], -h), h);
+    float e0 = p[0], e1 = p[1], e2 = p[2] - cz;
+    float L = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+    if (L > 0.0f) {
+      float il = 1.0f / L;
+      g[0] = e0 * il; g[1] = e1 * il; g[2] = e2 * il;
+    } else {
+      g[0] = 1.f; g[1] = 0.f; g[2] = 0.f;
+    }
+    f = L - B.params[0];
+  }
+  float w0 = B.R[0] * g[0] + B.R[1] * g[1] + B.R[2] * g[2];
+  float w1 = B.R[3] * g[0] + B.R[4] * g[1] + B.R[5] * g[2];
+  float w2 = B.R[6] * g[0] + B.R[7] * g[1] + B.R[8] * g[2];
+  float inl = 1.0f / sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+  n[0] = w0 * inl; n[1] = w1 * inl; n[2] = w2 * inl;
+  f = psi + xi.w;
+  float a0 = xi.x - f * n[0] - B.t[0];
+  float a1 = xi.y - f * n[1] - B.t[1];
+  float a2 = xi.z - f * n[2] - B.t[2];
+  V[0] = B.nu[0] + B.om[1] * a2 - B.om[2] * a1;
+  V[1] = B.nu[1] + B.om[2] * a0 - B.om[0] * a2;
+  V[2] = B.nu[2] + B.om[0] * a1 - B.om[1] * a0;
+}
+
+// Orthonormal tangent pair (e2, e3) for a unit normal (Duff et al. 2017,
+// "Building an Orthonormal Basis, Revisited").
+__device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], float t2[3]) {
+  float sg = n[2] >= 0.0f ? 1.0f : -1.0f;
+  float a = -1.0f / (sg + n[2]);
+  float b = n[0] * n[1] * a;
+  t1[0] = 1.0f + sg * n[0] * n[0] * a; t1[1] = sg * b; t1[2] = -sg * n[0];
+  t2[0] = b; t2[1] = sg + n[1] * n[1] * a; t2[2] = -n[1];
+}
+
+// ------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ void set_error(Ctl* ctl, int code, int step) {
+  if (atomicCAS(&ctl->err, 0, code) == 0) atomicExch(&ctl->fail_step, step);
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_begin(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->err = 0;
+    ctl->fail_step = -1;
+    ctl->steps_done = 0;
+    ctl->summed = 0;
+  }
+}
+
+// Cell keys and bucket counters.  rank[i] is the arrival order of i in its
+// bucket; the order inside a bucket is irrelevant downstream because partner
+// lists are sorted.
+__global__ __launch_bounds__(kBlock) void k_key(int n, const float4* __restrict__ x, float inv_c, int nh,
+                                                EnvTables env, int32_t* __restrict__ h,
+                                                int32_t* __restrict__ rank, int32_t* __restrict__ counts,
+                                                Ctl* ctl, int step) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->err == 0) {
+    ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0;
+  }
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 p = x[i];
+  bool ok = true;
+  int k0 = cell_coord(p.x, inv_c, ok);
+  int k1 = cell_coord(p.y, inv_c, ok);
+  int k2 = cell_coord(p.z, inv_c, ok);
+  int bucket;
+  if (env.env_of) {
+    int e = env.env_of[i];
+    bucket = env.boff[e] + hash_cell(k0, k1, k2, env.nh[e]);
+  } else {
+    bucket = hash_cell(k0, k1, k2, nh);
+  }
+  if (!ok) set_error(ctl, 5 /* GG_ERR_NONFINITE */, step);
+  h[i] = bucket;
+  rank[i] = atomicAdd(&counts[bucket], 1);
+}
+
+// Block-local exclusive scan of kScanTile counters; zeroes the counters for
+// the next step and writes the block total.
+__global__ __launch_bounds__(kBlock) void k_scan_a(int m, int32_t* __restrict__ counts,
+                                                   int32_t* __restrict__ start, int32_t* __restrict__ bsum) {
+  __shared__ int wsum[kBlock / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  int v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = base + q;
+    v[q] = e < m ? counts[e] : 0;
+    if (e < m) counts[e] = 0;
+  }
+  const int t = v[0] + v[1] + v[2] + v[3];
+  const int s = wave_incl_scan(t);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 63) wsum[wid] = s;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wid; ++w) off += wsum[w];
+  int run = off + s - t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = base + q;
+    if (e < m) start[e] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = run;
+}
+
+// Exclusive scan of the block totals (one block); start[m] = total.
+__global__ __launch_bounds__(1024) void k_scan_b(int nb, int32_t* __restrict__ bsum, int m,
+                                                 int32_t* __restrict__ start) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int e = base + threadIdx.x;
+    const int t = e < nb ? bsum[e] : 0;
+    const int s = wave_incl_scan(t);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 63) wsum[wid] = s;
+    __syncthreads();
+    int off = carry;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    if (e < nb) bsum[e] = off + s - t;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = off + s;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) start[m] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_c(int m, const int32_t* __restrict__ bsum,
+                                                   int32_t* __restrict__ start) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e < m) start[e] += bsum[e / kScanTile];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __restrict__ h,
+                                                    const int32_t* __restrict__ rank,
+                                                    const int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ sidx) {
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  sidx[start[h[i]] + rank[i]] = i;
+}
+
+// Contact detection, one thread per particle.  Candidates come from the
+// buckets of the particle's cell and its 26 neighbours; a candidate counts only
+// if it lies in the queried cell (aliasing buckets), so each pair is found once
+// per member.  The partner list is kept sorted in LDS (insertion), bodies
+// follow the particles in body order.  Also seeds the Jacobi iterate
+// w = v + dt g and the split inverse mass s_i.
+__global__ __launch_bounds__(kBlock) void k_detect(
+    int n, int K, const float4* __restrict__ x, const float4* __restrict__ v, float inv_c, int nh,
+    EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    const DevBody* __restrict__ bodies, int n_bodies, float gx, float gy, float gz, float dt,
+    int mass_split, int32_t* __restrict__ ncon, int32_t* __restrict__ partner, float* __restrict__ Psi,
+    float4* __restrict__ w, Ctl* ctl, int step) {
+  extern __shared__ int lds_list[];
+  if (ctl->err) return;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
+  const bool active = i < n;
+  int cnt = 0, cand = 0, npp = 0, npb = 0;
+  if (active) {
+    int* L = lds_list + threadIdx.x;
+    const int B = blockDim.x;
+    const float4 p = x[i];
+    bool ok = true;
+    const int k0 = cell_coord(p.x, inv_c, ok);
+    const int k1 = cell_coord(p.y, inv_c, ok);
+    const int k2 = cell_coord(p.z, inv_c, ok);
+    int tab_n = nh, tab_off = 0, b_lo = 0, b_hi = n_bodies;
+    if (env.env_of) {
+      const int e = env.env_of[i];
+      tab_n = env.nh[e];
+      tab_off = env.boff[e];
+      b_lo = env.body_lo[e];
+      b_hi = env.body_hi[e];
+    }
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int c0 = k0 + dx, c1 = k1 + dy, c2 = k2 + dz;
+          const int hb = tab_off + hash_cell(c0, c1, c2, tab_n);
+          const int s = start[hb], e = start[hb + 1];
+          for (int q = s; q < e; ++q) {
+            const int j = sidx[q];
+            if (j == i) continue;
+            const float4 pj = x[j];
+            bool okj = true;
+            if (cell_coord(pj.x, inv_c, okj) != c0 || cell_coord(pj.y, inv_c, okj) != c1 ||
+                cell_coord(pj.z, inv_c, okj) != c2)
+              continue;
+            ++cand;
+            if (!pair_touch(p, pj)) continue;
+            if (j > i) ++npp;
+            if (cnt < K) {
+              int pos = cnt;
+              while (pos > 0 && L[(pos - 1) * B] > j) {
+                L[pos * B] = L[(pos - 1) * B];
+                --pos;
+              }
+              L[pos * B] = j;
+            }
+            ++cnt;
+          }
+        }
+    for (int b = b_lo; b < b_hi; ++b) {
+      if (body_touch(bodies[b], p)) {
+        if (cnt < K) L[cnt * B] = -1 - b;
+        ++cnt;
+        ++npb;
+      }
+    }
+    const int kept = cnt < K ? cnt : K;
+    for (int k = 0; k < kept; ++k) {
+      const int j = L[k * B];
+      const int sl = ell_slot(i, k, K);
+      partner[sl] = j;
+      Psi[sl] = j >= 0 ? pair_gap(p, x[j]) : body_gap(bodies[-1 - j], p);
+    }
+    ncon[i] = kept;
+    if (cnt > K) set_error(ctl, 4 /* GG_ERR_CAPACITY */, step);
+    const float4 vi = v[i];
+    const float s_i = mass_split ? (float)cnt * vi.w : vi.w;
+    w[i] = make_float4(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
+  }
+  // statistics: one atomic per wavefront
+  unsigned long long a = wave_sum_u64((unsigned long long)npp);
+  unsigned long long b2 = wave_sum_u64((unsigned long long)npb);
+  unsigned long long c = wave_sum_u64((unsigned long long)cand);
+  int mx = wave_max_i32(cnt);
+  if ((threadIdx.x & 63) == 0) {
+    if (a) atomicAdd(&ctl->n_pp, a);
+    if (b2) atomicAdd(&ctl->n_pb, b2);
+    if (a + b2) atomicAdd(&ctl->summed, a + b2);
+    if (c) atomicAdd(&ctl->cand, c);
+    if (mx) atomicMax(&ctl->max_cnt, mx);
+  }
+}
+
+// One projected-Jacobi sweep (Alg. 1).  Every contact reads the iterate of the
+// previous sweep (w_in) and its own accumulated impulse, forms the contact
+// velocity u = R_c^T (w_lo - w_hi) (or w_i - V_c for a body), takes the step
+// y = lam - mt (u + alpha psi/dt e1), clamps y_n >= 0 and scales the
+// tangential part to radius mu y_n (Eqs. (2)-(3)); the particle then sums its
+// contacts' impulses in partner order: w_i = w0_i + (1/m_i) sum sigma P_c.
+// mt = 1/(s_lo + s_hi) for a pair, 1/s_i for a body (mass splitting).
+// mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
+// optionally dv instead of w_out).
+__global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __restrict__ x,
+                                                float4* __restrict__ v, const float4* __restrict__ w_in,
+                                                float4* __restrict__ w_out, const int32_t* __restrict__ ncon,
+                                                const int32_t* __restrict__ partner,
+                                                const float* __restrict__ Psi, float* __restrict__ Px,
+                                                float* __restrict__ Py, float* __restrict__ Pz,
+                                                const DevBody* __restrict__ bodies, float gx, float gy,
+                                                float gz, float dt, float alpha_dt, float mu, float relax,
+                                                int mode, float4* __restrict__ dv, const Ctl* ctl) {
+  if (ctl->err) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const bool first = mode & 1, last = mode & 2;
+  const float4 xi = x[i];
+  const float4 vi = v[i];
+  const float4 wi = w_in[i];
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  const int c = ncon[i];
+  for (int k = 0; k < c; ++k) {
+    const int slot = ell_slot(i, k, K);
+    const int j = partner[slot];
+    float P0 = 0.f, P1 = 0.f, P2 = 0.f;
+    if (!first) {
+      P0 = Px[slot]; P1 = Py[slot]; P2 = Pz[slot];
+    }
+    float nrm[3], psi, u[3], mt, sg;
+    if (j >= 0) {
+      const float4 xj = x[j];
+      const float4 wj = w_in[j];
+      const bool lo = i < j;
+      const float4 xl = lo ? xi : xj, xh = lo ? xj : xi;
+      const float4 wl = lo ? wi : wj, wh = lo ? wj : wi;
+      const float d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
+      const float L = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+      if (L > 0.0f) {
+        const float il = 1.0f / L;
+        nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
+      } else {
+        nrm[0] = 0.f; nrm[1] = 0.f; nrm[2] = 1.f;
+      }
+      psi = Psi[slot];
+      u[0] = wl.x - wh.x; u[1] = wl.y - wh.y; u[2] = wl.z - wh.z;
+      mt = 1.0f / (wl.w + wh.w);
+      sg = lo ? 1.0f : -1.0f;
+    } else {
+      float V[3];
+      psi = Psi[slot];
+      body_geometry(bodies[-1 - j], xi, psi, nrm, V);
+      u[0] = wi.x - V[0]; u[1] = wi.y - V[1]; u[2] = wi.z - V[2];
+      mt = 1.0f / wi.w;
+      sg = 1.0f;
+    }
+    float t1[3], t2[3];
+    tangent_basis(nrm, t1, t2);
+    const float ln = nrm[0] * P0 + nrm[1] * P1 + nrm[2] * P2;
+    const float l1 = t1[0] * P0 + t1[1] * P1 + t1[2] * P2;
+    const float l2 = t2[0] * P0 + t2[1] * P1 + t2[2] * P2;
+    const float un = nrm[0] * u[0] + nrm[1] * u[1] + nrm[2] * u[2];
+    const float u1 = t1[0] * u[0] + t1[1] * u[1] + t1[2] * u[2];
+    const float u2 = t2[0] * u[0] + t2[1] * u[1] + t2[2] * u[2];
+    float yn = ln - mt * (un + alpha_dt * psi);
+    float y1 = l1 - mt * u1;
+    float y2 = l2 - mt * u2;
+    yn = fmaxf(yn, 0.0f);
+    const float s = sqrtf(y1 * y1 + y2 * y2);
+    if (s > mu * yn) {
+      const float f = mu * yn / s;
+      y1 *= f;
+      y2 *= f;
+    }
+    float Q0 = yn * nrm[0] + y1 * t1[0] + y2 * t2[0];
+    float Q1 = yn * nrm[1] + y1 * t1[1] + y2 * t2[1];
+    float Q2 = yn * nrm[2] + y1 * t1[2] + y2 * t2[2];
+    if (relax != 1.0f) {
+      Q0 = P0 + relax * (Q0 - P0);
+      Q1 = P1 + relax * (Q1 - P1);
+      Q2 = P2 + relax * (Q2 - P2);
+    }
+    Px[slot] = Q0; Py[slot] = Q1; Pz[slot] = Q2;
+    a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
+  }
+  const float im = vi.w;
+  const float n0 = vi.x + dt * gx + im * a0;
+  const float n1 = vi.y + dt * gy + im * a1;
+  const float n2 = vi.z + dt * gz + im * a2;
+  if (last) {
+    v[i] = make_float4(n0, n1, n2, im);
+    if (dv) dv[i] = make_float4(im * a0, im * a1, im * a2, 0.0f);
+  } else {
+    w_out[i] = make_float4(n0, n1, n2, wi.w);
+  }
+}
+
+// Positions from the new velocities (Eq. (5)), x' = x + dt v'.
+__global__ __launch_bounds__(kBlock) void k_integrate(int n, float4* __restrict__ x,
+                                                      const float4* __restrict__ v, float dt, Ctl* ctl) {
+  if (ctl->err) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->steps_done, 1);
+  if (i >= n) return;
+  float4 p = x[i];
+  const float4 q = v[i];
+  p.x += dt * q.x; p.y += dt * q.y; p.z += dt * q.z;
+  x[i] = p;
+}
+
+// ---------------------------------------------------------------- readout
+__global__ void k_pack3(int n, const float4* __restrict__ a, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 q = a[i];
+  out[3 * i] = q.x; out[3 * i + 1] = q.y; out[3 * i + 2] = q.z;
+}
+
+__global__ void k_pack_w(int n, const float4* __restrict__ a, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i].w;
+}
+
+__global__ void k_widen(int n, const int32_t* __restrict__ a, int64_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i];
+}
+
+}  // namespace ggk

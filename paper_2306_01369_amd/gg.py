@@ -1,0 +1,257 @@
+"""Thin Python binding of libgg (include/gg.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels behind the C ABI; this
+module converts NumPy arrays / torch tensors to pointers and status codes to
+exceptions.  It fails loudly when the library has not been built: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgg.so")
+
+GG_OK, GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP, GG_ERR_CAPACITY, GG_ERR_NONFINITE, GG_ERR_NO_TAPE, \
+    GG_ERR_UNSUPPORTED = range(8)
+GG_MEM_HOST, GG_MEM_DEVICE = 0, 1
+GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS = 1, 2
+FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "stats": 5, "dv": 6,
+         "radius": 7}
+SHAPES = {"plane": 0, "box": 1, "capsule": 2}
+
+EXPORTS = ("gg_create", "gg_set_bodies", "gg_step", "gg_step_backward", "gg_read", "gg_destroy",
+           "gg_status_string", "gg_error_detail")
+
+
+class GGError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"gg status {status}: {detail}")
+
+
+class CapacityError(GGError):
+    pass
+
+
+class Body(C.Structure):
+    _fields_ = [("env", C.c_int32), ("shape", C.c_int32), ("params", C.c_float * 4),
+                ("pose", C.c_float * 12), ("twist", C.c_float * 6)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_float), ("alpha", C.c_float), ("mu", C.c_float), ("gravity", C.c_float * 3),
+                ("n_iters", C.c_int32), ("cell_size", C.c_float), ("hash_size", C.c_int64),
+                ("relax", C.c_float), ("mass_split", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("max_contacts_per_particle", C.c_int32), ("precision", C.c_int32),
+                ("density", C.c_float), ("flags", C.c_uint32), ("device", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("steps_total", C.c_int64), ("n_pp", C.c_int64),
+                ("n_pb", C.c_int64), ("candidates", C.c_int64), ("max_contacts", C.c_int64),
+                ("capacity", C.c_int64), ("last_status", C.c_int64), ("n", C.c_int64),
+                ("n_buckets", C.c_int64), ("ms_detect", C.c_double), ("ms_pja", C.c_double),
+                ("ms_integrate", C.c_double), ("pja_launches", C.c_int64),
+                ("contacts_summed", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libgg.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.gg_create.restype = i32
+        L.gg_create.argtypes = [C.POINTER(Params), i32, vp, i64, vp, vp, vp, i32, C.POINTER(vp)]
+        L.gg_set_bodies.restype = i32
+        L.gg_set_bodies.argtypes = [vp, i32, vp, i32]
+        L.gg_step.restype = i32
+        L.gg_step.argtypes = [vp, i32, vp, i32]
+        L.gg_step_backward.restype = i32
+        L.gg_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+        L.gg_read.restype = i32
+        L.gg_read.argtypes = [vp, i32, vp, i64, C.POINTER(i64), i32]
+        L.gg_destroy.restype = None
+        L.gg_destroy.argtypes = [vp]
+        L.gg_status_string.restype = C.c_char_p
+        L.gg_status_string.argtypes = [i32]
+        L.gg_error_detail.restype = C.c_char_p
+        L.gg_error_detail.argtypes = []
+        _LIB = L
+    return _LIB
+
+
+def _check(st):
+    if st != GG_OK:
+        detail = lib().gg_error_detail().decode()
+        if st == GG_ERR_CAPACITY:
+            raise CapacityError(st, detail)
+        raise GGError(st, detail)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, dtype, shape=None):
+    """(pointer, where, keepalive) for a NumPy array or a torch tensor."""
+    if a is None:
+        return None, GG_MEM_HOST, None
+    if _is_torch(a):
+        import torch
+        tdt = {np.float32: torch.float32, np.int64: torch.int64}[dtype]
+        t = a.detach()
+        if t.dtype != tdt:
+            t = t.to(tdt)
+        t = t.contiguous()
+        return C.c_void_p(t.data_ptr()), (GG_MEM_DEVICE if t.is_cuda else GG_MEM_HOST), t
+    arr = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if shape is not None:
+        arr = arr.reshape(shape)
+    return arr.ctypes.data_as(C.c_void_p), GG_MEM_HOST, arr
+
+
+def make_body(d):
+    """gg_body from a scenes-style dict (shape, params, R, t, nu, omega, env)."""
+    b = Body()
+    b.env = int(d.get("env", 0))
+    b.shape = SHAPES[d["shape"]] if isinstance(d["shape"], str) else int(d["shape"])
+    for q in range(4):
+        b.params[q] = float(d["params"][q])
+    R = np.asarray(d["R"], np.float64).reshape(3, 3)
+    t = np.asarray(d["t"], np.float64)
+    for r in range(3):
+        for c in range(3):
+            b.pose[4 * r + c] = float(R[r, c])
+        b.pose[4 * r + 3] = float(t[r])
+    for q in range(3):
+        b.twist[q] = float(d["nu"][q])
+        b.twist[3 + q] = float(d["omega"][q])
+    return b
+
+
+class Sim:
+    """One gg_sim handle.  Positions/velocities/radii may be NumPy arrays (host)
+    or torch tensors (host or device)."""
+
+    def __init__(self, x, v, radius, bodies=(), *, dt=1e-3, alpha=0.2, mu=0.5, n_iters=20,
+                 gravity=(0.0, 0.0, -9.81), cell_size=0.0, hash_size=0, relax=1.0, mass_split=True,
+                 max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
+                 profile=False, diagnostics=False):
+        L = lib()
+        P = Params()
+        P.dt, P.alpha, P.mu = dt, alpha, mu
+        for a in range(3):
+            P.gravity[a] = gravity[a]
+        P.n_iters = n_iters
+        P.cell_size = cell_size
+        P.hash_size = int(hash_size)
+        P.relax = relax
+        P.mass_split = 1 if mass_split else 0
+        P.max_contacts_per_particle = int(max_contacts)
+        P.density = density
+        P.flags = (GG_FLAG_PROFILE if profile else 0) | (GG_FLAG_DIAGNOSTICS if diagnostics else 0)
+        P.device = device
+        P.stream = stream
+        n = int(x.shape[0])
+        px, wx, kx = _arg(x, np.float32, (-1, 3))
+        pv, wv, kv = _arg(v, np.float32, (-1, 3))
+        pr, wr, kr = _arg(radius, np.float32)
+        if len({wx, wv, wr}) != 1:
+            raise ValueError("x, v and radius must all live on the host or all on the device")
+        offs = None
+        n_envs = 1
+        if env_offsets is not None:
+            offs = np.ascontiguousarray(env_offsets, np.int64)
+            n_envs = len(offs) - 1
+        h = C.c_void_p()
+        st = L.gg_create(C.byref(P), n_envs, None if offs is None else offs.ctypes.data_as(C.c_void_p), n,
+                         px, pv, pr, wx, C.byref(h))
+        _check(st)
+        self._h = h
+        self.n = n
+        self.n_envs = n_envs
+        self.params = P
+        self.n_bodies = 0
+        if bodies:
+            self.set_bodies(bodies)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_bodies(self, bodies):
+        arr = (Body * max(1, len(bodies)))(*[make_body(b) if isinstance(b, dict) else b for b in bodies])
+        _check(lib().gg_set_bodies(self._h, len(bodies), arr, GG_MEM_HOST))
+        self.n_bodies = len(bodies)
+
+    def step(self, n_steps=1, twists=None):
+        pt, wt, kt = _arg(twists, np.float32)
+        _check(lib().gg_step(self._h, int(n_steps), pt, wt))
+
+    def read_bytes(self, field):
+        w = C.c_int64(0)
+        _check(lib().gg_read(self._h, FIELD[field], None, 0, C.byref(w), GG_MEM_HOST))
+        return int(w.value)
+
+    def read(self, field, out=None):
+        """NumPy copy of a field, or copy into a given device tensor ``out``."""
+        nbytes = self.read_bytes(field)
+        if out is not None:
+            w = C.c_int64(0)
+            _check(lib().gg_read(self._h, FIELD[field], C.c_void_p(out.data_ptr()),
+                                 out.numel() * out.element_size(), C.byref(w),
+                                 GG_MEM_DEVICE if out.is_cuda else GG_MEM_HOST))
+            return out
+        if field == "stats":
+            s = Stats()
+            w = C.c_int64(0)
+            _check(lib().gg_read(self._h, FIELD[field], C.byref(s), C.sizeof(s), C.byref(w), GG_MEM_HOST))
+            return s.as_dict()
+        dtype, cols = {"pos": (np.float32, 3), "vel": (np.float32, 3), "dv": (np.float32, 3),
+                       "radius": (np.float32, 0), "cell_index": (np.int64, 0), "contacts": (np.int32, 2),
+                       "impulses": (np.float32, 3)}[field]
+        item = np.dtype(dtype).itemsize * max(cols, 1)
+        rows = nbytes // item
+        arr = np.empty((rows, cols) if cols else (rows,), dtype)
+        w = C.c_int64(0)
+        if nbytes:
+            _check(lib().gg_read(self._h, FIELD[field], arr.ctypes.data_as(C.c_void_p), nbytes, C.byref(w),
+                                 GG_MEM_HOST))
+        return arr
+
+    def stats(self):
+        return self.read("stats")
+
+    def backward(self, dL_dx=None, dL_dv=None):
+        _check(lib().gg_step_backward(self._h, None, None, None, None, None, GG_MEM_HOST))
+
+
+def scene_sim(scene, **kw):
+    """Sim initialised from a scenes.Scene (host arrays)."""
+    args = dict(dt=scene.dt, alpha=scene.alpha, mu=scene.mu, n_iters=scene.n_iters,
+                gravity=scene.gravity, env_offsets=scene.env_offsets)
+    args.update(kw)
+    return Sim(scene.x, scene.v, scene.radius, scene.bodies, **args)
