@@ -85,11 +85,74 @@ def copy_calibration(mib=512, reps=5):
     log(f"copy calibration: {reps} copies of {mib} MiB")
 
 
+def bench_batched(args):
+    """256 independent environments of U{8192..65536} spheres stepped in one
+    launch sequence, against the same environments stepped one by one."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    steps = args.steps if args.steps_given else 100
+    log("generating 256 batched environments")
+    sc = scenes.batched_scene(n_steps=steps + args.warmup)
+    n = sc.n
+    tw = np.ascontiguousarray(sc.twists)
+    sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters,
+                 env_offsets=sc.env_offsets, profile=True)
+    if args.warmup:
+        sim.step(args.warmup, twists=tw[:args.warmup])
+    torch.cuda.synchronize()
+    log(f"batched: n={n}, timing {steps} steps")
+    t0 = time.perf_counter()
+    sim.step(steps, twists=tw[args.warmup:args.warmup + steps])
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    # plain loop: every environment its own simulation, stepped in turn
+    n_envs = len(sc.env_offsets) - 1
+    plain_steps = max(1, min(steps, args.plain_steps))
+    sims = []
+    nb_env = len(sc.bodies) // n_envs
+    for e in range(n_envs):
+        a, b = int(sc.env_offsets[e]), int(sc.env_offsets[e + 1])
+        bodies = [dict(bd, env=0) for bd in sc.bodies[e * nb_env:(e + 1) * nb_env]]
+        sims.append((gg.Sim(sc.x[a:b], sc.v[a:b], sc.radius[a:b], bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
+                            n_iters=sc.n_iters), np.ascontiguousarray(tw[:, e * nb_env:(e + 1) * nb_env])))
+    for sm, t in sims:
+        sm.step(min(args.warmup, 2), twists=t[:min(args.warmup, 2)])
+    torch.cuda.synchronize()
+    log(f"plain loop: {n_envs} sims, timing {plain_steps} steps")
+    t0 = time.perf_counter()
+    for k in range(plain_steps):
+        for sm, t in sims:
+            sm.step(1, twists=t[args.warmup + k:args.warmup + k + 1])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) * steps / plain_steps
+    for sm, _ in sims:
+        sm.close()
+    value = n * steps / t_batched
+    return {
+        "metric": "batched particle-steps/s (256 envs, 20 PJA iters)",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_batched / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched: 256 walled beds of U{8192..65536} spheres r=3mm, capsule tools with "
+                               "random piecewise-constant twists, dt=1 ms, 20 PJA sweeps",
+                   "n": n, "n_envs": n_envs, "plain_loop_steps_timed": plain_steps},
+        "speedup_vs_plain_loop": t_plain / t_batched,
+        "plain_loop_particle_steps_per_s": n * steps / t_plain,
+        "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
+                               "integrate": st["ms_integrate"] / steps},
+        "detect_fallback_items": st["detect_fallback"], "detect_items": st["detect_items"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=["scoop", "batched"], default="scoop")
+    ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -101,6 +164,13 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         copy_calibration()
+        return
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 200
+    if args.workload == "batched":
+        out = bench_batched(args)
+        print(json.dumps(out), flush=True)
         return
 
     from paper_2306_01369_amd import gg, scenes

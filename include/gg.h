@@ -95,6 +95,13 @@ typedef struct {
   int32_t precision; /* 0 = binary32 (only value supported) */
   float density;     /* grain density for m = rho 4/3 pi r^3; 0 -> 2500 */
   uint32_t flags;    /* GG_FLAG_* */
+  int32_t reorder_every;  /* steps between re-sorts of the internal particle order along a
+                             Z-order curve (memory locality only; results do not depend on
+                             it); 0 -> 8, < 0 -> never */
+  int32_t tile_max_cells; /* detection tile limit in cells (item box + halo); 0 -> 512 */
+  int32_t tile_max_stage; /* detection tile limit in staged particles; 0 -> 768 */
+  int32_t tile_node_shift;/* detection work items follow Z-order nodes of 2^shift cells
+                             (6 = 4x4x4), at most 128 particles each; 0 -> 6 */
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL */
 } gg_params;
@@ -168,6 +175,9 @@ typedef struct {
   double ms_integrate;    /* profiled: position update, summed */
   int64_t pja_launches;   /* profiled: projected-Jacobi launches timed */
   int64_t contacts_summed;/* contacts (pairs + body) summed over the steps of the last call */
+  int64_t detect_fallback;/* detection work items (up to 128 particles each) that queried cells
+                             one particle at a time instead of through an LDS tile, last detection */
+  int64_t detect_items;   /* detection work items */
 } gg_stats;
 
 /* Copy a field into dst (where says where dst lives).  If dst is NULL only

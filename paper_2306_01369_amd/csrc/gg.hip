@@ -122,6 +122,17 @@ struct gg_sim {
 
   // device buffers
   float4 *x = nullptr, *v = nullptr, *wa = nullptr, *wb = nullptr, *dv = nullptr;
+  float4 *x2 = nullptr, *v2 = nullptr;                 // permutation targets
+  int32_t *orig = nullptr, *orig2 = nullptr;            // caller index of each internal slot
+  unsigned long long *mk[2] = {nullptr, nullptr};      // Z-order keys (radix ping-pong)
+  int32_t *mv[2] = {nullptr, nullptr};                 // permutation values
+  int32_t *rs_hist = nullptr, *rs_bsum = nullptr;      // radix histograms and their scan
+  int rs_nb = 0, rs_passes = 0;
+  float4* xs = nullptr;                                // bucket-ordered positions
+  int32_t* os = nullptr;                               // bucket-ordered original indices
+  int32_t *it_f = nullptr, *it_e = nullptr, *it_first = nullptr, *it_g = nullptr, *it_h = nullptr;
+  int32_t *item_start = nullptr, *it_bsum = nullptr;
+  int64_t steps_global = 0;
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
   float *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
@@ -172,6 +183,9 @@ gg_status check_params(const gg_params* p) {
   if (p->precision != 0) return fail(GG_ERR_UNSUPPORTED, "only precision 0 (binary32) is built");
   if (!(p->density >= 0.0f) || !std::isfinite(p->density)) return fail(GG_ERR_INVALID, "density must be finite and >= 0");
   if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS)) return fail(GG_ERR_INVALID, "unknown flag bits");
+  if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
+  if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
+  if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
   if (p->device < 0) return fail(GG_ERR_INVALID, "device must be >= 0");
   return GG_OK;
 }
@@ -224,7 +238,9 @@ ggk::EnvTables env_tables(const gg_sim* s) {
 }
 
 void free_all(gg_sim* s) {
-  void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->h, s->rank, s->counts, s->bstart, s->bsum,
+  void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->x2, s->v2, s->orig, s->orig2, s->mk[0], s->mk[1],
+                  s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
+                  s->it_g, s->it_h, s->item_start, s->it_bsum, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp};
   for (void* b : bufs)
@@ -357,6 +373,16 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (s->p.relax == 0.0f) s->p.relax = 1.0f;
   if (s->p.density == 0.0f) s->p.density = 2500.0f;
   if (s->p.checkpoint_every == 0) s->p.checkpoint_every = 10;
+  if (s->p.reorder_every == 0) s->p.reorder_every = 8;
+  if (s->p.tile_max_cells == 0) s->p.tile_max_cells = 512;
+  if (s->p.tile_max_stage == 0) s->p.tile_max_stage = 768;
+  if (s->p.tile_node_shift == 0) s->p.tile_node_shift = 6;
+  {
+    int bits = 30;
+    while ((1 << (bits - 30)) < n_envs) ++bits;
+    s->rs_passes = (bits + ggk::kRsBits - 1) / ggk::kRsBits;
+    s->rs_nb = (int)((n + ggk::kRsItems - 1) / ggk::kRsItems);
+  }
   s->dev = params->device;
   s->n = n;
   s->n_envs = n_envs;
@@ -397,7 +423,18 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
             dev_alloc(&s->bstart, (size_t)total + 1) == hipSuccess &&
             dev_alloc(&s->bsum, (size_t)(total + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
             dev_alloc(&s->sidx, N) == hipSuccess && dev_alloc(&s->ncon, N) == hipSuccess &&
-            dev_alloc(&s->ctl, 1) == hipSuccess;
+            dev_alloc(&s->ctl, 1) == hipSuccess && dev_alloc(&s->x2, N) == hipSuccess &&
+            dev_alloc(&s->v2, N) == hipSuccess && dev_alloc(&s->orig, N) == hipSuccess &&
+            dev_alloc(&s->orig2, N) == hipSuccess && dev_alloc(&s->mk[0], N) == hipSuccess &&
+            dev_alloc(&s->mk[1], N) == hipSuccess && dev_alloc(&s->mv[0], N) == hipSuccess &&
+            dev_alloc(&s->mv[1], N) == hipSuccess &&
+            dev_alloc(&s->rs_hist, (size_t)256 * std::max(1, s->rs_nb) + 1) == hipSuccess &&
+            dev_alloc(&s->rs_bsum, (size_t)(256 * std::max(1, s->rs_nb) + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
+            dev_alloc(&s->xs, N) == hipSuccess && dev_alloc(&s->os, N) == hipSuccess &&
+            dev_alloc(&s->it_f, N + 1) == hipSuccess && dev_alloc(&s->it_e, N + 1) == hipSuccess &&
+            dev_alloc(&s->it_first, N + 1) == hipSuccess && dev_alloc(&s->it_g, N + 1) == hipSuccess &&
+            dev_alloc(&s->it_h, N + 1) == hipSuccess && dev_alloc(&s->item_start, N + 2) == hipSuccess &&
+            dev_alloc(&s->it_bsum, (N + 1 + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess;
   if (ok && (s->p.flags & GG_FLAG_DIAGNOSTICS)) ok = dev_alloc(&s->dv, N) == hipSuccess;
   if (ok && n_envs > 1) {
     ok = dev_alloc(&s->env_of, N) == hipSuccess && dev_alloc(&s->d_env_nh, (size_t)n_envs) == hipSuccess &&
@@ -425,6 +462,12 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   }
   if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total * 4);
   if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
+  if (e == hipSuccess && n > 0) {
+    ggk::k_iota<<<(int)((n + 255) / 256), 256>>>((int)n, s->orig);
+    ggk::k_item_fixed<<<(int)((n + 255) / 256), 256>>>((int)n, s->item_start, &s->ctl->items);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
   if (e == hipSuccess && n_envs > 1) {
     std::vector<int32_t> eo(N, 0);
     for (int q = 0; q < n_envs; ++q)
@@ -566,27 +609,64 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int m = (int)s->n_buckets;
   const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
-  int dblock = K <= 32 ? 256 : (K <= 64 ? 128 : 64);
-  const int dgrid = (n + dblock - 1) / dblock;
-  const size_t dlds = (size_t)dblock * K * sizeof(int);
+  const int dgrid = std::max(1, std::min((n + 31) / 32, 2048));
+  const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
+  const size_t dlds = ((((size_t)max_cells + 1) * 4 + 15) & ~(size_t)15) + (size_t)max_stage * (16 + 4 + 4);
   const ggk::EnvTables et = env_tables(s);
   const int nh1 = s->env_nh[0];
   const float dt = s->p.dt, gx = s->p.gravity[0], gy = s->p.gravity[1], gz = s->p.gravity[2];
   const float alpha_dt = s->p.alpha / s->p.dt;
+  const int rs_m = 256 * s->rs_nb;
+  const int rs_nbs = (rs_m + ggk::kScanTile - 1) / ggk::kScanTile;
   hipStream_t S = s->stream;
 
   ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
   for (int st = 0; st < n_steps && n > 0; ++st) {
     const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st], S));
+    const int64_t g = s->steps_global + st;
+    if (s->p.reorder_every > 0 && g % s->p.reorder_every == 0) {
+      // Z-order re-sort of the internal particle order (locality only)
+      ggk::k_morton_keys<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, s->env_of, s->mk[0]);
+      for (int pass = 0; pass < s->rs_passes; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
+        ggk::k_scan_a<<<rs_nbs, ggk::kBlock, 0, S>>>(rs_m, s->rs_hist, s->rs_hist, s->rs_bsum, 0);
+        ggk::k_scan_b<<<1, 1024, 0, S>>>(rs_nbs, s->rs_bsum, rs_m, s->rs_hist);
+        ggk::k_scan_c<<<(rs_m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(rs_m, s->rs_bsum, s->rs_hist);
+        ggk::k_rs_scatter<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass == 0 ? nullptr : s->mv[src],
+                                                             s->mk[dst], s->mv[dst], pass * ggk::kRsBits, s->rs_nb,
+                                                             s->rs_hist);
+      }
+      ggk::k_permute<<<grid, ggk::kBlock, 0, S>>>(n, s->mv[s->rs_passes & 1], s->x, s->v, s->orig, s->x2, s->v2,
+                                                  s->orig2);
+      std::swap(s->x, s->x2);
+      std::swap(s->v, s->v2);
+      std::swap(s->orig, s->orig2);
+      // detection work items: runs of <= kDetBlock particles within one Z-order node
+      const unsigned long long* keys = s->mk[s->rs_passes & 1];
+      const int it_nbs = (n + ggk::kScanTile - 1) / ggk::kScanTile;
+      ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift, s->it_f);
+      ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_bsum, 0);
+      ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
+      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
+      ggk::k_node_first<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first);
+      ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, ggk::kDetBlock, s->it_g);
+      ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->it_bsum, 0);
+      ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_h);
+      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
+      ggk::k_item_starts<<<grid, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->item_start);
+      ggk::k_copy_i32<<<1, 64, 0, S>>>(s->it_h + n, &s->ctl->items);
+    }
     ggk::k_key<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
-    ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum);
+    ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
     ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
     ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
-    ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, s->sidx);
-    ggk::k_detect<<<dgrid, dblock, dlds, S>>>(n, K, s->x, s->v, s->inv_c, nh1, et, s->bstart, s->sidx, bod, nb,
-                                              gx, gy, gz, dt, s->p.mass_split, s->ncon, s->partner, s->Psi, s->wa,
-                                              s->ctl, st);
+    ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, s->x, s->orig, s->sidx, s->xs, s->os);
+    ggk::k_detect<<<dgrid, ggk::kDetBlock, dlds, S>>>(n, K, s->x, s->v, s->orig, s->inv_c, nh1, et, s->bstart,
+                                                       s->sidx, s->xs, s->os, s->item_start, &s->ctl->items, bod, nb,
+                                                       gx, gy, gz, dt, s->p.mass_split, max_cells, max_stage,
+                                                       s->ncon, s->partner, s->Psi, s->wa, s->ctl, st);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
     float4* win = s->wa;
     float4* wout = s->wb;
@@ -620,12 +700,15 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
     }
   s->stats.steps_done = done;
   s->stats.steps_total += done;
+  s->steps_global += n_steps;
   if (n > 0) {
     s->stats.n_pp = (int64_t)c.n_pp;
     s->stats.n_pb = (int64_t)c.n_pb;
     s->stats.candidates = (int64_t)c.cand;
     s->stats.max_contacts = c.max_cnt;
     s->stats.contacts_summed = (int64_t)c.summed;
+    s->stats.detect_fallback = c.fallback;
+    s->stats.detect_items = c.items;
   }
   s->stats.capacity = K;
   if (prof && n > 0) {
@@ -701,11 +784,13 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
       field == GG_FIELD_CELL_INDEX) {
     gg_status st = ensure_tmp(s, (size_t)need);
     if (st != GG_OK) return st;
-    if (field == GG_FIELD_POS) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->x, (float*)s->tmp);
-    if (field == GG_FIELD_VEL) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->v, (float*)s->tmp);
-    if (field == GG_FIELD_DV) ggk::k_pack3<<<blocks, 256, 0, s->stream>>>((int)n, s->dv, (float*)s->tmp);
-    if (field == GG_FIELD_RADIUS) ggk::k_pack_w<<<blocks, 256, 0, s->stream>>>((int)n, s->x, (float*)s->tmp);
-    if (field == GG_FIELD_CELL_INDEX) ggk::k_widen<<<blocks, 256, 0, s->stream>>>((int)n, s->h, (int64_t*)s->tmp);
+    float* f = (float*)s->tmp;
+    if (field == GG_FIELD_POS) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->x, f);
+    if (field == GG_FIELD_VEL) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->v, f);
+    if (field == GG_FIELD_DV) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->dv, f);
+    if (field == GG_FIELD_RADIUS) ggk::k_unpermute_w<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->x, f);
+    if (field == GG_FIELD_CELL_INDEX)
+      ggk::k_unpermute_i64<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->h, (int64_t*)s->tmp);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(dst, s->tmp, (size_t)need, kind, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -713,10 +798,11 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
   }
   // contacts / impulses: gather the per-particle lists into the canonical order
   const size_t slots = (size_t)s->n_pad * s->K;
-  std::vector<int32_t> cnt(n), part(slots);
+  std::vector<int32_t> cnt(n), part(slots), org(n);
   std::vector<float> px, py, pz;
   HIPCHK(s, hipMemcpyAsync(cnt.data(), s->ncon, n * 4, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipMemcpyAsync(part.data(), s->partner, slots * 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(org.data(), s->orig, n * 4, hipMemcpyDeviceToHost, s->stream));
   if (field == GG_FIELD_IMPULSES) {
     px.resize(slots); py.resize(slots); pz.resize(slots);
     HIPCHK(s, hipMemcpyAsync(px.data(), s->Px, slots * 4, hipMemcpyDeviceToHost, s->stream));
@@ -724,33 +810,40 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
     HIPCHK(s, hipMemcpyAsync(pz.data(), s->Pz, slots * 4, hipMemcpyDeviceToHost, s->stream));
   }
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  std::vector<int32_t> pairs;
-  std::vector<float> imp;
-  std::vector<int32_t> bpairs;
-  std::vector<float> bimp;
-  pairs.reserve(2 * (size_t)s->stats.n_pp);
+  struct Rec {
+    int32_t a, b;
+    size_t slot;
+  };
+  std::vector<Rec> pp, pb;
+  pp.reserve((size_t)s->stats.n_pp);
   const int K = s->K;
   for (int64_t i = 0; i < n; ++i) {
     for (int k = 0; k < cnt[i]; ++k) {
       const size_t sl = (size_t)(i >> 6) * ((size_t)K << 6) + ((size_t)k << 6) + (size_t)(i & 63);
-      const int32_t j = part[sl];
-      if (j > i) {
-        pairs.push_back((int32_t)i);
-        pairs.push_back(j);
-        if (field == GG_FIELD_IMPULSES) {
-          imp.push_back(px[sl]); imp.push_back(py[sl]); imp.push_back(pz[sl]);
-        }
-      } else if (j < 0) {
-        bpairs.push_back((int32_t)i);
-        bpairs.push_back(-1 - j);
-        if (field == GG_FIELD_IMPULSES) {
-          bimp.push_back(px[sl]); bimp.push_back(py[sl]); bimp.push_back(pz[sl]);
-        }
+      const int32_t code = part[sl];
+      if (code >= 0) {
+        if ((code & ggk::kHiFlag) == 0) pp.push_back({org[i], org[code & (ggk::kHiFlag - 1)], sl});
+      } else {
+        pb.push_back({org[i], -1 - code, sl});
       }
     }
   }
-  pairs.insert(pairs.end(), bpairs.begin(), bpairs.end());
-  imp.insert(imp.end(), bimp.begin(), bimp.end());
+  auto by_pair = [](const Rec& u, const Rec& w) { return u.a != w.a ? u.a < w.a : u.b < w.b; };
+  std::sort(pp.begin(), pp.end(), by_pair);
+  std::sort(pb.begin(), pb.end(), by_pair);
+  std::vector<int32_t> pairs;
+  std::vector<float> imp;
+  for (const auto* L : {&pp, &pb})
+    for (const Rec& r : *L) {
+      if (field == GG_FIELD_CONTACTS) {
+        pairs.push_back(r.a);
+        pairs.push_back(r.b);
+      } else {
+        imp.push_back(px[r.slot]);
+        imp.push_back(py[r.slot]);
+        imp.push_back(pz[r.slot]);
+      }
+    }
   const void* src = field == GG_FIELD_CONTACTS ? (const void*)pairs.data() : (const void*)imp.data();
   const int64_t have = field == GG_FIELD_CONTACTS ? (int64_t)pairs.size() * 4 : (int64_t)imp.size() * 4;
   if (have != need) return fail(GG_ERR_HIP, "contact list size disagrees with the detection counters");

@@ -1,26 +1,33 @@
 // Device kernels of the granular contact step for gfx950 (CDNA4, wave64).
 //
 // Per timestep (arXiv 2306.01369, Sec. II):
+//   k_morton_keys, k_rs_*, k_permute
+//              (every few steps) re-sort the particle state along a Z-order
+//              curve over the cells, a 64-bit LSD radix sort with wave64
+//              ballot ranking; the order only affects memory locality
 //   k_key      cell coordinates and spatial hash (Eq. (6)); bucket counters
 //   k_scan_*   exclusive prefix sum of the bucket counters -> bucket_start
 //   k_scatter  particles into hash-bucket order (stands in for Alg. 2's lists)
-//   k_detect   27-cell query, sphere test, SDF body tests (Sec. II-B, II-C, Eq. (7));
-//              writes each particle's sorted partner list
+//   k_detect   27-cell query from LDS-staged cell tiles, sphere test, SDF body
+//              tests (Sec. II-B, II-C, Eq. (7)); writes each particle's partners
 //   k_pja      one projected-Jacobi sweep (Alg. 1) over all contacts, gathered
 //              per particle; the last sweep also writes the new velocity
 //   k_integrate  positions from the new velocities (Eq. (5))
 //
 // Layout.  Particle state is structure-of-arrays float4: x = (x, y, z, r),
 // v = (vx, vy, vz, 1/m), w = (wx, wy, wz, s) with s = n_i/m_i (the split inverse
-// mass).  Every contact is stored once per member ("half contacts") in an
+// mass), and orig = the caller's index of each (internally reordered)
+// particle.  Every contact is stored once per member ("half contacts") in an
 // ELL table of K slots per particle, laid out slot-major within groups of 64
 // particles: slot(i, k) = (i/64)*64K + 64k + i%64, so the k-th contact of the 64
 // lanes of a wavefront is one contiguous 256-byte row.  Each half contact holds
-// the partner (>= 0 particle, < 0 body -1-b) and the world-frame impulse on the
-// lower-indexed member; both halves compute it with identical arithmetic from
-// identical inputs, so the two copies agree bit for bit and no atomics or
-// second pass are needed.  Sums run in partner order, so results are
-// deterministic and independent of the launch shape.
+// the partner (>= 0 particle, with a flag when this particle has the higher
+// original index; < 0 body -1-b), the gap psi and the world-frame impulse on
+// the member with the lower original index; both halves compute it with
+// identical arithmetic from identical inputs, so the two copies agree bit for
+// bit and no atomics or second pass are needed.  Partners are listed in a
+// canonical order (neighbour cell, then original index), so results are
+// deterministic and independent of the internal order and launch shape.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,6 +35,8 @@
 namespace ggk {
 
 constexpr int kBlock = 256;
+constexpr int kRsBits = 8;
+constexpr int kDetBlock = 128;
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
 
@@ -49,6 +58,8 @@ struct Ctl {                    // device control block, one per simulation
   unsigned long long n_pb;      // body contacts (last detection)
   unsigned long long cand;      // ordered candidate pairs (last detection)
   unsigned long long summed;    // contacts summed over the steps of the current call
+  int32_t fallback;             // detection work items that took the per-particle path (last detection)
+  int32_t items;                // detection work items (set when they are built)
 };
 
 struct EnvTables {   // per-environment hash tables (batched form)
@@ -306,15 +317,128 @@ __global__ void k_begin(Ctl* ctl) {
   }
 }
 
+// ------------------------------------------------- spatial (Morton) order
+// The internal particle order follows a Z-order curve over the cells so that a
+// workgroup's particles occupy a compact block of cells and their neighbours
+// sit nearby in memory.  Keys: environment in the high bits, then the Morton
+// code of the low 10 bits of each cell coordinate (wrap-around only costs
+// locality, never correctness).
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 1023u;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const float4* __restrict__ x, float inv_c,
+                                                        const int32_t* __restrict__ env_of,
+                                                        unsigned long long* __restrict__ keys) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 p = x[i];
+  bool ok = true;
+  const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
+  const uint32_t m = spread10((uint32_t)(k0 + 512)) | (spread10((uint32_t)(k1 + 512)) << 1) |
+                     (spread10((uint32_t)(k2 + 512)) << 2);
+  const unsigned long long e = env_of ? (unsigned long long)env_of[i] : 0ull;
+  keys[i] = (e << 30) | (unsigned long long)m;
+}
+
+// LSD radix sort, 8-bit digits, stable.  Each block owns kRsItems consecutive
+// keys, processed in rounds of 256 (item = base + 256*round + thread).
+constexpr int kRsRounds = 16;
+constexpr int kRsItems = kBlock * kRsRounds;
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(int n, const unsigned long long* __restrict__ keys, int shift,
+                                                    int nb, int32_t* __restrict__ ghist) {
+  __shared__ int hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kRsItems;
+  for (int r = 0; r < kRsRounds; ++r) {
+    const int it = base + r * kBlock + threadIdx.x;
+    if (it < n) atomicAdd(&hist[(int)((keys[it] >> shift) & 255ull)], 1);
+  }
+  __syncthreads();
+  ghist[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Stable scatter: within a round, a key's rank among equal digits is (equal
+// digits in earlier wavefronts) + (equal digits in earlier lanes), the latter
+// from an 8-ballot match of the digit.
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(int n, const unsigned long long* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin,
+                                                       unsigned long long* __restrict__ kout,
+                                                       int32_t* __restrict__ vout, int shift, int nb,
+                                                       const int32_t* __restrict__ gscan) {
+  __shared__ int base_d[256];
+  __shared__ int wcnt[kBlock / 64][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  base_d[threadIdx.x] = gscan[threadIdx.x * nb + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int base = blockIdx.x * kRsItems;
+  for (int r = 0; r < kRsRounds; ++r) {
+    const int it = base + r * kBlock + threadIdx.x;
+    const bool valid = it < n;
+    unsigned long long key = valid ? kin[it] : 0ull;
+    const int val = valid ? (vin ? vin[it] : it) : 0;
+    const int d = (int)((key >> shift) & 255ull);
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long bal = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? bal : ~bal;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = base_d[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      add += wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = 0;
+    }
+    base_d[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// Apply the permutation (new position k takes old index perm[k]) to the state.
+__global__ __launch_bounds__(kBlock) void k_permute(int n, const int32_t* __restrict__ perm,
+                                                    const float4* __restrict__ xi, const float4* __restrict__ vi,
+                                                    const int32_t* __restrict__ oi, float4* __restrict__ xo,
+                                                    float4* __restrict__ vo, int32_t* __restrict__ oo) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int j = perm[k];
+  xo[k] = xi[j];
+  vo[k] = vi[j];
+  oo[k] = oi[j];
+}
+
+// ------------------------------------------------------ hash-bucket table
 // Cell keys and bucket counters.  rank[i] is the arrival order of i in its
-// bucket; the order inside a bucket is irrelevant downstream because partner
-// lists are sorted.
+// bucket; the order inside a bucket is irrelevant downstream because the
+// members of each cell are re-sorted by original index when staged.
 __global__ __launch_bounds__(kBlock) void k_key(int n, const float4* __restrict__ x, float inv_c, int nh,
                                                 EnvTables env, int32_t* __restrict__ h,
                                                 int32_t* __restrict__ rank, int32_t* __restrict__ counts,
                                                 Ctl* ctl, int step) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->err == 0) {
-    ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0;
+    ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0; ctl->fallback = 0;
   }
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -335,10 +459,11 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const float4* __restrict_
   rank[i] = atomicAdd(&counts[bucket], 1);
 }
 
-// Block-local exclusive scan of kScanTile counters; zeroes the counters for
-// the next step and writes the block total.
+// Block-local exclusive scan of kScanTile counters; zeroes the counters when
+// asked (the bucket counters are reused next step) and writes the block total.
 __global__ __launch_bounds__(kBlock) void k_scan_a(int m, int32_t* __restrict__ counts,
-                                                   int32_t* __restrict__ start, int32_t* __restrict__ bsum) {
+                                                   int32_t* __restrict__ start, int32_t* __restrict__ bsum,
+                                                   int zero) {
   __shared__ int wsum[kBlock / 64];
   const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
   int v[4];
@@ -346,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_a(int m, int32_t* __restrict__ 
   for (int q = 0; q < 4; ++q) {
     int e = base + q;
     v[q] = e < m ? counts[e] : 0;
-    if (e < m) counts[e] = 0;
+    if (zero && e < m) counts[e] = 0;
   }
   const int t = v[0] + v[1] + v[2] + v[3];
   const int s = wave_incl_scan(t);
@@ -395,117 +520,332 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(int m, const int32_t* __restr
   if (e < m) start[e] += bsum[e / kScanTile];
 }
 
+// Particles into bucket order: index, position and original index, so that a
+// bucket's members are read with independent loads.
 __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __restrict__ h,
                                                     const int32_t* __restrict__ rank,
-                                                    const int32_t* __restrict__ start,
-                                                    int32_t* __restrict__ sidx) {
+                                                    const int32_t* __restrict__ start, const float4* __restrict__ x,
+                                                    const int32_t* __restrict__ orig, int32_t* __restrict__ sidx,
+                                                    float4* __restrict__ xs, int32_t* __restrict__ os) {
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
-  sidx[start[h[i]] + rank[i]] = i;
+  const int q = start[h[i]] + rank[i];
+  sidx[q] = i;
+  xs[q] = x[i];
+  os[q] = orig[i];
 }
 
-// Contact detection, one thread per particle.  Candidates come from the
-// buckets of the particle's cell and its 26 neighbours; a candidate counts only
-// if it lies in the queried cell (aliasing buckets), so each pair is found once
-// per member.  The partner list is kept sorted in LDS (insertion), bodies
-// follow the particles in body order.  Also seeds the Jacobi iterate
-// w = v + dt g and the split inverse mass s_i.
-__global__ __launch_bounds__(kBlock) void k_detect(
-    int n, int K, const float4* __restrict__ x, const float4* __restrict__ v, float inv_c, int nh,
-    EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
-    const DevBody* __restrict__ bodies, int n_bodies, float gx, float gy, float gz, float dt,
-    int mass_split, int32_t* __restrict__ ncon, int32_t* __restrict__ partner, float* __restrict__ Psi,
-    float4* __restrict__ w, Ctl* ctl, int step) {
-  extern __shared__ int lds_list[];
+// ----------------------------------------------- detection work items
+// Work items are runs of at most kDetBlock consecutive particles of one
+// Z-order node (2^node_shift cells), so each item's cells form a compact box.
+// Built after every re-sort from the sorted keys.
+__global__ __launch_bounds__(kBlock) void k_node_flags(int n, const unsigned long long* __restrict__ keys,
+                                                       int node_shift, int32_t* __restrict__ f) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  f[k] = (k == 0 || (keys[k] >> node_shift) != (keys[k - 1] >> node_shift)) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_node_first(int n, const int32_t* __restrict__ f,
+                                                       const int32_t* __restrict__ e, int32_t* __restrict__ first) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < n && f[k]) first[e[k]] = k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_item_flags(int n, const int32_t* __restrict__ f,
+                                                       const int32_t* __restrict__ e,
+                                                       const int32_t* __restrict__ first, int item,
+                                                       int32_t* __restrict__ g) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int node = e[k] + f[k] - 1;
+  g[k] = ((k - first[node]) % item) == 0 ? 1 : 0;
+}
+
+// item_start[0 .. n_items] (n_items = scan total, item_start[n_items] = n)
+__global__ __launch_bounds__(kBlock) void k_item_starts(int n, const int32_t* __restrict__ g,
+                                                        const int32_t* __restrict__ hsc,
+                                                        int32_t* __restrict__ item_start) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < n && g[k]) item_start[hsc[k]] = k;
+  if (k == 0) item_start[hsc[n]] = n;
+}
+
+// Fixed items of kDetBlock particles (used until the first re-sort).
+__global__ __launch_bounds__(kBlock) void k_item_fixed(int n, int32_t* __restrict__ item_start,
+                                                       int32_t* __restrict__ n_items) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int ni = (n + kDetBlock - 1) / kDetBlock;
+  if (k < ni) item_start[k] = k * kDetBlock;
+  if (k == 0) {
+    item_start[ni] = n;
+    *n_items = ni;
+  }
+}
+
+// ------------------------------------------------------------ detection
+constexpr int32_t kHiFlag = 1 << 30;   // partner entry: this particle is the higher original index
+
+__device__ __forceinline__ int block_min(int v, int* red) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wid] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = min(r, red[w]);
+  return r;
+}
+
+__device__ __forceinline__ int block_max(int v, int* red) { return -block_min(-v, red); }
+
+// In-place exclusive scan of a[0..m) in LDS by the whole block; a[m] = total.
+__device__ void block_exclusive_scan(int* a, int m, int* red) {
+  const int T = blockDim.x;
+  const int per = (m + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(b + per, m);
+  int loc = 0;
+  for (int q = b; q < e; ++q) loc += a[q];
+  const int incl = wave_incl_scan(loc);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 63) red[wid] = incl;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wid; ++w) off += red[w];
+  int run = off + incl - loc;
+  for (int q = b; q < e; ++q) {
+    const int t = a[q];
+    a[q] = run;
+    run += t;
+  }
+  if (threadIdx.x == T - 1) a[m] = run;
+  __syncthreads();
+}
+
+// Write contact k of particle i (when within capacity).
+__device__ __forceinline__ void put_contact(int i, int k, int K, int32_t code, float psi, int32_t* partner,
+                                            float* Psi) {
+  if (k < K) {
+    const int sl = ell_slot(i, k, K);
+    partner[sl] = code;
+    Psi[sl] = psi;
+  }
+}
+
+// Contact detection over work items (runs of at most kDetBlock particles of one
+// Z-order node); each workgroup takes a contiguous range of items.
+// Tile path: the bounding box of the item's cells, widened by one cell, is
+// looked up once per cell through the hash table (bucket of Eq. (6), members
+// filtered by their own cell since buckets alias); the members are staged in
+// LDS sorted by original index, and every particle tests the 27 cells around
+// it from LDS.  Fallback path (box or staging larger than the LDS budget, or
+// an item spanning environments): each particle queries its 27 cells
+// directly.  Both paths list partners in the same canonical order (neighbour
+// cell, then original index), then bodies in body order, so results do not
+// depend on the internal order or on the path taken.  Also seeds the Jacobi
+// iterate w = v + dt g and the split inverse mass s_i = n_i / m_i.
+__global__ __launch_bounds__(kDetBlock) void k_detect(
+    int n, int K, const float4* __restrict__ x, const float4* __restrict__ v, const int32_t* __restrict__ orig,
+    float inv_c, int nh, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    const float4* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
+    const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, float gx,
+    float gy, float gz, float dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
+    int32_t* __restrict__ partner, float* __restrict__ Psi, float4* __restrict__ w, Ctl* ctl, int step) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int red[kDetBlock / 64];
   if (ctl->err) return;
-  const int i = xcd_block() * blockDim.x + threadIdx.x;
-  const bool active = i < n;
-  int cnt = 0, cand = 0, npp = 0, npb = 0;
-  if (active) {
-    int* L = lds_list + threadIdx.x;
-    const int B = blockDim.x;
-    const float4 p = x[i];
+  int* cell_off = (int*)smem;                                             // max_cells + 1
+  float4* st_x = (float4*)(smem + ((((max_cells + 1) * 4) + 15) & ~15));  // max_stage
+  int* st_j = (int*)(st_x + max_stage);                                    // max_stage
+  int* st_o = st_j + max_stage;                                            // max_stage
+
+  const int n_items = *n_items_ptr;
+  const int per = (n_items + gridDim.x - 1) / gridDim.x;
+  const int blk = xcd_block();
+  const int it0 = min(blk * per, n_items), it1 = min(it0 + per, n_items);
+  int cand = 0, npp = 0, npb = 0, mx = 0, fb = 0;
+  const int BIG = 0x3fffffff;
+
+  for (int item = it0; item < it1; ++item) {
+    const int i = item_start[item] + threadIdx.x;
+    const bool active = i < item_start[item + 1];
+    const float4 p = active ? x[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int oi = active ? orig[i] : 0;
     bool ok = true;
-    const int k0 = cell_coord(p.x, inv_c, ok);
-    const int k1 = cell_coord(p.y, inv_c, ok);
-    const int k2 = cell_coord(p.z, inv_c, ok);
+    const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
+    const int e_i = (env.env_of && active) ? env.env_of[i] : 0;
     int tab_n = nh, tab_off = 0, b_lo = 0, b_hi = n_bodies;
-    if (env.env_of) {
-      const int e = env.env_of[i];
-      tab_n = env.nh[e];
-      tab_off = env.boff[e];
-      b_lo = env.body_lo[e];
-      b_hi = env.body_hi[e];
+    if (env.env_of && active) {
+      tab_n = env.nh[e_i];
+      tab_off = env.boff[e_i];
+      b_lo = env.body_lo[e_i];
+      b_hi = env.body_hi[e_i];
     }
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int c0 = k0 + dx, c1 = k1 + dy, c2 = k2 + dz;
-          const int hb = tab_off + hash_cell(c0, c1, c2, tab_n);
-          const int s = start[hb], e = start[hb + 1];
-          for (int q = s; q < e; ++q) {
+    const int lo0 = block_min(active ? k0 : BIG, red), hi0 = block_max(active ? k0 : -BIG, red);
+    const int lo1 = block_min(active ? k1 : BIG, red), hi1 = block_max(active ? k1 : -BIG, red);
+    const int lo2 = block_min(active ? k2 : BIG, red), hi2 = block_max(active ? k2 : -BIG, red);
+    const int elo = block_min(active ? e_i : BIG, red), ehi = block_max(active ? e_i : -BIG, red);
+    bool tile = (elo == ehi) && (hi0 - lo0 < 256) && (hi1 - lo1 < 256) && (hi2 - lo2 < 256);
+    const int Dx = hi0 - lo0 + 3, Dy = hi1 - lo1 + 3, Dz = hi2 - lo2 + 3;
+    const int NC = tile ? Dx * Dy * Dz : 0;
+    tile = tile && NC <= max_cells;
+    const int ex = lo0 - 1, ey = lo1 - 1, ez = lo2 - 1;
+    int t_n = nh, t_off = 0;
+    if (env.env_of && tile) {
+      t_n = env.nh[elo];
+      t_off = env.boff[elo];
+    }
+    if (tile) {
+      for (int c = threadIdx.x; c < NC; c += kDetBlock) {
+        const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
+        const int hb = t_off + hash_cell(cx, cy, cz, t_n);
+        const int s0 = start[hb], s1 = start[hb + 1];
+        int cnt = 0;
+        for (int q = s0; q < s1; ++q) {
+          const float4 pj = xs[q];
+          bool okj = true;
+          cnt += (cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
+                  cell_coord(pj.z, inv_c, okj) == cz);
+        }
+        cell_off[c] = cnt;
+      }
+      __syncthreads();
+      block_exclusive_scan(cell_off, NC, red);
+      tile = cell_off[NC] <= max_stage;
+    }
+    int cnt = 0;
+    if (tile) {
+      for (int c = threadIdx.x; c < NC; c += kDetBlock) {
+        const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
+        const int hb = t_off + hash_cell(cx, cy, cz, t_n);
+        const int s0 = start[hb], s1 = start[hb + 1];
+        const int first = cell_off[c];
+        int pos = first;
+        for (int q = s0; q < s1; ++q) {
+          const float4 pj = xs[q];
+          bool okj = true;
+          if (cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
+              cell_coord(pj.z, inv_c, okj) == cz) {
+            // insertion by original index keeps each cell's members sorted
+            const int oj = os[q];
             const int j = sidx[q];
-            if (j == i) continue;
-            const float4 pj = x[j];
-            bool okj = true;
-            if (cell_coord(pj.x, inv_c, okj) != c0 || cell_coord(pj.y, inv_c, okj) != c1 ||
-                cell_coord(pj.z, inv_c, okj) != c2)
-              continue;
-            ++cand;
-            if (!pair_touch(p, pj)) continue;
-            if (j > i) ++npp;
-            if (cnt < K) {
-              int pos = cnt;
-              while (pos > 0 && L[(pos - 1) * B] > j) {
-                L[pos * B] = L[(pos - 1) * B];
-                --pos;
-              }
-              L[pos * B] = j;
+            int at = pos;
+            while (at > first && st_o[at - 1] > oj) {
+              st_x[at] = st_x[at - 1];
+              st_j[at] = st_j[at - 1];
+              st_o[at] = st_o[at - 1];
+              --at;
             }
-            ++cnt;
+            st_x[at] = pj;
+            st_j[at] = j;
+            st_o[at] = oj;
+            ++pos;
           }
         }
-    for (int b = b_lo; b < b_hi; ++b) {
-      if (body_touch(bodies[b], p)) {
-        if (cnt < K) L[cnt * B] = -1 - b;
-        ++cnt;
-        ++npb;
+      }
+      __syncthreads();
+      if (active) {
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int c = ((k2 + dz - ez) * Dy + (k1 + dy - ey)) * Dx + (k0 + dx - ex);
+              const int s0 = cell_off[c], s1 = cell_off[c + 1];
+              for (int q = s0; q < s1; ++q) {
+                const int j = st_j[q];
+                if (j == i) continue;
+                ++cand;
+                const float4 pj = st_x[q];
+                if (!pair_touch(p, pj)) continue;
+                const int oj = st_o[q];
+                npp += oi < oj;
+                put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
+                ++cnt;
+              }
+            }
+      }
+    } else {
+      fb += (threadIdx.x == 0);
+      if (active) {
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int c0 = k0 + dx, c1 = k1 + dy, c2 = k2 + dz;
+              const int hb = tab_off + hash_cell(c0, c1, c2, tab_n);
+              const int s0 = start[hb], s1 = start[hb + 1];
+              const int first = cnt;
+              for (int q = s0; q < s1; ++q) {
+                const float4 pj = xs[q];
+                bool okj = true;
+                if (cell_coord(pj.x, inv_c, okj) != c0 || cell_coord(pj.y, inv_c, okj) != c1 ||
+                    cell_coord(pj.z, inv_c, okj) != c2)
+                  continue;
+                const int j = sidx[q];
+                if (j == i) continue;
+                ++cand;
+                if (!pair_touch(p, pj)) continue;
+                const int oj = os[q];
+                npp += oi < oj;
+                // keep this cell's partners sorted by original index (in place)
+                int at = cnt;
+                if (cnt < K) {
+                  while (at > first) {
+                    const int prev = partner[ell_slot(i, at - 1, K)];
+                    if (orig[prev & (kHiFlag - 1)] < oj) break;
+                    partner[ell_slot(i, at, K)] = prev;
+                    Psi[ell_slot(i, at, K)] = Psi[ell_slot(i, at - 1, K)];
+                    --at;
+                  }
+                }
+                put_contact(i, at, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
+                ++cnt;
+              }
+            }
       }
     }
-    const int kept = cnt < K ? cnt : K;
-    for (int k = 0; k < kept; ++k) {
-      const int j = L[k * B];
-      const int sl = ell_slot(i, k, K);
-      partner[sl] = j;
-      Psi[sl] = j >= 0 ? pair_gap(p, x[j]) : body_gap(bodies[-1 - j], p);
+    if (active) {
+      for (int b = b_lo; b < b_hi; ++b) {
+        if (body_touch(bodies[b], p)) {
+          put_contact(i, cnt, K, -1 - b, body_gap(bodies[b], p), partner, Psi);
+          ++cnt;
+          ++npb;
+        }
+      }
+      ncon[i] = cnt < K ? cnt : K;
+      if (cnt > K) set_error(ctl, 4 /* GG_ERR_CAPACITY */, step);
+      mx = max(mx, cnt);
+      const float4 vi = v[i];
+      const float s_i = mass_split ? (float)cnt * vi.w : vi.w;
+      w[i] = make_float4(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
     }
-    ncon[i] = kept;
-    if (cnt > K) set_error(ctl, 4 /* GG_ERR_CAPACITY */, step);
-    const float4 vi = v[i];
-    const float s_i = mass_split ? (float)cnt * vi.w : vi.w;
-    w[i] = make_float4(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
+    __syncthreads();  // LDS is reused by the next item
   }
   // statistics: one atomic per wavefront
   unsigned long long a = wave_sum_u64((unsigned long long)npp);
   unsigned long long b2 = wave_sum_u64((unsigned long long)npb);
   unsigned long long c = wave_sum_u64((unsigned long long)cand);
-  int mx = wave_max_i32(cnt);
+  mx = wave_max_i32(mx);
   if ((threadIdx.x & 63) == 0) {
     if (a) atomicAdd(&ctl->n_pp, a);
     if (b2) atomicAdd(&ctl->n_pb, b2);
     if (a + b2) atomicAdd(&ctl->summed, a + b2);
     if (c) atomicAdd(&ctl->cand, c);
     if (mx) atomicMax(&ctl->max_cnt, mx);
+    if (fb) atomicAdd(&ctl->fallback, fb);
   }
 }
 
-// One projected-Jacobi sweep (Alg. 1).  Every contact reads the iterate of the
-// previous sweep (w_in) and its own accumulated impulse, forms the contact
-// velocity u = R_c^T (w_lo - w_hi) (or w_i - V_c for a body), takes the step
-// y = lam - mt (u + alpha psi/dt e1), clamps y_n >= 0 and scales the
-// tangential part to radius mu y_n (Eqs. (2)-(3)); the particle then sums its
-// contacts' impulses in partner order: w_i = w0_i + (1/m_i) sum sigma P_c.
-// mt = 1/(s_lo + s_hi) for a pair, 1/s_i for a body (mass splitting).
+// ------------------------------------------------------ projected Jacobi
+// One sweep (Alg. 1).  Every contact reads the iterate of the previous sweep
+// (w_in) and its own accumulated world impulse P (on the member with the lower
+// original index, or on the particle for a body contact), forms the contact
+// velocity u = w_lo - w_hi (or w_i - V for a body), and takes the step
+// y = P - mt (u + alpha psi/dt n) in the contact frame (e1 = n): the normal
+// part is clamped at 0 and the tangential part y - (y.n) n scaled to length at
+// most mu y.n (Eqs. (2)-(3)); the frame's tangent axes never need to be built
+// because the projection is isotropic in the tangent plane.  mt = 1/(s_lo +
+// s_hi) for a pair, 1/s_i for a body (mass splitting).  The particle then sums
+// its contacts' impulses in list order: w_i = w0_i + (1/m_i) sum sigma P_c.
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
 // optionally dv instead of w_out).
 __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __restrict__ x,
@@ -528,59 +868,52 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
-    const int j = partner[slot];
+    const int code = partner[slot];
+    const float psi = Psi[slot];
     float P0 = 0.f, P1 = 0.f, P2 = 0.f;
     if (!first) {
       P0 = Px[slot]; P1 = Py[slot]; P2 = Pz[slot];
     }
-    float nrm[3], psi, u[3], mt, sg;
-    if (j >= 0) {
+    float n0, n1, n2, u0, u1, u2, mt, sg;
+    if (code >= 0) {
+      const int j = code & (kHiFlag - 1);
+      const bool lo = (code & kHiFlag) == 0;
       const float4 xj = x[j];
       const float4 wj = w_in[j];
-      const bool lo = i < j;
       const float4 xl = lo ? xi : xj, xh = lo ? xj : xi;
       const float4 wl = lo ? wi : wj, wh = lo ? wj : wi;
       const float d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
       const float L = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
       if (L > 0.0f) {
         const float il = 1.0f / L;
-        nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
+        n0 = d0 * il; n1 = d1 * il; n2 = d2 * il;
       } else {
-        nrm[0] = 0.f; nrm[1] = 0.f; nrm[2] = 1.f;
+        n0 = 0.f; n1 = 0.f; n2 = 1.f;
       }
-      psi = Psi[slot];
-      u[0] = wl.x - wh.x; u[1] = wl.y - wh.y; u[2] = wl.z - wh.z;
+      u0 = wl.x - wh.x; u1 = wl.y - wh.y; u2 = wl.z - wh.z;
       mt = 1.0f / (wl.w + wh.w);
       sg = lo ? 1.0f : -1.0f;
     } else {
-      float V[3];
-      psi = Psi[slot];
-      body_geometry(bodies[-1 - j], xi, psi, nrm, V);
-      u[0] = wi.x - V[0]; u[1] = wi.y - V[1]; u[2] = wi.z - V[2];
+      float nb[3], V[3];
+      body_geometry(bodies[-1 - code], xi, psi, nb, V);
+      n0 = nb[0]; n1 = nb[1]; n2 = nb[2];
+      u0 = wi.x - V[0]; u1 = wi.y - V[1]; u2 = wi.z - V[2];
       mt = 1.0f / wi.w;
       sg = 1.0f;
     }
-    float t1[3], t2[3];
-    tangent_basis(nrm, t1, t2);
-    const float ln = nrm[0] * P0 + nrm[1] * P1 + nrm[2] * P2;
-    const float l1 = t1[0] * P0 + t1[1] * P1 + t1[2] * P2;
-    const float l2 = t2[0] * P0 + t2[1] * P1 + t2[2] * P2;
-    const float un = nrm[0] * u[0] + nrm[1] * u[1] + nrm[2] * u[2];
-    const float u1 = t1[0] * u[0] + t1[1] * u[1] + t1[2] * u[2];
-    const float u2 = t2[0] * u[0] + t2[1] * u[1] + t2[2] * u[2];
-    float yn = ln - mt * (un + alpha_dt * psi);
-    float y1 = l1 - mt * u1;
-    float y2 = l2 - mt * u2;
-    yn = fmaxf(yn, 0.0f);
-    const float s = sqrtf(y1 * y1 + y2 * y2);
-    if (s > mu * yn) {
-      const float f = mu * yn / s;
-      y1 *= f;
-      y2 *= f;
+    const float bias = alpha_dt * psi;
+    const float y0 = P0 - mt * (u0 + bias * n0);
+    const float y1 = P1 - mt * (u1 + bias * n1);
+    const float y2 = P2 - mt * (u2 + bias * n2);
+    const float yn = n0 * y0 + n1 * y1 + n2 * y2;
+    float t0 = y0 - yn * n0, t1 = y1 - yn * n1, t2 = y2 - yn * n2;
+    const float ynp = fmaxf(yn, 0.0f);
+    const float ts = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+    if (ts > mu * ynp) {
+      const float f = mu * ynp / ts;
+      t0 *= f; t1 *= f; t2 *= f;
     }
-    float Q0 = yn * nrm[0] + y1 * t1[0] + y2 * t2[0];
-    float Q1 = yn * nrm[1] + y1 * t1[1] + y2 * t2[1];
-    float Q2 = yn * nrm[2] + y1 * t1[2] + y2 * t2[2];
+    float Q0 = ynp * n0 + t0, Q1 = ynp * n1 + t1, Q2 = ynp * n2 + t2;
     if (relax != 1.0f) {
       Q0 = P0 + relax * (Q0 - P0);
       Q1 = P1 + relax * (Q1 - P1);
@@ -615,21 +948,35 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int n, float4* __restrict_
 }
 
 // ---------------------------------------------------------------- readout
-__global__ void k_pack3(int n, const float4* __restrict__ a, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float4 q = a[i];
-  out[3 * i] = q.x; out[3 * i + 1] = q.y; out[3 * i + 2] = q.z;
+// Internal (Z-ordered) arrays back to the caller's order: out[orig[k]] = a[k].
+__global__ void k_unpermute3(int n, const int32_t* __restrict__ orig, const float4* __restrict__ a,
+                             float* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float4 q = a[k];
+  const int o = orig[k];
+  out[3 * o] = q.x; out[3 * o + 1] = q.y; out[3 * o + 2] = q.z;
 }
 
-__global__ void k_pack_w(int n, const float4* __restrict__ a, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i].w;
+__global__ void k_unpermute_w(int n, const int32_t* __restrict__ orig, const float4* __restrict__ a,
+                              float* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[orig[k]] = a[k].w;
 }
 
-__global__ void k_widen(int n, const int32_t* __restrict__ a, int64_t* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i];
+__global__ void k_unpermute_i64(int n, const int32_t* __restrict__ orig, const int32_t* __restrict__ a,
+                                int64_t* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[orig[k]] = a[k];
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ void k_iota(int n, int32_t* __restrict__ a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[k] = k;
 }
 
 }  // namespace ggk

@@ -48,7 +48,9 @@ class Params(C.Structure):
                 ("n_iters", C.c_int32), ("cell_size", C.c_float), ("hash_size", C.c_int64),
                 ("relax", C.c_float), ("mass_split", C.c_int32), ("checkpoint_every", C.c_int32),
                 ("max_contacts_per_particle", C.c_int32), ("precision", C.c_int32),
-                ("density", C.c_float), ("flags", C.c_uint32), ("device", C.c_int32),
+                ("density", C.c_float), ("flags", C.c_uint32), ("reorder_every", C.c_int32),
+                ("tile_max_cells", C.c_int32), ("tile_max_stage", C.c_int32),
+                ("tile_node_shift", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
@@ -58,7 +60,8 @@ class Stats(C.Structure):
                 ("capacity", C.c_int64), ("last_status", C.c_int64), ("n", C.c_int64),
                 ("n_buckets", C.c_int64), ("ms_detect", C.c_double), ("ms_pja", C.c_double),
                 ("ms_integrate", C.c_double), ("pja_launches", C.c_int64),
-                ("contacts_summed", C.c_int64)]
+                ("contacts_summed", C.c_int64), ("detect_fallback", C.c_int64),
+                ("detect_items", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,6 +77,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(there is no CPU fallback)")
+        # torch bundles its own HIP runtime with the same soname; load it first so
+        # that a process using both shares one runtime (two runtimes in one
+        # process cannot both open the device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.gg_create.restype = i32
@@ -152,7 +162,8 @@ class Sim:
     def __init__(self, x, v, radius, bodies=(), *, dt=1e-3, alpha=0.2, mu=0.5, n_iters=20,
                  gravity=(0.0, 0.0, -9.81), cell_size=0.0, hash_size=0, relax=1.0, mass_split=True,
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
-                 profile=False, diagnostics=False):
+                 profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
+                 tile_max_stage=0, tile_node_shift=0):
         L = lib()
         P = Params()
         P.dt, P.alpha, P.mu = dt, alpha, mu
@@ -166,6 +177,10 @@ class Sim:
         P.max_contacts_per_particle = int(max_contacts)
         P.density = density
         P.flags = (GG_FLAG_PROFILE if profile else 0) | (GG_FLAG_DIAGNOSTICS if diagnostics else 0)
+        P.reorder_every = int(reorder_every)
+        P.tile_max_cells = int(tile_max_cells)
+        P.tile_max_stage = int(tile_max_stage)
+        P.tile_node_shift = int(tile_node_shift)
         P.device = device
         P.stream = stream
         n = int(x.shape[0])

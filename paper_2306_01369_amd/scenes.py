@@ -299,6 +299,18 @@ def random_spheres(n, box, r, rng, r_jitter=0.0):
     return _f32(x), _f32(rad)
 
 
+def loose_lattice(n, r, origin, rng, spacing_factor=2.02, jitter_frac=0.06, shuffle=True):
+    """n spheres on the first n sites of a cubic lattice (spacing
+    spacing_factor * r, jitter U(+-jitter_frac * r) per coordinate), in random
+    index order when shuffle is set: a physical (not over-packed) random input
+    whose index order is not spatial."""
+    side = int(math.ceil(n ** (1.0 / 3.0))) if n else 0
+    pos = jittered_lattice((side, side, side), spacing_factor * r, origin, jitter_frac * r, rng)[:n]
+    if shuffle and n:
+        pos = pos[rng.permutation(n)]
+    return _f32(pos), np.full(n, r, np.float32)
+
+
 def scaled(scene: Scene, n: int, seed=0):
     """A smaller bed of the same structure as ``scene`` (same radius and
     packing) for tests that need the full-size recipe at oracle-friendly size."""

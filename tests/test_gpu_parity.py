@@ -210,7 +210,7 @@ def test_determinism_bitwise():
 def test_pair_impulse_copies_are_equal_and_opposite():
     # momentum: g = 0, no bodies, the total momentum is conserved to binary32 rounding
     rng = np.random.default_rng(9)
-    x, r = scenes.random_spheres(4000, ((0, 0.2), (0, 0.2), (0, 0.2)), 0.005, rng, r_jitter=0.2)
+    x, r = scenes.loose_lattice(4000, 0.005, (0, 0, 0), rng, spacing_factor=2.0, jitter_frac=0.1)
     v = (rng.normal(size=(4000, 3))).astype(np.float32)
     say("momentum")
     sim = gg.Sim(x, v, r, gravity=(0, 0, 0), mu=0.4)
@@ -230,10 +230,10 @@ def test_pair_impulse_copies_are_equal_and_opposite():
 def test_small_and_ragged_sizes(n):
     say("ragged", n)
     rng = np.random.default_rng(n)
-    x, r = scenes.random_spheres(n, ((0, 0.05), (0, 0.05), (0.005, 0.05)), 0.004, rng) if n else \
-        (np.zeros((0, 3), np.float32), np.zeros(0, np.float32))
-    v = np.zeros((n, 3), np.float32)
-    bodies = scenes.walled_box(0, 0.05, 0, 0.05)
+    x, r = scenes.loose_lattice(n, 0.004, (0.004, 0.004, 0.0039), rng)
+    v = (rng.normal(size=(n, 3)) * 0.05).astype(np.float32)
+    side = 0.004 * 2.02 * math.ceil(n ** (1 / 3)) if n else 0.05
+    bodies = scenes.walled_box(0, side, 0, side)
     if n == 0:
         sim = gg.Sim(x, v, r, bodies)
         sim.step(3)
@@ -289,7 +289,7 @@ def test_multi_env_contacts_and_buckets():
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     xs = []
     for e, c in enumerate(counts):
-        xe, _ = scenes.random_spheres(c, ((0, 0.04), (0, 0.04), (0.004, 0.04)), 0.004, rng)
+        xe, _ = scenes.loose_lattice(c, 0.004, (0.004, 0.004, 0.0039), rng, spacing_factor=2.0, jitter_frac=0.1)
         xs.append(xe)
     x = np.concatenate(xs).astype(np.float32)      # all envs overlap in space
     r = np.full(len(x), 0.004, np.float32)
@@ -297,7 +297,7 @@ def test_multi_env_contacts_and_buckets():
     env = np.repeat(np.arange(len(counts)), counts).astype(np.int32)
     bodies = []
     for e in range(len(counts)):
-        bodies += scenes.walled_box(0, 0.04, 0, 0.04, env=e)
+        bodies += scenes.walled_box(0, 0.08, 0, 0.08, env=e)
     say("multi-env", counts)
     sim = gg.Sim(x, v, r, bodies, env_offsets=off, diagnostics=True)
     sim.step(1)
@@ -347,3 +347,38 @@ def test_twists_per_step_move_the_tool():
         orc.set_twists(tw[k])
         orc.step()
     assert np.abs(sim.read("pos") - orc.x).max() < 1e-4
+
+
+# ------------------------------------------------- layout independence
+
+def _run_bits(scene, steps, **kw):
+    sim = gg.scene_sim(scene, **kw)
+    sim.step(steps)
+    out = (sim.read("pos").tobytes(), sim.read("vel").tobytes(), sim.read("contacts").tobytes(),
+           sim.read("impulses").tobytes(), sim.read("cell_index").tobytes())
+    st = sim.stats()
+    sim.close()
+    return out, st
+
+
+@pytest.mark.parametrize("reorder", [1, 3, -1])
+def test_results_independent_of_internal_order(reorder):
+    # the Z-order re-sort changes only memory layout: every output is bitwise
+    # the same for any re-sort interval, including never
+    s = scenes.drop_scene()
+    say("reorder", reorder)
+    ref, _ = _run_bits(s, 50, reorder_every=8)
+    got, _ = _run_bits(s, 50, reorder_every=reorder)
+    assert got == ref
+
+
+def test_tile_and_per_particle_detection_agree_bitwise():
+    s = scenes.column_scene(n=5000, r=0.004)
+    rng = np.random.default_rng(1)
+    s.x = s.x[rng.permutation(s.n)]            # caller order not spatial
+    say("tile vs fallback")
+    tiled, st_t = _run_bits(s, 12)
+    per_particle, st_f = _run_bits(s, 12, tile_max_cells=27)
+    assert st_t["detect_fallback"] < st_f["detect_fallback"]
+    assert st_f["detect_fallback"] == st_f["detect_items"] > 0
+    assert tiled == per_particle
