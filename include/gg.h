@@ -77,6 +77,8 @@ typedef struct {
 /* Flags for gg_params.flags */
 #define GG_FLAG_PROFILE 1u     /* time detection and projected-Jacobi phases with HIP events */
 #define GG_FLAG_DIAGNOSTICS 2u /* keep the last step's velocity change (GG_FIELD_DV) */
+#define GG_FLAG_TAPE 4u        /* differentiable: keep checkpoints of every gg_step call for
+                                  gg_step_backward (one environment only) */
 
 /* Simulation parameters.  Zero selects the stated default. */
 typedef struct {

@@ -67,7 +67,7 @@ def lib():
         L.ggo_step.argtypes = [P(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, P(Body), C.c_int32, C.c_int64,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_int32, C.c_void_p, C.c_void_p]
+                               C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]
         L.ggo_num_threads.restype = C.c_int32
         L.ggo_sizeof_body.restype = C.c_int32
         L.ggo_sizeof_params.restype = C.c_int32
@@ -236,17 +236,28 @@ class Oracle:
         self.cell_size = cell_size
         self.stats = np.zeros(4, np.int64)
 
-    def set_twists(self, tw):
-        """tw: (n_bodies, 6) (nu, omega) for the next step."""
+    def set_twists(self, tw, binary32=True):
+        """tw: (n_bodies, 6) (nu, omega) for the next step, rounded to binary32
+        (the values the GPU path receives) unless binary32 is False."""
+        rnd = (lambda a: float(np.float32(a))) if binary32 else float
         for b in range(self.nb):
             for q in range(3):
-                self.B[b].nu[q] = float(np.float32(tw[b][q]))
-                self.B[b].omega[q] = float(np.float32(tw[b][3 + q]))
+                self.B[b].nu[q] = rnd(tw[b][q])
+                self.B[b].omega[q] = rnd(tw[b][3 + q])
 
-    def step(self, detail=False, n_hist=0, advance_bodies=True):
+    def step(self, detail=False, n_hist=0, advance_bodies=True, fixed=None):
+        """One step.  fixed = (pairs (C,2) int32, n_pp) uses that contact list
+        instead of detecting (the contact set held fixed)."""
         n = self.n
         cap = 0
-        if detail:
+        fx, fpp, fpb = None, 0, 0
+        if fixed is not None:
+            fx = np.ascontiguousarray(fixed[0], np.int32)
+            fpp = int(fixed[1])
+            fpb = len(fx) - fpp
+        if detail and fixed is not None:
+            cap = len(fx)
+        elif detail:
             # count first (dry detection) to size the outputs
             xf = self.x.astype(np.float32)
             pp, _ = pp_hashgrid(xf, self.r, self.P.inv_c, self.P.n_h, self.env)
@@ -261,7 +272,8 @@ class Oracle:
         hist = np.zeros((max(n_hist, 1), capm, 3)) if (detail and n_hist) else None
         Cn = lib().ggo_step(C.byref(self.P), n, _ptr(self.x), _ptr(self.v), _ptr(self.r), _ptr(self.env),
                             self.nb, self.B, 1 if advance_bodies else 0, cap, _ptr(pairs), _ptr(imp),
-                            _ptr(psi), _ptr(nrm), _ptr(dv), int(n_hist), _ptr(hist), _ptr(self.stats))
+                            _ptr(psi), _ptr(nrm), _ptr(dv), int(n_hist), _ptr(hist), _ptr(self.stats),
+                            _ptr(fx), fpp, fpb)
         if not detail:
             return None
         assert Cn == cap

@@ -388,14 +388,21 @@ void ggo_advance_bodies(int32_t nb, Body* bodies, double dt) {
 int64_t ggo_step(const Params* P, int64_t n, double* x, double* v, const float* radius,
                  const int32_t* env, int32_t nb, Body* bodies, int32_t advance_bodies, int64_t cap,
                  int32_t* pairs, double* impulses, double* psi_out, double* normals, double* dv, int32_t n_hist,
-                 double* lam_hist, int64_t* stats) {
-  // ---- detection on binary32 positions
+                 double* lam_hist, int64_t* stats, const int32_t* fixed_pairs, int64_t fixed_pp,
+                 int64_t fixed_pb) {
+  // ---- detection on binary32 positions, or a given contact list (to
+  // differentiate with the contact set held fixed)
   std::vector<float> xf(3 * n);
   for (int64_t q = 0; q < 3 * n; ++q) xf[q] = (float)x[q];
   std::vector<std::pair<int32_t, int32_t>> pp, pb;
   int64_t cand = 0;
-  pp_contacts_grid(n, xf.data(), radius, env, P->inv_c, P->n_h, pp, &cand);
-  pb_contacts(n, xf.data(), radius, env, nb, bodies, pb);
+  if (fixed_pairs) {
+    for (int64_t c = 0; c < fixed_pp; ++c) pp.emplace_back(fixed_pairs[2 * c], fixed_pairs[2 * c + 1]);
+    for (int64_t c = fixed_pp; c < fixed_pp + fixed_pb; ++c) pb.emplace_back(fixed_pairs[2 * c], fixed_pairs[2 * c + 1]);
+  } else {
+    pp_contacts_grid(n, xf.data(), radius, env, P->inv_c, P->n_h, pp, &cand);
+    pb_contacts(n, xf.data(), radius, env, nb, bodies, pb);
+  }
   const int64_t C = (int64_t)(pp.size() + pb.size());
   if (stats) {
     stats[0] = cand;

@@ -2,6 +2,7 @@
 // device buffers, kinematic body poses, and the per-step launch sequence.
 #include "gg.h"
 #include "kernels.hip.h"
+#include "adjoint.hip.h"
 
 #include <hip/hip_runtime.h>
 
@@ -151,6 +152,13 @@ struct gg_sim {
   gg_stats stats{};
   bool contacts_valid = false;
   std::vector<HostBody> pose_hist;  // scratch for gg_step
+  // record of the last differentiable call (GG_FLAG_TAPE)
+  bool tape_ok = false;
+  int tape_steps = 0;
+  std::vector<HostBody> tape_poses;   // (steps + 1) x bodies, double precision
+  std::vector<float> tape_twists;     // steps x bodies x 6
+  float4* ck = nullptr;               // checkpoints: per segment x then v
+  size_t ck_cap = 0;
 };
 
 namespace {
@@ -182,7 +190,7 @@ gg_status check_params(const gg_params* p) {
     return fail(GG_ERR_INVALID, "max_contacts_per_particle must be in [0, 256]");
   if (p->precision != 0) return fail(GG_ERR_UNSUPPORTED, "only precision 0 (binary32) is built");
   if (!(p->density >= 0.0f) || !std::isfinite(p->density)) return fail(GG_ERR_INVALID, "density must be finite and >= 0");
-  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS)) return fail(GG_ERR_INVALID, "unknown flag bits");
+  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS | GG_FLAG_TAPE)) return fail(GG_ERR_INVALID, "unknown flag bits");
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
@@ -240,7 +248,7 @@ ggk::EnvTables env_tables(const gg_sim* s) {
 void free_all(gg_sim* s) {
   void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->x2, s->v2, s->orig, s->orig2, s->mk[0], s->mk[1],
                   s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
-                  s->it_g, s->it_h, s->item_start, s->it_bsum, s->h, s->rank, s->counts, s->bstart, s->bsum,
+                  s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp};
   for (void* b : bufs)
@@ -280,6 +288,117 @@ gg_status upload_env_bodies(gg_sim* s) {
     HIPCHK(s, hipMemcpy(s->d_body_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
   }
   return GG_OK;
+}
+
+// Buffers one step reads and writes.  w[l] (l = 0..I-1) receives the Jacobi
+// iterate after sweep l (w[0] from detection); P*[l] (l = 1..I) the impulses of
+// sweep l.  The plain step alternates two iterate buffers and updates one
+// impulse array in place; the recorded step (for the adjoint) keeps all.
+struct StepIO {
+  float4* x;
+  float4* v;
+  int32_t* ncon;
+  int32_t* partner;
+  float* Psi;
+  std::vector<float4*> w;
+  std::vector<float*> Px, Py, Pz;
+  float4* dv;
+};
+
+StepIO plain_io(gg_sim* s) {
+  StepIO io;
+  io.x = s->x;
+  io.v = s->v;
+  io.ncon = s->ncon;
+  io.partner = s->partner;
+  io.Psi = s->Psi;
+  const int I = s->p.n_iters;
+  io.w.resize(I + 1);
+  io.Px.assign(I + 1, s->Px);
+  io.Py.assign(I + 1, s->Py);
+  io.Pz.assign(I + 1, s->Pz);
+  for (int l = 0; l <= I; ++l) io.w[l] = (l & 1) ? s->wb : s->wa;
+  io.dv = s->dv;
+  return io;
+}
+
+// Z-order re-sort of the internal particle order and rebuild of the detection
+// work items (memory locality only; results do not depend on it).
+void launch_reorder(gg_sim* s) {
+  const int n = (int)s->n;
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  const int rs_m = 256 * s->rs_nb;
+  const int rs_nbs = (rs_m + ggk::kScanTile - 1) / ggk::kScanTile;
+  hipStream_t S = s->stream;
+  ggk::k_morton_keys<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, s->env_of, s->mk[0]);
+  for (int pass = 0; pass < s->rs_passes; ++pass) {
+    const int src = pass & 1, dst = src ^ 1;
+    ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
+    ggk::k_scan_a<<<rs_nbs, ggk::kBlock, 0, S>>>(rs_m, s->rs_hist, s->rs_hist, s->rs_bsum, 0);
+    ggk::k_scan_b<<<1, 1024, 0, S>>>(rs_nbs, s->rs_bsum, rs_m, s->rs_hist);
+    ggk::k_scan_c<<<(rs_m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(rs_m, s->rs_bsum, s->rs_hist);
+    ggk::k_rs_scatter<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass == 0 ? nullptr : s->mv[src], s->mk[dst],
+                                                         s->mv[dst], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
+  }
+  ggk::k_permute<<<grid, ggk::kBlock, 0, S>>>(n, s->mv[s->rs_passes & 1], s->x, s->v, s->orig, s->x2, s->v2,
+                                              s->orig2);
+  std::swap(s->x, s->x2);
+  std::swap(s->v, s->v2);
+  std::swap(s->orig, s->orig2);
+  const unsigned long long* keys = s->mk[s->rs_passes & 1];
+  const int it_nbs = (n + ggk::kScanTile - 1) / ggk::kScanTile;
+  ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift, s->it_f);
+  ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_bsum, 0);
+  ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
+  ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
+  ggk::k_node_first<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first);
+  ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, ggk::kDetBlock, s->it_g);
+  ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->it_bsum, 0);
+  ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_h);
+  ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
+  ggk::k_item_starts<<<grid, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->item_start);
+  ggk::k_copy_i32<<<1, 64, 0, S>>>(s->it_h + n, &s->ctl->items);
+}
+
+// Bucket table and contact detection of one step.
+void launch_detect(gg_sim* s, const StepIO& io, int st, const ggk::DevBody* bod) {
+  const int n = (int)s->n;
+  const int nb = (int)s->bodies.size();
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  const int m = (int)s->n_buckets;
+  const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
+  const int dgrid = std::max(1, std::min((n + 31) / 32, 2048));
+  const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
+  const size_t dlds = ((((size_t)2 * max_cells + 1) * 4 + 15) & ~(size_t)15) + (size_t)max_stage * (16 + 4 + 4);
+  const ggk::EnvTables et = env_tables(s);
+  const int nh1 = s->env_nh[0];
+  hipStream_t S = s->stream;
+  ggk::k_key<<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
+  ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
+  ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
+  ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
+  ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, s->xs, s->os);
+  ggk::k_detect<<<dgrid, ggk::kDetBlock, dlds, S>>>(n, s->K, io.x, io.v, s->orig, s->inv_c, nh1, et, s->bstart,
+                                                     s->sidx, s->xs, s->os, s->item_start, &s->ctl->items, bod, nb,
+                                                     s->p.gravity[0], s->p.gravity[1], s->p.gravity[2], s->p.dt,
+                                                     s->p.mass_split, max_cells, max_stage, io.ncon, io.partner,
+                                                     io.Psi, io.w[0], s->ctl, st);
+}
+
+// The projected-Jacobi sweeps of one step (the last one writes the velocity).
+void launch_sweeps(gg_sim* s, const StepIO& io, const ggk::DevBody* bod) {
+  const int n = (int)s->n;
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  const int I = s->p.n_iters;
+  const float alpha_dt = s->p.alpha / s->p.dt;
+  for (int it = 0; it < I; ++it) {
+    const int l = it + 1;
+    const int mode = (it == 0 ? 1 : 0) | (it == I - 1 ? 2 : 0);
+    ggk::k_pja<<<grid, ggk::kBlock, 0, s->stream>>>(
+        n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
+        io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, s->p.gravity[0], s->p.gravity[1], s->p.gravity[2],
+        s->p.dt, alpha_dt, s->p.mu, s->p.relax, mode, io.dv, s->ctl);
+  }
 }
 
 }  // namespace
@@ -607,76 +726,39 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
   const int n = (int)s->n;
   const int K = s->K;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
-  const int m = (int)s->n_buckets;
-  const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
-  const int dgrid = std::max(1, std::min((n + 31) / 32, 2048));
-  const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
-  const size_t dlds = ((((size_t)max_cells + 1) * 4 + 15) & ~(size_t)15) + (size_t)max_stage * (16 + 4 + 4);
-  const ggk::EnvTables et = env_tables(s);
-  const int nh1 = s->env_nh[0];
-  const float dt = s->p.dt, gx = s->p.gravity[0], gy = s->p.gravity[1], gz = s->p.gravity[2];
-  const float alpha_dt = s->p.alpha / s->p.dt;
-  const int rs_m = 256 * s->rs_nb;
-  const int rs_nbs = (rs_m + ggk::kScanTile - 1) / ggk::kScanTile;
+  const float dt = s->p.dt;
   hipStream_t S = s->stream;
 
+  const bool taped = (s->p.flags & GG_FLAG_TAPE) != 0;
+  s->tape_ok = false;
+  if (taped && n > 0) {
+    const int C = s->p.checkpoint_every;
+    const int nseg = (n_steps + C - 1) / C;
+    const size_t need_ck = (size_t)nseg * 2 * (size_t)n;
+    if (need_ck > s->ck_cap) {
+      if (s->ck) HIPCHK(s, hipFree(s->ck));
+      s->ck = nullptr;
+      s->ck_cap = 0;
+      if (dev_alloc(&s->ck, need_ck) != hipSuccess) return fail(GG_ERR_OOM, "checkpoint allocation failed");
+      s->ck_cap = need_ck;
+    }
+  }
   ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
   for (int st = 0; st < n_steps && n > 0; ++st) {
     const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st], S));
     const int64_t g = s->steps_global + st;
-    if (s->p.reorder_every > 0 && g % s->p.reorder_every == 0) {
-      // Z-order re-sort of the internal particle order (locality only)
-      ggk::k_morton_keys<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, s->env_of, s->mk[0]);
-      for (int pass = 0; pass < s->rs_passes; ++pass) {
-        const int src = pass & 1, dst = src ^ 1;
-        ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
-        ggk::k_scan_a<<<rs_nbs, ggk::kBlock, 0, S>>>(rs_m, s->rs_hist, s->rs_hist, s->rs_bsum, 0);
-        ggk::k_scan_b<<<1, 1024, 0, S>>>(rs_nbs, s->rs_bsum, rs_m, s->rs_hist);
-        ggk::k_scan_c<<<(rs_m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(rs_m, s->rs_bsum, s->rs_hist);
-        ggk::k_rs_scatter<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass == 0 ? nullptr : s->mv[src],
-                                                             s->mk[dst], s->mv[dst], pass * ggk::kRsBits, s->rs_nb,
-                                                             s->rs_hist);
-      }
-      ggk::k_permute<<<grid, ggk::kBlock, 0, S>>>(n, s->mv[s->rs_passes & 1], s->x, s->v, s->orig, s->x2, s->v2,
-                                                  s->orig2);
-      std::swap(s->x, s->x2);
-      std::swap(s->v, s->v2);
-      std::swap(s->orig, s->orig2);
-      // detection work items: runs of <= kDetBlock particles within one Z-order node
-      const unsigned long long* keys = s->mk[s->rs_passes & 1];
-      const int it_nbs = (n + ggk::kScanTile - 1) / ggk::kScanTile;
-      ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift, s->it_f);
-      ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_bsum, 0);
-      ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
-      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
-      ggk::k_node_first<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first);
-      ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, ggk::kDetBlock, s->it_g);
-      ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->it_bsum, 0);
-      ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_h);
-      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
-      ggk::k_item_starts<<<grid, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->item_start);
-      ggk::k_copy_i32<<<1, 64, 0, S>>>(s->it_h + n, &s->ctl->items);
+    // a differentiable call keeps one internal order throughout (re-sorted only at its start)
+    if (s->p.reorder_every > 0 && (taped ? st == 0 : g % s->p.reorder_every == 0)) launch_reorder(s);
+    if (taped && st % s->p.checkpoint_every == 0) {
+      float4* ckx = s->ck + (size_t)(st / s->p.checkpoint_every) * 2 * n;
+      HIPCHK(s, hipMemcpyAsync(ckx, s->x, (size_t)n * sizeof(float4), hipMemcpyDeviceToDevice, S));
+      HIPCHK(s, hipMemcpyAsync(ckx + n, s->v, (size_t)n * sizeof(float4), hipMemcpyDeviceToDevice, S));
     }
-    ggk::k_key<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
-    ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
-    ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
-    ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
-    ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, s->x, s->orig, s->sidx, s->xs, s->os);
-    ggk::k_detect<<<dgrid, ggk::kDetBlock, dlds, S>>>(n, K, s->x, s->v, s->orig, s->inv_c, nh1, et, s->bstart,
-                                                       s->sidx, s->xs, s->os, s->item_start, &s->ctl->items, bod, nb,
-                                                       gx, gy, gz, dt, s->p.mass_split, max_cells, max_stage,
-                                                       s->ncon, s->partner, s->Psi, s->wa, s->ctl, st);
+    const StepIO io = plain_io(s);
+    launch_detect(s, io, st, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
-    float4* win = s->wa;
-    float4* wout = s->wb;
-    for (int it = 0; it < s->p.n_iters; ++it) {
-      int mode = (it == 0 ? 1 : 0) | (it == s->p.n_iters - 1 ? 2 : 0);
-      ggk::k_pja<<<grid, ggk::kBlock, 0, S>>>(n, K, s->x, s->v, win, wout, s->ncon, s->partner, s->Psi, s->Px, s->Py,
-                                              s->Pz, bod, gx, gy, gz, dt, alpha_dt, s->p.mu, s->p.relax, mode,
-                                              s->dv, s->ctl);
-      std::swap(win, wout);
-    }
+    launch_sweeps(s, io, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
     ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->v, dt, s->ctl);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
@@ -736,13 +818,264 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
     return fail((gg_status)c.err, "non-finite or out-of-range position at step " + std::to_string(c.fail_step));
   }
   s->contacts_valid = n > 0;
+  if (taped && n > 0) {
+    s->tape_ok = true;
+    s->tape_steps = n_steps;
+    s->tape_twists.assign((size_t)n_steps * nb * 6, 0.0f);
+    for (int st = 0; st < n_steps; ++st)
+      for (int b = 0; b < nb; ++b) {
+        const HostBody& H = s->pose_hist[(size_t)st * nb + b];
+        for (int q = 0; q < 3; ++q) {
+          s->tape_twists[((size_t)st * nb + b) * 6 + q] = (float)H.nu[q];
+          s->tape_twists[((size_t)st * nb + b) * 6 + 3 + q] = (float)H.om[q];
+        }
+      }
+    s->tape_poses = s->pose_hist;
+  }
   return GG_OK;
 }
 
-gg_status gg_step_backward(gg_sim* s, const float*, const float*, float*, float*, float*, gg_mem) {
+// Left Jacobian of SO(3): Exp(phi + d) ~= Exp([J_l(phi) d]x) Exp(phi).
+static void so3_left_jacobian(const double phi[3], double J[9]) {
+  const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  const double th = std::sqrt(th2);
+  double a, b;
+  if (th < 1e-6) {
+    a = 0.5 - th2 / 24.0;
+    b = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    a = (1.0 - std::cos(th)) / th2;
+    b = (th - std::sin(th)) / (th2 * th);
+  }
+  const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double kk = 0;
+      for (int m = 0; m < 3; ++m) kk += K[3 * r + m] * K[3 * m + c];
+      J[3 * r + c] = (r == c ? 1.0 : 0.0) + a * K[3 * r + c] + b * kk;
+    }
+}
+
+static void so3_exp(const double phi[3], double E[9]) {
+  HostBody tmp{};
+  for (int q = 0; q < 9; ++q) tmp.R[q] = (q % 4 == 0) ? 1.0 : 0.0;
+  for (int q = 0; q < 3; ++q) tmp.om[q] = phi[q];
+  advance_pose(tmp, 1.0);
+  std::memcpy(E, tmp.R, sizeof(tmp.R));
+}
+
+gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, float* dL_dx0, float* dL_dv0,
+                           float* dL_dtwists, gg_mem where) {
   g_detail.clear();
   if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
-  return fail(GG_ERR_UNSUPPORTED, "the adjoint pass is not built in this version");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (!(s->p.flags & GG_FLAG_TAPE)) return fail(GG_ERR_NO_TAPE, "the simulation was created without GG_FLAG_TAPE");
+  if (!s->tape_ok || s->tape_steps <= 0) return fail(GG_ERR_NO_TAPE, "no successful differentiable gg_step to reverse");
+  if (s->n_envs != 1) return fail(GG_ERR_UNSUPPORTED, "the adjoint is built for one environment");
+  const int n = (int)s->n;
+  const int nb = (int)s->bodies.size();
+  const int N = s->tape_steps;
+  const int I = s->p.n_iters;
+  const int C = s->p.checkpoint_every;
+  const int K = s->K;
+  const size_t slots = (size_t)s->n_pad * K;
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  hipStream_t S = s->stream;
+  DeviceGuard g(s->dev);
+  if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+
+  // ---- device buffers for one segment of recorded steps and the adjoint
+  std::vector<void*> owned;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) return nullptr;
+    owned.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+  };
+  const size_t n4 = (size_t)n * sizeof(float4);
+  float4* tx = (float4*)alloc(n4 * C);
+  float4* tv = (float4*)alloc(n4 * C);
+  int32_t* tncon = (int32_t*)alloc((size_t)n * 4 * C);
+  int32_t* tpart = (int32_t*)alloc(slots * 4 * C);
+  float* tpsi = (float*)alloc(slots * 4 * C);
+  float4* tw = (float4*)alloc(n4 * (size_t)I * C);
+  float* tP = (float*)alloc(slots * 4 * 3 * (size_t)std::max(I - 1, 1) * C);
+  float* Plast = (float*)alloc(slots * 4 * 3);
+  float4* xw = (float4*)alloc(n4);
+  float4* vw = (float4*)alloc(n4);
+  float4* xb = (float4*)alloc(n4);
+  float4* vb = (float4*)alloc(n4);
+  float4* xbn = (float4*)alloc(n4);
+  float4* vbn = (float4*)alloc(n4);
+  float4* wba = (float4*)alloc(n4);
+  float4* wbb = (float4*)alloc(n4);
+  float4* w0b = (float4*)alloc(n4);
+  float* adj = (float*)alloc(slots * 4 * 10);
+  float* part = (float*)alloc((size_t)grid * std::max(nb, 1) * 18 * 4);
+  float* bgrad = (float*)alloc((size_t)std::max(nb, 1) * 18 * 4 * N);
+  float* io3 = (float*)alloc((size_t)n * 12 * 2);
+  for (void* p : owned)
+    if (!p) {
+      release();
+      return fail(GG_ERR_OOM, "adjoint workspace allocation failed");
+    }
+  if (owned.size() != 21) {
+    release();
+    return fail(GG_ERR_OOM, "adjoint workspace allocation failed");
+  }
+  ggk::AdjSlots A;
+  A.cx = adj; A.cy = adj + slots; A.cz = adj + 2 * slots;
+  A.nx = adj + 3 * slots; A.ny = adj + 4 * slots; A.nz = adj + 5 * slots;
+  A.ps = adj + 6 * slots;
+  A.vx = adj + 7 * slots; A.vy = adj + 8 * slots; A.vz = adj + 9 * slots;
+
+  // ---- final-state adjoints into the internal order
+  const hipMemcpyKind kin = where == GG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const hipMemcpyKind kout = where == GG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+#define BWCHK(expr)                         \
+  do {                                      \
+    hipError_t _e = (expr);                 \
+    if (_e != hipSuccess) {                 \
+      release();                            \
+      return hip_fail(s, _e, #expr);        \
+    }                                       \
+  } while (0)
+  if (dL_dx) BWCHK(hipMemcpyAsync(io3, dL_dx, (size_t)n * 12, kin, S));
+  if (dL_dv) BWCHK(hipMemcpyAsync(io3 + 3 * (size_t)n, dL_dv, (size_t)n * 12, kin, S));
+  ggk::k_gather3<<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dx ? io3 : nullptr, xbn);
+  ggk::k_gather3<<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dv ? io3 + 3 * (size_t)n : nullptr, vbn);
+
+  const float dt = s->p.dt;
+  const float alpha_dt = s->p.alpha / s->p.dt;
+  const int nseg = (N + C - 1) / C;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * C, s1 = std::min(N, s0 + C);
+    // recompute the segment from its checkpoint, recording every step
+    BWCHK(hipMemcpyAsync(xw, s->ck + (size_t)seg * 2 * n, n4, hipMemcpyDeviceToDevice, S));
+    BWCHK(hipMemcpyAsync(vw, s->ck + (size_t)seg * 2 * n + n, n4, hipMemcpyDeviceToDevice, S));
+    for (int st = s0; st < s1; ++st) {
+      const int r = st - s0;
+      const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
+      BWCHK(hipMemcpyAsync(tx + (size_t)r * n, xw, n4, hipMemcpyDeviceToDevice, S));
+      BWCHK(hipMemcpyAsync(tv + (size_t)r * n, vw, n4, hipMemcpyDeviceToDevice, S));
+      StepIO io;
+      io.x = xw;
+      io.v = vw;
+      io.ncon = tncon + (size_t)r * n;
+      io.partner = tpart + slots * r;
+      io.Psi = tpsi + slots * r;
+      io.w.resize(I + 1);
+      io.Px.resize(I + 1); io.Py.resize(I + 1); io.Pz.resize(I + 1);
+      for (int l = 0; l < I; ++l) io.w[l] = tw + ((size_t)r * I + l) * n;
+      io.w[I] = wba;  // unused: the last sweep writes the velocity
+      for (int l = 1; l <= I; ++l) {
+        float* base = (l < I) ? tP + (((size_t)r * std::max(I - 1, 1) + (l - 1)) * 3) * slots : Plast;
+        io.Px[l] = base; io.Py[l] = base + slots; io.Pz[l] = base + 2 * slots;
+      }
+      io.Px[0] = io.Px[1]; io.Py[0] = io.Py[1]; io.Pz[0] = io.Pz[1];
+      io.dv = nullptr;
+      launch_detect(s, io, st, bod);
+      launch_sweeps(s, io, bod);
+      ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, s->ctl);
+    }
+    // reverse the segment
+    for (int st = s1 - 1; st >= s0; --st) {
+      const int r = st - s0;
+      const float4* xk = tx + (size_t)r * n;
+      const float4* vk = tv + (size_t)r * n;
+      const int32_t* nc = tncon + (size_t)r * n;
+      const int32_t* pt = tpart + slots * r;
+      const float* ps = tpsi + slots * r;
+      const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
+      ggk::k_adj_begin<<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
+      ggk::k_zero_f<<<(int)((slots * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(slots * 10, adj);
+      float4* win = wba;
+      float4* wout = wbb;
+      for (int l = I; l >= 1; --l) {
+        const float4* wprev = tw + ((size_t)r * I + (l - 1)) * n;
+        const float* Pp = (l >= 2) ? tP + (((size_t)r * std::max(I - 1, 1) + (l - 2)) * 3) * slots : nullptr;
+        ggk::k_pja_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
+                                                    Pp ? Pp + slots : nullptr, Pp ? Pp + 2 * slots : nullptr, A, bod,
+                                                    alpha_dt, s->p.mu, s->p.relax, l == 1 ? 1 : 0);
+        std::swap(win, wout);
+      }
+      ggk::k_adj_vbar<<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);
+      ggk::k_geom_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, nc, pt, ps, A, bod, nb, xb, part);
+      if (nb > 0)
+        ggk::k_body_reduce<<<nb * 18, ggk::kBlock, 0, S>>>(grid, nb, part, bgrad + (size_t)st * nb * 18);
+      std::swap(xb, xbn);
+      std::swap(vb, vbn);
+    }
+  }
+  BWCHK(hipGetLastError());
+  // ---- outputs
+  ggk::k_unpermute3<<<grid, 256, 0, S>>>(n, s->orig, xbn, io3);
+  ggk::k_unpermute3<<<grid, 256, 0, S>>>(n, s->orig, vbn, io3 + 3 * (size_t)n);
+  if (dL_dx0) BWCHK(hipMemcpyAsync(dL_dx0, io3, (size_t)n * 12, kout, S));
+  if (dL_dv0) BWCHK(hipMemcpyAsync(dL_dv0, io3 + 3 * (size_t)n, (size_t)n * 12, kout, S));
+  std::vector<float> hb((size_t)std::max(nb, 1) * 18 * N, 0.0f);
+  if (nb > 0) BWCHK(hipMemcpyAsync(hb.data(), bgrad, hb.size() * 4, hipMemcpyDeviceToHost, S));
+  BWCHK(hipStreamSynchronize(S));
+  release();
+#undef BWCHK
+
+  // ---- twists: direct (body point velocity) plus the pose chain, in double
+  if (dL_dtwists) {
+    std::vector<float> out((size_t)N * nb * 6, 0.0f);
+    for (int b = 0; b < nb; ++b) {
+      double Racc[9] = {0}, tacc[3] = {0};  // adjoint of the pose after step st
+      for (int st = N - 1; st >= 0; --st) {
+        const HostBody& P0 = s->tape_poses[(size_t)st * nb + b];      // pose at step st
+        const HostBody& P1 = s->tape_poses[(size_t)(st + 1) * nb + b];  // pose after step st
+        const float* gq = &hb[((size_t)st * nb + b) * 18];
+        double gnu[3], gom[3];
+        for (int q = 0; q < 3; ++q) {
+          gnu[q] = gq[q] + dt * tacc[q];
+          gom[q] = gq[3 + q];
+        }
+        // R1 = E R0 with E = Exp(dt omega): d/d omega through the left Jacobian
+        const double phi[3] = {dt * P0.om[0], dt * P0.om[1], dt * P0.om[2]};
+        double M[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int m = 0; m < 3; ++m) acc += Racc[3 * r + m] * P1.R[3 * c + m];
+            M[3 * r + c] = acc;
+          }
+        const double gxi[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+        double J[9];
+        so3_left_jacobian(phi, J);
+        for (int q = 0; q < 3; ++q) gom[q] += dt * (J[q] * gxi[0] + J[3 + q] * gxi[1] + J[6 + q] * gxi[2]);
+        for (int q = 0; q < 3; ++q) {
+          out[((size_t)st * nb + b) * 6 + q] = (float)gnu[q];
+          out[((size_t)st * nb + b) * 6 + 3 + q] = (float)gom[q];
+        }
+        // adjoint of the pose at step st: back through the advance, plus this step's geometry
+        double E[9];
+        so3_exp(phi, E);
+        double R0b[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int m = 0; m < 3; ++m) acc += E[3 * m + r] * Racc[3 * m + c];
+            R0b[3 * r + c] = acc;
+          }
+        for (int q = 0; q < 9; ++q) Racc[q] = R0b[q] + gq[6 + q];
+        for (int q = 0; q < 3; ++q) tacc[q] += gq[15 + q];
+      }
+    }
+    if (where == GG_MEM_HOST) {
+      std::memcpy(dL_dtwists, out.data(), out.size() * 4);
+    } else {
+      HIPCHK(s, hipMemcpy(dL_dtwists, out.data(), out.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
+  return GG_OK;
 }
 
 gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written, gg_mem where) {

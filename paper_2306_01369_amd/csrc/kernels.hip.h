@@ -633,18 +633,38 @@ __device__ __forceinline__ void put_contact(int i, int k, int K, int32_t code, f
   }
 }
 
+// Block-wide min of 8 integers (max via negation) with one pair of barriers.
+__device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] = min(v[q], __shfl_xor(v[q], o, 64));
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[wid][q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int r = red[0][q];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = min(r, red[w][q]);
+    v[q] = r;
+  }
+}
+
 // Contact detection over work items (runs of at most kDetBlock particles of one
 // Z-order node); each workgroup takes a contiguous range of items.
 // Tile path: the bounding box of the item's cells, widened by one cell, is
-// looked up once per cell through the hash table (bucket of Eq. (6), members
-// filtered by their own cell since buckets alias); the members are staged in
-// LDS sorted by original index, and every particle tests the 27 cells around
-// it from LDS.  Fallback path (box or staging larger than the LDS budget, or
-// an item spanning environments): each particle queries its 27 cells
-// directly.  Both paths list partners in the same canonical order (neighbour
-// cell, then original index), then bodies in body order, so results do not
-// depend on the internal order or on the path taken.  Also seeds the Jacobi
-// iterate w = v + dt g and the split inverse mass s_i = n_i / m_i.
+// looked up once per cell through the hash table (bucket of Eq. (6)); the
+// buckets' members are copied to LDS, marked by whether they lie in the cell
+// queried (buckets alias), and each cell's members are sorted by original
+// index; every particle then tests the 27 cells around it from LDS.  Fallback
+// path (box or staging larger than the LDS budget, or an item spanning
+// environments): each particle queries its 27 cells directly.  Both paths list
+// partners in the same canonical order (neighbour cell, then original index),
+// then bodies in body order, so results do not depend on the internal order or
+// on the path taken.  Also seeds the Jacobi iterate w = v + dt g and the split
+// inverse mass s_i = n_i / m_i.
 __global__ __launch_bounds__(kDetBlock) void k_detect(
     int n, int K, const float4* __restrict__ x, const float4* __restrict__ v, const int32_t* __restrict__ orig,
     float inv_c, int nh, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
@@ -653,12 +673,14 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     float gy, float gz, float dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, float* __restrict__ Psi, float4* __restrict__ w, Ctl* ctl, int step) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int red8[kDetBlock / 64][8];
   __shared__ int red[kDetBlock / 64];
   if (ctl->err) return;
-  int* cell_off = (int*)smem;                                             // max_cells + 1
-  float4* st_x = (float4*)(smem + ((((max_cells + 1) * 4) + 15) & ~15));  // max_stage
-  int* st_j = (int*)(st_x + max_stage);                                    // max_stage
-  int* st_o = st_j + max_stage;                                            // max_stage
+  int* cell_off = (int*)smem;                                  // max_cells + 1
+  int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
+  float4* st_x = (float4*)(smem + ((((2 * max_cells + 1) * 4) + 15) & ~15));  // max_stage
+  int* st_j = (int*)(st_x + max_stage);                        // max_stage (-1: other cell)
+  int* st_o = st_j + max_stage;                                // max_stage
 
   const int n_items = *n_items_ptr;
   const int per = (n_items + gridDim.x - 1) / gridDim.x;
@@ -682,33 +704,28 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
       b_lo = env.body_lo[e_i];
       b_hi = env.body_hi[e_i];
     }
-    const int lo0 = block_min(active ? k0 : BIG, red), hi0 = block_max(active ? k0 : -BIG, red);
-    const int lo1 = block_min(active ? k1 : BIG, red), hi1 = block_max(active ? k1 : -BIG, red);
-    const int lo2 = block_min(active ? k2 : BIG, red), hi2 = block_max(active ? k2 : -BIG, red);
-    const int elo = block_min(active ? e_i : BIG, red), ehi = block_max(active ? e_i : -BIG, red);
-    bool tile = (elo == ehi) && (hi0 - lo0 < 256) && (hi1 - lo1 < 256) && (hi2 - lo2 < 256);
+    int bb[8] = {active ? k0 : BIG, active ? k1 : BIG, active ? k2 : BIG, active ? e_i : BIG,
+                 active ? -k0 : BIG, active ? -k1 : BIG, active ? -k2 : BIG, active ? -e_i : BIG};
+    block_min8(bb, red8);
+    const int lo0 = bb[0], lo1 = bb[1], lo2 = bb[2], hi0 = -bb[4], hi1 = -bb[5], hi2 = -bb[6];
+    bool tile = (bb[3] == -bb[7]) && (hi0 - lo0 < 256) && (hi1 - lo1 < 256) && (hi2 - lo2 < 256);
     const int Dx = hi0 - lo0 + 3, Dy = hi1 - lo1 + 3, Dz = hi2 - lo2 + 3;
     const int NC = tile ? Dx * Dy * Dz : 0;
     tile = tile && NC <= max_cells;
     const int ex = lo0 - 1, ey = lo1 - 1, ez = lo2 - 1;
     int t_n = nh, t_off = 0;
     if (env.env_of && tile) {
-      t_n = env.nh[elo];
-      t_off = env.boff[elo];
+      t_n = env.nh[bb[3]];
+      t_off = env.boff[bb[3]];
     }
     if (tile) {
+      // bucket extents of every cell of the box: independent loads
       for (int c = threadIdx.x; c < NC; c += kDetBlock) {
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
         const int hb = t_off + hash_cell(cx, cy, cz, t_n);
-        const int s0 = start[hb], s1 = start[hb + 1];
-        int cnt = 0;
-        for (int q = s0; q < s1; ++q) {
-          const float4 pj = xs[q];
-          bool okj = true;
-          cnt += (cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
-                  cell_coord(pj.z, inv_c, okj) == cz);
-        }
-        cell_off[c] = cnt;
+        const int s0 = start[hb];
+        cell_s[c] = s0;
+        cell_off[c] = start[hb + 1] - s0;
       }
       __syncthreads();
       block_exclusive_scan(cell_off, NC, red);
@@ -716,32 +733,32 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     }
     int cnt = 0;
     if (tile) {
+      // copy the members, mark those of other cells, sort by original index
       for (int c = threadIdx.x; c < NC; c += kDetBlock) {
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
-        const int hb = t_off + hash_cell(cx, cy, cz, t_n);
-        const int s0 = start[hb], s1 = start[hb + 1];
-        const int first = cell_off[c];
-        int pos = first;
-        for (int q = s0; q < s1; ++q) {
-          const float4 pj = xs[q];
+        const int s0 = cell_s[c], first = cell_off[c], m = cell_off[c + 1] - first;
+        for (int u = 0; u < m; ++u) {
+          const float4 pj = xs[s0 + u];
           bool okj = true;
-          if (cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
-              cell_coord(pj.z, inv_c, okj) == cz) {
-            // insertion by original index keeps each cell's members sorted
-            const int oj = os[q];
-            const int j = sidx[q];
-            int at = pos;
-            while (at > first && st_o[at - 1] > oj) {
-              st_x[at] = st_x[at - 1];
-              st_j[at] = st_j[at - 1];
-              st_o[at] = st_o[at - 1];
-              --at;
-            }
-            st_x[at] = pj;
-            st_j[at] = j;
-            st_o[at] = oj;
-            ++pos;
+          const bool mine = cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
+                            cell_coord(pj.z, inv_c, okj) == cz;
+          st_x[first + u] = pj;
+          st_j[first + u] = mine ? sidx[s0 + u] : -1;
+          st_o[first + u] = mine ? os[s0 + u] : 0x7fffffff;
+        }
+        for (int u = 1; u < m; ++u) {
+          const float4 kx = st_x[first + u];
+          const int kj = st_j[first + u], ko = st_o[first + u];
+          int at = first + u;
+          while (at > first && st_o[at - 1] > ko) {
+            st_x[at] = st_x[at - 1];
+            st_j[at] = st_j[at - 1];
+            st_o[at] = st_o[at - 1];
+            --at;
           }
+          st_x[at] = kx;
+          st_j[at] = kj;
+          st_o[at] = ko;
         }
       }
       __syncthreads();
@@ -753,6 +770,7 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
               const int s0 = cell_off[c], s1 = cell_off[c + 1];
               for (int q = s0; q < s1; ++q) {
                 const int j = st_j[q];
+                if (j < 0) break;          // members of other cells sort last
                 if (j == i) continue;
                 ++cand;
                 const float4 pj = st_x[q];
@@ -847,14 +865,15 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
 // s_hi) for a pair, 1/s_i for a body (mass splitting).  The particle then sums
 // its contacts' impulses in list order: w_i = w0_i + (1/m_i) sum sigma P_c.
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
-// optionally dv instead of w_out).
+// optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
+// (the same arrays, or per-sweep arrays when the sweeps are recorded).
 __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __restrict__ x,
                                                 float4* __restrict__ v, const float4* __restrict__ w_in,
                                                 float4* __restrict__ w_out, const int32_t* __restrict__ ncon,
                                                 const int32_t* __restrict__ partner,
-                                                const float* __restrict__ Psi, float* __restrict__ Px,
-                                                float* __restrict__ Py, float* __restrict__ Pz,
-                                                const DevBody* __restrict__ bodies, float gx, float gy,
+                                                const float* __restrict__ Psi, const float* Pix,
+                                                const float* Piy, const float* Piz, float* Px, float* Py,
+                                                float* Pz, const DevBody* __restrict__ bodies, float gx, float gy,
                                                 float gz, float dt, float alpha_dt, float mu, float relax,
                                                 int mode, float4* __restrict__ dv, const Ctl* ctl) {
   if (ctl->err) return;
@@ -872,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
     const float psi = Psi[slot];
     float P0 = 0.f, P1 = 0.f, P2 = 0.f;
     if (!first) {
-      P0 = Px[slot]; P1 = Py[slot]; P2 = Pz[slot];
+      P0 = Pix[slot]; P1 = Piy[slot]; P2 = Piz[slot];
     }
     float n0, n1, n2, u0, u1, u2, mt, sg;
     if (code >= 0) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgg.so")
 GG_OK, GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP, GG_ERR_CAPACITY, GG_ERR_NONFINITE, GG_ERR_NO_TAPE, \
     GG_ERR_UNSUPPORTED = range(8)
 GG_MEM_HOST, GG_MEM_DEVICE = 0, 1
-GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS = 1, 2
+GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS, GG_FLAG_TAPE = 1, 2, 4
 FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "stats": 5, "dv": 6,
          "radius": 7}
 SHAPES = {"plane": 0, "box": 1, "capsule": 2}
@@ -163,7 +163,7 @@ class Sim:
                  gravity=(0.0, 0.0, -9.81), cell_size=0.0, hash_size=0, relax=1.0, mass_split=True,
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
                  profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
-                 tile_max_stage=0, tile_node_shift=0):
+                 tile_max_stage=0, tile_node_shift=0, differentiable=False, checkpoint_every=0):
         L = lib()
         P = Params()
         P.dt, P.alpha, P.mu = dt, alpha, mu
@@ -176,7 +176,9 @@ class Sim:
         P.mass_split = 1 if mass_split else 0
         P.max_contacts_per_particle = int(max_contacts)
         P.density = density
-        P.flags = (GG_FLAG_PROFILE if profile else 0) | (GG_FLAG_DIAGNOSTICS if diagnostics else 0)
+        P.flags = (GG_FLAG_PROFILE if profile else 0) | (GG_FLAG_DIAGNOSTICS if diagnostics else 0) | \
+            (GG_FLAG_TAPE if differentiable else 0)
+        P.checkpoint_every = int(checkpoint_every)
         P.reorder_every = int(reorder_every)
         P.tile_max_cells = int(tile_max_cells)
         P.tile_max_stage = int(tile_max_stage)
@@ -224,6 +226,7 @@ class Sim:
 
     def step(self, n_steps=1, twists=None):
         pt, wt, kt = _arg(twists, np.float32)
+        self.last_steps = int(n_steps)
         _check(lib().gg_step(self._h, int(n_steps), pt, wt))
 
     def read_bytes(self, field):
@@ -260,8 +263,21 @@ class Sim:
     def stats(self):
         return self.read("stats")
 
-    def backward(self, dL_dx=None, dL_dv=None):
-        _check(lib().gg_step_backward(self._h, None, None, None, None, None, GG_MEM_HOST))
+    def backward(self, dL_dx=None, dL_dv=None, n_steps=None):
+        """Gradients of the last (differentiable) step call: returns
+        (dL/dx0, dL/dv0, dL/dtwists) as NumPy arrays given dL/dx, dL/dv of the
+        final state (None = zero)."""
+        n = self.n
+        gx = None if dL_dx is None else np.ascontiguousarray(dL_dx, np.float32).reshape(n, 3)
+        gv = None if dL_dv is None else np.ascontiguousarray(dL_dv, np.float32).reshape(n, 3)
+        ox = np.zeros((n, 3), np.float32)
+        ov = np.zeros((n, 3), np.float32)
+        steps = self.last_steps if n_steps is None else n_steps
+        ot = np.zeros((steps, self.n_bodies, 6), np.float32)
+        p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        _check(lib().gg_step_backward(self._h, p(gx), p(gv), p(ox), p(ov), p(ot) if ot.size else None,
+                                      GG_MEM_HOST))
+        return ox, ov, ot
 
 
 def scene_sim(scene, **kw):
@@ -270,3 +286,35 @@ def scene_sim(scene, **kw):
                 gravity=scene.gravity, env_offsets=scene.env_offsets)
     args.update(kw)
     return Sim(scene.x, scene.v, scene.radius, scene.bodies, **args)
+
+
+def rollout_function():
+    """torch.autograd.Function over a differentiable rollout:
+    (x0, v0, twists) -> (x_final, v_final).  Each forward builds a simulation
+    from (x0, v0) with GG_FLAG_TAPE, runs len(twists) steps and keeps it for the
+    backward, which calls gg_step_backward (checkpointed recompute + adjoint
+    kernels).  ``setup`` carries radius, bodies and Sim keyword arguments."""
+    import torch
+
+    class Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x0, v0, twists, setup):
+            sim = Sim(x0.detach().cpu().numpy(), v0.detach().cpu().numpy(), setup["radius"], setup["bodies"],
+                      differentiable=True, **setup.get("kwargs", {}))
+            tw = twists.detach().cpu().numpy().astype(np.float32)
+            sim.step(tw.shape[0], twists=tw)
+            ctx.sim = sim
+            x = torch.from_numpy(sim.read("pos")).to(x0.device)
+            v = torch.from_numpy(sim.read("vel")).to(x0.device)
+            return x, v
+
+        @staticmethod
+        def backward(ctx, gx, gv):
+            sim = ctx.sim
+            ox, ov, ot = sim.backward(None if gx is None else gx.detach().cpu().numpy(),
+                                      None if gv is None else gv.detach().cpu().numpy())
+            sim.close()
+            dev = gx.device if gx is not None else gv.device
+            return (torch.from_numpy(ox).to(dev), torch.from_numpy(ov).to(dev), torch.from_numpy(ot).to(dev), None)
+
+    return Rollout

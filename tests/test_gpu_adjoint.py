@@ -1,0 +1,151 @@
+"""GPU adjoint (gg_step_backward) against FP64 central finite differences of
+the oracle: directional derivatives of a rollout loss with respect to initial
+positions, initial velocities and per-step tool twists.  The contact set is
+frozen by construction; directions whose +-h runs change a contact list are
+redrawn."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_01369_amd import gg, scenes
+from gradcheck import TargetLoss, fd_directional
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-3
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _setup(n=2000, steps=8, seed=0):
+    r = 0.004
+    rng = np.random.default_rng(seed)
+    x = scenes.packed_bed(n, r, 0.0, 0.1, 0.0, 0.1, rng).astype(np.float32)
+    top = float(x[:, 2].max()) + r
+    R = scenes.random_rotation(np.random.default_rng(seed + 1))
+    cap = scenes.capsule_tool((0.05, 0.05, top + 0.012 + 0.002), 0.012, 0.03, R=R)
+    # make the capsule's lowest point start 2 mm above the bed
+    axis = R[:, 2]
+    cap["t"] = np.array([0.05, 0.05, top + 0.002 + 0.012 + 0.03 * abs(axis[2])])
+    bodies = scenes.walled_box(0.0, 0.1, 0.0, 0.1) + [cap]
+    tw = np.zeros((steps, len(bodies), 6), np.float32)
+    tw[:, -1, :3] = (0.05, -0.03, -0.6)        # into the bed
+    tw[:, -1, 3:] = (1.0, -2.0, 0.5)
+    tw = tw.astype(np.float32).astype(np.float64)
+    v = (rng.normal(size=(n, 3)) * 0.01).astype(np.float32)
+    loss = TargetLoss((0.07, 0.07, top - 0.01), (0.03, 0.03, 0.02), width=1e-3, vel_weight=(0.02, -0.01, 0.03))
+    return x, v, np.full(n, r, np.float32), bodies, tw, loss
+
+
+def _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3):
+    sim = gg.Sim(x, v, r, bodies, differentiable=True, checkpoint_every=checkpoint_every)
+    sim.step(tw.shape[0], twists=tw.astype(np.float32))
+    xN = sim.read("pos").astype(np.float64)
+    vN = sim.read("vel").astype(np.float64)
+    gx, gv = loss.grads(xN, vN)
+    out = sim.backward(gx, gv)
+    st = sim.stats()
+    sim.close()
+    return out, st
+
+
+def test_adjoint_matches_fd_directional_derivatives():
+    x, v, r, bodies, tw, loss = _setup()
+    say("adjoint vs FD: n", len(x), "steps", tw.shape[0])
+    (gx0, gv0, gtw), st = _gpu_grads(x, v, r, bodies, tw, loss)
+    assert st["n_pb"] > 0 and st["n_pp"] > 1000
+    rng = np.random.default_rng(42)
+    checked = 0
+    # Resting contacts sit at psi ~ 0 (the Baumgarte equilibrium), so free
+    # detection flips some of them under any perturbation of positions; the
+    # reference therefore holds every step's contact set fixed, as the adjoint does.
+    kinds = ["x0", "v0", "twist", "all", "x0", "twist"]
+    for kind in kinds:
+        for attempt in range(1):
+            dx = rng.normal(size=x.shape) if kind in ("x0", "all") else np.zeros(x.shape)
+            dv = rng.normal(size=v.shape) if kind in ("v0", "all") else np.zeros(v.shape)
+            dt_ = np.zeros_like(tw)
+            if kind in ("twist", "all"):
+                dt_[:, -1, :] = rng.normal(size=(tw.shape[0], 6))
+            # perturbation of ~1e-9 in the largest component: small enough that
+            # near-touching pairs rarely flip, large enough for FP64 differences
+            h = 1e-9 / max(np.abs(dx).max(), np.abs(dv).max(), np.abs(dt_).max())
+            fd, same = fd_directional(loss, x.astype(np.float64), v.astype(np.float64), r, bodies, tw,
+                                      (dx, dv, dt_), h)
+            say(kind, "free detection keeps the contact sets:", same)
+            an = np.sum(gx0 * dx) + np.sum(gv0 * dv) + np.sum(gtw * dt_)
+            err = abs(an - fd) / max(abs(fd), 1e-12)
+            say(kind, "adjoint", an, "fd", fd, "rel err", err)
+            assert err <= REL_TOL, (kind, an, fd, err)
+            checked += 1
+            break
+    assert checked >= 4
+
+
+def test_adjoint_is_deterministic_and_checkpoint_independent():
+    x, v, r, bodies, tw, loss = _setup(n=1200, steps=7, seed=3)
+    say("adjoint determinism")
+    (a0, a1, a2), _ = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=2)
+    (b0, b1, b2), _ = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=2)
+    (c0, c1, c2), _ = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=7)
+    for p, q in ((a0, b0), (a1, b1), (a2, b2)):
+        assert p.tobytes() == q.tobytes()
+    for p, q in ((a0, c0), (a1, c1), (a2, c2)):
+        assert p.tobytes() == q.tobytes()
+    assert np.abs(a0).max() > 0 and np.abs(a2).max() > 0
+
+
+def test_backward_requires_a_tape():
+    x, v, r, bodies, tw, loss = _setup(n=300, steps=2)
+    say("no tape")
+    sim = gg.Sim(x, v, r, bodies)
+    sim.step(2, twists=tw.astype(np.float32))
+    with pytest.raises(gg.GGError) as e:
+        sim.backward(np.zeros((len(x), 3)), None)
+    assert e.value.status == gg.GG_ERR_NO_TAPE
+    sim2 = gg.Sim(x, v, r, bodies, differentiable=True)
+    with pytest.raises(gg.GGError) as e:
+        sim2.backward(np.zeros((len(x), 3)), None, n_steps=0)
+    assert e.value.status == gg.GG_ERR_NO_TAPE
+
+
+def test_free_fall_adjoint_closed_form():
+    # no contacts: x_N = x0 + N dt v0 + c, v_N = v0 + c'
+    n = 100
+    rng = np.random.default_rng(5)
+    x = (rng.uniform(0, 1, (n, 3)) + 5.0).astype(np.float32)
+    x = scenes.loose_lattice(n, 0.01, (5.0, 5.0, 5.0), rng, spacing_factor=3.0)[0]
+    v = rng.normal(size=(n, 3)).astype(np.float32)
+    r = np.full(n, 0.01, np.float32)
+    say("free fall adjoint")
+    sim = gg.Sim(x, v, r, [], differentiable=True, checkpoint_every=4)
+    N = 9
+    sim.step(N)
+    gx = rng.normal(size=(n, 3)).astype(np.float32)
+    gv = rng.normal(size=(n, 3)).astype(np.float32)
+    ox, ov, _ = sim.backward(gx, gv)
+    np.testing.assert_allclose(ox, gx, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(ov, gv + N * 1e-3 * gx, rtol=1e-5, atol=1e-6)
+
+
+def test_autograd_function_round_trip():
+    torch = pytest.importorskip("torch")
+    x, v, r, bodies, tw, loss = _setup(n=800, steps=4, seed=7)
+    say("autograd")
+    Rollout = gg.rollout_function()
+    x0 = torch.tensor(x, dtype=torch.float32, requires_grad=True)
+    v0 = torch.tensor(v, dtype=torch.float32, requires_grad=True)
+    t = torch.tensor(tw, dtype=torch.float32, requires_grad=True)
+    xN, vN = Rollout.apply(x0, v0, t, {"radius": r, "bodies": bodies})
+    c = torch.tensor(loss.c, dtype=torch.float32)
+    L = (vN @ c).sum() + xN[:, 2].sum()
+    L.backward()
+    (gx0, gv0, gtw), _ = _gpu_grads(x, v, r, bodies, tw, type("Lin", (), {
+        "grads": staticmethod(lambda X, V: (np.tile([0.0, 0.0, 1.0], (len(X), 1)), np.tile(loss.c, (len(V), 1))))})())
+    np.testing.assert_allclose(x0.grad.numpy(), gx0, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(t.grad.numpy(), gtw, rtol=1e-5, atol=1e-6)
