@@ -136,12 +136,26 @@ gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg
  * range or becomes non-finite. */
 gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem where);
 
-/* Reverse-mode gradient of the last gg_step call (differentiable extension of
- * the method; see the design notes).  dL_dx, dL_dv: n x 3 gradients with
- * respect to the final positions and velocities; outputs dL_dx0, dL_dv0
- * (n x 3) and dL_dtwists (n_steps x n_bodies x 6), any may be NULL.
- * Returns GG_ERR_NO_TAPE when no differentiable forward was recorded;
- * this build records none and returns GG_ERR_UNSUPPORTED. */
+/* Reverse-mode gradient of the last gg_step call, for a simulation created
+ * with GG_FLAG_TAPE and one environment.  This differentiates the discrete
+ * step of Eqs. (2)-(5) and Alg. 1 (the impulse sweeps, the contact gaps and
+ * normals of Eq. (1) and the body SDFs, the rigid-body pose update and the
+ * symplectic-Euler integration) with each step's contact set held fixed, the
+ * set being piecewise constant in the inputs.  The forward kept (x, v) every
+ * params.checkpoint_every steps; each segment is recomputed from its
+ * checkpoint before its steps are reversed, so device memory grows with
+ * n_steps / checkpoint_every plus one segment's contacts.
+ * dL_dx, dL_dv: n x 3 float32 gradients of the loss with respect to the final
+ * positions and velocities, caller's particle order; NULL means zero.
+ * Outputs (any may be NULL): dL_dx0, dL_dv0 (n x 3) with respect to the
+ * positions and velocities at the start of the call, and dL_dtwists
+ * (n_steps x n_bodies x 6, same layout as gg_step's twists) with respect to
+ * each body's twist in each step.  where applies to all six arrays.
+ * Errors: GG_ERR_NO_TAPE if the simulation has no tape or the last gg_step
+ * failed; GG_ERR_UNSUPPORTED for more than one environment; GG_ERR_OOM if the
+ * workspace cannot be allocated; GG_ERR_HIP if the recomputed contact counts
+ * differ from the recorded forward.  The tape stays valid, so the call may be
+ * repeated with other loss gradients. */
 gg_status gg_step_backward(gg_sim* sim, const float* dL_dx, const float* dL_dv, float* dL_dx0,
                            float* dL_dv0, float* dL_dtwists, gg_mem where);
 
@@ -180,6 +194,8 @@ typedef struct {
   int64_t detect_fallback;/* detection work items (up to 128 particles each) that queried cells
                              one particle at a time instead of through an LDS tile, last detection */
   int64_t detect_items;   /* detection work items */
+  int64_t device_bytes_peak; /* largest device memory in use (whole device, hipMemGetInfo)
+                                seen after this simulation's allocations, backward included */
 } gg_stats;
 
 /* Copy a field into dst (where says where dst lives).  If dst is NULL only

@@ -1,0 +1,127 @@
+"""Autotuner for the launch shape of the contact step.
+
+Chooses, for a given workload, the detection work-item node size
+(``tile_node_shift``: Z-order nodes of 2^shift cells), the LDS budget of a
+detection tile (``tile_max_cells``, ``tile_max_stage``) and the interval between
+spatial re-sorts (``reorder_every``), by timing a few steps of each candidate
+through the C ABI.  These parameters change only memory layout and work
+decomposition: every output is bitwise identical across them (the GPU tests
+check this), so the choice is free of numerical side effects.  The cell size
+and hash-table size are left at the method's defaults (c = 2 r_max (1 + 2^-10),
+n_h = 2 n per environment, the heuristic of Sec. II-B) because they change the
+summation order of partner lists.
+
+Results are cached in a JSON file keyed by device, particle count, particles
+per cell and body count.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import gg
+
+CACHE_ENV = "GG_AUTOTUNE_CACHE"
+
+
+def _cache_path():
+    return os.environ.get(CACHE_ENV, os.path.join(os.path.expanduser("~"), ".cache", "gg_autotune.json"))
+
+
+def node_dims(shift):
+    """Cells per axis of a Z-order node of 2^shift cells (x gets the extra bits)."""
+    bx = (shift + 2) // 3
+    by = (shift + 1) // 3
+    bz = shift // 3
+    return 1 << bx, 1 << by, 1 << bz
+
+
+def particles_per_cell(x, radius):
+    """Mean particles per occupied cell at the default cell size."""
+    r = np.asarray(radius, np.float32)
+    c = 2.0 * float(r.max()) * (1.0 + 2.0 ** -10)
+    k = np.floor(np.asarray(x, np.float64) / c + 0.5).astype(np.int64)
+    k -= k.min(axis=0)
+    key = (k[:, 0] * 1_000_003 + k[:, 1]) * 1_000_033 + k[:, 2]
+    return len(x) / max(1, len(np.unique(key)))
+
+
+def candidates(ppc):
+    """Launch shapes worth timing for ppc particles per occupied cell: nodes of
+    roughly 32..160 particles, LDS budget for the node's box plus a one-cell
+    halo and one cell of drift."""
+    out = []
+    for shift in range(2, 10):
+        dx, dy, dz = node_dims(shift)
+        per_node = ppc * dx * dy * dz
+        if not 24 <= per_node <= 180:
+            continue
+        cells = (dx + 3) * (dy + 3) * (dz + 3)
+        stage = int(math.ceil(cells * (ppc + 0.6) * 1.1))
+        if stage > 2048 or cells > 4096:
+            continue
+        for reorder in (4, 8, 16):
+            out.append({"tile_node_shift": shift, "tile_max_cells": cells, "tile_max_stage": stage,
+                        "reorder_every": reorder})
+    return out
+
+
+def key_of(n, ppc, n_bodies):
+    try:
+        import torch
+        dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    except Exception:  # torch missing or no device
+        dev = "unknown"
+    return f"{dev}|n2^{int(round(math.log2(max(n, 1))))}|ppc{ppc:.1f}|bodies{n_bodies}"
+
+
+def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=True, verbose=False):
+    """Return the fastest launch-shape parameters for this workload (a dict of
+    gg.Sim keyword arguments)."""
+    sim_kwargs = dict(sim_kwargs or {})
+    ppc = particles_per_cell(x, radius)
+    key = key_of(len(x), ppc, len(bodies))
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return dict(cache[key]["params"])
+    best, best_t, results = None, float("inf"), []
+    for cand in candidates(ppc):
+        kw = dict(sim_kwargs)
+        kw.update(cand)
+        kw["profile"] = True
+        try:
+            sim = gg.Sim(x, v, radius, bodies, **kw)
+            sim.step(warmup)
+            t0 = time.perf_counter()
+            sim.step(steps)
+            t = (time.perf_counter() - t0) / steps
+            st = sim.stats()
+            sim.close()
+        except gg.GGError as e:
+            if verbose:
+                print("autotune: candidate failed", cand, e)
+            continue
+        results.append((t, cand, st["detect_fallback"]))
+        if verbose:
+            print(f"autotune: {cand} -> {1e3 * t:.3f} ms/step, fallback items {st['detect_fallback']}")
+        if t < best_t:
+            best, best_t = cand, t
+    if best is None:
+        return {}
+    if use_cache:
+        cache[key] = {"params": best, "ms_per_step": 1e3 * best_t}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return dict(best)

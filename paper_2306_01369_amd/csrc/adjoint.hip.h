@@ -8,6 +8,8 @@
 // contact geometry (normals, gaps, body point velocities) differentiated with
 // respect to positions, body poses and twists (SDF gradients and Hessians).
 //
+// Recorded impulses and the adjoint's per-contact state are indexed compactly,
+// pofs[i] + k with pofs the prefix sum of the contact counts.
 // Per half contact the adjoint keeps a carry (the adjoint of the impulse of the
 // previous sweep, identical bits in both halves of a pair, as the forward's
 // impulse copies) and accumulators of the adjoints of the normal, the gap and
@@ -79,9 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     float4* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
     const float* __restrict__ Psi, const float* __restrict__ Ppx, const float* __restrict__ Ppy,
     const float* __restrict__ Ppz, AdjSlots A, const DevBody* __restrict__ bodies, float alpha_dt, float mu,
-    float relax, int first_sweep) {
+    float relax, int first_sweep, const int32_t* __restrict__ pofs) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  const int pbase = pofs[i];
   const float4 xi = x[i];
   const float4 vi = v[i];
   const float4 wi = w_prev[i];
@@ -90,14 +93,15 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
+    const int q = pbase + k;   // compact index of the recorded impulse and adjoint state
     const int code = partner[slot];
     const float psi = Psi[slot];
     float P[3] = {0.f, 0.f, 0.f};
     if (!first_sweep) {
-      P[0] = Ppx[slot]; P[1] = Ppy[slot]; P[2] = Ppz[slot];
+      P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
     }
     float nrm[3], u[3], mt, Pb[3];
-    const float carry[3] = {A.cx[slot], A.cy[slot], A.cz[slot]};
+    const float carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
     bool lo = true, body = code < 0;
     if (!body) {
       const int j = code & (kHiFlag - 1);
@@ -139,17 +143,17 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     float yb[3], nb[3] = {0.f, 0.f, 0.f};
     proj_adjoint(y, nrm, mu, Qb, yb, nb);
     const float keep = 1.0f - relax;
-    A.cx[slot] = yb[0] + keep * Pb[0];
-    A.cy[slot] = yb[1] + keep * Pb[1];
-    A.cz[slot] = yb[2] + keep * Pb[2];
+    A.cx[q] = yb[0] + keep * Pb[0];
+    A.cy[q] = yb[1] + keep * Pb[1];
+    A.cz[q] = yb[2] + keep * Pb[2];
     const float ub[3] = {-mt * yb[0], -mt * yb[1], -mt * yb[2]};
     const float bb = -mt * dot3f(yb, nrm);
-    A.nx[slot] += nb[0] - mt * bias * yb[0];
-    A.ny[slot] += nb[1] - mt * bias * yb[1];
-    A.nz[slot] += nb[2] - mt * bias * yb[2];
-    A.ps[slot] += alpha_dt * bb;
+    A.nx[q] += nb[0] - mt * bias * yb[0];
+    A.ny[q] += nb[1] - mt * bias * yb[1];
+    A.nz[q] += nb[2] - mt * bias * yb[2];
+    A.ps[q] += alpha_dt * bb;
     if (body) {
-      A.vx[slot] -= ub[0]; A.vy[slot] -= ub[1]; A.vz[slot] -= ub[2];
+      A.vx[q] -= ub[0]; A.vy[q] -= ub[1]; A.vz[q] -= ub[2];
     }
     const float sg = lo ? 1.0f : -1.0f;
     acc[0] += sg * ub[0]; acc[1] += sg * ub[1]; acc[2] += sg * ub[2];
@@ -275,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
                                                      const int32_t* __restrict__ partner,
                                                      const float* __restrict__ Psi, AdjSlots A,
                                                      const DevBody* __restrict__ bodies, int n_bodies,
-                                                     float4* __restrict__ xbar, float* __restrict__ part) {
+                                                     const int32_t* __restrict__ pofs, float4* __restrict__ xbar,
+                                                     float* __restrict__ part) {
   __shared__ float red[kBlock];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
@@ -297,8 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
       const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       if (!(L > 0.0f)) continue;
       const float nr[3] = {d[0] / L, d[1] / L, d[2] / L};
-      const float nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
-      const float psb = A.ps[slot];
+      const int q = pofs[i] + k;
+      const float nb[3] = {A.nx[q], A.ny[q], A.nz[q]};
+      const float psb = A.ps[q];
       const float nn = dot3f(nr, nb);
       const float sg = lo ? 1.0f : -1.0f;
       for (int a = 0; a < 3; ++a) xb[a] += sg * ((nb[a] - nn * nr[a]) / L + psb * nr[a]);
@@ -325,9 +331,10 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
         const float psi = Psi[slot];
         const float f = psi + xi.w;
         const float a[3] = {xi.x - f * nr[0] - B.t[0], xi.y - f * nr[1] - B.t[1], xi.z - f * nr[2] - B.t[2]};
-        const float Vb[3] = {A.vx[slot], A.vy[slot], A.vz[slot]};
-        const float nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
-        const float psb = A.ps[slot];
+        const int qq = pofs[i] + k;
+        const float Vb[3] = {A.vx[qq], A.vy[qq], A.vz[qq]};
+        const float nb[3] = {A.nx[qq], A.ny[qq], A.nz[qq]};
+        const float psb = A.ps[qq];
         // V = nu + om x a
         acc[0] += Vb[0]; acc[1] += Vb[1]; acc[2] += Vb[2];
         acc[3] += a[1] * Vb[2] - a[2] * Vb[1];

@@ -159,9 +159,19 @@ struct gg_sim {
   std::vector<float> tape_twists;     // steps x bodies x 6
   float4* ck = nullptr;               // checkpoints: per segment x then v
   size_t ck_cap = 0;
+  unsigned long long* d_counts = nullptr;  // per step (pairs, body contacts) of a differentiable call
+  size_t d_counts_cap = 0;
+  std::vector<unsigned long long> tape_counts;
 };
 
 namespace {
+
+// Device memory in use (whole device) into the peak statistic.
+void sample_memory(gg_sim* s) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+    s->stats.device_bytes_peak = std::max<int64_t>(s->stats.device_bytes_peak, (int64_t)(tot - fr));
+}
 
 gg_status hip_fail(gg_sim* s, hipError_t e, const char* what) {
   if (s) s->failed = true;
@@ -223,6 +233,7 @@ gg_status ensure_ell(gg_sim* s, int K) {
   s->K = K;
   s->stats.capacity = K;
   s->contacts_valid = false;
+  sample_memory(s);
   return GG_OK;
 }
 
@@ -248,7 +259,7 @@ ggk::EnvTables env_tables(const gg_sim* s) {
 void free_all(gg_sim* s) {
   void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->x2, s->v2, s->orig, s->orig2, s->mk[0], s->mk[1],
                   s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
-                  s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->h, s->rank, s->counts, s->bstart, s->bsum,
+                  s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp};
   for (void* b : bufs)
@@ -303,6 +314,7 @@ struct StepIO {
   std::vector<float4*> w;
   std::vector<float*> Px, Py, Pz;
   float4* dv;
+  int32_t* pofs = nullptr;  // compact impulse offsets (recorded steps), else ELL slots
 };
 
 StepIO plain_io(gg_sim* s) {
@@ -397,7 +409,7 @@ void launch_sweeps(gg_sim* s, const StepIO& io, const ggk::DevBody* bod) {
     ggk::k_pja<<<grid, ggk::kBlock, 0, s->stream>>>(
         n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
         io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, s->p.gravity[0], s->p.gravity[1], s->p.gravity[2],
-        s->p.dt, alpha_dt, s->p.mu, s->p.relax, mode, io.dv, s->ctl);
+        s->p.dt, alpha_dt, s->p.mu, s->p.relax, mode, io.dv, io.pofs, s->ctl);
   }
 }
 
@@ -601,6 +613,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (e != hipSuccess) return bail(hip_fail(nullptr, e, "upload"));
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
+  sample_memory(s);
   *out = s;
   return GG_OK;
 }
@@ -742,6 +755,13 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
       if (dev_alloc(&s->ck, need_ck) != hipSuccess) return fail(GG_ERR_OOM, "checkpoint allocation failed");
       s->ck_cap = need_ck;
     }
+    if ((size_t)n_steps * 2 > s->d_counts_cap) {
+      if (s->d_counts) HIPCHK(s, hipFree(s->d_counts));
+      s->d_counts = nullptr;
+      s->d_counts_cap = 0;
+      if (dev_alloc(&s->d_counts, (size_t)n_steps * 2) != hipSuccess) return fail(GG_ERR_OOM, "count allocation failed");
+      s->d_counts_cap = (size_t)n_steps * 2;
+    }
   }
   ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
   for (int st = 0; st < n_steps && n > 0; ++st) {
@@ -757,6 +777,7 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
     }
     const StepIO io = plain_io(s);
     launch_detect(s, io, st, bod);
+    if (taped) ggk::k_record_counts<<<1, 64, 0, S>>>(s->ctl, s->d_counts + 2 * (size_t)st);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
     launch_sweeps(s, io, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
@@ -782,6 +803,7 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
     }
   s->stats.steps_done = done;
   s->stats.steps_total += done;
+  sample_memory(s);
   s->steps_global += n_steps;
   if (n > 0) {
     s->stats.n_pp = (int64_t)c.n_pp;
@@ -831,6 +853,9 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
         }
       }
     s->tape_poses = s->pose_hist;
+    s->tape_counts.assign((size_t)n_steps * 2, 0);
+    HIPCHK(s, hipMemcpy(s->tape_counts.data(), s->d_counts, (size_t)n_steps * 2 * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost));
   }
   return GG_OK;
 }
@@ -898,14 +923,29 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
     owned.clear();
   };
   const size_t n4 = (size_t)n * sizeof(float4);
+  // half contacts of every recorded step (a pair counts in both rows)
+  std::vector<size_t> hc(N);
+  size_t hc_max_seg = 1, hc_max = 1;
+  for (int st = 0; st < N; ++st) {
+    hc[st] = 2 * (size_t)s->tape_counts[2 * st] + (size_t)s->tape_counts[2 * st + 1];
+    hc_max = std::max(hc_max, hc[st]);
+  }
+  for (int seg = 0; seg * C < N; ++seg) {
+    size_t sum = 0;
+    for (int st = seg * C; st < std::min(N, seg * C + C); ++st) sum += hc[st];
+    hc_max_seg = std::max(hc_max_seg, sum);
+  }
+  const size_t nsw = (size_t)std::max(I - 1, 1);
   float4* tx = (float4*)alloc(n4 * C);
   float4* tv = (float4*)alloc(n4 * C);
   int32_t* tncon = (int32_t*)alloc((size_t)n * 4 * C);
   int32_t* tpart = (int32_t*)alloc(slots * 4 * C);
   float* tpsi = (float*)alloc(slots * 4 * C);
   float4* tw = (float4*)alloc(n4 * (size_t)I * C);
-  float* tP = (float*)alloc(slots * 4 * 3 * (size_t)std::max(I - 1, 1) * C);
-  float* Plast = (float*)alloc(slots * 4 * 3);
+  float* tP = (float*)alloc(hc_max_seg * 4 * 3 * nsw);
+  float* Plast = (float*)alloc(hc_max * 4 * 3);
+  int32_t* tpofs = (int32_t*)alloc(((size_t)n + 1) * 4 * C);
+  int32_t* pbsum = (int32_t*)alloc(((size_t)n + ggk::kScanTile) / ggk::kScanTile * 4 + 16);
   float4* xw = (float4*)alloc(n4);
   float4* vw = (float4*)alloc(n4);
   float4* xb = (float4*)alloc(n4);
@@ -915,7 +955,7 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   float4* wba = (float4*)alloc(n4);
   float4* wbb = (float4*)alloc(n4);
   float4* w0b = (float4*)alloc(n4);
-  float* adj = (float*)alloc(slots * 4 * 10);
+  float* adj = (float*)alloc(hc_max * 4 * 10);
   float* part = (float*)alloc((size_t)grid * std::max(nb, 1) * 18 * 4);
   float* bgrad = (float*)alloc((size_t)std::max(nb, 1) * 18 * 4 * N);
   float* io3 = (float*)alloc((size_t)n * 12 * 2);
@@ -924,15 +964,16 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       release();
       return fail(GG_ERR_OOM, "adjoint workspace allocation failed");
     }
-  if (owned.size() != 21) {
+  if (owned.size() != 23) {
     release();
     return fail(GG_ERR_OOM, "adjoint workspace allocation failed");
   }
+  sample_memory(s);
   ggk::AdjSlots A;
-  A.cx = adj; A.cy = adj + slots; A.cz = adj + 2 * slots;
-  A.nx = adj + 3 * slots; A.ny = adj + 4 * slots; A.nz = adj + 5 * slots;
-  A.ps = adj + 6 * slots;
-  A.vx = adj + 7 * slots; A.vy = adj + 8 * slots; A.vz = adj + 9 * slots;
+  A.cx = adj; A.cy = adj + hc_max; A.cz = adj + 2 * hc_max;
+  A.nx = adj + 3 * hc_max; A.ny = adj + 4 * hc_max; A.nz = adj + 5 * hc_max;
+  A.ps = adj + 6 * hc_max;
+  A.vx = adj + 7 * hc_max; A.vy = adj + 8 * hc_max; A.vz = adj + 9 * hc_max;
 
   // ---- final-state adjoints into the internal order
   const hipMemcpyKind kin = where == GG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -958,6 +999,8 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
     // recompute the segment from its checkpoint, recording every step
     BWCHK(hipMemcpyAsync(xw, s->ck + (size_t)seg * 2 * n, n4, hipMemcpyDeviceToDevice, S));
     BWCHK(hipMemcpyAsync(vw, s->ck + (size_t)seg * 2 * n + n, n4, hipMemcpyDeviceToDevice, S));
+    std::vector<size_t> pstart(C + 1, 0);   // first recorded impulse of each step of the segment
+    for (int st = s0; st < s1; ++st) pstart[st - s0 + 1] = pstart[st - s0] + hc[st] * 3 * nsw;
     for (int st = s0; st < s1; ++st) {
       const int r = st - s0;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
@@ -974,12 +1017,25 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       for (int l = 0; l < I; ++l) io.w[l] = tw + ((size_t)r * I + l) * n;
       io.w[I] = wba;  // unused: the last sweep writes the velocity
       for (int l = 1; l <= I; ++l) {
-        float* base = (l < I) ? tP + (((size_t)r * std::max(I - 1, 1) + (l - 1)) * 3) * slots : Plast;
-        io.Px[l] = base; io.Py[l] = base + slots; io.Pz[l] = base + 2 * slots;
+        float* base = (l < I) ? tP + pstart[r] + (size_t)(l - 1) * 3 * hc[st] : Plast;
+        io.Px[l] = base; io.Py[l] = base + hc[st]; io.Pz[l] = base + 2 * hc[st];
       }
       io.Px[0] = io.Px[1]; io.Py[0] = io.Py[1]; io.Pz[0] = io.Pz[1];
       io.dv = nullptr;
+      io.pofs = tpofs + (size_t)r * (n + 1);
       launch_detect(s, io, st, bod);
+      // compact offsets of this step's contacts; the recorded count must match
+      const int pnb = (n + ggk::kScanTile - 1) / ggk::kScanTile;
+      ggk::k_scan_a<<<pnb, ggk::kBlock, 0, S>>>(n, io.ncon, io.pofs, pbsum, 0);
+      ggk::k_scan_b<<<1, 1024, 0, S>>>(pnb, pbsum, n, io.pofs);
+      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, pbsum, io.pofs);
+      int32_t total = -1;
+      BWCHK(hipMemcpyAsync(&total, io.pofs + n, 4, hipMemcpyDeviceToHost, S));
+      BWCHK(hipStreamSynchronize(S));
+      if ((size_t)total != hc[st]) {
+        release();
+        return fail(GG_ERR_HIP, "recomputed contacts differ from the recorded forward");
+      }
       launch_sweeps(s, io, bod);
       ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, s->ctl);
     }
@@ -993,19 +1049,20 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       const float* ps = tpsi + slots * r;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
       ggk::k_adj_begin<<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
-      ggk::k_zero_f<<<(int)((slots * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(slots * 10, adj);
+      ggk::k_zero_f<<<(int)((hc_max * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(hc_max * 10, adj);
       float4* win = wba;
       float4* wout = wbb;
+      const int32_t* po = tpofs + (size_t)r * (n + 1);
       for (int l = I; l >= 1; --l) {
         const float4* wprev = tw + ((size_t)r * I + (l - 1)) * n;
-        const float* Pp = (l >= 2) ? tP + (((size_t)r * std::max(I - 1, 1) + (l - 2)) * 3) * slots : nullptr;
+        const float* Pp = (l >= 2) ? tP + pstart[r] + (size_t)(l - 2) * 3 * hc[st] : nullptr;
         ggk::k_pja_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
-                                                    Pp ? Pp + slots : nullptr, Pp ? Pp + 2 * slots : nullptr, A, bod,
-                                                    alpha_dt, s->p.mu, s->p.relax, l == 1 ? 1 : 0);
+                                                    Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr, A,
+                                                    bod, alpha_dt, s->p.mu, s->p.relax, l == 1 ? 1 : 0, po);
         std::swap(win, wout);
       }
       ggk::k_adj_vbar<<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);
-      ggk::k_geom_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, nc, pt, ps, A, bod, nb, xb, part);
+      ggk::k_geom_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, nc, pt, ps, A, bod, nb, po, xb, part);
       if (nb > 0)
         ggk::k_body_reduce<<<nb * 18, ggk::kBlock, 0, S>>>(grid, nb, part, bgrad + (size_t)st * nb * 18);
       std::swap(xb, xbn);

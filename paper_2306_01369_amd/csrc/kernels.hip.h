@@ -866,7 +866,8 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
 // its contacts' impulses in list order: w_i = w0_i + (1/m_i) sum sigma P_c.
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
-// (the same arrays, or per-sweep arrays when the sweeps are recorded).
+// (the same arrays, or per-sweep arrays when the sweeps are recorded, then
+// indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
 __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __restrict__ x,
                                                 float4* __restrict__ v, const float4* __restrict__ w_in,
                                                 float4* __restrict__ w_out, const int32_t* __restrict__ ncon,
@@ -875,11 +876,13 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
                                                 const float* Piy, const float* Piz, float* Px, float* Py,
                                                 float* Pz, const DevBody* __restrict__ bodies, float gx, float gy,
                                                 float gz, float dt, float alpha_dt, float mu, float relax,
-                                                int mode, float4* __restrict__ dv, const Ctl* ctl) {
+                                                int mode, float4* __restrict__ dv, const int32_t* __restrict__ pofs,
+                                                const Ctl* ctl) {
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   const bool first = mode & 1, last = mode & 2;
+  const int pbase = pofs ? pofs[i] : 0;
   const float4 xi = x[i];
   const float4 vi = v[i];
   const float4 wi = w_in[i];
@@ -887,11 +890,12 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
+    const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
     const int code = partner[slot];
     const float psi = Psi[slot];
     float P0 = 0.f, P1 = 0.f, P2 = 0.f;
     if (!first) {
-      P0 = Pix[slot]; P1 = Piy[slot]; P2 = Piz[slot];
+      P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
     }
     float n0, n1, n2, u0, u1, u2, mt, sg;
     if (code >= 0) {
@@ -938,7 +942,7 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
       Q1 = P1 + relax * (Q1 - P1);
       Q2 = P2 + relax * (Q2 - P2);
     }
-    Px[slot] = Q0; Py[slot] = Q1; Pz[slot] = Q2;
+    Px[ps] = Q0; Py[ps] = Q1; Pz[ps] = Q2;
     a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
   }
   const float im = vi.w;
@@ -987,6 +991,14 @@ __global__ void k_unpermute_i64(int n, const int32_t* __restrict__ orig, const i
                                 int64_t* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) out[orig[k]] = a[k];
+}
+
+// Contact counts of the last detection into per-step slots (differentiable calls).
+__global__ void k_record_counts(const Ctl* __restrict__ ctl, unsigned long long* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = ctl->n_pp;
+    out[1] = ctl->n_pb;
+  }
 }
 
 __global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {

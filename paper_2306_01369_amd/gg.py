@@ -61,7 +61,7 @@ class Stats(C.Structure):
                 ("n_buckets", C.c_int64), ("ms_detect", C.c_double), ("ms_pja", C.c_double),
                 ("ms_integrate", C.c_double), ("pja_launches", C.c_int64),
                 ("contacts_summed", C.c_int64), ("detect_fallback", C.c_int64),
-                ("detect_items", C.c_int64)]
+                ("detect_items", C.c_int64), ("device_bytes_peak", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

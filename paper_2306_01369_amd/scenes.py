@@ -289,6 +289,63 @@ def polydisperse_radii(n, rng, median=0.002, sigma=0.25, lo=0.001, hi=0.004):
     return np.clip(r, lo, hi)
 
 
+def large_scene(seed=0, n=1 << 22, side=2.0):
+    """4,194,304 spheres with lognormal radii (median 2 mm, sigma 0.25, clipped
+    to [1, 4] mm) filling a walled side x side m box, in random index order,
+    with a box tool (0.05 x 0.3 x 0.2 m) and a capsule tool (radius 2 cm, 15 cm
+    between cap centres) above the bed, moving down into it.
+
+    The bed is built to settle within a few tens of steps: the radii are sorted
+    and cut into horizontal layers, each a square lattice whose spacing is
+    2.04 times the largest radius in it (jitter U(+-1.5%) of that radius across,
+    U(+-0.5%) up);
+    the layers are stacked in random order, each 2% of the radius sum above the
+    one below, so the start has no contacts and compacts by grains sinking
+    into the hollows of the layer beneath (falls of at most a few mm)."""
+    rng = np.random.default_rng(seed)
+    rad = np.sort(polydisperse_radii(n, rng))
+    pos = np.zeros((n, 3))
+    layers = []
+    k = 0
+    while k < n:
+        # the layer's largest radius sets its spacing; it only grows as the
+        # layer shrinks, so the loop ends
+        rl = float(rad[k])
+        while True:
+            per_row = int(math.floor((side - 2.0 * rl) / (2.04 * rl))) + 1
+            cnt = min(n - k, per_row * per_row)
+            r_end = float(rad[k + cnt - 1])
+            if r_end <= rl:
+                break
+            rl = r_end
+        layers.append((k, cnt, per_row, 2.04 * rl, rl))
+        k += cnt
+    order = rng.permutation(len(layers))
+    z = 0.0
+    prev_r = 0.0
+    for li in order:
+        k0, cnt, per_row, sp, rl = layers[li]
+        z += (prev_r + rl) * 1.02 if prev_r else rl * 1.02
+        idx = np.arange(cnt)
+        row, col = np.divmod(idx, per_row)
+        o = 0.5 * (side - (per_row - 1) * sp)
+        pos[k0:k0 + cnt, 0] = o + sp * col
+        pos[k0:k0 + cnt, 1] = o + sp * row
+        pos[k0:k0 + cnt, 2] = z
+        pos[k0:k0 + cnt, :2] += rng.uniform(-0.015 * rl, 0.015 * rl, size=(cnt, 2))
+        pos[k0:k0 + cnt, 2] += rng.uniform(-0.005 * rl, 0.005 * rl, size=cnt)
+        prev_r = rl
+    perm = rng.permutation(n)
+    pos, rad = pos[perm], rad[perm]
+    top = z + prev_r
+    box = box_tool((0.6, 1.0, top + 0.11), (0.025, 0.15, 0.1), nu=(0.2, 0.0, -0.3))
+    cap = capsule_tool((1.4, 1.0, top + 0.03), 0.02, 0.075, nu=(-0.2, 0.0, -0.3), omega=(0.0, 1.0, 0.0),
+                       R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
+    bodies = walled_box(0.0, side, 0.0, side) + [box, cap]
+    return Scene(f"large-{n}", _f32(pos), np.zeros((n, 3), np.float32), _f32(rad), bodies, dt=1e-3,
+                 n_iters=64, mu=0.5, alpha=0.2, n_steps=100)
+
+
 def random_spheres(n, box, r, rng, r_jitter=0.0):
     """Uniform random centres in ``box`` = ((x0,x1),(y0,y1),(z0,z1)); radii
     r*(1+U(-r_jitter, r_jitter)).  Used for small brute-force tests."""

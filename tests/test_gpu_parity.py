@@ -382,3 +382,17 @@ def test_tile_and_per_particle_detection_agree_bitwise():
     assert st_t["detect_fallback"] < st_f["detect_fallback"]
     assert st_f["detect_fallback"] == st_f["detect_items"] > 0
     assert tiled == per_particle
+
+
+def test_autotuned_launch_shape_keeps_results_bitwise(tmp_path, monkeypatch):
+    from paper_2306_01369_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    s = scenes.column_scene(n=6000, r=0.004)
+    say("autotune")
+    params = autotune.tune(s.x, s.v, s.radius, s.bodies, steps=2, warmup=1)
+    assert "tile_node_shift" in params
+    again = autotune.tune(s.x, s.v, s.radius, s.bodies)      # from the cache
+    assert again == params
+    ref, _ = _run_bits(s, 15)
+    got, st = _run_bits(s, 15, **params)
+    assert got == ref
