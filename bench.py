@@ -92,21 +92,26 @@ def bench_batched(args):
     import torch
     steps = args.steps if args.steps_given else 100
     log("generating 256 batched environments")
-    sc = scenes.batched_scene(n_steps=steps + args.warmup)
+    sc = scenes.batched_scene(n_steps=max(steps + args.warmup, 8 + args.plain_steps))
     n = sc.n
     tw = np.ascontiguousarray(sc.twists)
-    sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters,
-                 env_offsets=sc.env_offsets, profile=True)
+    kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters, env_offsets=sc.env_offsets)
+    sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, graph=True, **kw)
     if args.warmup:
         sim.step(args.warmup, twists=tw[:args.warmup])
+    # one more call of the timed length captures its launch sequence
+    prof = gg.Sim(sim.read("pos"), sim.read("vel"), sc.radius, sc.bodies, profile=True, **kw)
     torch.cuda.synchronize()
-    log(f"batched: n={n}, timing {steps} steps")
+    log(f"batched: n={n}, timing {steps} steps (one graph launch)")
     t0 = time.perf_counter()
     sim.step(steps, twists=tw[args.warmup:args.warmup + steps])
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
-    st = sim.stats()
     sim.close()
+    # phase split from a profiled copy (events between phases; not the timed run)
+    prof.step(5, twists=tw[args.warmup:args.warmup + 5])
+    st = prof.stats()
+    prof.close()
     # plain loop: every environment its own simulation, stepped in turn
     n_envs = len(sc.env_offsets) - 1
     plain_steps = max(1, min(steps, args.plain_steps))
@@ -116,15 +121,17 @@ def bench_batched(args):
         a, b = int(sc.env_offsets[e]), int(sc.env_offsets[e + 1])
         bodies = [dict(bd, env=0) for bd in sc.bodies[e * nb_env:(e + 1) * nb_env]]
         sims.append((gg.Sim(sc.x[a:b], sc.v[a:b], sc.radius[a:b], bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
-                            n_iters=sc.n_iters), np.ascontiguousarray(tw[:, e * nb_env:(e + 1) * nb_env])))
+                            n_iters=sc.n_iters, graph=True), np.ascontiguousarray(tw[:, e * nb_env:(e + 1) * nb_env])))
+    # one-step calls: eight warm-up calls capture the graph of every re-sort phase
     for sm, t in sims:
-        sm.step(min(args.warmup, 2), twists=t[:min(args.warmup, 2)])
+        for k in range(8):
+            sm.step(1, twists=t[k:k + 1])
     torch.cuda.synchronize()
     log(f"plain loop: {n_envs} sims, timing {plain_steps} steps")
     t0 = time.perf_counter()
     for k in range(plain_steps):
         for sm, t in sims:
-            sm.step(1, twists=t[args.warmup + k:args.warmup + k + 1])
+            sm.step(1, twists=t[8 + k:8 + k + 1])
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) * steps / plain_steps
     for sm, _ in sims:
@@ -137,12 +144,51 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched: 256 walled beds of U{8192..65536} spheres r=3mm, capsule tools with "
                                "random piecewise-constant twists, dt=1 ms, 20 PJA sweeps",
-                   "n": n, "n_envs": n_envs, "plain_loop_steps_timed": plain_steps},
+                   "n": n, "n_envs": n_envs, "plain_loop_steps_timed": plain_steps,
+                   "launch": "whole call as one captured HIP graph; the plain loop replays one graph per "
+                             "environment and step"},
         "speedup_vs_plain_loop": t_plain / t_batched,
         "plain_loop_particle_steps_per_s": n * steps / t_plain,
-        "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
-                               "integrate": st["ms_integrate"] / steps},
+        "phases_ms_per_step_profiled": {"keys_sort_detect": st["ms_detect"] / 5, "pja": st["ms_pja"] / 5,
+                                        "integrate": st["ms_integrate"] / 5},
         "detect_fallback_items": st["detect_fallback"], "detect_items": st["detect_items"],
+    }
+
+
+def bench_drop(args):
+    """4096 spheres dropped into a 0.2 m box (latency-bound): time per step with
+    direct launches and with the captured graph, and launches per step."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    steps = args.steps if args.steps_given else 100
+    sc = scenes.drop_scene()
+    out = {}
+    for mode in ("direct", "graph"):
+        sim = gg.scene_sim(sc, graph=(mode == "graph"))
+        # four warm-up calls visit every (re-sort phase, buffer parity) a call of
+        # 100 steps can start in, so the timed call replays a captured graph
+        for _ in range(4):
+            sim.step(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        out[mode] = (time.perf_counter() - t0) / steps
+        sim.close()
+    I = sc.n_iters
+    launches = 6 + I + 1                     # keys, 3 scans, scatter, detect, sweeps, integrate
+    resort = 1 + 4 * 5 + 1 + 11              # keys, 4 radix passes x 5, permute, work items
+    return {
+        "metric": "drop-pile step latency (4096 spheres, 20 PJA iters)",
+        "value": 1e6 * out["graph"], "unit": "us/step", "n_gpus": 1, "steps": steps, "warmup": 4 * steps,
+        "ms_per_step": 1e3 * out["graph"], "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "drop: 4096 spheres r=5 mm from a 16^3 lattice into a 0.2 m walled box, "
+                               "100 steps from rest", "n": sc.n},
+        "us_per_step_direct_launches": 1e6 * out["direct"],
+        "us_per_step_graph": 1e6 * out["graph"],
+        "launches_per_step": launches,
+        "resort_launches_every_8_steps": resort,
     }
 
 
@@ -227,7 +273,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large"], default="scoop")
+    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop"], default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
@@ -245,8 +291,8 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 200
-    if args.workload in ("batched", "large"):
-        out = bench_batched(args) if args.workload == "batched" else bench_large(args)
+    if args.workload in ("batched", "large", "drop"):
+        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

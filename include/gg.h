@@ -79,6 +79,11 @@ typedef struct {
 #define GG_FLAG_DIAGNOSTICS 2u /* keep the last step's velocity change (GG_FIELD_DV) */
 #define GG_FLAG_TAPE 4u        /* differentiable: keep checkpoints of every gg_step call for
                                   gg_step_backward (one environment only) */
+#define GG_FLAG_GRAPH 8u       /* replay gg_step's launch sequence from a captured HIP graph:
+                                  the first call with a given step count (and re-sort phase)
+                                  captures it, later ones replay it; results are bitwise those
+                                  of direct launches.  Ignored with GG_FLAG_PROFILE or
+                                  GG_FLAG_TAPE. */
 
 /* Simulation parameters.  Zero selects the stated default. */
 typedef struct {
@@ -94,7 +99,9 @@ typedef struct {
   int32_t mass_split;/* 1: per-contact mass m/n_i (mass splitting); 0: plain masses */
   int32_t checkpoint_every;          /* backward pass: steps per checkpoint (0 -> 10) */
   int32_t max_contacts_per_particle; /* 0 -> bound from the radius ratio + bodies */
-  int32_t precision; /* 0 = binary32 (only value supported) */
+  int32_t precision; /* 0: binary32 state and arithmetic; 1: binary64 state and arithmetic
+                        (a check build: contact decisions stay the binary32 predicates on
+                        the state rounded to binary32; inputs and outputs stay float) */
   float density;     /* grain density for m = rho 4/3 pi r^3; 0 -> 2500 */
   uint32_t flags;    /* GG_FLAG_* */
   int32_t reorder_every;  /* steps between re-sorts of the internal particle order along a

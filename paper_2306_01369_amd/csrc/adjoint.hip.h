@@ -21,33 +21,36 @@
 
 namespace ggk {
 
+template <typename R>
 struct AdjSlots {         // per half-contact adjoint state (SoA)
-  float *cx, *cy, *cz;    // carry: adjoint of the impulse of the previous sweep
-  float *nx, *ny, *nz;    // accumulated adjoint of the contact normal (lower-index orientation)
-  float *ps;              // accumulated adjoint of the gap psi
-  float *vx, *vy, *vz;    // accumulated adjoint of the body point velocity V
+  R *cx, *cy, *cz;    // carry: adjoint of the impulse of the previous sweep
+  R *nx, *ny, *nz;    // accumulated adjoint of the contact normal (lower-index orientation)
+  R *ps;              // accumulated adjoint of the gap psi
+  R *vx, *vy, *vz;    // accumulated adjoint of the body point velocity V
 };
 
-__device__ __forceinline__ float dot3f(const float a[3], const float b[3]) {
+template <typename R>
+__device__ __forceinline__ R dot3f(const R a[3], const R b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 // Adjoint of the projection Q = proj(y, n) of the forward sweep, given Qbar.
 // Returns ybar and adds the normal's share to nbar.
-__device__ __forceinline__ void proj_adjoint(const float y[3], const float n[3], float mu, const float Qb[3],
-                                             float yb[3], float nb[3]) {
-  const float yn = dot3f(n, y);
-  float t[3] = {y[0] - yn * n[0], y[1] - yn * n[1], y[2] - yn * n[2]};
-  const float ynp = fmaxf(yn, 0.0f);
-  const float ts = sqrtf(dot3f(t, t));
+template <typename R>
+__device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, const R Qb[3],
+                                             R yb[3], R nb[3]) {
+  const R yn = dot3f(n, y);
+  R t[3] = {y[0] - yn * n[0], y[1] - yn * n[1], y[2] - yn * n[2]};
+  const R ynp = fmax(yn, R(0));
+  const R ts = sqrt(dot3f(t, t));
   const bool scaled = ts > mu * ynp;
-  if (yn <= 0.0f) {
+  if (yn <= R(0)) {
     if (scaled) {  // Q = 0 identically
-      yb[0] = yb[1] = yb[2] = 0.0f;
+      yb[0] = yb[1] = yb[2] = R(0);
       return;
     }
     // Q = y - (n.y) n
-    const float qn = dot3f(Qb, n);
+    const R qn = dot3f(Qb, n);
     for (int a = 0; a < 3; ++a) {
       yb[a] = Qb[a] - qn * n[a];
       nb[a] += -qn * y[a] - yn * Qb[a];
@@ -59,13 +62,13 @@ __device__ __forceinline__ void proj_adjoint(const float y[3], const float n[3],
     return;
   }
   // Q = yn n + mu yn t/|t|
-  const float it = 1.0f / ts;
-  const float th[3] = {t[0] * it, t[1] * it, t[2] * it};
-  const float qt = dot3f(Qb, th);
-  const float k = mu * yn * it;
-  float g[3];
+  const R it = R(1) / ts;
+  const R th[3] = {t[0] * it, t[1] * it, t[2] * it};
+  const R qt = dot3f(Qb, th);
+  const R k = mu * yn * it;
+  R g[3];
   for (int a = 0; a < 3; ++a) g[a] = k * (Qb[a] - qt * th[a]);
-  const float acoef = dot3f(Qb, n) + mu * qt - dot3f(g, n);
+  const R acoef = dot3f(Qb, n) + mu * qt - dot3f(g, n);
   for (int a = 0; a < 3; ++a) {
     yb[a] = g[a] + acoef * n[a];
     nb[a] += yn * (Qb[a] - g[a]) + acoef * y[a];
@@ -75,79 +78,80 @@ __device__ __forceinline__ void proj_adjoint(const float y[3], const float n[3],
 // One reverse sweep: from wbar_in (adjoint of iterate l) to wbar_out (adjoint of
 // iterate l-1).  Recomputes y of sweep l from the recorded impulses P^(l-1) and
 // iterate w^(l-1).  Also accumulates wbar_in into the adjoint of w0.
+template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pja_adj(
-    int n, int K, const float4* __restrict__ x, const float4* __restrict__ v,
-    const float4* __restrict__ w_prev, const float4* __restrict__ wbar_in, float4* __restrict__ wbar_out,
-    float4* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
-    const float* __restrict__ Psi, const float* __restrict__ Ppx, const float* __restrict__ Ppy,
-    const float* __restrict__ Ppz, AdjSlots A, const DevBody* __restrict__ bodies, float alpha_dt, float mu,
-    float relax, int first_sweep, const int32_t* __restrict__ pofs) {
+    int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
+    const V4<R>* __restrict__ w_prev, const V4<R>* __restrict__ wbar_in, V4<R>* __restrict__ wbar_out,
+    V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
+    const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
+    const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
+    R relax, int first_sweep, const int32_t* __restrict__ pofs) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int pbase = pofs[i];
-  const float4 xi = x[i];
-  const float4 vi = v[i];
-  const float4 wi = w_prev[i];
-  const float4 bi = wbar_in[i];
-  float acc[3] = {0.f, 0.f, 0.f};
+  const V4<R> xi = x[i];
+  const V4<R> vi = v[i];
+  const V4<R> wi = w_prev[i];
+  const V4<R> bi = wbar_in[i];
+  R acc[3] = {R(0), R(0), R(0)};
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
     const int q = pbase + k;   // compact index of the recorded impulse and adjoint state
     const int code = partner[slot];
-    const float psi = Psi[slot];
-    float P[3] = {0.f, 0.f, 0.f};
+    const R psi = Psi[slot];
+    R P[3] = {R(0), R(0), R(0)};
     if (!first_sweep) {
       P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
     }
-    float nrm[3], u[3], mt, Pb[3];
-    const float carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
+    R nrm[3], u[3], mt, Pb[3];
+    const R carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
     bool lo = true, body = code < 0;
     if (!body) {
       const int j = code & (kHiFlag - 1);
       lo = (code & kHiFlag) == 0;
-      const float4 xj = x[j];
-      const float4 wj = w_prev[j];
-      const float4 bj = wbar_in[j];
-      const float imj = v[j].w;
-      const float4 xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const float4 wl = lo ? wi : wj, wh = lo ? wj : wi;
-      const float4 bl = lo ? bi : bj, bh = lo ? bj : bi;
-      const float iml = lo ? vi.w : imj, imh = lo ? imj : vi.w;
-      const float d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
-      const float L = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-      if (L > 0.0f) {
-        const float il = 1.0f / L;
+      const V4<R> xj = x[j];
+      const V4<R> wj = w_prev[j];
+      const V4<R> bj = wbar_in[j];
+      const R imj = v[j].w;
+      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
+      const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
+      const V4<R> bl = lo ? bi : bj, bh = lo ? bj : bi;
+      const R iml = lo ? vi.w : imj, imh = lo ? imj : vi.w;
+      const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
+      const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      if (L > R(0)) {
+        const R il = R(1) / L;
         nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
       } else {
-        nrm[0] = 0.f; nrm[1] = 0.f; nrm[2] = 1.f;
+        nrm[0] = R(0); nrm[1] = R(0); nrm[2] = R(1);
       }
       u[0] = wl.x - wh.x; u[1] = wl.y - wh.y; u[2] = wl.z - wh.z;
-      mt = 1.0f / (wl.w + wh.w);
+      mt = R(1) / (wl.w + wh.w);
       Pb[0] = carry[0] + iml * bl.x - imh * bh.x;
       Pb[1] = carry[1] + iml * bl.y - imh * bh.y;
       Pb[2] = carry[2] + iml * bl.z - imh * bh.z;
     } else {
-      float V[3];
-      body_geometry(bodies[-1 - code], xi, psi, nrm, V);
+      R V[3];
+      body_geometry<R>(bodies[-1 - code], xi, psi, nrm, V);
       u[0] = wi.x - V[0]; u[1] = wi.y - V[1]; u[2] = wi.z - V[2];
-      mt = 1.0f / wi.w;
+      mt = R(1) / wi.w;
       Pb[0] = carry[0] + vi.w * bi.x;
       Pb[1] = carry[1] + vi.w * bi.y;
       Pb[2] = carry[2] + vi.w * bi.z;
     }
-    const float bias = alpha_dt * psi;
-    float y[3];
+    const R bias = alpha_dt * psi;
+    R y[3];
     for (int a = 0; a < 3; ++a) y[a] = P[a] - mt * (u[a] + bias * nrm[a]);
-    const float Qb[3] = {relax * Pb[0], relax * Pb[1], relax * Pb[2]};
-    float yb[3], nb[3] = {0.f, 0.f, 0.f};
+    const R Qb[3] = {relax * Pb[0], relax * Pb[1], relax * Pb[2]};
+    R yb[3], nb[3] = {R(0), R(0), R(0)};
     proj_adjoint(y, nrm, mu, Qb, yb, nb);
-    const float keep = 1.0f - relax;
+    const R keep = R(1) - relax;
     A.cx[q] = yb[0] + keep * Pb[0];
     A.cy[q] = yb[1] + keep * Pb[1];
     A.cz[q] = yb[2] + keep * Pb[2];
-    const float ub[3] = {-mt * yb[0], -mt * yb[1], -mt * yb[2]};
-    const float bb = -mt * dot3f(yb, nrm);
+    const R ub[3] = {-mt * yb[0], -mt * yb[1], -mt * yb[2]};
+    const R bb = -mt * dot3f(yb, nrm);
     A.nx[q] += nb[0] - mt * bias * yb[0];
     A.ny[q] += nb[1] - mt * bias * yb[1];
     A.nz[q] += nb[2] - mt * bias * yb[2];
@@ -155,77 +159,81 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     if (body) {
       A.vx[q] -= ub[0]; A.vy[q] -= ub[1]; A.vz[q] -= ub[2];
     }
-    const float sg = lo ? 1.0f : -1.0f;
+    const R sg = lo ? R(1) : R(-1);
     acc[0] += sg * ub[0]; acc[1] += sg * ub[1]; acc[2] += sg * ub[2];
   }
-  wbar_out[i] = make_float4(acc[0], acc[1], acc[2], 0.0f);
-  float4 z = w0bar[i];
+  wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], R(0));
+  V4<R> z = w0bar[i];
   z.x += bi.x; z.y += bi.y; z.z += bi.z;
   w0bar[i] = z;
 }
 
 // Start of the reverse of one step: xbar^k = xbar^{k+1} (positions pass through),
 // wbar^(I) = vbar^{k+1} + dt xbar^{k+1}; clears the per-particle w0 adjoint.
-__global__ __launch_bounds__(kBlock) void k_adj_begin(int n, const float4* __restrict__ xbar_next,
-                                                      const float4* __restrict__ vbar_next, float dt,
-                                                      float4* __restrict__ xbar, float4* __restrict__ wbar,
-                                                      float4* __restrict__ w0bar) {
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_begin(int n, const V4<R>* __restrict__ xbar_next,
+                                                      const V4<R>* __restrict__ vbar_next, R dt,
+                                                      V4<R>* __restrict__ xbar, V4<R>* __restrict__ wbar,
+                                                      V4<R>* __restrict__ w0bar) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const float4 a = xbar_next[i], b = vbar_next[i];
+  const V4<R> a = xbar_next[i], b = vbar_next[i];
   xbar[i] = a;
-  wbar[i] = make_float4(b.x + dt * a.x, b.y + dt * a.y, b.z + dt * a.z, 0.f);
-  w0bar[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  wbar[i] = mk4<R>(b.x + dt * a.x, b.y + dt * a.y, b.z + dt * a.z, R(0));
+  w0bar[i] = mk4<R>(R(0), R(0), R(0), R(0));
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_f(size_t m, float* __restrict__ a) {
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_zero_f(size_t m, R* __restrict__ a) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e < m) a[e] = 0.0f;
+  if (e < m) a[e] = R(0);
 }
 
 // vbar^k = adjoint of w0 (w0 = v + dt g), including the last reverse sweep's output.
-__global__ __launch_bounds__(kBlock) void k_adj_vbar(int n, const float4* __restrict__ w0bar,
-                                                     const float4* __restrict__ wbar0, float4* __restrict__ vbar) {
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_adj_vbar(int n, const V4<R>* __restrict__ w0bar,
+                                                     const V4<R>* __restrict__ wbar0, V4<R>* __restrict__ vbar) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const float4 a = w0bar[i], b = wbar0[i];
-  vbar[i] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, 0.f);
+  const V4<R> a = w0bar[i], b = wbar0[i];
+  vbar[i] = mk4<R>(a.x + b.x, a.y + b.y, a.z + b.z, R(0));
 }
 
 // Body-frame SDF Hessian applied to a vector (symmetric), at the point where
 // the unit gradient g was evaluated (Sec. II-C primitives).
-__device__ __forceinline__ void sdf_hess_apply(const DevBody& B, const float p[3], const float g[3],
-                                               const float in[3], float out[3]) {
-  out[0] = out[1] = out[2] = 0.0f;
+template <typename R>
+__device__ __forceinline__ void sdf_hess_apply(const DevBody& B, const R p[3], const R g[3],
+                                               const R in[3], R out[3]) {
+  out[0] = out[1] = out[2] = R(0);
   if (B.shape == 1) {
-    float q[3], m[3];
+    R q[3], m[3];
     bool outside = false;
     for (int c = 0; c < 3; ++c) {
-      q[c] = fabsf(p[c]) - B.params[c];
-      m[c] = fmaxf(q[c], 0.0f);
-      outside = outside || (q[c] > 0.0f);
+      q[c] = fabs(p[c]) - B.params[c];
+      m[c] = fmax(q[c], R(0));
+      outside = outside || (q[c] > R(0));
     }
     if (!outside) return;
-    const float L = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    const R L = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
     // H = S P_A (I - mh mh^T) P_A S / L,  mh = m / L, S = diag(sign p)
-    float s[3], w[3];
+    R s[3], w[3];
     for (int c = 0; c < 3; ++c) {
-      s[c] = p[c] < 0.0f ? -1.0f : 1.0f;
-      w[c] = q[c] > 0.0f ? s[c] * in[c] : 0.0f;
+      s[c] = p[c] < R(0) ? R(-1) : R(1);
+      w[c] = q[c] > R(0) ? s[c] * in[c] : R(0);
     }
-    const float mh[3] = {m[0] / L, m[1] / L, m[2] / L};
-    const float d = mh[0] * w[0] + mh[1] * w[1] + mh[2] * w[2];
-    for (int c = 0; c < 3; ++c) out[c] = q[c] > 0.0f ? s[c] * (w[c] - d * mh[c]) / L : 0.0f;
+    const R mh[3] = {m[0] / L, m[1] / L, m[2] / L};
+    const R d = mh[0] * w[0] + mh[1] * w[1] + mh[2] * w[2];
+    for (int c = 0; c < 3; ++c) out[c] = q[c] > R(0) ? s[c] * (w[c] - d * mh[c]) / L : R(0);
   } else if (B.shape == 2) {
-    const float h = B.params[1];
-    const float cz = fminf(fmaxf(p[2], -h), h);
-    const float e[3] = {p[0], p[1], p[2] - cz};
-    const float L = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-    if (!(L > 0.0f)) return;
-    const float dz = (p[2] > -h && p[2] < h) ? 0.0f : 1.0f;
+    const R h = B.params[1];
+    const R cz = fmin(fmax(p[2], -h), h);
+    const R e[3] = {p[0], p[1], p[2] - cz};
+    const R L = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!(L > R(0))) return;
+    const R dz = (p[2] > -h && p[2] < h) ? R(0) : R(1);
     // H = D (I - g g^T) D / L, D = diag(1, 1, dz)
-    const float w[3] = {in[0], in[1], dz * in[2]};
-    const float gw = g[0] * w[0] + g[1] * w[1] + g[2] * w[2];
+    const R w[3] = {in[0], in[1], dz * in[2]};
+    const R gw = g[0] * w[0] + g[1] * w[1] + g[2] * w[2];
     out[0] = (w[0] - gw * g[0]) / L;
     out[1] = (w[1] - gw * g[1]) / L;
     out[2] = dz * (w[2] - gw * g[2]) / L;
@@ -233,39 +241,40 @@ __device__ __forceinline__ void sdf_hess_apply(const DevBody& B, const float p[3
 }
 
 // Unit body-frame SDF gradient and value (same branches as the forward).
-__device__ __forceinline__ float sdf_grad(const DevBody& B, const float p[3], float g[3]) {
+template <typename R>
+__device__ __forceinline__ R sdf_grad(const DevBody& B, const R p[3], R g[3]) {
   if (B.shape == 0) {
-    g[0] = 0.f; g[1] = 0.f; g[2] = 1.f;
+    g[0] = R(0); g[1] = R(0); g[2] = R(1);
     return p[2];
   }
   if (B.shape == 1) {
-    float q[3], m[3];
+    R q[3], m[3];
     bool outside = false;
     for (int c = 0; c < 3; ++c) {
-      q[c] = fabsf(p[c]) - B.params[c];
-      m[c] = fmaxf(q[c], 0.0f);
-      outside = outside || (q[c] > 0.0f);
+      q[c] = fabs(p[c]) - B.params[c];
+      m[c] = fmax(q[c], R(0));
+      outside = outside || (q[c] > R(0));
     }
     if (outside) {
-      const float L = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-      for (int c = 0; c < 3; ++c) g[c] = (p[c] < 0.0f ? -1.0f : 1.0f) * m[c] / L;
+      const R L = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      for (int c = 0; c < 3; ++c) g[c] = (p[c] < R(0) ? R(-1) : R(1)) * m[c] / L;
       return L;
     }
     int a = 0;
     if (q[1] > q[a]) a = 1;
     if (q[2] > q[a]) a = 2;
-    g[0] = g[1] = g[2] = 0.f;
-    g[a] = p[a] < 0.0f ? -1.0f : 1.0f;
+    g[0] = g[1] = g[2] = R(0);
+    g[a] = p[a] < R(0) ? R(-1) : R(1);
     return q[a];
   }
-  const float h = B.params[1];
-  const float cz = fminf(fmaxf(p[2], -h), h);
-  const float e[3] = {p[0], p[1], p[2] - cz};
-  const float L = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-  if (L > 0.0f) {
+  const R h = B.params[1];
+  const R cz = fmin(fmax(p[2], -h), h);
+  const R e[3] = {p[0], p[1], p[2] - cz};
+  const R L = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  if (L > R(0)) {
     for (int c = 0; c < 3; ++c) g[c] = e[c] / L;
   } else {
-    g[0] = 1.f; g[1] = 0.f; g[2] = 0.f;
+    g[0] = R(1); g[1] = R(0); g[2] = R(0);
   }
   return L - B.params[0];
 }
@@ -274,19 +283,20 @@ __device__ __forceinline__ float sdf_grad(const DevBody& B, const float p[3], fl
 // body-velocity adjoints of every half contact; body pose and twist adjoints
 // reduced per workgroup and body (LDS tree, fixed order) into
 // part[block][body][18] = (nu, omega, R row-major, t).
-__global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4* __restrict__ x,
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* __restrict__ x,
                                                      const int32_t* __restrict__ ncon,
                                                      const int32_t* __restrict__ partner,
-                                                     const float* __restrict__ Psi, AdjSlots A,
+                                                     const R* __restrict__ Psi, AdjSlots<R> A,
                                                      const DevBody* __restrict__ bodies, int n_bodies,
-                                                     const int32_t* __restrict__ pofs, float4* __restrict__ xbar,
-                                                     float* __restrict__ part) {
-  __shared__ float red[kBlock];
+                                                     const int32_t* __restrict__ pofs, V4<R>* __restrict__ xbar,
+                                                     R* __restrict__ part) {
+  __shared__ R red[kBlock];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
-  float4 xi = make_float4(0.f, 0.f, 0.f, 0.f);
+  V4<R> xi = mk4<R>(R(0), R(0), R(0), R(0));
   int c = 0;
-  float xb[3] = {0.f, 0.f, 0.f};
+  R xb[3] = {R(0), R(0), R(0)};
   if (active) {
     xi = x[i];
     c = ncon[i];
@@ -296,73 +306,76 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
       if (code < 0) continue;
       const int j = code & (kHiFlag - 1);
       const bool lo = (code & kHiFlag) == 0;
-      const float4 xj = x[j];
-      const float4 xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const float d[3] = {xl.x - xh.x, xl.y - xh.y, xl.z - xh.z};
-      const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (!(L > 0.0f)) continue;
-      const float nr[3] = {d[0] / L, d[1] / L, d[2] / L};
+      const V4<R> xj = x[j];
+      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
+      const R d[3] = {xl.x - xh.x, xl.y - xh.y, xl.z - xh.z};
+      const R L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(L > R(0))) continue;
+      const R nr[3] = {d[0] / L, d[1] / L, d[2] / L};
       const int q = pofs[i] + k;
-      const float nb[3] = {A.nx[q], A.ny[q], A.nz[q]};
-      const float psb = A.ps[q];
-      const float nn = dot3f(nr, nb);
-      const float sg = lo ? 1.0f : -1.0f;
+      const R nb[3] = {A.nx[q], A.ny[q], A.nz[q]};
+      const R psb = A.ps[q];
+      const R nn = dot3f(nr, nb);
+      const R sg = lo ? R(1) : R(-1);
       for (int a = 0; a < 3; ++a) xb[a] += sg * ((nb[a] - nn * nr[a]) / L + psb * nr[a]);
     }
   }
   // body contacts: one pass per body so the block reduction has a fixed order
   for (int b = 0; b < n_bodies; ++b) {
-    float acc[18];
-    for (int q = 0; q < 18; ++q) acc[q] = 0.f;
+    R acc[18];
+    for (int q = 0; q < 18; ++q) acc[q] = R(0);
     const DevBody& B = bodies[b];
+    const auto* BR = PoseOf<R>::R(B);
+    const auto* Bt = PoseOf<R>::t(B);
+    const auto* Bom = PoseOf<R>::om(B);
     if (active) {
       for (int k = 0; k < c; ++k) {
         const int slot = ell_slot(i, k, K);
         if (partner[slot] != -1 - b) continue;
-        float pnt[3];
+        R pnt[3];
         {
-          const float dd[3] = {xi.x - B.t[0], xi.y - B.t[1], xi.z - B.t[2]};
-          for (int cc = 0; cc < 3; ++cc) pnt[cc] = B.R[cc] * dd[0] + B.R[3 + cc] * dd[1] + B.R[6 + cc] * dd[2];
+          const R dd[3] = {xi.x - Bt[0], xi.y - Bt[1], xi.z - Bt[2]};
+          for (int cc = 0; cc < 3; ++cc) pnt[cc] = BR[cc] * dd[0] + BR[3 + cc] * dd[1] + BR[6 + cc] * dd[2];
         }
-        float g[3];
+        R g[3];
         sdf_grad(B, pnt, g);
-        float nr[3];
-        for (int r = 0; r < 3; ++r) nr[r] = B.R[3 * r] * g[0] + B.R[3 * r + 1] * g[1] + B.R[3 * r + 2] * g[2];
-        const float psi = Psi[slot];
-        const float f = psi + xi.w;
-        const float a[3] = {xi.x - f * nr[0] - B.t[0], xi.y - f * nr[1] - B.t[1], xi.z - f * nr[2] - B.t[2]};
+        R nr[3];
+        for (int r = 0; r < 3; ++r) nr[r] = BR[3 * r] * g[0] + BR[3 * r + 1] * g[1] + BR[3 * r + 2] * g[2];
+        const R psi = Psi[slot];
+        const R f = psi + xi.w;
+        const R a[3] = {xi.x - f * nr[0] - Bt[0], xi.y - f * nr[1] - Bt[1], xi.z - f * nr[2] - Bt[2]};
         const int qq = pofs[i] + k;
-        const float Vb[3] = {A.vx[qq], A.vy[qq], A.vz[qq]};
-        const float nb[3] = {A.nx[qq], A.ny[qq], A.nz[qq]};
-        const float psb = A.ps[qq];
+        const R Vb[3] = {A.vx[qq], A.vy[qq], A.vz[qq]};
+        const R nb[3] = {A.nx[qq], A.ny[qq], A.nz[qq]};
+        const R psb = A.ps[qq];
         // V = nu + om x a
         acc[0] += Vb[0]; acc[1] += Vb[1]; acc[2] += Vb[2];
         acc[3] += a[1] * Vb[2] - a[2] * Vb[1];
         acc[4] += a[2] * Vb[0] - a[0] * Vb[2];
         acc[5] += a[0] * Vb[1] - a[1] * Vb[0];
-        const float om[3] = {B.om[0], B.om[1], B.om[2]};
-        const float ab[3] = {Vb[1] * om[2] - Vb[2] * om[1], Vb[2] * om[0] - Vb[0] * om[2],
+        const R om[3] = {Bom[0], Bom[1], Bom[2]};
+        const R ab[3] = {Vb[1] * om[2] - Vb[2] * om[1], Vb[2] * om[0] - Vb[0] * om[2],
                              Vb[0] * om[1] - Vb[1] * om[0]};
         // a = pc - t, pc = x - f n
-        float tb[3] = {-ab[0], -ab[1], -ab[2]};
+        R tb[3] = {-ab[0], -ab[1], -ab[2]};
         for (int q = 0; q < 3; ++q) xb[q] += ab[q];
-        const float fb = psb - dot3f(nr, ab);
-        float ntot[3];
+        const R fb = psb - dot3f(nr, ab);
+        R ntot[3];
         for (int q = 0; q < 3; ++q) ntot[q] = nb[q] - f * ab[q];
         // n = R g
-        float Rb[9];
-        float gb[3];
-        for (int q = 0; q < 3; ++q) gb[q] = B.R[q] * ntot[0] + B.R[3 + q] * ntot[1] + B.R[6 + q] * ntot[2];
+        R Rb[9];
+        R gb[3];
+        for (int q = 0; q < 3; ++q) gb[q] = BR[q] * ntot[0] + BR[3 + q] * ntot[1] + BR[6 + q] * ntot[2];
         for (int r = 0; r < 3; ++r)
           for (int q = 0; q < 3; ++q) Rb[3 * r + q] = ntot[r] * g[q];
         // g = grad F(p), f = F(p)
-        float pb[3];
+        R pb[3];
         sdf_hess_apply(B, pnt, g, gb, pb);
         for (int q = 0; q < 3; ++q) pb[q] += fb * g[q];
         // p = R^T (x - t)
-        float Rp[3];
-        for (int r = 0; r < 3; ++r) Rp[r] = B.R[3 * r] * pb[0] + B.R[3 * r + 1] * pb[1] + B.R[3 * r + 2] * pb[2];
-        const float dd[3] = {xi.x - B.t[0], xi.y - B.t[1], xi.z - B.t[2]};
+        R Rp[3];
+        for (int r = 0; r < 3; ++r) Rp[r] = BR[3 * r] * pb[0] + BR[3 * r + 1] * pb[1] + BR[3 * r + 2] * pb[2];
+        const R dd[3] = {xi.x - Bt[0], xi.y - Bt[1], xi.z - Bt[2]};
         for (int q = 0; q < 3; ++q) {
           xb[q] += Rp[q];
           tb[q] -= Rp[q];
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
     }
   }
   if (active) {
-    float4 z = xbar[i];
+    V4<R> z = xbar[i];
     z.x += xb[0]; z.y += xb[1]; z.z += xb[2];
     xbar[i] = z;
   }
@@ -393,12 +406,13 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const float4*
 
 // out[b][q] = sum over blocks of part[block][b][q], fixed order (one block per
 // (body, component)).
-__global__ __launch_bounds__(kBlock) void k_body_reduce(int nblocks, int n_bodies, const float* __restrict__ part,
-                                                        float* __restrict__ out) {
-  __shared__ float red[kBlock];
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_body_reduce(int nblocks, int n_bodies, const R* __restrict__ part,
+                                                        R* __restrict__ out) {
+  __shared__ R red[kBlock];
   const int bq = blockIdx.x;  // b * 18 + q
   const int b = bq / 18, q = bq % 18;
-  float s = 0.f;
+  R s = R(0);
   for (int k = threadIdx.x; k < nblocks; k += kBlock) s += part[((size_t)k * n_bodies + b) * 18 + q];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -410,12 +424,13 @@ __global__ __launch_bounds__(kBlock) void k_body_reduce(int nblocks, int n_bodie
 }
 
 // caller order <-> internal order for adjoint vectors
+template <typename R>
 __global__ void k_gather3(int n, const int32_t* __restrict__ orig, const float* __restrict__ in3,
-                          float4* __restrict__ out) {
+                          V4<R>* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int o = orig[k];
-  out[k] = in3 ? make_float4(in3[3 * o], in3[3 * o + 1], in3[3 * o + 2], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+  out[k] = in3 ? mk4<R>((R)in3[3 * o], (R)in3[3 * o + 1], (R)in3[3 * o + 2], R(0)) : mk4<R>(R(0), R(0), R(0), R(0));
 }
 
 }  // namespace ggk

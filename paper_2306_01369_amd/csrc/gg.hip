@@ -84,11 +84,17 @@ ggk::DevBody to_dev(const HostBody& B) {
   d.shape = B.shape;
   d.env = B.env;
   for (int q = 0; q < 4; ++q) d.params[q] = B.params[q];
-  for (int q = 0; q < 9; ++q) d.R[q] = (float)B.R[q];
+  for (int q = 0; q < 9; ++q) {
+    d.R[q] = (float)B.R[q];
+    d.Rd[q] = B.R[q];
+  }
   for (int q = 0; q < 3; ++q) {
     d.t[q] = (float)B.t[q];
     d.nu[q] = (float)B.nu[q];
     d.om[q] = (float)B.om[q];
+    d.td[q] = B.t[q];
+    d.nud[q] = B.nu[q];
+    d.omd[q] = B.om[q];
   }
   return d;
 }
@@ -98,6 +104,11 @@ hipError_t dev_alloc(T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
   return hipMalloc((void**)p, count * sizeof(T));
+}
+
+hipError_t dev_alloc_bytes(void** p, size_t bytes) {
+  *p = nullptr;
+  return hipMalloc(p, bytes == 0 ? 16 : bytes);
 }
 
 }  // namespace
@@ -121,22 +132,25 @@ struct gg_sim {
   std::vector<HostBody> bodies;
   std::vector<int32_t> body_lo, body_hi;
 
-  // device buffers
-  float4 *x = nullptr, *v = nullptr, *wa = nullptr, *wb = nullptr, *dv = nullptr;
-  float4 *x2 = nullptr, *v2 = nullptr;                 // permutation targets
+  // device buffers.  Real-valued state is V4<R> / R of the build's precision
+  // (fp64: double), so those buffers are untyped here.
+  bool fp64 = false;
+  size_t es = 4, es4 = 16;                             // bytes of R and of V4<R>
+  void *x = nullptr, *v = nullptr, *wa = nullptr, *wb = nullptr, *dv = nullptr;
+  void *x2 = nullptr, *v2 = nullptr;                   // permutation targets
   int32_t *orig = nullptr, *orig2 = nullptr;            // caller index of each internal slot
   unsigned long long *mk[2] = {nullptr, nullptr};      // Z-order keys (radix ping-pong)
   int32_t *mv[2] = {nullptr, nullptr};                 // permutation values
   int32_t *rs_hist = nullptr, *rs_bsum = nullptr;      // radix histograms and their scan
   int rs_nb = 0, rs_passes = 0;
-  float4* xs = nullptr;                                // bucket-ordered positions
+  void* xs = nullptr;                                  // bucket-ordered positions
   int32_t* os = nullptr;                               // bucket-ordered original indices
   int32_t *it_f = nullptr, *it_e = nullptr, *it_first = nullptr, *it_g = nullptr, *it_h = nullptr;
   int32_t *item_start = nullptr, *it_bsum = nullptr;
   int64_t steps_global = 0;
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
-  float *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
+  void *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
   int32_t *env_of = nullptr, *d_env_nh = nullptr, *d_env_boff = nullptr, *d_body_lo = nullptr,
           *d_body_hi = nullptr;
   ggk::DevBody* d_bodies = nullptr;
@@ -157,11 +171,25 @@ struct gg_sim {
   int tape_steps = 0;
   std::vector<HostBody> tape_poses;   // (steps + 1) x bodies, double precision
   std::vector<float> tape_twists;     // steps x bodies x 6
-  float4* ck = nullptr;               // checkpoints: per segment x then v
+  void* ck = nullptr;                 // checkpoints: per segment x then v (V4<R>)
   size_t ck_cap = 0;
   unsigned long long* d_counts = nullptr;  // per step (pairs, body contacts) of a differentiable call
   size_t d_counts_cap = 0;
   std::vector<unsigned long long> tape_counts;
+  // captured launch sequences of gg_step (GG_FLAG_GRAPH)
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int n_steps = 0, nb = 0;
+    int64_t phase = 0;
+    uint64_t epoch = 0;
+    void *x0 = nullptr, *x1 = nullptr, *v1 = nullptr;
+    int32_t* o1 = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<Graph> graphs;
+  uint64_t epoch = 1;  // bumped whenever a buffer a captured launch names is reallocated
+  uint64_t graph_clock = 0;
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -198,9 +226,10 @@ gg_status check_params(const gg_params* p) {
   if (p->checkpoint_every < 0) return fail(GG_ERR_INVALID, "checkpoint_every must be >= 0");
   if (p->max_contacts_per_particle < 0 || p->max_contacts_per_particle > 256)
     return fail(GG_ERR_INVALID, "max_contacts_per_particle must be in [0, 256]");
-  if (p->precision != 0) return fail(GG_ERR_UNSUPPORTED, "only precision 0 (binary32) is built");
+  if (p->precision != 0 && p->precision != 1) return fail(GG_ERR_INVALID, "precision must be 0 or 1");
   if (!(p->density >= 0.0f) || !std::isfinite(p->density)) return fail(GG_ERR_INVALID, "density must be finite and >= 0");
-  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS | GG_FLAG_TAPE)) return fail(GG_ERR_INVALID, "unknown flag bits");
+  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS | GG_FLAG_TAPE | GG_FLAG_GRAPH))
+    return fail(GG_ERR_INVALID, "unknown flag bits");
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
@@ -226,13 +255,14 @@ gg_status ensure_ell(gg_sim* s, int K) {
   (void)hipFree(s->Psi);
   s->partner = nullptr; s->Px = s->Py = s->Pz = s->Psi = nullptr;
   size_t slots = (size_t)s->n_pad * (size_t)K;
-  if (dev_alloc(&s->partner, slots) != hipSuccess || dev_alloc(&s->Px, slots) != hipSuccess ||
-      dev_alloc(&s->Py, slots) != hipSuccess || dev_alloc(&s->Pz, slots) != hipSuccess ||
-      dev_alloc(&s->Psi, slots) != hipSuccess)
+  if (dev_alloc(&s->partner, slots) != hipSuccess || dev_alloc_bytes(&s->Px, slots * s->es) != hipSuccess ||
+      dev_alloc_bytes(&s->Py, slots * s->es) != hipSuccess || dev_alloc_bytes(&s->Pz, slots * s->es) != hipSuccess ||
+      dev_alloc_bytes(&s->Psi, slots * s->es) != hipSuccess)
     return fail(GG_ERR_OOM, "contact table allocation failed");
   s->K = K;
   s->stats.capacity = K;
   s->contacts_valid = false;
+  ++s->epoch;
   sample_memory(s);
   return GG_OK;
 }
@@ -268,6 +298,9 @@ void free_all(gg_sim* s) {
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   s->events.clear();
+  for (auto& G : s->graphs) (void)hipGraphExecDestroy(G.exec);
+  s->graphs.clear();
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -305,44 +338,48 @@ gg_status upload_env_bodies(gg_sim* s) {
 // iterate after sweep l (w[0] from detection); P*[l] (l = 1..I) the impulses of
 // sweep l.  The plain step alternates two iterate buffers and updates one
 // impulse array in place; the recorded step (for the adjoint) keeps all.
+template <typename R>
 struct StepIO {
-  float4* x;
-  float4* v;
+  ggk::V4<R>* x;
+  ggk::V4<R>* v;
   int32_t* ncon;
   int32_t* partner;
-  float* Psi;
-  std::vector<float4*> w;
-  std::vector<float*> Px, Py, Pz;
-  float4* dv;
+  R* Psi;
+  std::vector<ggk::V4<R>*> w;
+  std::vector<R*> Px, Py, Pz;
+  ggk::V4<R>* dv;
   int32_t* pofs = nullptr;  // compact impulse offsets (recorded steps), else ELL slots
 };
 
-StepIO plain_io(gg_sim* s) {
-  StepIO io;
-  io.x = s->x;
-  io.v = s->v;
+template <typename R>
+StepIO<R> plain_io(gg_sim* s) {
+  StepIO<R> io;
+  io.x = (ggk::V4<R>*)s->x;
+  io.v = (ggk::V4<R>*)s->v;
   io.ncon = s->ncon;
   io.partner = s->partner;
-  io.Psi = s->Psi;
+  io.Psi = (R*)s->Psi;
   const int I = s->p.n_iters;
   io.w.resize(I + 1);
-  io.Px.assign(I + 1, s->Px);
-  io.Py.assign(I + 1, s->Py);
-  io.Pz.assign(I + 1, s->Pz);
-  for (int l = 0; l <= I; ++l) io.w[l] = (l & 1) ? s->wb : s->wa;
-  io.dv = s->dv;
+  io.Px.assign(I + 1, (R*)s->Px);
+  io.Py.assign(I + 1, (R*)s->Py);
+  io.Pz.assign(I + 1, (R*)s->Pz);
+  for (int l = 0; l <= I; ++l) io.w[l] = (ggk::V4<R>*)((l & 1) ? s->wb : s->wa);
+  io.dv = (ggk::V4<R>*)s->dv;
   return io;
 }
 
 // Z-order re-sort of the internal particle order and rebuild of the detection
 // work items (memory locality only; results do not depend on it).
+template <typename R>
 void launch_reorder(gg_sim* s) {
+  using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int rs_m = 256 * s->rs_nb;
   const int rs_nbs = (rs_m + ggk::kScanTile - 1) / ggk::kScanTile;
   hipStream_t S = s->stream;
-  ggk::k_morton_keys<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->inv_c, s->env_of, s->mk[0]);
+  ggk::k_morton_keys<R><<<grid, ggk::kBlock, 0, S>>>(n, (const V*)s->x, s->inv_c, s->env_of, s->mk[0]);
   for (int pass = 0; pass < s->rs_passes; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
@@ -352,8 +389,8 @@ void launch_reorder(gg_sim* s) {
     ggk::k_rs_scatter<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass == 0 ? nullptr : s->mv[src], s->mk[dst],
                                                          s->mv[dst], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
   }
-  ggk::k_permute<<<grid, ggk::kBlock, 0, S>>>(n, s->mv[s->rs_passes & 1], s->x, s->v, s->orig, s->x2, s->v2,
-                                              s->orig2);
+  ggk::k_permute<R><<<grid, ggk::kBlock, 0, S>>>(n, s->mv[s->rs_passes & 1], (const V*)s->x, (const V*)s->v,
+                                                 s->orig, (V*)s->x2, (V*)s->v2, s->orig2);
   std::swap(s->x, s->x2);
   std::swap(s->v, s->v2);
   std::swap(s->orig, s->orig2);
@@ -372,8 +409,16 @@ void launch_reorder(gg_sim* s) {
   ggk::k_copy_i32<<<1, 64, 0, S>>>(s->it_h + n, &s->ctl->items);
 }
 
+// Bytes of dynamic LDS of a detection tile.
+size_t detect_lds_bytes(const gg_sim* s) {
+  const size_t max_cells = (size_t)s->p.tile_max_cells, max_stage = (size_t)s->p.tile_max_stage;
+  return (((2 * max_cells + 1) * 4 + 31) & ~(size_t)31) + max_stage * (s->es4 + 4 + 4);
+}
+
 // Bucket table and contact detection of one step.
-void launch_detect(gg_sim* s, const StepIO& io, int st, const ggk::DevBody* bod) {
+template <typename R>
+void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod) {
+  using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int nb = (int)s->bodies.size();
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
@@ -381,37 +426,148 @@ void launch_detect(gg_sim* s, const StepIO& io, int st, const ggk::DevBody* bod)
   const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
   const int dgrid = std::max(1, std::min((n + 31) / 32, 2048));
   const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
-  const size_t dlds = ((((size_t)2 * max_cells + 1) * 4 + 15) & ~(size_t)15) + (size_t)max_stage * (16 + 4 + 4);
+  const size_t dlds = detect_lds_bytes(s);
   const ggk::EnvTables et = env_tables(s);
   const int nh1 = s->env_nh[0];
   hipStream_t S = s->stream;
-  ggk::k_key<<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
+  ggk::k_key<R><<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
   ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
   ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
-  ggk::k_scatter<<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, s->xs, s->os);
-  ggk::k_detect<<<dgrid, ggk::kDetBlock, dlds, S>>>(n, s->K, io.x, io.v, s->orig, s->inv_c, nh1, et, s->bstart,
-                                                     s->sidx, s->xs, s->os, s->item_start, &s->ctl->items, bod, nb,
-                                                     s->p.gravity[0], s->p.gravity[1], s->p.gravity[2], s->p.dt,
-                                                     s->p.mass_split, max_cells, max_stage, io.ncon, io.partner,
-                                                     io.Psi, io.w[0], s->ctl, st);
+  ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
+                                                 s->os);
+  ggk::k_detect<R><<<dgrid, ggk::kDetBlock, dlds, S>>>(
+      n, s->K, io.x, io.v, s->orig, s->inv_c, nh1, et, s->bstart, s->sidx, (const V*)s->xs, s->os, s->item_start,
+      &s->ctl->items, bod, nb, (R)s->p.gravity[0], (R)s->p.gravity[1], (R)s->p.gravity[2], (R)s->p.dt,
+      s->p.mass_split, max_cells, max_stage, io.ncon, io.partner, io.Psi, io.w[0], s->ctl, st);
 }
 
 // The projected-Jacobi sweeps of one step (the last one writes the velocity).
-void launch_sweeps(gg_sim* s, const StepIO& io, const ggk::DevBody* bod) {
+template <typename R>
+void launch_sweeps(gg_sim* s, const StepIO<R>& io, const ggk::DevBody* bod) {
   const int n = (int)s->n;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int I = s->p.n_iters;
-  const float alpha_dt = s->p.alpha / s->p.dt;
+  const R alpha_dt = (R)s->p.alpha / (R)s->p.dt;
   for (int it = 0; it < I; ++it) {
     const int l = it + 1;
     const int mode = (it == 0 ? 1 : 0) | (it == I - 1 ? 2 : 0);
-    ggk::k_pja<<<grid, ggk::kBlock, 0, s->stream>>>(
+    ggk::k_pja<R><<<grid, ggk::kBlock, 0, s->stream>>>(
         n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
-        io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, s->p.gravity[0], s->p.gravity[1], s->p.gravity[2],
-        s->p.dt, alpha_dt, s->p.mu, s->p.relax, mode, io.dv, io.pofs, s->ctl);
+        io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
+        (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
   }
 }
+
+// Enqueue the launches of n_steps steps on s->stream (eager or under capture).
+template <typename R>
+gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof) {
+  using V = ggk::V4<R>;
+  const int n = (int)s->n;
+  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
+  const R dt = (R)s->p.dt;
+  hipStream_t S = s->stream;
+  ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
+  for (int st = 0; st < n_steps && n > 0; ++st) {
+    const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st], S));
+    const int64_t g = s->steps_global + st;
+    // a differentiable call keeps one internal order throughout (re-sorted only at its start)
+    if (s->p.reorder_every > 0 && (taped ? st == 0 : g % s->p.reorder_every == 0)) launch_reorder<R>(s);
+    if (taped && st % s->p.checkpoint_every == 0) {
+      V* ckx = (V*)s->ck + (size_t)(st / s->p.checkpoint_every) * 2 * n;
+      HIPCHK(s, hipMemcpyAsync(ckx, s->x, (size_t)n * sizeof(V), hipMemcpyDeviceToDevice, S));
+      HIPCHK(s, hipMemcpyAsync(ckx + n, s->v, (size_t)n * sizeof(V), hipMemcpyDeviceToDevice, S));
+    }
+    const StepIO<R> io = plain_io<R>(s);
+    launch_detect<R>(s, io, st, bod);
+    if (taped) ggk::k_record_counts<<<1, 64, 0, S>>>(s->ctl, s->d_counts + 2 * (size_t)st);
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
+    launch_sweeps<R>(s, io, bod);
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
+    ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, (V*)s->x, (const V*)s->v, dt, s->ctl);
+    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
+  }
+  return GG_OK;
+}
+
+gg_status enqueue_steps(gg_sim* s, int n_steps, int nb, bool taped, bool prof) {
+  return s->fp64 ? enqueue_steps_t<double>(s, n_steps, nb, taped, prof)
+                 : enqueue_steps_t<float>(s, n_steps, nb, taped, prof);
+}
+
+// Replay (capturing first if needed) the launch sequence of n_steps steps.  A
+// capture is keyed by everything its launches name that can change between
+// calls: the step count, the re-sort phase, which of the two state buffers is
+// current, the body count and the allocation epoch.
+gg_status launch_graphed(gg_sim* s, int n_steps, int nb) {
+  const int64_t R = s->p.reorder_every;
+  const int64_t phase = R > 0 ? s->steps_global % R : 0;
+  gg_sim::Graph* hit = nullptr;
+  for (auto& G : s->graphs)
+    if (G.n_steps == n_steps && G.phase == phase && G.x0 == s->x && G.nb == nb && G.epoch == s->epoch) hit = &G;
+  if (!hit) {
+    if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    gg_sim::Graph G;
+    G.n_steps = n_steps;
+    G.phase = phase;
+    G.x0 = s->x;
+    G.nb = nb;
+    G.epoch = s->epoch;
+    void *x0 = s->x, *v0 = s->v;
+    int32_t* o0 = s->orig;
+    hipStream_t user = s->stream;
+    s->stream = s->cap_stream;
+    hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+    gg_status st = GG_OK;
+    if (e == hipSuccess) st = enqueue_steps(s, n_steps, nb, false, false);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &graph);
+    s->stream = user;
+    G.x1 = s->x;
+    G.v1 = s->v;
+    G.o1 = s->orig;
+    // nothing ran: restore the pointer state the capture walked through
+    s->x = x0;
+    s->v = v0;
+    s->orig = o0;
+    if (s->x != G.x1) {
+      s->x2 = G.x1;
+      s->v2 = G.v1;
+      s->orig2 = G.o1;
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
+    if (st != GG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiateWithFlags(&G.exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+    if (s->graphs.size() >= 8) {
+      size_t old = 0;
+      for (size_t k = 1; k < s->graphs.size(); ++k)
+        if (s->graphs[k].used < s->graphs[old].used) old = k;
+      (void)hipGraphExecDestroy(s->graphs[old].exec);
+      s->graphs.erase(s->graphs.begin() + (long)old);
+    }
+    s->graphs.push_back(G);
+    hit = &s->graphs.back();
+  }
+  hit->used = ++s->graph_clock;
+  HIPCHK(s, hipGraphLaunch(hit->exec, s->stream));
+  if (hit->x1 != s->x) {
+    std::swap(s->x, s->x2);
+    std::swap(s->v, s->v2);
+    std::swap(s->orig, s->orig2);
+  }
+  return GG_OK;
+}
+
+template <typename R>
+gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* dL_dx0, float* dL_dv0,
+                     float* dL_dtwists, gg_mem where);
 
 }  // namespace
 
@@ -514,6 +670,9 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     s->rs_passes = (bits + ggk::kRsBits - 1) / ggk::kRsBits;
     s->rs_nb = (int)((n + ggk::kRsItems - 1) / ggk::kRsItems);
   }
+  s->fp64 = s->p.precision == 1;
+  s->es = s->fp64 ? 8 : 4;
+  s->es4 = 4 * s->es;
   s->dev = params->device;
   s->n = n;
   s->n_envs = n_envs;
@@ -547,26 +706,27 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     s->own_stream = true;
   }
   const size_t N = (size_t)std::max<int64_t>(n, 1);
-  bool ok = dev_alloc(&s->x, N) == hipSuccess && dev_alloc(&s->v, N) == hipSuccess &&
-            dev_alloc(&s->wa, N) == hipSuccess && dev_alloc(&s->wb, N) == hipSuccess &&
+  const size_t N4 = N * s->es4;
+  bool ok = dev_alloc_bytes(&s->x, N4) == hipSuccess && dev_alloc_bytes(&s->v, N4) == hipSuccess &&
+            dev_alloc_bytes(&s->wa, N4) == hipSuccess && dev_alloc_bytes(&s->wb, N4) == hipSuccess &&
             dev_alloc(&s->h, N) == hipSuccess && dev_alloc(&s->rank, N) == hipSuccess &&
             dev_alloc(&s->counts, (size_t)total) == hipSuccess &&
             dev_alloc(&s->bstart, (size_t)total + 1) == hipSuccess &&
             dev_alloc(&s->bsum, (size_t)(total + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
             dev_alloc(&s->sidx, N) == hipSuccess && dev_alloc(&s->ncon, N) == hipSuccess &&
-            dev_alloc(&s->ctl, 1) == hipSuccess && dev_alloc(&s->x2, N) == hipSuccess &&
-            dev_alloc(&s->v2, N) == hipSuccess && dev_alloc(&s->orig, N) == hipSuccess &&
+            dev_alloc(&s->ctl, 1) == hipSuccess && dev_alloc_bytes(&s->x2, N4) == hipSuccess &&
+            dev_alloc_bytes(&s->v2, N4) == hipSuccess && dev_alloc(&s->orig, N) == hipSuccess &&
             dev_alloc(&s->orig2, N) == hipSuccess && dev_alloc(&s->mk[0], N) == hipSuccess &&
             dev_alloc(&s->mk[1], N) == hipSuccess && dev_alloc(&s->mv[0], N) == hipSuccess &&
             dev_alloc(&s->mv[1], N) == hipSuccess &&
             dev_alloc(&s->rs_hist, (size_t)256 * std::max(1, s->rs_nb) + 1) == hipSuccess &&
             dev_alloc(&s->rs_bsum, (size_t)(256 * std::max(1, s->rs_nb) + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
-            dev_alloc(&s->xs, N) == hipSuccess && dev_alloc(&s->os, N) == hipSuccess &&
+            dev_alloc_bytes(&s->xs, N4) == hipSuccess && dev_alloc(&s->os, N) == hipSuccess &&
             dev_alloc(&s->it_f, N + 1) == hipSuccess && dev_alloc(&s->it_e, N + 1) == hipSuccess &&
             dev_alloc(&s->it_first, N + 1) == hipSuccess && dev_alloc(&s->it_g, N + 1) == hipSuccess &&
             dev_alloc(&s->it_h, N + 1) == hipSuccess && dev_alloc(&s->item_start, N + 2) == hipSuccess &&
             dev_alloc(&s->it_bsum, (N + 1 + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess;
-  if (ok && (s->p.flags & GG_FLAG_DIAGNOSTICS)) ok = dev_alloc(&s->dv, N) == hipSuccess;
+  if (ok && (s->p.flags & GG_FLAG_DIAGNOSTICS)) ok = dev_alloc_bytes(&s->dv, N4) == hipSuccess;
   if (ok && n_envs > 1) {
     ok = dev_alloc(&s->env_of, N) == hipSuccess && dev_alloc(&s->d_env_nh, (size_t)n_envs) == hipSuccess &&
          dev_alloc(&s->d_env_boff, (size_t)n_envs) == hipSuccess &&
@@ -578,18 +738,26 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     return bail(fail(GG_ERR_OOM, "pinned allocation failed"));
 
   // ---- upload state: x = (x, r), v = (v, 1/m)
-  std::vector<float4> hx4(N), hv4(N);
+  std::vector<float4> hx4(s->fp64 ? 0 : N), hv4(s->fp64 ? 0 : N);
+  std::vector<double4> hx8(s->fp64 ? N : 0), hv8(s->fp64 ? N : 0);
   const double rho = (double)s->p.density;
   for (int64_t i = 0; i < n; ++i) {
     double r = hr[i];
     double m = rho * (4.0 / 3.0) * M_PI * r * r * r;
-    hx4[i] = make_float4(hx[3 * i], hx[3 * i + 1], hx[3 * i + 2], hr[i]);
-    hv4[i] = make_float4(hv[3 * i], hv[3 * i + 1], hv[3 * i + 2], (float)(1.0 / m));
+    if (s->fp64) {
+      hx8[i] = make_double4(hx[3 * i], hx[3 * i + 1], hx[3 * i + 2], hr[i]);
+      hv8[i] = make_double4(hv[3 * i], hv[3 * i + 1], hv[3 * i + 2], 1.0 / m);
+    } else {
+      hx4[i] = make_float4(hx[3 * i], hx[3 * i + 1], hx[3 * i + 2], hr[i]);
+      hv4[i] = make_float4(hv[3 * i], hv[3 * i + 1], hv[3 * i + 2], (float)(1.0 / m));
+    }
   }
   hipError_t e = hipSuccess;
   if (n > 0) {
-    if (e == hipSuccess) e = hipMemcpy(s->x, hx4.data(), n * sizeof(float4), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->v, hv4.data(), n * sizeof(float4), hipMemcpyHostToDevice);
+    const void* px = s->fp64 ? (const void*)hx8.data() : (const void*)hx4.data();
+    const void* pv = s->fp64 ? (const void*)hv8.data() : (const void*)hv4.data();
+    if (e == hipSuccess) e = hipMemcpy(s->x, px, n * s->es4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->v, pv, n * s->es4, hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total * 4);
   if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
@@ -738,8 +906,6 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
 
   const int n = (int)s->n;
   const int K = s->K;
-  const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
-  const float dt = s->p.dt;
   hipStream_t S = s->stream;
 
   const bool taped = (s->p.flags & GG_FLAG_TAPE) != 0;
@@ -752,7 +918,8 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
       if (s->ck) HIPCHK(s, hipFree(s->ck));
       s->ck = nullptr;
       s->ck_cap = 0;
-      if (dev_alloc(&s->ck, need_ck) != hipSuccess) return fail(GG_ERR_OOM, "checkpoint allocation failed");
+      if (dev_alloc_bytes(&s->ck, need_ck * s->es4) != hipSuccess)
+        return fail(GG_ERR_OOM, "checkpoint allocation failed");
       s->ck_cap = need_ck;
     }
     if ((size_t)n_steps * 2 > s->d_counts_cap) {
@@ -763,26 +930,13 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
       s->d_counts_cap = (size_t)n_steps * 2;
     }
   }
-  ggk::k_begin<<<1, 64, 0, S>>>(s->ctl);
-  for (int st = 0; st < n_steps && n > 0; ++st) {
-    const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
-    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st], S));
-    const int64_t g = s->steps_global + st;
-    // a differentiable call keeps one internal order throughout (re-sorted only at its start)
-    if (s->p.reorder_every > 0 && (taped ? st == 0 : g % s->p.reorder_every == 0)) launch_reorder(s);
-    if (taped && st % s->p.checkpoint_every == 0) {
-      float4* ckx = s->ck + (size_t)(st / s->p.checkpoint_every) * 2 * n;
-      HIPCHK(s, hipMemcpyAsync(ckx, s->x, (size_t)n * sizeof(float4), hipMemcpyDeviceToDevice, S));
-      HIPCHK(s, hipMemcpyAsync(ckx + n, s->v, (size_t)n * sizeof(float4), hipMemcpyDeviceToDevice, S));
-    }
-    const StepIO io = plain_io(s);
-    launch_detect(s, io, st, bod);
-    if (taped) ggk::k_record_counts<<<1, 64, 0, S>>>(s->ctl, s->d_counts + 2 * (size_t)st);
-    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
-    launch_sweeps(s, io, bod);
-    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
-    ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, s->x, s->v, dt, s->ctl);
-    if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
+  const bool graphed = (s->p.flags & GG_FLAG_GRAPH) && !prof && !taped && n > 0;
+  if (graphed) {
+    gg_status gs = launch_graphed(s, n_steps, nb);
+    if (gs != GG_OK) return gs;
+  } else {
+    gg_status es = enqueue_steps(s, n_steps, nb, taped, prof);
+    if (es != GG_OK) return es;
   }
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipMemcpyAsync(s->h_ctl, s->ctl, sizeof(ggk::Ctl), hipMemcpyDeviceToHost, S));
@@ -898,6 +1052,19 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   if (!(s->p.flags & GG_FLAG_TAPE)) return fail(GG_ERR_NO_TAPE, "the simulation was created without GG_FLAG_TAPE");
   if (!s->tape_ok || s->tape_steps <= 0) return fail(GG_ERR_NO_TAPE, "no successful differentiable gg_step to reverse");
   if (s->n_envs != 1) return fail(GG_ERR_UNSUPPORTED, "the adjoint is built for one environment");
+  return s->fp64 ? backward_t<double>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where)
+                 : backward_t<float>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reverse pass of the last recorded call in the build's precision R.
+template <typename R>
+gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* dL_dx0, float* dL_dv0,
+                     float* dL_dtwists, gg_mem where) {
+  using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int nb = (int)s->bodies.size();
   const int N = s->tape_steps;
@@ -922,7 +1089,7 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
     for (void* p : owned) (void)hipFree(p);
     owned.clear();
   };
-  const size_t n4 = (size_t)n * sizeof(float4);
+  const size_t n4 = (size_t)n * sizeof(V);
   // half contacts of every recorded step (a pair counts in both rows)
   std::vector<size_t> hc(N);
   size_t hc_max_seg = 1, hc_max = 1;
@@ -936,28 +1103,28 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
     hc_max_seg = std::max(hc_max_seg, sum);
   }
   const size_t nsw = (size_t)std::max(I - 1, 1);
-  float4* tx = (float4*)alloc(n4 * C);
-  float4* tv = (float4*)alloc(n4 * C);
+  V* tx = (V*)alloc(n4 * C);
+  V* tv = (V*)alloc(n4 * C);
   int32_t* tncon = (int32_t*)alloc((size_t)n * 4 * C);
   int32_t* tpart = (int32_t*)alloc(slots * 4 * C);
-  float* tpsi = (float*)alloc(slots * 4 * C);
-  float4* tw = (float4*)alloc(n4 * (size_t)I * C);
-  float* tP = (float*)alloc(hc_max_seg * 4 * 3 * nsw);
-  float* Plast = (float*)alloc(hc_max * 4 * 3);
+  R* tpsi = (R*)alloc(slots * sizeof(R) * C);
+  V* tw = (V*)alloc(n4 * (size_t)I * C);
+  R* tP = (R*)alloc(hc_max_seg * sizeof(R) * 3 * nsw);
+  R* Plast = (R*)alloc(hc_max * sizeof(R) * 3);
   int32_t* tpofs = (int32_t*)alloc(((size_t)n + 1) * 4 * C);
   int32_t* pbsum = (int32_t*)alloc(((size_t)n + ggk::kScanTile) / ggk::kScanTile * 4 + 16);
-  float4* xw = (float4*)alloc(n4);
-  float4* vw = (float4*)alloc(n4);
-  float4* xb = (float4*)alloc(n4);
-  float4* vb = (float4*)alloc(n4);
-  float4* xbn = (float4*)alloc(n4);
-  float4* vbn = (float4*)alloc(n4);
-  float4* wba = (float4*)alloc(n4);
-  float4* wbb = (float4*)alloc(n4);
-  float4* w0b = (float4*)alloc(n4);
-  float* adj = (float*)alloc(hc_max * 4 * 10);
-  float* part = (float*)alloc((size_t)grid * std::max(nb, 1) * 18 * 4);
-  float* bgrad = (float*)alloc((size_t)std::max(nb, 1) * 18 * 4 * N);
+  V* xw = (V*)alloc(n4);
+  V* vw = (V*)alloc(n4);
+  V* xb = (V*)alloc(n4);
+  V* vb = (V*)alloc(n4);
+  V* xbn = (V*)alloc(n4);
+  V* vbn = (V*)alloc(n4);
+  V* wba = (V*)alloc(n4);
+  V* wbb = (V*)alloc(n4);
+  V* w0b = (V*)alloc(n4);
+  R* adj = (R*)alloc(hc_max * sizeof(R) * 10);
+  R* part = (R*)alloc((size_t)grid * std::max(nb, 1) * 18 * sizeof(R));
+  R* bgrad = (R*)alloc((size_t)std::max(nb, 1) * 18 * sizeof(R) * N);
   float* io3 = (float*)alloc((size_t)n * 12 * 2);
   for (void* p : owned)
     if (!p) {
@@ -969,7 +1136,7 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
     return fail(GG_ERR_OOM, "adjoint workspace allocation failed");
   }
   sample_memory(s);
-  ggk::AdjSlots A;
+  ggk::AdjSlots<R> A;
   A.cx = adj; A.cy = adj + hc_max; A.cz = adj + 2 * hc_max;
   A.nx = adj + 3 * hc_max; A.ny = adj + 4 * hc_max; A.nz = adj + 5 * hc_max;
   A.ps = adj + 6 * hc_max;
@@ -988,17 +1155,17 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   } while (0)
   if (dL_dx) BWCHK(hipMemcpyAsync(io3, dL_dx, (size_t)n * 12, kin, S));
   if (dL_dv) BWCHK(hipMemcpyAsync(io3 + 3 * (size_t)n, dL_dv, (size_t)n * 12, kin, S));
-  ggk::k_gather3<<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dx ? io3 : nullptr, xbn);
-  ggk::k_gather3<<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dv ? io3 + 3 * (size_t)n : nullptr, vbn);
+  ggk::k_gather3<R><<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dx ? io3 : nullptr, xbn);
+  ggk::k_gather3<R><<<grid, ggk::kBlock, 0, S>>>(n, s->orig, dL_dv ? io3 + 3 * (size_t)n : nullptr, vbn);
 
-  const float dt = s->p.dt;
-  const float alpha_dt = s->p.alpha / s->p.dt;
+  const R dt = (R)s->p.dt;
+  const R alpha_dt = (R)s->p.alpha / (R)s->p.dt;
   const int nseg = (N + C - 1) / C;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * C, s1 = std::min(N, s0 + C);
     // recompute the segment from its checkpoint, recording every step
-    BWCHK(hipMemcpyAsync(xw, s->ck + (size_t)seg * 2 * n, n4, hipMemcpyDeviceToDevice, S));
-    BWCHK(hipMemcpyAsync(vw, s->ck + (size_t)seg * 2 * n + n, n4, hipMemcpyDeviceToDevice, S));
+    BWCHK(hipMemcpyAsync(xw, (V*)s->ck + (size_t)seg * 2 * n, n4, hipMemcpyDeviceToDevice, S));
+    BWCHK(hipMemcpyAsync(vw, (V*)s->ck + (size_t)seg * 2 * n + n, n4, hipMemcpyDeviceToDevice, S));
     std::vector<size_t> pstart(C + 1, 0);   // first recorded impulse of each step of the segment
     for (int st = s0; st < s1; ++st) pstart[st - s0 + 1] = pstart[st - s0] + hc[st] * 3 * nsw;
     for (int st = s0; st < s1; ++st) {
@@ -1006,7 +1173,7 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
       BWCHK(hipMemcpyAsync(tx + (size_t)r * n, xw, n4, hipMemcpyDeviceToDevice, S));
       BWCHK(hipMemcpyAsync(tv + (size_t)r * n, vw, n4, hipMemcpyDeviceToDevice, S));
-      StepIO io;
+      StepIO<R> io;
       io.x = xw;
       io.v = vw;
       io.ncon = tncon + (size_t)r * n;
@@ -1017,13 +1184,13 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       for (int l = 0; l < I; ++l) io.w[l] = tw + ((size_t)r * I + l) * n;
       io.w[I] = wba;  // unused: the last sweep writes the velocity
       for (int l = 1; l <= I; ++l) {
-        float* base = (l < I) ? tP + pstart[r] + (size_t)(l - 1) * 3 * hc[st] : Plast;
+        R* base = (l < I) ? tP + pstart[r] + (size_t)(l - 1) * 3 * hc[st] : Plast;
         io.Px[l] = base; io.Py[l] = base + hc[st]; io.Pz[l] = base + 2 * hc[st];
       }
       io.Px[0] = io.Px[1]; io.Py[0] = io.Py[1]; io.Pz[0] = io.Pz[1];
       io.dv = nullptr;
       io.pofs = tpofs + (size_t)r * (n + 1);
-      launch_detect(s, io, st, bod);
+      launch_detect<R>(s, io, st, bod);
       // compact offsets of this step's contacts; the recorded count must match
       const int pnb = (n + ggk::kScanTile - 1) / ggk::kScanTile;
       ggk::k_scan_a<<<pnb, ggk::kBlock, 0, S>>>(n, io.ncon, io.pofs, pbsum, 0);
@@ -1036,47 +1203,47 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
         release();
         return fail(GG_ERR_HIP, "recomputed contacts differ from the recorded forward");
       }
-      launch_sweeps(s, io, bod);
-      ggk::k_integrate<<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, s->ctl);
+      launch_sweeps<R>(s, io, bod);
+      ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, s->ctl);
     }
     // reverse the segment
     for (int st = s1 - 1; st >= s0; --st) {
       const int r = st - s0;
-      const float4* xk = tx + (size_t)r * n;
-      const float4* vk = tv + (size_t)r * n;
+      const V* xk = tx + (size_t)r * n;
+      const V* vk = tv + (size_t)r * n;
       const int32_t* nc = tncon + (size_t)r * n;
       const int32_t* pt = tpart + slots * r;
-      const float* ps = tpsi + slots * r;
+      const R* ps = tpsi + slots * r;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
-      ggk::k_adj_begin<<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
-      ggk::k_zero_f<<<(int)((hc_max * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(hc_max * 10, adj);
-      float4* win = wba;
-      float4* wout = wbb;
+      ggk::k_adj_begin<R><<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
+      ggk::k_zero_f<R><<<(int)((hc_max * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(hc_max * 10, adj);
+      V* win = wba;
+      V* wout = wbb;
       const int32_t* po = tpofs + (size_t)r * (n + 1);
       for (int l = I; l >= 1; --l) {
-        const float4* wprev = tw + ((size_t)r * I + (l - 1)) * n;
-        const float* Pp = (l >= 2) ? tP + pstart[r] + (size_t)(l - 2) * 3 * hc[st] : nullptr;
-        ggk::k_pja_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
+        const V* wprev = tw + ((size_t)r * I + (l - 1)) * n;
+        const R* Pp = (l >= 2) ? tP + pstart[r] + (size_t)(l - 2) * 3 * hc[st] : nullptr;
+        ggk::k_pja_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
                                                     Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr, A,
-                                                    bod, alpha_dt, s->p.mu, s->p.relax, l == 1 ? 1 : 0, po);
+                                                    bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
         std::swap(win, wout);
       }
-      ggk::k_adj_vbar<<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);
-      ggk::k_geom_adj<<<grid, ggk::kBlock, 0, S>>>(n, K, xk, nc, pt, ps, A, bod, nb, po, xb, part);
+      ggk::k_adj_vbar<R><<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);
+      ggk::k_geom_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, nc, pt, ps, A, bod, nb, po, xb, part);
       if (nb > 0)
-        ggk::k_body_reduce<<<nb * 18, ggk::kBlock, 0, S>>>(grid, nb, part, bgrad + (size_t)st * nb * 18);
+        ggk::k_body_reduce<R><<<nb * 18, ggk::kBlock, 0, S>>>(grid, nb, part, bgrad + (size_t)st * nb * 18);
       std::swap(xb, xbn);
       std::swap(vb, vbn);
     }
   }
   BWCHK(hipGetLastError());
   // ---- outputs
-  ggk::k_unpermute3<<<grid, 256, 0, S>>>(n, s->orig, xbn, io3);
-  ggk::k_unpermute3<<<grid, 256, 0, S>>>(n, s->orig, vbn, io3 + 3 * (size_t)n);
+  ggk::k_unpermute3<R><<<grid, 256, 0, S>>>(n, s->orig, xbn, io3);
+  ggk::k_unpermute3<R><<<grid, 256, 0, S>>>(n, s->orig, vbn, io3 + 3 * (size_t)n);
   if (dL_dx0) BWCHK(hipMemcpyAsync(dL_dx0, io3, (size_t)n * 12, kout, S));
   if (dL_dv0) BWCHK(hipMemcpyAsync(dL_dv0, io3 + 3 * (size_t)n, (size_t)n * 12, kout, S));
-  std::vector<float> hb((size_t)std::max(nb, 1) * 18 * N, 0.0f);
-  if (nb > 0) BWCHK(hipMemcpyAsync(hb.data(), bgrad, hb.size() * 4, hipMemcpyDeviceToHost, S));
+  std::vector<R> hb((size_t)std::max(nb, 1) * 18 * N, R(0));
+  if (nb > 0) BWCHK(hipMemcpyAsync(hb.data(), bgrad, hb.size() * sizeof(R), hipMemcpyDeviceToHost, S));
   BWCHK(hipStreamSynchronize(S));
   release();
 #undef BWCHK
@@ -1089,7 +1256,7 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
       for (int st = N - 1; st >= 0; --st) {
         const HostBody& P0 = s->tape_poses[(size_t)st * nb + b];      // pose at step st
         const HostBody& P1 = s->tape_poses[(size_t)(st + 1) * nb + b];  // pose after step st
-        const float* gq = &hb[((size_t)st * nb + b) * 18];
+        const R* gq = &hb[((size_t)st * nb + b) * 18];
         double gnu[3], gom[3];
         for (int q = 0; q < 3; ++q) {
           gnu[q] = gq[q] + dt * tacc[q];
@@ -1135,6 +1302,11 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   return GG_OK;
 }
 
+
+}  // namespace
+
+extern "C" {
+
 gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written, gg_mem where) {
   g_detail.clear();
   if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
@@ -1175,10 +1347,19 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
     gg_status st = ensure_tmp(s, (size_t)need);
     if (st != GG_OK) return st;
     float* f = (float*)s->tmp;
-    if (field == GG_FIELD_POS) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->x, f);
-    if (field == GG_FIELD_VEL) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->v, f);
-    if (field == GG_FIELD_DV) ggk::k_unpermute3<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->dv, f);
-    if (field == GG_FIELD_RADIUS) ggk::k_unpermute_w<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->x, f);
+    const void* src = field == GG_FIELD_POS ? s->x : field == GG_FIELD_VEL ? s->v : field == GG_FIELD_DV ? s->dv : s->x;
+    if (field == GG_FIELD_POS || field == GG_FIELD_VEL || field == GG_FIELD_DV) {
+      if (s->fp64)
+        ggk::k_unpermute3<double><<<blocks, 256, 0, s->stream>>>((int)n, s->orig, (const double4*)src, f);
+      else
+        ggk::k_unpermute3<float><<<blocks, 256, 0, s->stream>>>((int)n, s->orig, (const float4*)src, f);
+    }
+    if (field == GG_FIELD_RADIUS) {
+      if (s->fp64)
+        ggk::k_unpermute_w<double><<<blocks, 256, 0, s->stream>>>((int)n, s->orig, (const double4*)s->x, f);
+      else
+        ggk::k_unpermute_w<float><<<blocks, 256, 0, s->stream>>>((int)n, s->orig, (const float4*)s->x, f);
+    }
     if (field == GG_FIELD_CELL_INDEX)
       ggk::k_unpermute_i64<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->h, (int64_t*)s->tmp);
     HIPCHK(s, hipGetLastError());
@@ -1189,17 +1370,27 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
   // contacts / impulses: gather the per-particle lists into the canonical order
   const size_t slots = (size_t)s->n_pad * s->K;
   std::vector<int32_t> cnt(n), part(slots), org(n);
-  std::vector<float> px, py, pz;
+  std::vector<unsigned char> px, py, pz;   // impulses as stored (R = float or double)
   HIPCHK(s, hipMemcpyAsync(cnt.data(), s->ncon, n * 4, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipMemcpyAsync(part.data(), s->partner, slots * 4, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipMemcpyAsync(org.data(), s->orig, n * 4, hipMemcpyDeviceToHost, s->stream));
   if (field == GG_FIELD_IMPULSES) {
-    px.resize(slots); py.resize(slots); pz.resize(slots);
-    HIPCHK(s, hipMemcpyAsync(px.data(), s->Px, slots * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpyAsync(py.data(), s->Py, slots * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipMemcpyAsync(pz.data(), s->Pz, slots * 4, hipMemcpyDeviceToHost, s->stream));
+    px.resize(slots * s->es); py.resize(slots * s->es); pz.resize(slots * s->es);
+    HIPCHK(s, hipMemcpyAsync(px.data(), s->Px, slots * s->es, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(py.data(), s->Py, slots * s->es, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(pz.data(), s->Pz, slots * s->es, hipMemcpyDeviceToHost, s->stream));
   }
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  auto imp_at = [&](const std::vector<unsigned char>& a, size_t sl) -> float {
+    if (s->fp64) {
+      double d;
+      std::memcpy(&d, a.data() + sl * 8, 8);
+      return (float)d;
+    }
+    float f;
+    std::memcpy(&f, a.data() + sl * 4, 4);
+    return f;
+  };
   struct Rec {
     int32_t a, b;
     size_t slot;
@@ -1229,9 +1420,9 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
         pairs.push_back(r.a);
         pairs.push_back(r.b);
       } else {
-        imp.push_back(px[r.slot]);
-        imp.push_back(py[r.slot]);
-        imp.push_back(pz[r.slot]);
+        imp.push_back(imp_at(px, r.slot));
+        imp.push_back(imp_at(py, r.slot));
+        imp.push_back(imp_at(pz, r.slot));
       }
     }
   const void* src = field == GG_FIELD_CONTACTS ? (const void*)pairs.data() : (const void*)imp.data();

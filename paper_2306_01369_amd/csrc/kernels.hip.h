@@ -14,6 +14,12 @@
 //              per particle; the last sweep also writes the new velocity
 //   k_integrate  positions from the new velocities (Eq. (5))
 //
+// Precision.  Every state-carrying kernel is a template over the real type R:
+// float (the production build) or double (a build for gradient and parity
+// checks against an FP64 reference).  The discrete decisions (cell index, the
+// sphere and SDF contact predicates) are binary32 in both, on the state rounded
+// to binary32, so both builds take the same decisions from the same state.
+//
 // Layout.  Particle state is structure-of-arrays float4: x = (x, y, z, r),
 // v = (vx, vy, vz, 1/m), w = (wx, wy, wz, s) with s = n_i/m_i (the split inverse
 // mass), and orig = the caller's index of each (internally reordered)
@@ -40,13 +46,49 @@ constexpr int kDetBlock = 128;
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
 
-struct DevBody {  // one body at one step; 96 bytes
+struct DevBody {  // one body at one step; 240 bytes
   int32_t shape, env;
   float params[4];
   float R[9];  // world <- body, row major
   float t[3];
   float nu[3];
   float om[3];
+  double Rd[9], td[3], nud[3], omd[3];  // the same pose and twist in double (FP64 build geometry)
+};
+
+// Four-vectors of the real type R.
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename R> using V4 = typename Vec4<R>::type;
+
+template <typename R>
+__device__ __forceinline__ V4<R> mk4(R a, R b, R c, R d) {
+  V4<R> q;
+  q.x = a; q.y = b; q.z = c; q.w = d;
+  return q;
+}
+
+// The state rounded to binary32 (identity for the binary32 build).
+__device__ __forceinline__ float4 f32of(const float4 p) { return p; }
+__device__ __forceinline__ float4 f32of(const double4 p) {
+  return make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
+}
+
+// Body pose and twist in the precision of the geometry: binary32 fields for the
+// binary32 build, double fields for the double build.
+template <typename R> struct PoseOf;
+template <> struct PoseOf<float> {
+  static __device__ __forceinline__ const float* R(const DevBody& B) { return B.R; }
+  static __device__ __forceinline__ const float* t(const DevBody& B) { return B.t; }
+  static __device__ __forceinline__ const float* nu(const DevBody& B) { return B.nu; }
+  static __device__ __forceinline__ const float* om(const DevBody& B) { return B.om; }
+};
+template <> struct PoseOf<double> {
+  static __device__ __forceinline__ const double* R(const DevBody& B) { return B.Rd; }
+  static __device__ __forceinline__ const double* t(const DevBody& B) { return B.td; }
+  static __device__ __forceinline__ const double* nu(const DevBody& B) { return B.nud; }
+  static __device__ __forceinline__ const double* om(const DevBody& B) { return B.omd; }
 };
 
 struct Ctl {                    // device control block, one per simulation
@@ -123,16 +165,20 @@ __device__ __forceinline__ bool pair_touch(const float4 a, const float4 b) {
   return D <= S;
 }
 
-// Body-frame point p = R^T (x - t), fixed summation order.
-__device__ __forceinline__ void to_body(const DevBody& B, float x0, float x1, float x2, float p[3]) {
+// Body-frame point p = R^T (x - t), fixed summation order (binary32 pose and
+// arithmetic for R = float, double for R = double).
+template <typename R>
+__device__ __forceinline__ void to_body(const DevBody& B, R x0, R x1, R x2, R p[3]) {
 #pragma clang fp contract(off)
-  float d0 = x0 - B.t[0], d1 = x1 - B.t[1], d2 = x2 - B.t[2];
+  const auto* Rm = PoseOf<R>::R(B);
+  const auto* tv = PoseOf<R>::t(B);
+  R d0 = x0 - tv[0], d1 = x1 - tv[1], d2 = x2 - tv[2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    float a0 = B.R[0 * 3 + c] * d0;
-    float a1 = B.R[1 * 3 + c] * d1;
-    float a2 = B.R[2 * 3 + c] * d2;
-    float s = a0 + a1;
+    R a0 = Rm[0 * 3 + c] * d0;
+    R a1 = Rm[1 * 3 + c] * d1;
+    R a2 = Rm[2 * 3 + c] * d2;
+    R s = a0 + a1;
     p[c] = s + a2;
   }
 }
@@ -142,7 +188,7 @@ __device__ __forceinline__ void to_body(const DevBody& B, float x0, float x1, fl
 __device__ __forceinline__ float sdf_decide(const DevBody& B, float x0, float x1, float x2) {
 #pragma clang fp contract(off)
   float p[3];
-  to_body(B, x0, x1, x2, p);
+  to_body<float>(B, x0, x1, x2, p);
   if (B.shape == 0) return p[2];
   if (B.shape == 1) {
     float q0 = fabsf(p[0]) - B.params[0];
@@ -177,21 +223,33 @@ __device__ __forceinline__ bool body_touch(const DevBody& B, const float4 xi) {
 // spheres), free of cancellation: differences and squares of binary32 inputs
 // are exact in double precision, and psi = (D - S) / (sqrt(D) + s).  The
 // expression is symmetric in (i, j), so both members of a pair store the same bits.
-__device__ __forceinline__ float pair_gap(const float4 a, const float4 b) {
-  const double d0 = (double)a.x - (double)b.x;
-  const double d1 = (double)a.y - (double)b.y;
-  const double d2 = (double)a.z - (double)b.z;
+template <typename Q>
+__device__ __forceinline__ Q pair_gap(const Q a_x, const Q a_y, const Q a_z, const Q a_w, const Q b_x, const Q b_y,
+                                      const Q b_z, const Q b_w) {
+  const double d0 = (double)a_x - (double)b_x;
+  const double d1 = (double)a_y - (double)b_y;
+  const double d2 = (double)a_z - (double)b_z;
   const double D = d0 * d0 + d1 * d1 + d2 * d2;
-  const double s = (double)a.w + (double)b.w;
-  return (float)((D - s * s) / (sqrt(D) + s));
+  const double s = (double)a_w + (double)b_w;
+  return (Q)((D - s * s) / (sqrt(D) + s));
+}
+__device__ __forceinline__ float pair_gap(const float4 a, const float4 b) {
+  return pair_gap<float>(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+}
+__device__ __forceinline__ double pair_gap(const double4 a, const double4 b) {
+  return pair_gap<double>(a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
 }
 
-// Signed gap f(X^-1 x) - r of a body contact in double precision (Eq. (7)).
-__device__ __forceinline__ float body_gap(const DevBody& B, const float4 xi) {
-  double d[3] = {(double)xi.x - B.t[0], (double)xi.y - B.t[1], (double)xi.z - B.t[2]};
+// Signed gap f(X^-1 x) - r of a body contact in double precision (Eq. (7)),
+// from the pose of the build's precision.
+template <typename R>
+__device__ __forceinline__ R body_gap(const DevBody& B, const V4<R> xi) {
+  const auto* Rm = PoseOf<R>::R(B);
+  const auto* tv = PoseOf<R>::t(B);
+  double d[3] = {(double)xi.x - tv[0], (double)xi.y - tv[1], (double)xi.z - tv[2]};
   double p[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = (double)B.R[c] * d[0] + (double)B.R[3 + c] * d[1] + (double)B.R[6 + c] * d[2];
+  for (int c = 0; c < 3; ++c) p[c] = (double)Rm[c] * d[0] + (double)Rm[3 + c] * d[1] + (double)Rm[6 + c] * d[2];
   double f;
   if (B.shape == 0) {
     f = p[2];
@@ -205,78 +263,72 @@ __device__ __forceinline__ float body_gap(const DevBody& B, const float4 xi) {
     double e2 = p[2] - cz;
     f = sqrt(p[0] * p[0] + p[1] * p[1] + e2 * e2) - (double)B.params[0];
   }
-  return (float)(f - (double)xi.w);
+  return (R)(f - (double)xi.w);
 }
 
 // Contact geometry for a body contact with stored gap psi: world normal
 // n = R grad f / |R grad f| and the velocity of the body's material point at
 // the contact point pc = x - f n, V = nu + om x (pc - t).
-__device__ __forceinline__ void body_geometry(const DevBody& B, const float4 xi, float psi, float n[3],
-                                              float V[3]) {
-  float p[3];
-  to_body(B, xi.x, xi.y, xi.z, p);
-  float g[3], f;
+template <typename R>
+__device__ __forceinline__ void body_geometry(const DevBody& B, const V4<R> xi, R psi, R n[3], R V[3]) {
+  const auto* Rm = PoseOf<R>::R(B);
+  const auto* tv = PoseOf<R>::t(B);
+  const auto* nu = PoseOf<R>::nu(B);
+  const auto* om = PoseOf<R>::om(B);
+  R p[3];
+  to_body<R>(B, xi.x, xi.y, xi.z, p);
+  R g[3], f;
   if (B.shape == 0) {
-    g[0] = 0.f; g[1] = 0.f; g[2] = 1.f;
+    g[0] = R(0); g[1] = R(0); g[2] = R(1);
     f = p[2];
   } else if (B.shape == 1) {
-    float q[3], m[3];
+    R q[3], m[3];
     bool outside = false;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      q[c] = fabsf(p[c]) - B.params[c];
-      m[c] = fmaxf(q[c], 0.0f);
-      outside = outside || (q[c] > 0.0f);
+      q[c] = fabs(p[c]) - (R)B.params[c];
+      m[c] = fmax(q[c], R(0));
+      outside = outside || (q[c] > R(0));
     }
     if (outside) {
-      float L = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-      float il = 1.0f / L;
+      R L = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      R il = R(1) / L;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) g[c] = (p[c] < 0.0f ? -1.0f : 1.0f) * m[c] * il;
+      for (int c = 0; c < 3; ++c) g[c] = (p[c] < R(0) ? R(-1) : R(1)) * m[c] * il;
       f = L;
     } else {
       int a = 0;
       if (q[1] > q[a]) a = 1;
       if (q[2] > q[a]) a = 2;
-      g[0] = g[1] = g[2] = 0.f;
-      g[a] = p[a] < 0.0f ? -1.0f : 1.0f;
+      g[0] = g[1] = g[2] = R(0);
+      g[a] = p[a] < R(0) ? R(-1) : R(1);
       f = q[a];
     }
   } else {
-    float h = B.params[1];
-    float cz = fminf(fmaxf(p[2], -h), h);
-    float e0 = p[0], e1 = p[1], e2 = p[2] - cz;
-    float L = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-    if (L > 0.0f) {
-      float il = 1.0f / L;
+    R h = B.params[1];
+    R cz = fmin(fmax(p[2], -h), h);
+    R e0 = p[0], e1 = p[1], e2 = p[2] - cz;
+    R L = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    if (L > R(0)) {
+      R il = R(1) / L;
       g[0] = e0 * il; g[1] = e1 * il; g[2] = e2 * il;
     } else {
-      g[0] = 1.f; g[1] = 0.f; g[2] = 0.f;
+      g[0] = R(1); g[1] = R(0); g[2] = R(0);
     }
-    f = L - B.params[0];
+    f = L - (R)B.params[0];
   }
-  float w0 = B.R[0] * g[0] + B.R[1] * g[1] + B.R[2] * g[2];
-  float w1 = B.R[3] * g[0] + B.R[4] * g[1] + B.R[5] * g[2];
-  float w2 = B.R[6] * g[0] + B.R[7] * g[1] + B.R[8] * g[2];
-  float inl = 1.0f / sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+  R w0 = Rm[0] * g[0] + Rm[1] * g[1] + Rm[2] * g[2];
+  R w1 = Rm[3] * g[0] + Rm[4] * g[1] + Rm[5] * g[2];
+  R w2 = Rm[6] * g[0] + Rm[7] * g[1] + Rm[8] * g[2];
+  R inl = R(1) / sqrt(w0 * w0 + w1 * w1 + w2 * w2);
   n[0] = w0 * inl; n[1] = w1 * inl; n[2] = w2 * inl;
   f = psi + xi.w;
-  float a0 = xi.x - f * n[0] - B.t[0];
-  float a1 = xi.y - f * n[1] - B.t[1];
-  float a2 = xi.z - f * n[2] - B.t[2];
-  V[0] = B.nu[0] + B.om[1] * a2 - B.om[2] * a1;
-  V[1] = B.nu[1] + B.om[2] * a0 - B.om[0] * a2;
-  V[2] = B.nu[2] + B.om[0] * a1 - B.om[1] * a0;
-}
-
-// Orthonormal tangent pair (e2, e3) for a unit normal (Duff et al. 2017,
-// "Building an Orthonormal Basis, Revisited").
-__device__ __forceinline__ void tangent_basis(const float n[3], float t1[3], float t2[3]) {
-  float sg = n[2] >= 0.0f ? 1.0f : -1.0f;
-  float a = -1.0f / (sg + n[2]);
-  float b = n[0] * n[1] * a;
-  t1[0] = 1.0f + sg * n[0] * n[0] * a; t1[1] = sg * b; t1[2] = -sg * n[0];
-  t2[0] = b; t2[1] = sg + n[1] * n[1] * a; t2[2] = -n[1];
+  R a0 = xi.x - f * n[0] - tv[0];
+  R a1 = xi.y - f * n[1] - tv[1];
+  R a2 = xi.z - f * n[2] - tv[2];
+  V[0] = nu[0] + om[1] * a2 - om[2] * a1;
+  V[1] = nu[1] + om[2] * a0 - om[0] * a2;
+  V[2] = nu[2] + om[0] * a1 - om[1] * a0;
 }
 
 // ------------------------------------------------------------- wave helpers
@@ -333,12 +385,13 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const float4* __restrict__ x, float inv_c,
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const V4<R>* __restrict__ x, float inv_c,
                                                         const int32_t* __restrict__ env_of,
                                                         unsigned long long* __restrict__ keys) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const float4 p = x[i];
+  const float4 p = f32of(x[i]);
   bool ok = true;
   const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
   const uint32_t m = spread10((uint32_t)(k0 + 512)) | (spread10((uint32_t)(k1 + 512)) << 1) |
@@ -417,10 +470,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(int n, const unsigned lon
 }
 
 // Apply the permutation (new position k takes old index perm[k]) to the state.
+template <typename R>
 __global__ __launch_bounds__(kBlock) void k_permute(int n, const int32_t* __restrict__ perm,
-                                                    const float4* __restrict__ xi, const float4* __restrict__ vi,
-                                                    const int32_t* __restrict__ oi, float4* __restrict__ xo,
-                                                    float4* __restrict__ vo, int32_t* __restrict__ oo) {
+                                                    const V4<R>* __restrict__ xi, const V4<R>* __restrict__ vi,
+                                                    const int32_t* __restrict__ oi, V4<R>* __restrict__ xo,
+                                                    V4<R>* __restrict__ vo, int32_t* __restrict__ oo) {
   const int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   const int j = perm[k];
@@ -433,7 +487,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(int n, const int32_t* __rest
 // Cell keys and bucket counters.  rank[i] is the arrival order of i in its
 // bucket; the order inside a bucket is irrelevant downstream because the
 // members of each cell are re-sorted by original index when staged.
-__global__ __launch_bounds__(kBlock) void k_key(int n, const float4* __restrict__ x, float inv_c, int nh,
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__ x, float inv_c, int nh,
                                                 EnvTables env, int32_t* __restrict__ h,
                                                 int32_t* __restrict__ rank, int32_t* __restrict__ counts,
                                                 Ctl* ctl, int step) {
@@ -442,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const float4* __restrict_
   }
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
-  const float4 p = x[i];
+  const float4 p = f32of(x[i]);
   bool ok = true;
   int k0 = cell_coord(p.x, inv_c, ok);
   int k1 = cell_coord(p.y, inv_c, ok);
@@ -522,11 +577,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(int m, const int32_t* __restr
 
 // Particles into bucket order: index, position and original index, so that a
 // bucket's members are read with independent loads.
+template <typename R>
 __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __restrict__ h,
                                                     const int32_t* __restrict__ rank,
-                                                    const int32_t* __restrict__ start, const float4* __restrict__ x,
+                                                    const int32_t* __restrict__ start, const V4<R>* __restrict__ x,
                                                     const int32_t* __restrict__ orig, int32_t* __restrict__ sidx,
-                                                    float4* __restrict__ xs, int32_t* __restrict__ os) {
+                                                    V4<R>* __restrict__ xs, int32_t* __restrict__ os) {
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   const int q = start[h[i]] + rank[i];
@@ -624,8 +680,9 @@ __device__ void block_exclusive_scan(int* a, int m, int* red) {
 }
 
 // Write contact k of particle i (when within capacity).
-__device__ __forceinline__ void put_contact(int i, int k, int K, int32_t code, float psi, int32_t* partner,
-                                            float* Psi) {
+template <typename R>
+__device__ __forceinline__ void put_contact(int i, int k, int K, int32_t code, R psi, int32_t* partner,
+                                            R* Psi) {
   if (k < K) {
     const int sl = ell_slot(i, k, K);
     partner[sl] = code;
@@ -665,20 +722,21 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // then bodies in body order, so results do not depend on the internal order or
 // on the path taken.  Also seeds the Jacobi iterate w = v + dt g and the split
 // inverse mass s_i = n_i / m_i.
+template <typename R>
 __global__ __launch_bounds__(kDetBlock) void k_detect(
-    int n, int K, const float4* __restrict__ x, const float4* __restrict__ v, const int32_t* __restrict__ orig,
+    int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
     float inv_c, int nh, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
-    const float4* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
-    const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, float gx,
-    float gy, float gz, float dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
-    int32_t* __restrict__ partner, float* __restrict__ Psi, float4* __restrict__ w, Ctl* ctl, int step) {
+    const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
+    const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
+    R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
+    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[kDetBlock / 64][8];
   __shared__ int red[kDetBlock / 64];
   if (ctl->err) return;
   int* cell_off = (int*)smem;                                  // max_cells + 1
   int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
-  float4* st_x = (float4*)(smem + ((((2 * max_cells + 1) * 4) + 15) & ~15));  // max_stage
+  V4<R>* st_x = (V4<R>*)(smem + ((((2 * max_cells + 1) * 4) + 31) & ~31));  // max_stage
   int* st_j = (int*)(st_x + max_stage);                        // max_stage (-1: other cell)
   int* st_o = st_j + max_stage;                                // max_stage
 
@@ -692,10 +750,11 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
   for (int item = it0; item < it1; ++item) {
     const int i = item_start[item] + threadIdx.x;
     const bool active = i < item_start[item + 1];
-    const float4 p = active ? x[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const V4<R> p = active ? x[i] : mk4<R>(R(0), R(0), R(0), R(0));
+    const float4 p32 = f32of(p);
     const int oi = active ? orig[i] : 0;
     bool ok = true;
-    const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
+    const int k0 = cell_coord(p32.x, inv_c, ok), k1 = cell_coord(p32.y, inv_c, ok), k2 = cell_coord(p32.z, inv_c, ok);
     const int e_i = (env.env_of && active) ? env.env_of[i] : 0;
     int tab_n = nh, tab_off = 0, b_lo = 0, b_hi = n_bodies;
     if (env.env_of && active) {
@@ -738,16 +797,17 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
         const int s0 = cell_s[c], first = cell_off[c], m = cell_off[c + 1] - first;
         for (int u = 0; u < m; ++u) {
-          const float4 pj = xs[s0 + u];
+          const V4<R> pj = xs[s0 + u];
+          const float4 pj32 = f32of(pj);
           bool okj = true;
-          const bool mine = cell_coord(pj.x, inv_c, okj) == cx && cell_coord(pj.y, inv_c, okj) == cy &&
-                            cell_coord(pj.z, inv_c, okj) == cz;
+          const bool mine = cell_coord(pj32.x, inv_c, okj) == cx && cell_coord(pj32.y, inv_c, okj) == cy &&
+                            cell_coord(pj32.z, inv_c, okj) == cz;
           st_x[first + u] = pj;
           st_j[first + u] = mine ? sidx[s0 + u] : -1;
           st_o[first + u] = mine ? os[s0 + u] : 0x7fffffff;
         }
         for (int u = 1; u < m; ++u) {
-          const float4 kx = st_x[first + u];
+          const V4<R> kx = st_x[first + u];
           const int kj = st_j[first + u], ko = st_o[first + u];
           int at = first + u;
           while (at > first && st_o[at - 1] > ko) {
@@ -773,8 +833,8 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
                 if (j < 0) break;          // members of other cells sort last
                 if (j == i) continue;
                 ++cand;
-                const float4 pj = st_x[q];
-                if (!pair_touch(p, pj)) continue;
+                const V4<R> pj = st_x[q];
+                if (!pair_touch(p32, f32of(pj))) continue;
                 const int oj = st_o[q];
                 npp += oi < oj;
                 put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
@@ -793,15 +853,16 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
               const int s0 = start[hb], s1 = start[hb + 1];
               const int first = cnt;
               for (int q = s0; q < s1; ++q) {
-                const float4 pj = xs[q];
+                const V4<R> pj = xs[q];
+                const float4 pj32 = f32of(pj);
                 bool okj = true;
-                if (cell_coord(pj.x, inv_c, okj) != c0 || cell_coord(pj.y, inv_c, okj) != c1 ||
-                    cell_coord(pj.z, inv_c, okj) != c2)
+                if (cell_coord(pj32.x, inv_c, okj) != c0 || cell_coord(pj32.y, inv_c, okj) != c1 ||
+                    cell_coord(pj32.z, inv_c, okj) != c2)
                   continue;
                 const int j = sidx[q];
                 if (j == i) continue;
                 ++cand;
-                if (!pair_touch(p, pj)) continue;
+                if (!pair_touch(p32, pj32)) continue;
                 const int oj = os[q];
                 npp += oi < oj;
                 // keep this cell's partners sorted by original index (in place)
@@ -823,8 +884,8 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     }
     if (active) {
       for (int b = b_lo; b < b_hi; ++b) {
-        if (body_touch(bodies[b], p)) {
-          put_contact(i, cnt, K, -1 - b, body_gap(bodies[b], p), partner, Psi);
+        if (body_touch(bodies[b], p32)) {
+          put_contact(i, cnt, K, -1 - b, body_gap<R>(bodies[b], p), partner, Psi);
           ++cnt;
           ++npb;
         }
@@ -832,9 +893,9 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
       ncon[i] = cnt < K ? cnt : K;
       if (cnt > K) set_error(ctl, 4 /* GG_ERR_CAPACITY */, step);
       mx = max(mx, cnt);
-      const float4 vi = v[i];
-      const float s_i = mass_split ? (float)cnt * vi.w : vi.w;
-      w[i] = make_float4(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
+      const V4<R> vi = v[i];
+      const R s_i = mass_split ? (R)cnt * vi.w : vi.w;
+      w[i] = mk4<R>(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -868,76 +929,77 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
 // indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
-__global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __restrict__ x,
-                                                float4* __restrict__ v, const float4* __restrict__ w_in,
-                                                float4* __restrict__ w_out, const int32_t* __restrict__ ncon,
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __restrict__ x,
+                                                V4<R>* __restrict__ v, const V4<R>* __restrict__ w_in,
+                                                V4<R>* __restrict__ w_out, const int32_t* __restrict__ ncon,
                                                 const int32_t* __restrict__ partner,
-                                                const float* __restrict__ Psi, const float* Pix,
-                                                const float* Piy, const float* Piz, float* Px, float* Py,
-                                                float* Pz, const DevBody* __restrict__ bodies, float gx, float gy,
-                                                float gz, float dt, float alpha_dt, float mu, float relax,
-                                                int mode, float4* __restrict__ dv, const int32_t* __restrict__ pofs,
+                                                const R* __restrict__ Psi, const R* Pix,
+                                                const R* Piy, const R* Piz, R* Px, R* Py,
+                                                R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
+                                                R gz, R dt, R alpha_dt, R mu, R relax,
+                                                int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
                                                 const Ctl* ctl) {
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   const bool first = mode & 1, last = mode & 2;
   const int pbase = pofs ? pofs[i] : 0;
-  const float4 xi = x[i];
-  const float4 vi = v[i];
-  const float4 wi = w_in[i];
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  const V4<R> xi = x[i];
+  const V4<R> vi = v[i];
+  const V4<R> wi = w_in[i];
+  R a0 = R(0), a1 = R(0), a2 = R(0);
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
     const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
     const int code = partner[slot];
-    const float psi = Psi[slot];
-    float P0 = 0.f, P1 = 0.f, P2 = 0.f;
+    const R psi = Psi[slot];
+    R P0 = R(0), P1 = R(0), P2 = R(0);
     if (!first) {
       P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
     }
-    float n0, n1, n2, u0, u1, u2, mt, sg;
+    R n0, n1, n2, u0, u1, u2, mt, sg;
     if (code >= 0) {
       const int j = code & (kHiFlag - 1);
       const bool lo = (code & kHiFlag) == 0;
-      const float4 xj = x[j];
-      const float4 wj = w_in[j];
-      const float4 xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const float4 wl = lo ? wi : wj, wh = lo ? wj : wi;
-      const float d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
-      const float L = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-      if (L > 0.0f) {
-        const float il = 1.0f / L;
+      const V4<R> xj = x[j];
+      const V4<R> wj = w_in[j];
+      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
+      const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
+      const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
+      const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      if (L > R(0)) {
+        const R il = R(1) / L;
         n0 = d0 * il; n1 = d1 * il; n2 = d2 * il;
       } else {
-        n0 = 0.f; n1 = 0.f; n2 = 1.f;
+        n0 = R(0); n1 = R(0); n2 = R(1);
       }
       u0 = wl.x - wh.x; u1 = wl.y - wh.y; u2 = wl.z - wh.z;
-      mt = 1.0f / (wl.w + wh.w);
-      sg = lo ? 1.0f : -1.0f;
+      mt = R(1) / (wl.w + wh.w);
+      sg = lo ? R(1) : R(-1);
     } else {
-      float nb[3], V[3];
-      body_geometry(bodies[-1 - code], xi, psi, nb, V);
+      R nb[3], V[3];
+      body_geometry<R>(bodies[-1 - code], xi, psi, nb, V);
       n0 = nb[0]; n1 = nb[1]; n2 = nb[2];
       u0 = wi.x - V[0]; u1 = wi.y - V[1]; u2 = wi.z - V[2];
-      mt = 1.0f / wi.w;
-      sg = 1.0f;
+      mt = R(1) / wi.w;
+      sg = R(1);
     }
-    const float bias = alpha_dt * psi;
-    const float y0 = P0 - mt * (u0 + bias * n0);
-    const float y1 = P1 - mt * (u1 + bias * n1);
-    const float y2 = P2 - mt * (u2 + bias * n2);
-    const float yn = n0 * y0 + n1 * y1 + n2 * y2;
-    float t0 = y0 - yn * n0, t1 = y1 - yn * n1, t2 = y2 - yn * n2;
-    const float ynp = fmaxf(yn, 0.0f);
-    const float ts = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+    const R bias = alpha_dt * psi;
+    const R y0 = P0 - mt * (u0 + bias * n0);
+    const R y1 = P1 - mt * (u1 + bias * n1);
+    const R y2 = P2 - mt * (u2 + bias * n2);
+    const R yn = n0 * y0 + n1 * y1 + n2 * y2;
+    R t0 = y0 - yn * n0, t1 = y1 - yn * n1, t2 = y2 - yn * n2;
+    const R ynp = fmax(yn, R(0));
+    const R ts = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
     if (ts > mu * ynp) {
-      const float f = mu * ynp / ts;
+      const R f = mu * ynp / ts;
       t0 *= f; t1 *= f; t2 *= f;
     }
-    float Q0 = ynp * n0 + t0, Q1 = ynp * n1 + t1, Q2 = ynp * n2 + t2;
-    if (relax != 1.0f) {
+    R Q0 = ynp * n0 + t0, Q1 = ynp * n1 + t1, Q2 = ynp * n2 + t2;
+    if (relax != R(1)) {
       Q0 = P0 + relax * (Q0 - P0);
       Q1 = P1 + relax * (Q1 - P1);
       Q2 = P2 + relax * (Q2 - P2);
@@ -945,46 +1007,50 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const float4* __re
     Px[ps] = Q0; Py[ps] = Q1; Pz[ps] = Q2;
     a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
   }
-  const float im = vi.w;
-  const float n0 = vi.x + dt * gx + im * a0;
-  const float n1 = vi.y + dt * gy + im * a1;
-  const float n2 = vi.z + dt * gz + im * a2;
+  const R im = vi.w;
+  const R n0 = vi.x + dt * gx + im * a0;
+  const R n1 = vi.y + dt * gy + im * a1;
+  const R n2 = vi.z + dt * gz + im * a2;
   if (last) {
-    v[i] = make_float4(n0, n1, n2, im);
-    if (dv) dv[i] = make_float4(im * a0, im * a1, im * a2, 0.0f);
+    v[i] = mk4<R>(n0, n1, n2, im);
+    if (dv) dv[i] = mk4<R>(im * a0, im * a1, im * a2, R(0));
   } else {
-    w_out[i] = make_float4(n0, n1, n2, wi.w);
+    w_out[i] = mk4<R>(n0, n1, n2, wi.w);
   }
 }
 
 // Positions from the new velocities (Eq. (5)), x' = x + dt v'.
-__global__ __launch_bounds__(kBlock) void k_integrate(int n, float4* __restrict__ x,
-                                                      const float4* __restrict__ v, float dt, Ctl* ctl) {
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__ x,
+                                                      const V4<R>* __restrict__ v, R dt, Ctl* ctl) {
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->steps_done, 1);
   if (i >= n) return;
-  float4 p = x[i];
-  const float4 q = v[i];
+  V4<R> p = x[i];
+  const V4<R> q = v[i];
   p.x += dt * q.x; p.y += dt * q.y; p.z += dt * q.z;
   x[i] = p;
 }
 
 // ---------------------------------------------------------------- readout
 // Internal (Z-ordered) arrays back to the caller's order: out[orig[k]] = a[k].
-__global__ void k_unpermute3(int n, const int32_t* __restrict__ orig, const float4* __restrict__ a,
+// (Values of the double build are rounded to binary32 on the way out.)
+template <typename R>
+__global__ void k_unpermute3(int n, const int32_t* __restrict__ orig, const V4<R>* __restrict__ a,
                              float* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const float4 q = a[k];
+  const V4<R> q = a[k];
   const int o = orig[k];
-  out[3 * o] = q.x; out[3 * o + 1] = q.y; out[3 * o + 2] = q.z;
+  out[3 * o] = (float)q.x; out[3 * o + 1] = (float)q.y; out[3 * o + 2] = (float)q.z;
 }
 
-__global__ void k_unpermute_w(int n, const int32_t* __restrict__ orig, const float4* __restrict__ a,
+template <typename R>
+__global__ void k_unpermute_w(int n, const int32_t* __restrict__ orig, const V4<R>* __restrict__ a,
                               float* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[orig[k]] = a[k].w;
+  if (k < n) out[orig[k]] = (float)a[k].w;
 }
 
 __global__ void k_unpermute_i64(int n, const int32_t* __restrict__ orig, const int32_t* __restrict__ a,

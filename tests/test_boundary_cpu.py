@@ -100,16 +100,17 @@ def test_create_rejects_bad_arguments_on_host(kw, status):
     assert e.value.status == status
 
 
-def test_precision_other_than_binary32_is_unsupported():
+@pytest.mark.parametrize("precision", [2, -1])
+def test_precision_other_than_binary32_or_binary64_is_rejected(precision):
     L = gg.lib()
     P = gg.Params()
-    P.dt, P.n_iters, P.precision = 1e-3, 20, 1
+    P.dt, P.n_iters, P.precision = 1e-3, 20, precision
     h = C.c_void_p()
     x = np.zeros((1, 3), np.float32)
     r = np.ones(1, np.float32)
     st = L.gg_create(C.byref(P), 1, None, 1, x.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p),
                      r.ctypes.data_as(C.c_void_p), 0, C.byref(h))
-    assert st == gg.GG_ERR_UNSUPPORTED
+    assert st == gg.GG_ERR_INVALID
     assert h.value is None
 
 

@@ -42,8 +42,9 @@ def _setup(n=2000, steps=8, seed=0):
     return x, v, np.full(n, r, np.float32), bodies, tw, loss
 
 
-def _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3, gravity=(0.0, 0.0, -9.81)):
-    sim = gg.Sim(x, v, r, bodies, differentiable=True, checkpoint_every=checkpoint_every, gravity=gravity)
+def _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3, gravity=(0.0, 0.0, -9.81), **sim_kw):
+    sim = gg.Sim(x, v, r, bodies, differentiable=True, checkpoint_every=checkpoint_every, gravity=gravity,
+                 **sim_kw)
     sim.step(tw.shape[0], twists=tw.astype(np.float32))
     xN = sim.read("pos").astype(np.float64)
     vN = sim.read("vel").astype(np.float64)
@@ -74,8 +75,8 @@ def _dynamic_setup(n=1500, steps=8, seed=11):
     return x, v, rad, bodies, tw, loss
 
 
-def _check_directions(x, v, r, bodies, tw, loss, kinds, tol, gravity=(0.0, 0.0, -9.81)):
-    (gx0, gv0, gtw), st = _gpu_grads(x, v, r, bodies, tw, loss, gravity=gravity)
+def _check_directions(x, v, r, bodies, tw, loss, kinds, tol, gravity=(0.0, 0.0, -9.81), precision=0, **kw):
+    (gx0, gv0, gtw), st = _gpu_grads(x, v, r, bodies, tw, loss, gravity=gravity, precision=precision, **kw)
     rng = np.random.default_rng(42)
     errs = []
     for kind in kinds:
@@ -88,19 +89,19 @@ def _check_directions(x, v, r, bodies, tw, loss, kinds, tol, gravity=(0.0, 0.0, 
         # accurate to ~1e-5 there)
         h = 1e-9 / max(np.abs(dx).max(), np.abs(dv).max(), np.abs(dt_).max())
         fd, same = fd_directional(loss, x.astype(np.float64), v.astype(np.float64), r, bodies, tw,
-                                  (dx, dv, dt_), h, gravity=gravity)
+                                  (dx, dv, dt_), h, gravity=gravity, **kw)
         an = np.sum(gx0 * dx) + np.sum(gv0 * dv) + np.sum(gtw * dt_)
         err = abs(an - fd) / max(abs(fd), 1e-12)
-        say(kind, "adjoint", an, "fd", fd, "rel err", err, "free detection same:", same)
+        say(kind, "precision", precision, "adjoint", an, "fd", fd, "rel err", err, "free detection same:", same)
         errs.append(err)
         assert err <= tol, (kind, an, fd, err)
     return errs, st
 
 
-def _contact_list_differences(x, v, r, bodies, tw, gravity=(0.0, 0.0, -9.81)):
+def _contact_list_differences(x, v, r, bodies, tw, gravity=(0.0, 0.0, -9.81), precision=0, **kw):
     """Per step: pairs in the GPU list but not the oracle's, and vice versa."""
-    sim = gg.Sim(x, v, r, bodies, gravity=gravity)
-    orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, bodies, gravity=gravity)
+    sim = gg.Sim(x, v, r, bodies, gravity=gravity, precision=precision, **kw)
+    orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, bodies, gravity=gravity, **kw)
     out = []
     for k in range(tw.shape[0]):
         sim.step(1, twists=tw[k:k + 1].astype(np.float32))
@@ -164,6 +165,35 @@ def test_adjoint_matches_fd_directional_derivatives():
             checked += 1
             break
     assert checked >= 4
+
+
+def _f32(a):
+    return float(np.float32(a))
+
+
+# Parameters every side can represent exactly: the double build receives them
+# through the binary32 ABI, the oracle takes the same values in FP64.
+EXACT_KW = dict(dt=_f32(1e-3), alpha=_f32(0.2))
+EXACT_G = (0.0, 0.0, _f32(-9.81))
+
+
+def test_fp64_build_follows_the_oracle_contact_sets_on_a_resting_bed():
+    x, v, r, bodies, tw, loss = _setup()
+    say("fp64 contact sets, resting bed")
+    diffs = _contact_list_differences(x, v, r, bodies, tw, gravity=EXACT_G, precision=1, **EXACT_KW)
+    say("contact list differences per step (gpu-only, oracle-only):", diffs)
+    assert all(a == 0 and b == 0 for a, b in diffs)
+
+
+def test_fp64_build_adjoint_matches_fd_on_a_resting_bed():
+    # the bar of 1e-3 on the bed the binary32 build is only guarded on: with the
+    # same contact sets as the oracle, the adjoint is exact up to FP64 rounding
+    x, v, r, bodies, tw, loss = _setup()
+    say("fp64 adjoint vs FD, resting bed: n", len(x), "steps", tw.shape[0])
+    errs, st = _check_directions(x, v, r, bodies, tw, loss, ["x0", "v0", "twist", "all", "x0", "twist"], REL_TOL,
+                                 gravity=EXACT_G, precision=1, **EXACT_KW)
+    assert st["n_pb"] > 0 and st["n_pp"] > 1000
+    say("fp64 max rel err", max(errs))
 
 
 def test_adjoint_is_deterministic_and_checkpoint_independent():

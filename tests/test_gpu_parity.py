@@ -396,3 +396,132 @@ def test_autotuned_launch_shape_keeps_results_bitwise(tmp_path, monkeypatch):
     ref, _ = _run_bits(s, 15)
     got, st = _run_bits(s, 15, **params)
     assert got == ref
+
+
+# ------------------------------------------------- graph replay, hash size
+
+def _bits(sim):
+    return sim.read("pos").tobytes(), sim.read("vel").tobytes()
+
+
+def test_graph_replay_matches_direct_launches():
+    # each call replays a captured launch sequence (captured on first use of a
+    # step count / re-sort phase / buffer parity); every replay must equal the
+    # direct launches bit for bit, with unrelated device work between replays
+    torch = pytest.importorskip("torch")
+    s = scenes.column_scene(n=3000, r=0.004)
+    top = float(s.x[:, 2].max())
+    tool = scenes.box_tool((0.03, 0.03, top + 0.02), (0.01, 0.01, 0.01))
+    bodies = s.bodies + [tool]
+    say("graph replay")
+    direct = gg.Sim(s.x, s.v, s.radius, bodies, reorder_every=4)
+    graphed = gg.Sim(s.x, s.v, s.radius, bodies, reorder_every=4, graph=True)
+    junk = torch.zeros(1 << 20, device="cuda:0")
+    calls = [(5, None), (5, None), (3, None), (5, None), (8, "tw"), (8, "tw"), (5, "bodies"), (5, None)]
+    for k, (steps, what) in enumerate(calls):
+        tw = None
+        if what == "tw":
+            tw = np.zeros((steps, len(bodies), 6), np.float32)
+            tw[:, -1, 2] = -0.5
+        if what == "bodies":
+            moved = dict(tool, t=tool["t"] + np.array([0.005, 0.0, 0.0]))
+            bodies2 = s.bodies + [moved]
+            direct.set_bodies(bodies2)
+            graphed.set_bodies(bodies2)
+        direct.step(steps, twists=tw)
+        graphed.step(steps, twists=tw)
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+        assert _bits(graphed) == _bits(direct), f"call {k}"
+        assert graphed.stats()["n_pp"] == direct.stats()["n_pp"]
+    assert float(junk[0]) == len(calls)
+
+
+def test_graph_replay_multi_env():
+    rng = np.random.default_rng(5)
+    counts = [500, 0, 1200, 64]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    x = np.concatenate([scenes.loose_lattice(c, 0.004, (0.004, 0.004, 0.0039), rng, spacing_factor=2.0,
+                                             jitter_frac=0.1)[0] for c in counts]).astype(np.float32)
+    r = np.full(len(x), 0.004, np.float32)
+    v = np.zeros_like(x)
+    bodies = []
+    for e in range(len(counts)):
+        bodies += scenes.walled_box(0, 0.08, 0, 0.08, env=e)
+    say("graph multi-env")
+    direct = gg.Sim(x, v, r, bodies, env_offsets=off)
+    graphed = gg.Sim(x, v, r, bodies, env_offsets=off, graph=True)
+    for k in range(4):
+        direct.step(6)
+        graphed.step(6)
+        assert _bits(graphed) == _bits(direct), f"call {k}"
+
+
+def test_hash_table_size_changes_no_result():
+    # partners are listed by (neighbour cell, original index), never by bucket,
+    # so n_h (and with it bucket aliasing) changes only speed: outputs and the
+    # candidate count are bitwise the same for any table size, down to n_h = 1
+    s = scenes.drop_scene()
+    say("hash size")
+    ref, st_ref = _run_bits(s, 12)
+    for nh in (1, 7, 4096, 3 * s.n + 1):
+        got, st = _run_bits(s, 12, hash_size=nh)
+        assert got[:4] == ref[:4], nh
+        assert st["candidates"] == st_ref["candidates"], nh
+
+
+# ------------------------------------------------- double build
+
+def _f32(a):
+    return float(np.float32(a))
+
+
+def test_fp64_build_tracks_the_oracle_trajectory():
+    # the double build computes what the FP64 oracle computes, up to FP64
+    # rounding order: after 40 steps of a bed under a moving tool the binary32
+    # readouts agree to their own rounding (the binary32 build drifts apart at
+    # ~1e-5 m in the same run, since the dynamics amplify rounding)
+    s = scenes.column_scene(n=2500, r=0.004)
+    top = float(s.x[:, 2].max())
+    tool = scenes.box_tool((0.03, 0.03, top + 0.011), (0.01, 0.01, 0.01), nu=(0.05, 0.0, -0.3))
+    bodies = s.bodies + [tool]
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=(0.0, 0.0, _f32(-9.81)))
+    say("fp64 trajectory")
+    sim = gg.Sim(s.x, s.v, s.radius, bodies, precision=1, diagnostics=True, **kw)
+    orc = O.Oracle(s.x.astype(np.float64), s.v.astype(np.float64), s.radius, bodies, **kw)
+    for k in range(40):
+        sim.step(1)
+        d = orc.step(detail=True)
+        np.testing.assert_array_equal(sim.read("contacts"), d["pairs"], err_msg=f"step {k}")
+    assert np.abs(sim.read("pos") - orc.x).max() <= 2e-8
+    assert np.abs(sim.read("vel") - orc.v).max() <= 1e-6 * max(1.0, np.abs(orc.v).max())
+    P = sim.read("impulses")
+    assert np.abs(P - d["impulses"]).max() <= 1e-6 * np.abs(d["impulses"]).max()
+    assert d["n_pb"] > 0
+
+
+def test_fp64_build_multi_env_and_graph_replay():
+    rng = np.random.default_rng(8)
+    counts = [400, 900]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    x = np.concatenate([scenes.loose_lattice(c, 0.004, (0.004, 0.004, 0.0039), rng, spacing_factor=2.0,
+                                             jitter_frac=0.1)[0] for c in counts]).astype(np.float32)
+    r = np.full(len(x), 0.004, np.float32)
+    v = np.zeros_like(x)
+    bodies = scenes.walled_box(0, 0.08, 0, 0.08, env=0) + scenes.walled_box(0, 0.08, 0, 0.08, env=1)
+    say("fp64 multi-env graph")
+    direct = gg.Sim(x, v, r, bodies, env_offsets=off, precision=1)
+    graphed = gg.Sim(x, v, r, bodies, env_offsets=off, precision=1, graph=True)
+    for k in range(3):
+        direct.step(9)
+        graphed.step(9)
+        assert _bits(graphed) == _bits(direct), f"call {k}"
+    env = np.repeat(np.arange(2), counts).astype(np.int32)
+    orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, bodies, env=env, dt=_f32(1e-3),
+                   alpha=_f32(0.2), gravity=(0.0, 0.0, _f32(-9.81)))
+    sim = gg.Sim(x, v, r, bodies, env_offsets=off, precision=1, dt=_f32(1e-3), alpha=_f32(0.2),
+                 gravity=(0.0, 0.0, _f32(-9.81)))
+    for k in range(5):
+        orc.step()
+    sim.step(5)
+    assert np.abs(sim.read("pos") - orc.x).max() <= 2e-8
