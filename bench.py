@@ -192,6 +192,62 @@ def bench_drop(args):
     }
 
 
+def bench_diff(args):
+    """32,768 grains, 50 steps with a capsule tool: plain forward, recorded
+    (differentiable) forward and its backward (checkpoint every 10 steps),
+    in the binary32 build and the double check build."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    sc = scenes.diff_scene()
+    steps = 50
+    nb = len(sc.bodies)
+    tw = np.zeros((steps, nb, 6), np.float32)
+    tw[:, -1, :3] = sc.bodies[-1]["nu"]
+    gx = np.zeros((sc.n, 3), np.float32)
+    gx[:, 2] = 1.0 / sc.n
+    res = {}
+    for prec in (0, 1):
+        kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters, precision=prec)
+        t = {}
+        for rep in range(2):                 # the first repetition warms up
+            sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps, twists=tw)
+            torch.cuda.synchronize()
+            t["plain"] = time.perf_counter() - t0
+            sim.close()
+            dsim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, differentiable=True, checkpoint_every=10, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dsim.step(steps, twists=tw)
+            torch.cuda.synchronize()
+            t["recorded"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            dsim.backward(gx, None)
+            torch.cuda.synchronize()
+            t["backward"] = time.perf_counter() - t0
+            st = dsim.stats()
+            dsim.close()
+        res[prec] = dict(t, peak=st["device_bytes_peak"])
+    f = res[0]
+    return {
+        "metric": "backward particle-steps/s (32,768 grains, 50 steps, 20 PJA iters)",
+        "value": sc.n * steps / f["backward"], "unit": "particle-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": 1e3 * f["backward"] / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "differentiable: 32,768 spheres r=3mm resting in a 0.3x0.3 m footprint, capsule "
+                               "tool, 50 steps, checkpoint every 10 steps, loss gradient w.r.t. x0 and twists",
+                   "n": sc.n},
+        "forward_plain_s": f["plain"], "forward_recorded_s": f["recorded"], "backward_s": f["backward"],
+        "backward_over_plain_forward": f["backward"] / f["plain"],
+        "forward_plus_backward_over_plain_forward": (f["recorded"] + f["backward"]) / f["plain"],
+        "fp64_build": {"forward_plain_s": res[1]["plain"], "forward_recorded_s": res[1]["recorded"],
+                       "backward_s": res[1]["backward"]},
+        "device_bytes_peak": max(res[0]["peak"], res[1]["peak"]),
+    }
+
+
 def bench_large(args):
     """4,194,304 polydisperse spheres, 64 sweeps, box + capsule tools: settle the
     layered start (untimed, 20 sweeps, tools still), time 80 forward steps, then a
@@ -273,7 +329,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop"], default="scoop")
+    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff"], default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
@@ -291,8 +347,9 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 200
-    if args.workload in ("batched", "large", "drop"):
-        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop}[args.workload](args)
+    if args.workload in ("batched", "large", "drop", "diff"):
+        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop,
+               "diff": bench_diff}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -27,6 +27,12 @@ class Body(C.Structure):
                 ("omega", C.c_double * 3)]
 
 
+class BodyTan(C.Structure):
+    """Tangents of a body's pose and twist (forward-mode derivatives)."""
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("nu", C.c_double * 3),
+                ("omega", C.c_double * 3)]
+
+
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
                 ("relax", C.c_double), ("density", C.c_double), ("g", C.c_double * 3),
@@ -68,11 +74,17 @@ def lib():
                                C.c_void_p, C.c_int32, P(Body), C.c_int32, C.c_int64,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]
+        L.ggo_step_jvp.restype = C.c_int64
+        L.ggo_step_jvp.argtypes = [P(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int32, P(Body), P(BodyTan), C.c_int32,
+                                   C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+        L.ggo_sizeof_body_tan.restype = C.c_int32
         L.ggo_num_threads.restype = C.c_int32
         L.ggo_sizeof_body.restype = C.c_int32
         L.ggo_sizeof_params.restype = C.c_int32
         assert L.ggo_sizeof_body() == C.sizeof(Body), "Body layout mismatch"
         assert L.ggo_sizeof_params() == C.sizeof(Params), "Params layout mismatch"
+        assert L.ggo_sizeof_body_tan() == C.sizeof(BodyTan), "BodyTan layout mismatch"
         _LIB = L
     return _LIB
 
@@ -283,6 +295,34 @@ class Oracle:
         if hist is not None:
             out["history"] = hist[:, :cap]
         return out
+
+    def start_tangents(self, dx=None, dv=None):
+        """Begin forward-mode differentiation: tangents of the current state
+        (zero where None) and zero tangents of the body poses."""
+        self.dx = np.zeros((self.n, 3)) if dx is None else np.array(dx, dtype=np.float64, copy=True).reshape(-1, 3)
+        self.dv = np.zeros((self.n, 3)) if dv is None else np.array(dv, dtype=np.float64, copy=True).reshape(-1, 3)
+        self.dB = (BodyTan * max(1, self.nb))()
+
+    def set_twist_tangents(self, dtw):
+        """dtw: (n_bodies, 6) tangents of (nu, omega) for the next step."""
+        for b in range(self.nb):
+            for q in range(3):
+                self.dB[b].nu[q] = float(dtw[b][q])
+                self.dB[b].omega[q] = float(dtw[b][3 + q])
+
+    def step_jvp(self, advance_bodies=True, fixed=None):
+        """One step carrying the tangents set by start_tangents (and
+        set_twist_tangents): afterwards self.dx, self.dv hold the directional
+        derivative of the state, with the decisions of the value run (the
+        contact set, the normal clamp, the tangential scaling test)."""
+        fx, fpp, fpb = None, 0, 0
+        if fixed is not None:
+            fx = np.ascontiguousarray(fixed[0], np.int32)
+            fpp = int(fixed[1])
+            fpb = len(fx) - fpp
+        return int(lib().ggo_step_jvp(C.byref(self.P), self.n, _ptr(self.x), _ptr(self.v), _ptr(self.dx),
+                                      _ptr(self.dv), _ptr(self.r), _ptr(self.env), self.nb, self.B, self.dB,
+                                      1 if advance_bodies else 0, _ptr(fx), fpp, fpb, _ptr(self.stats)))
 
     def body_pose(self, b):
         R = np.array(self.B[b].R[:]).reshape(3, 3)

@@ -569,3 +569,332 @@ int32_t ggo_sizeof_body() { return (int32_t)sizeof(Body); }
 int32_t ggo_sizeof_params() { return (int32_t)sizeof(Params); }
 
 }  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------- forward-mode JVP
+// The same step carried out on dual numbers (value, tangent): the tangent part
+// is the exact directional derivative of the step along the input tangents,
+// with every discrete decision (the contact set, the normal clamp max(y_n, 0)
+// with derivative [y_n > 0], the strict test for scaling the tangential part,
+// the SDF branch) taken on the value part.  The value part repeats the plain
+// step's operations in the same order, so it equals ggo_step's result bit for
+// bit (the tests check this).  Tangents of the body twists are inputs of each
+// step; tangents of the poses are carried along with the poses.
+
+struct Dual {
+  double v, d;
+};
+inline Dual mkd(double v) { return {v, 0.0}; }
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+inline Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+inline Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+inline Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+inline Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+inline Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+inline Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+inline Dual operator/(double a, Dual b) { return {a / b.v, -a * b.d / (b.v * b.v)}; }
+inline Dual dsqrt(Dual a) {
+  double s = std::sqrt(a.v);
+  return {s, s > 0 ? a.d / (2.0 * s) : 0.0};
+}
+inline Dual dsin(Dual a) { return {std::sin(a.v), std::cos(a.v) * a.d}; }
+inline Dual dcos(Dual a) { return {std::cos(a.v), -std::sin(a.v) * a.d}; }
+inline Dual dabs(Dual a) { return a.v < 0 ? -a : a; }
+inline Dual dot3d(const Dual a[3], const Dual b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+struct BodyTan {       // tangents of a body's pose and twist (mirrored by the Python wrapper)
+  double R[9], t[3], nu[3], omega[3];
+};
+
+struct DBody {
+  int32_t shape;
+  const float* params;
+  Dual R[9], t[3], nu[3], om[3];
+};
+
+// sdf_f64 on duals (same branches, decided on values).
+Dual sdf_dual(const DBody& b, const Dual p[3], Dual grad[3]) {
+  const Dual zero = mkd(0.0), one = mkd(1.0);
+  if (b.shape == PLANE) {
+    grad[0] = zero; grad[1] = zero; grad[2] = one;
+    return p[2];
+  }
+  if (b.shape == BOX) {
+    Dual q[3], m[3];
+    bool outside = false;
+    for (int c = 0; c < 3; ++c) {
+      q[c] = dabs(p[c]) - (double)b.params[c];
+      m[c] = q[c].v > 0 ? q[c] : zero;
+      if (q[c].v > 0) outside = true;
+    }
+    if (outside) {
+      Dual L = dsqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+      for (int c = 0; c < 3; ++c) grad[c] = (p[c].v < 0 ? -1.0 : 1.0) * m[c] / L;
+      return L;
+    }
+    int a = 0;
+    for (int c = 1; c < 3; ++c)
+      if (q[c].v > q[a].v) a = c;
+    grad[0] = grad[1] = grad[2] = zero;
+    grad[a] = mkd(p[a].v < 0 ? -1.0 : 1.0);
+    return q[a];
+  }
+  double h = b.params[1];
+  Dual cz = p[2].v < -h ? mkd(-h) : (p[2].v > h ? mkd(h) : p[2]);
+  Dual e[3] = {p[0], p[1], p[2] - cz};
+  Dual L = dsqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  if (L.v > 0) {
+    for (int c = 0; c < 3; ++c) grad[c] = e[c] / L;
+  } else {
+    grad[0] = one; grad[1] = zero; grad[2] = zero;
+  }
+  return L - (double)b.params[0];
+}
+
+void tangent_basis_dual(const Dual n[3], Dual t1[3], Dual t2[3]) {
+  double sgn = n[2].v >= 0 ? 1.0 : -1.0;
+  Dual a = -1.0 / (sgn + n[2]);
+  Dual b = n[0] * n[1] * a;
+  t1[0] = 1.0 + sgn * n[0] * n[0] * a; t1[1] = sgn * b; t1[2] = -sgn * n[0];
+  t2[0] = b; t2[1] = sgn + n[1] * n[1] * a; t2[2] = -n[1];
+}
+
+struct DContact {
+  int32_t i, j;
+  Dual n[3], t1[3], t2[3];
+  Dual psi;
+  Dual vel[3];
+};
+
+// Rodrigues update of one body on duals (ggo_advance_bodies): t += dt nu,
+// R = Exp(dt [omega]x) R.  At a zero rotation the exponential is I + [w]x to
+// first order, which carries the tangent of w exactly.
+void advance_body_dual(DBody& B, double dt) {
+  for (int a = 0; a < 3; ++a) B.t[a] = B.t[a] + dt * B.nu[a];
+  Dual w[3] = {B.om[0] * dt, B.om[1] * dt, B.om[2] * dt};
+  Dual th = dsqrt(dot3d(w, w));
+  Dual E[9];
+  if (th.v == 0) {
+    const Dual zero = mkd(0.0);
+    Dual K[9] = {zero, -w[2], w[1], w[2], zero, -w[0], -w[1], w[0], zero};
+    for (int q = 0; q < 9; ++q) E[q] = (q % 4 == 0 ? 1.0 : 0.0) + K[q];
+  } else {
+    Dual k[3] = {w[0] / th, w[1] / th, w[2] / th};
+    const Dual zero = mkd(0.0);
+    Dual K[9] = {zero, -k[2], k[1], k[2], zero, -k[0], -k[1], k[0], zero};
+    Dual K2[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        Dual sum = mkd(0.0);
+        for (int m = 0; m < 3; ++m) sum = sum + K[3 * r + m] * K[3 * m + c];
+        K2[3 * r + c] = sum;
+      }
+    for (int q = 0; q < 9; ++q) E[q] = (q % 4 == 0 ? 1.0 : 0.0) + dsin(th) * K[q] + (1.0 - dcos(th)) * K2[q];
+  }
+  Dual Rn[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      Dual sum = mkd(0.0);
+      for (int m = 0; m < 3; ++m) sum = sum + E[3 * r + m] * B.R[3 * m + c];
+      Rn[3 * r + c] = sum;
+    }
+  for (int q = 0; q < 9; ++q) B.R[q] = Rn[q];
+}
+
+}  // namespace
+
+extern "C" {
+
+// One timestep with tangents: x, v (values) and dx, dv (tangents) are updated
+// in place, as are the bodies and their tangents dbodies (the caller sets the
+// twist tangents of this step in dbodies[b].nu / .omega).  The contact list is
+// detected on the values, or given (fixed_*), as in ggo_step.  stats as there.
+int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* dx, double* dv,
+                     const float* radius, const int32_t* env, int32_t nb, Body* bodies, BodyTan* dbodies,
+                     int32_t advance_bodies, const int32_t* fixed_pairs, int64_t fixed_pp, int64_t fixed_pb,
+                     int64_t* stats) {
+  std::vector<float> xf(3 * n);
+  for (int64_t q = 0; q < 3 * n; ++q) xf[q] = (float)x[q];
+  std::vector<std::pair<int32_t, int32_t>> pp, pb;
+  int64_t cand = 0;
+  if (fixed_pairs) {
+    for (int64_t c = 0; c < fixed_pp; ++c) pp.emplace_back(fixed_pairs[2 * c], fixed_pairs[2 * c + 1]);
+    for (int64_t c = fixed_pp; c < fixed_pp + fixed_pb; ++c) pb.emplace_back(fixed_pairs[2 * c], fixed_pairs[2 * c + 1]);
+  } else {
+    pp_contacts_grid(n, xf.data(), radius, env, P->inv_c, P->n_h, pp, &cand);
+    pb_contacts(n, xf.data(), radius, env, nb, bodies, pb);
+  }
+  const int64_t C = (int64_t)(pp.size() + pb.size());
+  if (stats) {
+    stats[0] = cand;
+    stats[1] = (int64_t)pp.size();
+    stats[2] = (int64_t)pb.size();
+    stats[3] = 0;
+  }
+  std::vector<Dual> X(3 * n), V(3 * n);
+  for (int64_t q = 0; q < 3 * n; ++q) {
+    X[q] = {x[q], dx[q]};
+    V[q] = {v[q], dv[q]};
+  }
+  std::vector<DBody> DB(nb);
+  for (int b = 0; b < nb; ++b) {
+    DB[b].shape = bodies[b].shape;
+    DB[b].params = bodies[b].params;
+    for (int q = 0; q < 9; ++q) DB[b].R[q] = {bodies[b].R[q], dbodies[b].R[q]};
+    for (int q = 0; q < 3; ++q) {
+      DB[b].t[q] = {bodies[b].t[q], dbodies[b].t[q]};
+      DB[b].nu[q] = {bodies[b].nu[q], dbodies[b].nu[q]};
+      DB[b].om[q] = {bodies[b].omega[q], dbodies[b].omega[q]};
+    }
+  }
+
+  // ---- contact geometry
+  std::vector<DContact> cs(C);
+  std::vector<int32_t> count(n, 0);
+  for (int64_t c = 0; c < (int64_t)pp.size(); ++c) {
+    DContact& K = cs[c];
+    K.i = pp[c].first;
+    K.j = pp[c].second;
+    Dual d[3];
+    for (int a = 0; a < 3; ++a) d[a] = X[3 * K.i + a] - X[3 * K.j + a];
+    Dual L = dsqrt(dot3d(d, d));
+    double rs = (double)radius[K.i] + (double)radius[K.j];
+    if (L.v > 0) {
+      for (int a = 0; a < 3; ++a) K.n[a] = d[a] / L;
+    } else {
+      K.n[0] = mkd(0); K.n[1] = mkd(0); K.n[2] = mkd(1);
+    }
+    K.psi = L - rs;
+    K.vel[0] = K.vel[1] = K.vel[2] = mkd(0);
+    count[K.i]++;
+    count[K.j]++;
+  }
+  for (int64_t q = 0; q < (int64_t)pb.size(); ++q) {
+    DContact& K = cs[pp.size() + q];
+    K.i = pb[q].first;
+    int b = pb[q].second;
+    K.j = -1 - b;
+    const DBody& B = DB[b];
+    Dual d[3], p[3], g[3];
+    for (int a = 0; a < 3; ++a) d[a] = X[3 * K.i + a] - B.t[a];
+    for (int c = 0; c < 3; ++c) p[c] = B.R[0 * 3 + c] * d[0] + B.R[1 * 3 + c] * d[1] + B.R[2 * 3 + c] * d[2];
+    Dual f = sdf_dual(B, p, g);
+    for (int a = 0; a < 3; ++a) K.n[a] = B.R[3 * a + 0] * g[0] + B.R[3 * a + 1] * g[1] + B.R[3 * a + 2] * g[2];
+    Dual nn = dsqrt(dot3d(K.n, K.n));
+    for (int a = 0; a < 3; ++a) K.n[a] = K.n[a] / nn;
+    K.psi = f - (double)radius[K.i];
+    Dual pc[3], arm[3];
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = X[3 * K.i + a] - f * K.n[a];
+      arm[a] = pc[a] - B.t[a];
+    }
+    K.vel[0] = B.nu[0] + B.om[1] * arm[2] - B.om[2] * arm[1];
+    K.vel[1] = B.nu[1] + B.om[2] * arm[0] - B.om[0] * arm[2];
+    K.vel[2] = B.nu[2] + B.om[0] * arm[1] - B.om[1] * arm[0];
+    count[K.i]++;
+  }
+  for (auto& K : cs) tangent_basis_dual(K.n, K.t1, K.t2);
+
+  // ---- masses (no tangents: radii are fixed)
+  std::vector<double> mass(n), mt(C);
+  for (int64_t i = 0; i < n; ++i) mass[i] = particle_mass((double)radius[i], P->density);
+  for (int64_t c = 0; c < C; ++c) {
+    const DContact& K = cs[c];
+    double ni = P->mass_split ? (double)count[K.i] : 1.0;
+    if (K.j >= 0) {
+      double nj = P->mass_split ? (double)count[K.j] : 1.0;
+      mt[c] = 1.0 / (ni / mass[K.i] + nj / mass[K.j]);
+    } else {
+      mt[c] = mass[K.i] / ni;
+    }
+  }
+
+  // ---- projected Jacobi on duals
+  std::vector<Dual> w0(3 * n), w(3 * n), lam(3 * C, mkd(0.0)), lam_new(3 * C);
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) w0[3 * i + a] = V[3 * i + a] + P->dt * P->g[a];
+  w = w0;
+  std::vector<int64_t> start(n + 1, 0), inc;
+  for (int64_t c = 0; c < C; ++c) {
+    start[cs[c].i + 1]++;
+    if (cs[c].j >= 0) start[cs[c].j + 1]++;
+  }
+  for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+  inc.resize(start[n]);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t c = 0; c < C; ++c) {
+      inc[fill[cs[c].i]++] = c;
+      if (cs[c].j >= 0) inc[fill[cs[c].j]++] = c;
+    }
+  }
+  const double mu = P->mu, om = P->relax;
+  for (int32_t l = 1; l <= P->n_iters; ++l) {
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < C; ++c) {
+      const DContact& K = cs[c];
+      Dual u[3];
+      for (int a = 0; a < 3; ++a) u[a] = w[3 * K.i + a] - (K.j >= 0 ? w[3 * K.j + a] : K.vel[a]);
+      const Dual* L = &lam[3 * c];
+      Dual ln = dot3d(K.n, L), l1 = dot3d(K.t1, L), l2 = dot3d(K.t2, L);
+      Dual yn = ln - mt[c] * (dot3d(K.n, u) + P->alpha * K.psi / P->dt);
+      Dual y1 = l1 - mt[c] * dot3d(K.t1, u);
+      Dual y2 = l2 - mt[c] * dot3d(K.t2, u);
+      yn = yn.v > 0 ? yn : mkd(0.0);
+      Dual s = dsqrt(y1 * y1 + y2 * y2);
+      if (s.v > mu * yn.v) {
+        Dual f = mu * yn / s;
+        y1 = y1 * f;
+        y2 = y2 * f;
+      }
+      for (int a = 0; a < 3; ++a) {
+        Dual yw = yn * K.n[a] + y1 * K.t1[a] + y2 * K.t2[a];
+        lam_new[3 * c + a] = (1.0 - om) * L[a] + om * yw;
+      }
+    }
+    lam.swap(lam_new);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      Dual acc[3] = {mkd(0), mkd(0), mkd(0)};
+      for (int64_t q = start[i]; q < start[i + 1]; ++q) {
+        int64_t c = inc[q];
+        double sg = (cs[c].i == i) ? 1.0 : -1.0;
+        for (int a = 0; a < 3; ++a) acc[a] = acc[a] + sg * lam[3 * c + a];
+      }
+      for (int a = 0; a < 3; ++a) w[3 * i + a] = w0[3 * i + a] + acc[a] / mass[i];
+    }
+  }
+
+  // ---- symplectic Euler
+  for (int64_t q = 0; q < 3 * n; ++q) {
+    V[q] = w[q];
+    X[q] = X[q] + P->dt * V[q];
+    x[q] = X[q].v;
+    dx[q] = X[q].d;
+    v[q] = V[q].v;
+    dv[q] = V[q].d;
+  }
+  if (advance_bodies)
+    for (int b = 0; b < nb; ++b) advance_body_dual(DB[b], P->dt);
+  for (int b = 0; b < nb; ++b) {
+    for (int q = 0; q < 9; ++q) {
+      bodies[b].R[q] = DB[b].R[q].v;
+      dbodies[b].R[q] = DB[b].R[q].d;
+    }
+    for (int q = 0; q < 3; ++q) {
+      bodies[b].t[q] = DB[b].t[q].v;
+      dbodies[b].t[q] = DB[b].t[q].d;
+    }
+  }
+  return C;
+}
+
+int32_t ggo_sizeof_body_tan() { return (int32_t)sizeof(BodyTan); }
+
+}  // extern "C"

@@ -2,14 +2,15 @@
 
 Chooses, for a given workload, the detection work-item node size
 (``tile_node_shift``: Z-order nodes of 2^shift cells), the LDS budget of a
-detection tile (``tile_max_cells``, ``tile_max_stage``) and the interval between
-spatial re-sorts (``reorder_every``), by timing a few steps of each candidate
-through the C ABI.  These parameters change only memory layout and work
-decomposition: every output is bitwise identical across them (the GPU tests
-check this), so the choice is free of numerical side effects.  The cell size
-and hash-table size are left at the method's defaults (c = 2 r_max (1 + 2^-10),
-n_h = 2 n per environment, the heuristic of Sec. II-B) because they change the
-summation order of partner lists.
+detection tile (``tile_max_cells``, ``tile_max_stage``), the interval between
+spatial re-sorts (``reorder_every``) and then the hash-table size n_h (Eq. (6);
+Sec. II-B's heuristic is n_h = 2 n), by timing a few steps of each candidate
+through the C ABI.  These parameters change only memory layout, bucket
+aliasing and work decomposition: partners are listed by (neighbour cell,
+original index), never by bucket, so every output is bitwise identical across
+them (the GPU tests check this) and the choice is free of numerical side
+effects.  The cell size is left at its default (c = 2 r_max (1 + 2^-10)) because
+it changes which cell, and so which list position, a partner falls in.
 
 Results are cached in a JSON file keyed by device, particle count, particles
 per cell and body count.
@@ -70,6 +71,11 @@ def candidates(ppc):
     return out
 
 
+def hash_factors():
+    """Table sizes tried, as multiples of the particle count (2 is the default)."""
+    return (0.5, 1.0, 4.0, 8.0)
+
+
 def key_of(n, ppc, n_bodies):
     try:
         import torch
@@ -95,8 +101,8 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             cache = {}
         if key in cache:
             return dict(cache[key]["params"])
-    best, best_t, results = None, float("inf"), []
-    for cand in candidates(ppc):
+
+    def timed(cand):
         kw = dict(sim_kwargs)
         kw.update(cand)
         kw["profile"] = True
@@ -111,14 +117,25 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
         except gg.GGError as e:
             if verbose:
                 print("autotune: candidate failed", cand, e)
-            continue
-        results.append((t, cand, st["detect_fallback"]))
+            return None
         if verbose:
             print(f"autotune: {cand} -> {1e3 * t:.3f} ms/step, fallback items {st['detect_fallback']}")
-        if t < best_t:
+        return t
+
+    best, best_t = None, float("inf")
+    for cand in candidates(ppc):
+        t = timed(cand)
+        if t is not None and t < best_t:
             best, best_t = cand, t
     if best is None:
         return {}
+    # then the table size, with the best launch shape
+    n = len(x)
+    for factor in hash_factors():
+        cand = dict(best, hash_size=max(1, int(factor * n)))
+        t = timed(cand)
+        if t is not None and t < best_t:
+            best, best_t = cand, t
     if use_cache:
         cache[key] = {"params": best, "ms_per_step": 1e3 * best_t}
         os.makedirs(os.path.dirname(path), exist_ok=True)

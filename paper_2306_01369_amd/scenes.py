@@ -273,15 +273,23 @@ def batched_scene(seed=0, n_envs=256, lo=8192, hi=65536, r=0.003, n_steps=100,
 
 def diff_scene(seed=0, n=32768, r=0.003):
     """32,768 spheres (r = 3 mm) resting in a 0.3 x 0.3 m walled footprint
-    with a capsule tool 1 mm above the bed; 50 steps."""
+    (13 full layers and part of a 14th); a capsule tool (radius 2 cm, 15 cm
+    between cap centres, axis along y) whose lowest point starts 1 mm above
+    the full layers at x = 0.1 m, moving at (0.2, 0, -0.1) m/s; 50 steps."""
     rng = np.random.default_rng(seed)
     pos = packed_bed(n, r, 0.0, 0.3, 0.0, 0.3, rng)
-    top = float(pos[:, 2].max()) + r
+    top = surface_height(pos, r)
     Rm = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], float)   # axis along world y
-    cap = capsule_tool((0.1, 0.15, top + 0.001 + 0.02), 0.02, 0.075, nu=(0.2, 0, -0.05), R=Rm)
+    cap = capsule_tool((0.1, 0.15, top + 0.001 + 0.02), 0.02, 0.075, nu=(0.2, 0, -0.1), R=Rm)
     bodies = walled_box(0.0, 0.3, 0.0, 0.3) + [cap]
     return Scene(f"diff-{n}", _f32(pos), np.zeros((n, 3), np.float32),
                  np.full(n, r, np.float32), bodies, n_steps=50)
+
+
+def surface_height(pos, r):
+    """Top of the full layers of a bed: the 99th percentile of z plus r (a
+    partly filled top layer holds fewer than 1% of the grains)."""
+    return float(np.percentile(np.asarray(pos)[:, 2], 99.0)) + float(r)
 
 
 def polydisperse_radii(n, rng, median=0.002, sigma=0.25, lo=0.001, hi=0.004):

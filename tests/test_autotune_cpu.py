@@ -34,3 +34,8 @@ def test_candidates_fit_the_lds_budget():
             lds = (2 * c["tile_max_cells"] + 1) * 4 + c["tile_max_stage"] * 24
             assert lds <= 64 * 1024
             assert c["tile_max_stage"] <= 2048 and c["tile_max_cells"] <= 4096
+
+
+def test_hash_sizes_tried_exclude_the_default_and_stay_positive():
+    f = autotune.hash_factors()
+    assert 2.0 not in f and all(x > 0 for x in f)

@@ -258,3 +258,62 @@ def test_autograd_function_round_trip():
         "grads": staticmethod(lambda X, V: (np.tile([0.0, 0.0, 1.0], (len(X), 1)), np.tile(loss.c, (len(V), 1))))})())
     np.testing.assert_allclose(x0.grad.numpy(), gx0, rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(t.grad.numpy(), gtw, rtol=1e-5, atol=1e-6)
+
+
+def test_differentiable_bed_gradients_along_16_directions():
+    """32,768 grains (r = 3 mm) resting in a 0.3 x 0.3 m footprint, a capsule
+    tool pushing into the surface for 50 steps with per-step twists as
+    parameters; L = sum_i sigmoid(-SDF_target(x_i)/1 mm) for a 10 x 10 x 5 cm
+    target box straddling the bed surface ahead of the tool.  The adjoint
+    (checkpoint every 10 steps) against the oracle's exact forward-mode
+    derivative (dual numbers, the adjoint's decisions) along 8 unit directions
+    in x0 and 8 in the tool's twists: the double build within 1e-3; the binary32
+    build's error is reported beside it.  Central differences are printed for
+    comparison: they average across non-smooth points of the projection."""
+    from paper_2306_01369_amd import scenes as S
+    from gradcheck import jvp_directional, oracle_rollout
+    sc = S.diff_scene()
+    x, v, r, bodies = sc.x, sc.v, sc.radius, sc.bodies
+    steps = 50
+    nb = len(bodies)
+    tw = np.zeros((steps, nb, 6))
+    tw[:, -1, :3] = np.float32(sc.bodies[-1]["nu"])
+    top = S.surface_height(x, float(r[0]))
+    loss = TargetLoss((0.15, 0.15, top), (0.05, 0.05, 0.025), width=1e-3)
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=EXACT_G)
+    say("config-4 gradients: n", len(x), "steps", steps)
+    out = {}
+    for prec in (1, 0):
+        (gx0, gv0, gtw), st = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=10, precision=prec, **kw)
+        out[prec] = (gx0, gtw)
+        say("precision", prec, "contacts at the last step", st["n_pp"], st["n_pb"])
+    assert st["n_pp"] > 50000 and st["n_pb"] > 0
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    _, _, base = oracle_rollout(x64, v64, r, bodies, tw, detail=True, **kw)
+    rng = np.random.default_rng(2024)
+    errs = {0: [], 1: []}
+    for k in range(16):
+        dx = np.zeros(x.shape)
+        dt_ = np.zeros_like(tw)
+        if k < 8:
+            dx = rng.normal(size=x.shape)
+            dx /= np.linalg.norm(dx)
+        else:
+            dt_[:, -1, :] = rng.normal(size=(steps, 6))
+            dt_ /= np.linalg.norm(dt_)
+        ref = jvp_directional(loss, x64, v64, r, bodies, tw, (dx, np.zeros(x.shape), dt_), **kw)
+        for prec in (1, 0):
+            gx0, gtw = out[prec]
+            an = np.sum(gx0 * dx) + np.sum(gtw * dt_)
+            errs[prec].append(abs(an - ref) / max(abs(ref), 1e-12))
+        fd = None
+        if k in (0, 8):
+            h = 1e-6
+            xp, vp, _ = oracle_rollout(x64 + h * dx, v64, r, bodies, tw + h * dt_, fixed=base, **kw)
+            xm, vm, _ = oracle_rollout(x64 - h * dx, v64, r, bodies, tw - h * dt_, fixed=base, **kw)
+            fd = (loss(xp, vp) - loss(xm, vm)) / (2 * h)
+        say("direction", k, "x0" if k < 8 else "twist", "jvp", ref, "central difference", fd,
+            "rel err fp64", errs[1][-1], "fp32", errs[0][-1])
+        assert abs(ref) > 0
+    say("max rel err: fp64", max(errs[1]), "fp32", max(errs[0]))
+    assert max(errs[1]) <= REL_TOL
