@@ -192,7 +192,8 @@ typedef struct {
   int64_t capacity;       /* contact capacity per particle */
   int64_t last_status;    /* gg_status of the last gg_step call */
   int64_t n;              /* particles */
-  int64_t n_buckets;      /* hash buckets over all environments */
+  int64_t n_buckets;      /* buckets of the internal cell table over all environments (per
+                             environment hash_size rounded up to a multiple of 64) */
   double ms_detect;       /* profiled: cell keys + sort + detection, summed over the last call */
   double ms_pja;          /* profiled: projected-Jacobi sweeps, summed */
   double ms_integrate;    /* profiled: position update, summed */

@@ -123,8 +123,9 @@ struct gg_sim {
   int64_t n = 0;
   int32_t n_envs = 1;
   std::vector<int64_t> env_off;
-  std::vector<int32_t> env_nh, env_boff;
-  int64_t n_buckets = 0;
+  std::vector<int32_t> env_nh, env_boff;    // Eq. (6) table per env (the reported cell index)
+  std::vector<int32_t> env_tblk, env_toff;  // internal bucket table per env (blocks of 64 buckets)
+  int64_t n_buckets = 0;                    // internal buckets in all
   float cell = 0, inv_c = 0, r_max = 0, r_min = 0;
   int K = 0, K_pp = 0;
   int64_t n_pad = 0;
@@ -151,6 +152,8 @@ struct gg_sim {
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
   void *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
+  int32_t* h6 = nullptr;  // Eq. (6) cell index of each particle at the last detection
+  int32_t *d_env_tblk = nullptr, *d_env_toff = nullptr;
   int32_t *env_of = nullptr, *d_env_nh = nullptr, *d_env_boff = nullptr, *d_body_lo = nullptr,
           *d_body_hi = nullptr;
   ggk::DevBody* d_bodies = nullptr;
@@ -281,6 +284,8 @@ ggk::EnvTables env_tables(const gg_sim* s) {
   t.env_of = s->env_of;
   t.nh = s->d_env_nh;
   t.boff = s->d_env_boff;
+  t.tblk = s->d_env_tblk;
+  t.toff = s->d_env_toff;
   t.body_lo = s->d_body_lo;
   t.body_hi = s->d_body_hi;
   return t;
@@ -291,7 +296,8 @@ void free_all(gg_sim* s) {
                   s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
                   s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
-                  s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp};
+                  s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp, s->h6,
+                  s->d_env_tblk, s->d_env_toff};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (s->h_bodies) (void)hipHostFree(s->h_bodies);
@@ -429,15 +435,17 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   const size_t dlds = detect_lds_bytes(s);
   const ggk::EnvTables et = env_tables(s);
   const int nh1 = s->env_nh[0];
+  const int blk1 = s->env_tblk[0];
   hipStream_t S = s->stream;
-  ggk::k_key<R><<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, et, s->h, s->rank, s->counts, s->ctl, st);
+  ggk::k_key<R><<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, blk1, et, s->h, s->h6, s->rank, s->counts,
+                                             s->ctl, st);
   ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
   ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
   ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
                                                  s->os);
   ggk::k_detect<R><<<dgrid, ggk::kDetBlock, dlds, S>>>(
-      n, s->K, io.x, io.v, s->orig, s->inv_c, nh1, et, s->bstart, s->sidx, (const V*)s->xs, s->os, s->item_start,
+      n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os, s->item_start,
       &s->ctl->items, bod, nb, (R)s->p.gravity[0], (R)s->p.gravity[1], (R)s->p.gravity[2], (R)s->p.dt,
       s->p.mass_split, max_cells, max_stage, io.ncon, io.partner, io.Psi, io.w[0], s->ctl, st);
 }
@@ -643,15 +651,19 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (!(std::fabs(std::nearbyint(s)) < 1073741824.0f))
       return fail(GG_ERR_INVALID, "position too far from the origin for the cell size (|x/c| >= 2^30)");
   }
-  std::vector<int32_t> env_nh(n_envs), env_boff(n_envs);
-  int64_t total = 0;
+  std::vector<int32_t> env_nh(n_envs), env_boff(n_envs), env_tblk(n_envs), env_toff(n_envs);
+  int64_t total = 0, total_tab = 0;
   for (int e = 0; e < n_envs; ++e) {
     int64_t ne = off[e + 1] - off[e];
     int64_t nh = params->hash_size > 0 ? params->hash_size : std::max<int64_t>(1, 2 * ne);
     env_nh[e] = (int32_t)nh;
     env_boff[e] = (int32_t)total;
     total += nh;
-    if (total > ((int64_t)1 << 31) - 2) return fail(GG_ERR_INVALID, "total hash buckets exceed 2^31 - 2");
+    const int64_t blk = (nh + 63) / 64;
+    env_tblk[e] = (int32_t)blk;
+    env_toff[e] = (int32_t)total_tab;
+    total_tab += 64 * blk;
+    if (total_tab > ((int64_t)1 << 31) - 2) return fail(GG_ERR_INVALID, "total hash buckets exceed 2^31 - 2");
   }
 
   gg_sim* s = new (std::nothrow) gg_sim();
@@ -679,7 +691,9 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->env_off = off;
   s->env_nh = env_nh;
   s->env_boff = env_boff;
-  s->n_buckets = total;
+  s->env_tblk = env_tblk;
+  s->env_toff = env_toff;
+  s->n_buckets = total_tab;
   s->cell = cell;
   s->inv_c = inv_c;
   s->r_max = rmax;
@@ -689,7 +703,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->body_lo.assign(n_envs, 0);
   s->body_hi.assign(n_envs, 0);
   s->stats.n = n;
-  s->stats.n_buckets = total;
+  s->stats.n_buckets = total_tab;
 
   DeviceGuard g(s->dev);
   auto bail = [&](gg_status code) {
@@ -710,9 +724,10 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   bool ok = dev_alloc_bytes(&s->x, N4) == hipSuccess && dev_alloc_bytes(&s->v, N4) == hipSuccess &&
             dev_alloc_bytes(&s->wa, N4) == hipSuccess && dev_alloc_bytes(&s->wb, N4) == hipSuccess &&
             dev_alloc(&s->h, N) == hipSuccess && dev_alloc(&s->rank, N) == hipSuccess &&
-            dev_alloc(&s->counts, (size_t)total) == hipSuccess &&
-            dev_alloc(&s->bstart, (size_t)total + 1) == hipSuccess &&
-            dev_alloc(&s->bsum, (size_t)(total + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
+            dev_alloc(&s->h6, N) == hipSuccess &&
+            dev_alloc(&s->counts, (size_t)total_tab) == hipSuccess &&
+            dev_alloc(&s->bstart, (size_t)total_tab + 1) == hipSuccess &&
+            dev_alloc(&s->bsum, (size_t)(total_tab + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
             dev_alloc(&s->sidx, N) == hipSuccess && dev_alloc(&s->ncon, N) == hipSuccess &&
             dev_alloc(&s->ctl, 1) == hipSuccess && dev_alloc_bytes(&s->x2, N4) == hipSuccess &&
             dev_alloc_bytes(&s->v2, N4) == hipSuccess && dev_alloc(&s->orig, N) == hipSuccess &&
@@ -730,6 +745,8 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (ok && n_envs > 1) {
     ok = dev_alloc(&s->env_of, N) == hipSuccess && dev_alloc(&s->d_env_nh, (size_t)n_envs) == hipSuccess &&
          dev_alloc(&s->d_env_boff, (size_t)n_envs) == hipSuccess &&
+         dev_alloc(&s->d_env_tblk, (size_t)n_envs) == hipSuccess &&
+         dev_alloc(&s->d_env_toff, (size_t)n_envs) == hipSuccess &&
          dev_alloc(&s->d_body_lo, (size_t)n_envs) == hipSuccess &&
          dev_alloc(&s->d_body_hi, (size_t)n_envs) == hipSuccess;
   }
@@ -759,7 +776,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (e == hipSuccess) e = hipMemcpy(s->x, px, n * s->es4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->v, pv, n * s->es4, hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total * 4);
+  if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total_tab * 4);
   if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
   if (e == hipSuccess && n > 0) {
     ggk::k_iota<<<(int)((n + 255) / 256), 256>>>((int)n, s->orig);
@@ -774,6 +791,8 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     e = hipMemcpy(s->env_of, eo.data(), N * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->d_env_nh, env_nh.data(), n_envs * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->d_env_boff, env_boff.data(), n_envs * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_env_tblk, env_tblk.data(), n_envs * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_env_toff, env_toff.data(), n_envs * 4, hipMemcpyHostToDevice);
     std::vector<int32_t> zeros(n_envs, 0);
     if (e == hipSuccess) e = hipMemcpy(s->d_body_lo, zeros.data(), n_envs * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->d_body_hi, zeros.data(), n_envs * 4, hipMemcpyHostToDevice);
@@ -1361,7 +1380,7 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
         ggk::k_unpermute_w<float><<<blocks, 256, 0, s->stream>>>((int)n, s->orig, (const float4*)s->x, f);
     }
     if (field == GG_FIELD_CELL_INDEX)
-      ggk::k_unpermute_i64<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->h, (int64_t*)s->tmp);
+      ggk::k_unpermute_i64<<<blocks, 256, 0, s->stream>>>((int)n, s->orig, s->h6, (int64_t*)s->tmp);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(dst, s->tmp, (size_t)need, kind, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));

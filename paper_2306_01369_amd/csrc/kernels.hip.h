@@ -104,10 +104,12 @@ struct Ctl {                    // device control block, one per simulation
   int32_t items;                // detection work items (set when they are built)
 };
 
-struct EnvTables {   // per-environment hash tables (batched form)
+struct EnvTables {   // per-environment tables (batched form)
   const int32_t* env_of;       // particle -> env (nullptr: one env)
-  const int32_t* nh;           // buckets per env
-  const int32_t* boff;         // bucket offset per env
+  const int32_t* nh;           // Eq. (6) buckets per env (the reported cell index)
+  const int32_t* boff;         // Eq. (6) bucket offset per env
+  const int32_t* tblk;         // internal table: blocks of 64 buckets per env
+  const int32_t* toff;         // internal table: first bucket of env
   const int32_t* body_lo;      // first body of env (bodies sorted by env)
   const int32_t* body_hi;      // one past last body of env
 };
@@ -385,6 +387,29 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t morton_cell(int k0, int k1, int k2) {
+  return spread10((uint32_t)(k0 + 512)) | (spread10((uint32_t)(k1 + 512)) << 1) |
+         (spread10((uint32_t)(k2 + 512)) << 2);
+}
+
+// Bucket of a cell in the internal table that the counting sort and the
+// neighbour queries use (n_blk blocks of 64 buckets).  The Z-order node of
+// 4 x 4 x 4 cells holding the cell picks a block through a mixing hash
+// (Fibonacci hashing of the node number, then a multiply-shift range
+// reduction); the node's 64 cells take consecutive buckets of that block in
+// Z-order.  Cells that collide share a bucket and are told apart by their
+// coordinates, as with any spatial hash; since neighbouring cells mostly
+// share a block, a query's buckets and their members sit together in memory,
+// which the XOR hash of Eq. (6) scatters.  The reported cell index is still
+// Eq. (6).
+__device__ __forceinline__ int table_bucket(int k0, int k1, int k2, int n_blk) {
+  const uint32_t m = morton_cell(k0, k1, k2);
+  unsigned long long z = (unsigned long long)(m >> 6) * 0x9E3779B97F4A7C15ull;
+  z ^= z >> 31;
+  const uint32_t blk = (uint32_t)(((z >> 32) * (unsigned long long)(uint32_t)n_blk) >> 32);
+  return (int)(blk * 64u + (m & 63u));
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const V4<R>* __restrict__ x, float inv_c,
                                                         const int32_t* __restrict__ env_of,
@@ -394,8 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const V4<R>* __re
   const float4 p = f32of(x[i]);
   bool ok = true;
   const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
-  const uint32_t m = spread10((uint32_t)(k0 + 512)) | (spread10((uint32_t)(k1 + 512)) << 1) |
-                     (spread10((uint32_t)(k2 + 512)) << 2);
+  const uint32_t m = morton_cell(k0, k1, k2);
   const unsigned long long e = env_of ? (unsigned long long)env_of[i] : 0ull;
   keys[i] = (e << 30) | (unsigned long long)m;
 }
@@ -484,12 +508,14 @@ __global__ __launch_bounds__(kBlock) void k_permute(int n, const int32_t* __rest
 }
 
 // ------------------------------------------------------ hash-bucket table
-// Cell keys and bucket counters.  rank[i] is the arrival order of i in its
-// bucket; the order inside a bucket is irrelevant downstream because the
-// members of each cell are re-sorted by original index when staged.
+// Cell keys and bucket counters: the internal bucket (table_bucket) for the
+// counting sort, and the cell index of Eq. (6) (h6, reported to the caller).
+// rank[i] is the arrival order of i in its bucket; the order inside a bucket
+// is irrelevant downstream because the members of each cell are re-sorted by
+// original index when staged.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__ x, float inv_c, int nh,
-                                                EnvTables env, int32_t* __restrict__ h,
+__global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__ x, float inv_c, int nh, int n_blk,
+                                                EnvTables env, int32_t* __restrict__ h, int32_t* __restrict__ h6,
                                                 int32_t* __restrict__ rank, int32_t* __restrict__ counts,
                                                 Ctl* ctl, int step) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->err == 0) {
@@ -502,15 +528,18 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__
   int k0 = cell_coord(p.x, inv_c, ok);
   int k1 = cell_coord(p.y, inv_c, ok);
   int k2 = cell_coord(p.z, inv_c, ok);
-  int bucket;
+  int bucket, cell;
   if (env.env_of) {
     int e = env.env_of[i];
-    bucket = env.boff[e] + hash_cell(k0, k1, k2, env.nh[e]);
+    cell = env.boff[e] + hash_cell(k0, k1, k2, env.nh[e]);
+    bucket = env.toff[e] + table_bucket(k0, k1, k2, env.tblk[e]);
   } else {
-    bucket = hash_cell(k0, k1, k2, nh);
+    cell = hash_cell(k0, k1, k2, nh);
+    bucket = table_bucket(k0, k1, k2, n_blk);
   }
   if (!ok) set_error(ctl, 5 /* GG_ERR_NONFINITE */, step);
   h[i] = bucket;
+  h6[i] = cell;
   rank[i] = atomicAdd(&counts[bucket], 1);
 }
 
@@ -712,7 +741,7 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // Contact detection over work items (runs of at most kDetBlock particles of one
 // Z-order node); each workgroup takes a contiguous range of items.
 // Tile path: the bounding box of the item's cells, widened by one cell, is
-// looked up once per cell through the hash table (bucket of Eq. (6)); the
+// looked up once per cell through the bucket table (table_bucket); the
 // buckets' members are copied to LDS, marked by whether they lie in the cell
 // queried (buckets alias), and each cell's members are sorted by original
 // index; every particle then tests the 27 cells around it from LDS.  Fallback
@@ -725,7 +754,7 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 template <typename R>
 __global__ __launch_bounds__(kDetBlock) void k_detect(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
-    float inv_c, int nh, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    float inv_c, int n_blk, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
@@ -756,10 +785,10 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     bool ok = true;
     const int k0 = cell_coord(p32.x, inv_c, ok), k1 = cell_coord(p32.y, inv_c, ok), k2 = cell_coord(p32.z, inv_c, ok);
     const int e_i = (env.env_of && active) ? env.env_of[i] : 0;
-    int tab_n = nh, tab_off = 0, b_lo = 0, b_hi = n_bodies;
+    int tab_n = n_blk, tab_off = 0, b_lo = 0, b_hi = n_bodies;
     if (env.env_of && active) {
-      tab_n = env.nh[e_i];
-      tab_off = env.boff[e_i];
+      tab_n = env.tblk[e_i];
+      tab_off = env.toff[e_i];
       b_lo = env.body_lo[e_i];
       b_hi = env.body_hi[e_i];
     }
@@ -772,16 +801,16 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     const int NC = tile ? Dx * Dy * Dz : 0;
     tile = tile && NC <= max_cells;
     const int ex = lo0 - 1, ey = lo1 - 1, ez = lo2 - 1;
-    int t_n = nh, t_off = 0;
+    int t_n = n_blk, t_off = 0;
     if (env.env_of && tile) {
-      t_n = env.nh[bb[3]];
-      t_off = env.boff[bb[3]];
+      t_n = env.tblk[bb[3]];
+      t_off = env.toff[bb[3]];
     }
     if (tile) {
       // bucket extents of every cell of the box: independent loads
       for (int c = threadIdx.x; c < NC; c += kDetBlock) {
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
-        const int hb = t_off + hash_cell(cx, cy, cz, t_n);
+        const int hb = t_off + table_bucket(cx, cy, cz, t_n);
         const int s0 = start[hb];
         cell_s[c] = s0;
         cell_off[c] = start[hb + 1] - s0;
@@ -849,7 +878,7 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
           for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
               const int c0 = k0 + dx, c1 = k1 + dy, c2 = k2 + dz;
-              const int hb = tab_off + hash_cell(c0, c1, c2, tab_n);
+              const int hb = tab_off + table_bucket(c0, c1, c2, tab_n);
               const int s0 = start[hb], s1 = start[hb + 1];
               const int first = cnt;
               for (int q = s0; q < s1; ++q) {
