@@ -144,6 +144,7 @@ struct gg_sim {
   int32_t *mv[2] = {nullptr, nullptr};                 // permutation values
   int32_t *rs_hist = nullptr, *rs_bsum = nullptr;      // radix histograms and their scan
   int rs_nb = 0, rs_passes = 0;
+  int det_grid = 2048;  // detection workgroups: what the device holds at once (occupancy API)
   void* xs = nullptr;                                  // bucket-ordered positions
   int32_t* os = nullptr;                               // bucket-ordered original indices
   int32_t *it_f = nullptr, *it_e = nullptr, *it_first = nullptr, *it_g = nullptr, *it_h = nullptr;
@@ -430,7 +431,7 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int m = (int)s->n_buckets;
   const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
-  const int dgrid = std::max(1, std::min((n + 31) / 32, 2048));
+  const int dgrid = std::max(1, std::min((n + 31) / 32, s->det_grid));
   const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
   const size_t dlds = detect_lds_bytes(s);
   const ggk::EnvTables et = env_tables(s);
@@ -798,6 +799,19 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (e == hipSuccess) e = hipMemcpy(s->d_body_hi, zeros.data(), n_envs * 4, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return bail(hip_fail(nullptr, e, "upload"));
+  {
+    // detection workgroups: every resident slot once (each takes a contiguous
+    // run of work items), so no second partial wave of workgroups trails
+    int per_cu = 0, n_cu = 0;
+    const size_t dlds = detect_lds_bytes(s);
+    hipError_t oe = s->fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<double>,
+                                                                           ggk::kDetBlock, dlds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<float>,
+                                                                           ggk::kDetBlock, dlds);
+    if (oe == hipSuccess) oe = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->dev);
+    if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "occupancy query"));
+    s->det_grid = std::max(1, per_cu * n_cu);
+  }
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
   sample_memory(s);
