@@ -258,7 +258,7 @@ def bench_large(args):
     log("generating the polydisperse bed")
     sc = scenes.large_scene()
     n = sc.n
-    tile = {"tile_node_shift": 4, "tile_max_cells": 176, "tile_max_stage": 1536}
+    tile = {}
     still = [dict(b, nu=np.zeros(3), omega=np.zeros(3)) for b in sc.bodies]
     sim = gg.Sim(sc.x, sc.v, sc.radius, still, dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=20, **tile)
     settle = args.settle_steps
@@ -321,6 +321,8 @@ def bench_large(args):
         "device_bytes_peak": max(st["device_bytes_peak"], dst["device_bytes_peak"]),
         "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps},
         "detect_fallback_items": st["detect_fallback"], "detect_items": st["detect_items"],
+        "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
+                                            "detect_workgroups", "reorder_every")},
     }
 
 
@@ -411,6 +413,8 @@ def main():
                      "algorithmic_bytes_per_launch": algo},
         "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
                                "integrate": st["ms_integrate"] / steps},
+        "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
+                                            "detect_workgroups", "reorder_every")},
     }
     sim.close()
     if not args.skip_cpu_baseline:

@@ -107,10 +107,17 @@ typedef struct {
   int32_t reorder_every;  /* steps between re-sorts of the internal particle order along a
                              Z-order curve (memory locality only; results do not depend on
                              it); 0 -> 8, < 0 -> never */
-  int32_t tile_max_cells; /* detection tile limit in cells (item box + halo); 0 -> 512 */
-  int32_t tile_max_stage; /* detection tile limit in staged particles; 0 -> 768 */
+  int32_t tile_max_cells; /* detection tile limit in cells (item box + halo); 0 -> from the
+                             node size (box + one-cell halo + one cell of drift) */
+  int32_t tile_max_stage; /* detection tile limit in staged particles; 0 -> from the cells
+                             and the particles per cell */
   int32_t tile_node_shift;/* detection work items follow Z-order nodes of 2^shift cells
-                             (6 = 4x4x4), at most 128 particles each; 0 -> 6 */
+                             (6 = 4x4x4), at most tile_threads particles each; 0 -> the
+                             largest node whose particles (at the initial particles per
+                             occupied cell) fit one workgroup */
+  int32_t tile_threads;   /* detection workgroup size and work-item length: 64, 128 or
+                             256; 0 -> 256 from 2^18 particles, else 128.
+                             The tile parameters change speed only, never results. */
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL */
 } gg_params;
@@ -199,11 +206,18 @@ typedef struct {
   double ms_integrate;    /* profiled: position update, summed */
   int64_t pja_launches;   /* profiled: projected-Jacobi launches timed */
   int64_t contacts_summed;/* contacts (pairs + body) summed over the steps of the last call */
-  int64_t detect_fallback;/* detection work items (up to 128 particles each) that queried cells
-                             one particle at a time instead of through an LDS tile, last detection */
+  int64_t detect_fallback;/* detection work items (up to tile_threads particles each) that queried
+                             cells one particle at a time instead of through an LDS tile, last
+                             detection */
   int64_t detect_items;   /* detection work items */
   int64_t device_bytes_peak; /* largest device memory in use (whole device, hipMemGetInfo)
                                 seen after this simulation's allocations, backward included */
+  int32_t tile_threads;   /* detection launch shape in use (defaults resolved) */
+  int32_t tile_node_shift;
+  int32_t tile_max_cells;
+  int32_t tile_max_stage;
+  int32_t detect_workgroups; /* detection grid: workgroups resident at once on the device */
+  int32_t reorder_every;
 } gg_stats;
 
 /* Copy a field into dst (where says where dst lives).  If dst is NULL only

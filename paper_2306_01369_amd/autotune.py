@@ -1,7 +1,8 @@
 """Autotuner for the launch shape of the contact step.
 
 Chooses, for a given workload, the detection work-item node size
-(``tile_node_shift``: Z-order nodes of 2^shift cells), the LDS budget of a
+(``tile_node_shift``: Z-order nodes of 2^shift cells), the detection
+workgroup size (``tile_threads``), the LDS budget of a
 detection tile (``tile_max_cells``, ``tile_max_stage``), the interval between
 spatial re-sorts (``reorder_every``) and then the hash-table size n_h (Eq. (6);
 Sec. II-B's heuristic is n_h = 2 n), by timing a few steps of each candidate
@@ -52,22 +53,24 @@ def particles_per_cell(x, radius):
 
 
 def candidates(ppc):
-    """Launch shapes worth timing for ppc particles per occupied cell: nodes of
-    roughly 32..160 particles, LDS budget for the node's box plus a one-cell
-    halo and one cell of drift."""
+    """Launch shapes worth timing for ppc particles per occupied cell: for each
+    workgroup size (64, 128, 256 threads), nodes holding roughly 0.3 to 1.4
+    workgroups of particles, an LDS budget for the node's box plus a one-cell
+    halo and one cell of drift, and three re-sort intervals."""
     out = []
-    for shift in range(2, 10):
-        dx, dy, dz = node_dims(shift)
-        per_node = ppc * dx * dy * dz
-        if not 24 <= per_node <= 180:
-            continue
-        cells = (dx + 3) * (dy + 3) * (dz + 3)
-        stage = int(math.ceil(cells * (ppc + 0.6) * 1.1))
-        if stage > 2048 or cells > 4096:
-            continue
-        for reorder in (4, 8, 16):
-            out.append({"tile_node_shift": shift, "tile_max_cells": cells, "tile_max_stage": stage,
-                        "reorder_every": reorder})
+    for tb in (64, 128, 256):
+        for shift in range(2, 10):
+            dx, dy, dz = node_dims(shift)
+            per_node = ppc * dx * dy * dz
+            if not 0.3 * tb <= per_node <= 1.4 * tb:
+                continue
+            cells = (dx + 3) * (dy + 3) * (dz + 3)
+            stage = int(math.ceil(cells * (ppc + 0.6) * 1.1))
+            if stage > 2048 or cells > 4096:
+                continue
+            for reorder in (4, 8, 16):
+                out.append({"tile_node_shift": shift, "tile_max_cells": cells, "tile_max_stage": stage,
+                            "tile_threads": tb, "reorder_every": reorder})
     return out
 
 

@@ -53,6 +53,50 @@ int contact_bound(double r_min, double r_max) {
   return (int)std::ceil(1.25 * N);
 }
 
+// Mean particles per occupied cell (cells of edge 1/inv_c; environments
+// overlapping in space count together, which only matters for this estimate).
+double particles_per_cell(const std::vector<float>& x, int64_t n, float inv_c) {
+  if (n == 0) return 1.0;
+  size_t cap = 1;
+  while (cap < (size_t)n * 2) cap <<= 1;
+  std::vector<uint64_t> table(cap, ~0ull);
+  int64_t occupied = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t key = 0;
+    for (int a = 0; a < 3; ++a)
+      key = key * 2097143ull + (uint64_t)(int64_t)std::nearbyint(x[3 * i + a] * inv_c) + (1ull << 40);
+    uint64_t h = key * 0x9E3779B97F4A7C15ull;
+    size_t slot = (size_t)(h >> 20) & (cap - 1);
+    while (table[slot] != ~0ull && table[slot] != key) slot = (slot + 1) & (cap - 1);
+    if (table[slot] == ~0ull) {
+      table[slot] = key;
+      ++occupied;
+    }
+  }
+  return (double)n / (double)std::max<int64_t>(1, occupied);
+}
+
+// Detection launch shape from the particle count and the particles per cell:
+// the workgroup size (256 threads for large beds, 128 otherwise, so small
+// beds still spread over several workgroups), the largest Z-order node whose
+// particles fit one workgroup, and an LDS budget for the node's box
+// plus a one-cell halo and one cell of drift.  Only locality and work
+// decomposition depend on it, never results.
+void default_tile(int64_t n, double ppc, gg_params& p) {
+  if (p.tile_threads == 0) p.tile_threads = n >= (1 << 18) ? 256 : 128;
+  if (p.tile_node_shift == 0) {
+    int shift = 1;
+    while (shift < 12 && ppc * (double)(1 << (shift + 1)) <= (double)p.tile_threads) ++shift;
+    p.tile_node_shift = shift;
+  }
+  const int sh = p.tile_node_shift;
+  const int dx = 1 << ((sh + 2) / 3), dy = 1 << ((sh + 1) / 3), dz = 1 << (sh / 3);
+  const int cells = (dx + 3) * (dy + 3) * (dz + 3);
+  if (p.tile_max_cells == 0) p.tile_max_cells = std::min(cells, 4096);
+  if (p.tile_max_stage == 0)
+    p.tile_max_stage = std::min(2048, (int)std::ceil(p.tile_max_cells * (ppc + 0.6) * 1.1));
+}
+
 // Exp(dt [om]x) R by Rodrigues' formula, t += dt nu (double precision).
 void advance_pose(HostBody& B, double dt) {
   for (int a = 0; a < 3; ++a) B.t[a] += dt * B.nu[a];
@@ -237,6 +281,8 @@ gg_status check_params(const gg_params* p) {
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
+  if (p->tile_threads != 0 && p->tile_threads != 64 && p->tile_threads != 128 && p->tile_threads != 256)
+    return fail(GG_ERR_INVALID, "tile_threads must be 0, 64, 128 or 256");
   if (p->device < 0) return fail(GG_ERR_INVALID, "device must be >= 0");
   return GG_OK;
 }
@@ -408,7 +454,7 @@ void launch_reorder(gg_sim* s) {
   ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
   ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
   ggk::k_node_first<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first);
-  ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, ggk::kDetBlock, s->it_g);
+  ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, s->p.tile_threads, s->it_g);
   ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->it_bsum, 0);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_h);
   ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
@@ -422,17 +468,27 @@ size_t detect_lds_bytes(const gg_sim* s) {
   return (((2 * max_cells + 1) * 4 + 31) & ~(size_t)31) + max_stage * (s->es4 + 4 + 4);
 }
 
+// The detection kernel for a workgroup size of TB threads.
+template <typename R, int TB>
+void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, int dgrid, size_t dlds,
+                   int blk1, const ggk::EnvTables& et) {
+  using V = ggk::V4<R>;
+  ggk::k_detect<R, TB><<<dgrid, TB, dlds, s->stream>>>(
+      (int)s->n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os,
+      s->item_start, &s->ctl->items, bod, (int)s->bodies.size(), (R)s->p.gravity[0], (R)s->p.gravity[1],
+      (R)s->p.gravity[2], (R)s->p.dt, s->p.mass_split, s->p.tile_max_cells, s->p.tile_max_stage, io.ncon,
+      io.partner, io.Psi, io.w[0], s->ctl, st);
+}
+
 // Bucket table and contact detection of one step.
 template <typename R>
 void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod) {
   using V = ggk::V4<R>;
   const int n = (int)s->n;
-  const int nb = (int)s->bodies.size();
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int m = (int)s->n_buckets;
   const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
   const int dgrid = std::max(1, std::min((n + 31) / 32, s->det_grid));
-  const int max_cells = s->p.tile_max_cells, max_stage = s->p.tile_max_stage;
   const size_t dlds = detect_lds_bytes(s);
   const ggk::EnvTables et = env_tables(s);
   const int nh1 = s->env_nh[0];
@@ -445,10 +501,11 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
   ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
                                                  s->os);
-  ggk::k_detect<R><<<dgrid, ggk::kDetBlock, dlds, S>>>(
-      n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os, s->item_start,
-      &s->ctl->items, bod, nb, (R)s->p.gravity[0], (R)s->p.gravity[1], (R)s->p.gravity[2], (R)s->p.dt,
-      s->p.mass_split, max_cells, max_stage, io.ncon, io.partner, io.Psi, io.w[0], s->ctl, st);
+  switch (s->p.tile_threads) {
+    case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+    case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+    default: detect_kernel<R, 128>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+  }
 }
 
 // The projected-Jacobi sweeps of one step (the last one writes the velocity).
@@ -674,9 +731,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (s->p.density == 0.0f) s->p.density = 2500.0f;
   if (s->p.checkpoint_every == 0) s->p.checkpoint_every = 10;
   if (s->p.reorder_every == 0) s->p.reorder_every = 8;
-  if (s->p.tile_max_cells == 0) s->p.tile_max_cells = 512;
-  if (s->p.tile_max_stage == 0) s->p.tile_max_stage = 768;
-  if (s->p.tile_node_shift == 0) s->p.tile_node_shift = 6;
+  default_tile(n, particles_per_cell(hx, n, inv_c), s->p);
   {
     int bits = 30;
     while ((1 << (bits - 30)) < n_envs) ++bits;
@@ -781,7 +836,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
   if (e == hipSuccess && n > 0) {
     ggk::k_iota<<<(int)((n + 255) / 256), 256>>>((int)n, s->orig);
-    ggk::k_item_fixed<<<(int)((n + 255) / 256), 256>>>((int)n, s->item_start, &s->ctl->items);
+    ggk::k_item_fixed<<<(int)((n + 255) / 256), 256>>>((int)n, s->p.tile_threads, s->item_start, &s->ctl->items);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipDeviceSynchronize();
   }
@@ -804,14 +859,27 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     // run of work items), so no second partial wave of workgroups trails
     int per_cu = 0, n_cu = 0;
     const size_t dlds = detect_lds_bytes(s);
-    hipError_t oe = s->fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<double>,
-                                                                           ggk::kDetBlock, dlds)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<float>,
-                                                                           ggk::kDetBlock, dlds);
+    const int tb = s->p.tile_threads;
+    hipError_t oe;
+    if (s->fp64) {
+      oe = tb == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<double, 64>, tb, dlds)
+           : tb == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<double, 256>, tb, dlds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<double, 128>, tb, dlds);
+    } else {
+      oe = tb == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<float, 64>, tb, dlds)
+           : tb == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<float, 256>, tb, dlds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ggk::k_detect<float, 128>, tb, dlds);
+    }
     if (oe == hipSuccess) oe = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->dev);
     if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "occupancy query"));
     s->det_grid = std::max(1, per_cu * n_cu);
   }
+  s->stats.tile_threads = s->p.tile_threads;
+  s->stats.tile_node_shift = s->p.tile_node_shift;
+  s->stats.tile_max_cells = s->p.tile_max_cells;
+  s->stats.tile_max_stage = s->p.tile_max_stage;
+  s->stats.detect_workgroups = s->det_grid;
+  s->stats.reorder_every = s->p.reorder_every;
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
   sample_memory(s);

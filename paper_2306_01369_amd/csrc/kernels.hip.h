@@ -42,7 +42,7 @@ namespace ggk {
 
 constexpr int kBlock = 256;
 constexpr int kRsBits = 8;
-constexpr int kDetBlock = 128;
+constexpr int kDetBlock = 128;  // default detection workgroup (and work item) size
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
 
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int n, const int32_t* __rest
 }
 
 // ----------------------------------------------- detection work items
-// Work items are runs of at most kDetBlock consecutive particles of one
+// Work items are runs of at most TB (the detection workgroup size) consecutive particles of one
 // Z-order node (2^node_shift cells), so each item's cells form a compact box.
 // Built after every re-sort from the sorted keys.
 __global__ __launch_bounds__(kBlock) void k_node_flags(int n, const unsigned long long* __restrict__ keys,
@@ -656,12 +656,12 @@ __global__ __launch_bounds__(kBlock) void k_item_starts(int n, const int32_t* __
   if (k == 0) item_start[hsc[n]] = n;
 }
 
-// Fixed items of kDetBlock particles (used until the first re-sort).
-__global__ __launch_bounds__(kBlock) void k_item_fixed(int n, int32_t* __restrict__ item_start,
+// Fixed items of `item` particles (used until the first re-sort).
+__global__ __launch_bounds__(kBlock) void k_item_fixed(int n, int item, int32_t* __restrict__ item_start,
                                                        int32_t* __restrict__ n_items) {
   const int k = blockIdx.x * kBlock + threadIdx.x;
-  const int ni = (n + kDetBlock - 1) / kDetBlock;
-  if (k < ni) item_start[k] = k * kDetBlock;
+  const int ni = (n + item - 1) / item;
+  if (k < ni) item_start[k] = k * item;
   if (k == 0) {
     item_start[ni] = n;
     *n_items = ni;
@@ -738,7 +738,7 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
   }
 }
 
-// Contact detection over work items (runs of at most kDetBlock particles of one
+// Contact detection over work items (runs of at most TB particles of one
 // Z-order node); each workgroup takes a contiguous range of items.
 // Tile path: the bounding box of the item's cells, widened by one cell, is
 // looked up once per cell through the bucket table (table_bucket); the
@@ -751,8 +751,8 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // then bodies in body order, so results do not depend on the internal order or
 // on the path taken.  Also seeds the Jacobi iterate w = v + dt g and the split
 // inverse mass s_i = n_i / m_i.
-template <typename R>
-__global__ __launch_bounds__(kDetBlock) void k_detect(
+template <typename R, int TB>
+__global__ __launch_bounds__(TB) void k_detect(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
     float inv_c, int n_blk, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
@@ -760,8 +760,8 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int red8[kDetBlock / 64][8];
-  __shared__ int red[kDetBlock / 64];
+  __shared__ int red8[TB / 64][8];
+  __shared__ int red[TB / 64];
   if (ctl->err) return;
   int* cell_off = (int*)smem;                                  // max_cells + 1
   int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     }
     if (tile) {
       // bucket extents of every cell of the box: independent loads
-      for (int c = threadIdx.x; c < NC; c += kDetBlock) {
+      for (int c = threadIdx.x; c < NC; c += TB) {
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
         const int hb = t_off + table_bucket(cx, cy, cz, t_n);
         const int s0 = start[hb];
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(kDetBlock) void k_detect(
     int cnt = 0;
     if (tile) {
       // copy the members, mark those of other cells, sort by original index
-      for (int c = threadIdx.x; c < NC; c += kDetBlock) {
+      for (int c = threadIdx.x; c < NC; c += TB) {
         const int cx = ex + c % Dx, cy = ey + (c / Dx) % Dy, cz = ez + c / (Dx * Dy);
         const int s0 = cell_s[c], first = cell_off[c], m = cell_off[c + 1] - first;
         for (int u = 0; u < m; ++u) {

@@ -50,7 +50,7 @@ class Params(C.Structure):
                 ("max_contacts_per_particle", C.c_int32), ("precision", C.c_int32),
                 ("density", C.c_float), ("flags", C.c_uint32), ("reorder_every", C.c_int32),
                 ("tile_max_cells", C.c_int32), ("tile_max_stage", C.c_int32),
-                ("tile_node_shift", C.c_int32), ("device", C.c_int32),
+                ("tile_node_shift", C.c_int32), ("tile_threads", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
@@ -61,7 +61,9 @@ class Stats(C.Structure):
                 ("n_buckets", C.c_int64), ("ms_detect", C.c_double), ("ms_pja", C.c_double),
                 ("ms_integrate", C.c_double), ("pja_launches", C.c_int64),
                 ("contacts_summed", C.c_int64), ("detect_fallback", C.c_int64),
-                ("detect_items", C.c_int64), ("device_bytes_peak", C.c_int64)]
+                ("detect_items", C.c_int64), ("device_bytes_peak", C.c_int64),
+                ("tile_threads", C.c_int32), ("tile_node_shift", C.c_int32), ("tile_max_cells", C.c_int32),
+                ("tile_max_stage", C.c_int32), ("detect_workgroups", C.c_int32), ("reorder_every", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -163,7 +165,7 @@ class Sim:
                  gravity=(0.0, 0.0, -9.81), cell_size=0.0, hash_size=0, relax=1.0, mass_split=True,
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
                  profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
-                 tile_max_stage=0, tile_node_shift=0, differentiable=False, checkpoint_every=0,
+                 tile_max_stage=0, tile_node_shift=0, tile_threads=0, differentiable=False, checkpoint_every=0,
                  graph=False, precision=0):
         L = lib()
         P = Params()
@@ -185,6 +187,7 @@ class Sim:
         P.tile_max_cells = int(tile_max_cells)
         P.tile_max_stage = int(tile_max_stage)
         P.tile_node_shift = int(tile_node_shift)
+        P.tile_threads = int(tile_threads)
         P.device = device
         P.stream = stream
         n = int(x.shape[0])

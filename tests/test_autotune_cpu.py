@@ -33,6 +33,7 @@ def test_candidates_fit_the_lds_budget():
             assert c["tile_max_cells"] >= (dx + 2) * (dy + 2) * (dz + 2)
             lds = (2 * c["tile_max_cells"] + 1) * 4 + c["tile_max_stage"] * 24
             assert lds <= 64 * 1024
+            assert c["tile_threads"] in (64, 128, 256)
             assert c["tile_max_stage"] <= 2048 and c["tile_max_cells"] <= 4096
 
 

@@ -384,6 +384,18 @@ def test_tile_and_per_particle_detection_agree_bitwise():
     assert tiled == per_particle
 
 
+@pytest.mark.parametrize("threads,shift", [(64, 5), (64, 6), (256, 7)])
+def test_detection_workgroup_size_keeps_results_bitwise(threads, shift):
+    s = scenes.column_scene(n=5000, r=0.004)
+    rng = np.random.default_rng(2)
+    s.x = s.x[rng.permutation(s.n)]
+    say("detection workgroup", threads, shift)
+    ref, _ = _run_bits(s, 12)
+    got, st = _run_bits(s, 12, tile_threads=threads, tile_node_shift=shift)
+    assert got == ref
+    assert st["detect_items"] > 0
+
+
 def test_autotuned_launch_shape_keeps_results_bitwise(tmp_path, monkeypatch):
     from paper_2306_01369_amd import autotune
     monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
