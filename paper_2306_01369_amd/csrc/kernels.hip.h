@@ -224,10 +224,13 @@ __device__ __forceinline__ bool body_touch(const DevBody& B, const float4 xi) {
 // Signed gap of a particle pair, psi = ||xi - xj|| - (ri + rj) (Eq. (7) for two
 // spheres), free of cancellation: differences and squares of binary32 inputs
 // are exact in double precision, and psi = (D - S) / (sqrt(D) + s).  The
-// expression is symmetric in (i, j), so both members of a pair store the same bits.
+// expression is symmetric in (i, j) and evaluated without contraction, so
+// every kernel and both members of a pair obtain the same bits (the sweeps
+// recompute it rather than read it back).
 template <typename Q>
 __device__ __forceinline__ Q pair_gap(const Q a_x, const Q a_y, const Q a_z, const Q a_w, const Q b_x, const Q b_y,
                                       const Q b_z, const Q b_w) {
+#pragma clang fp contract(off)
   const double d0 = (double)a_x - (double)b_x;
   const double d1 = (double)a_y - (double)b_y;
   const double d2 = (double)a_z - (double)b_z;
@@ -954,6 +957,8 @@ __global__ __launch_bounds__(TB) void k_detect(
 // because the projection is isotropic in the tangent plane.  mt = 1/(s_lo +
 // s_hi) for a pair, 1/s_i for a body (mass splitting).  The particle then sums
 // its contacts' impulses in list order: w_i = w0_i + (1/m_i) sum sigma P_c.
+// The gap psi of a pair is recomputed from the two positions (pair_gap, the
+// bits detection stored), which saves streaming it; a body contact's is read.
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
@@ -983,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
     const int slot = ell_slot(i, k, K);
     const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
     const int code = partner[slot];
-    const R psi = Psi[slot];
+    R psi;
     R P0 = R(0), P1 = R(0), P2 = R(0);
     if (!first) {
       P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
@@ -994,6 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
       const bool lo = (code & kHiFlag) == 0;
       const V4<R> xj = x[j];
       const V4<R> wj = w_in[j];
+      psi = pair_gap(xi, xj);
       const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
       const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
       const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
@@ -1009,6 +1015,7 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
       sg = lo ? R(1) : R(-1);
     } else {
       R nb[3], V[3];
+      psi = Psi[slot];
       body_geometry<R>(bodies[-1 - code], xi, psi, nb, V);
       n0 = nb[0]; n1 = nb[1]; n2 = nb[2];
       u0 = wi.x - V[0]; u1 = wi.y - V[1]; u2 = wi.z - V[2];
