@@ -34,12 +34,16 @@ def _oracle_from_state(x, v, r, bodies, **kw):
                     np.asarray(r, np.float32), bodies, **kw)
 
 
-def _compare_one_step(x, v, r, bodies, label, **kw):
+def _compare_one_step(x, v, r, bodies, label, env_offsets=None, **kw):
     """Run one step on both sides from the same binary32 state and compare."""
     say(label, "n =", len(x), "bodies =", len(bodies))
-    sim = _sim_from_state(x, v, r, bodies, diagnostics=True, **kw)
+    sim = _sim_from_state(x, v, r, bodies, diagnostics=True, env_offsets=env_offsets, **kw)
     ok_kw = {k: kw[k] for k in ("dt", "alpha", "mu", "n_iters", "gravity", "mass_split", "hash_size", "cell_size")
              if k in kw}
+    if env_offsets is not None:
+        ok_kw["env"] = np.repeat(np.arange(len(env_offsets) - 1), np.diff(env_offsets)).astype(np.int32)
+        if "hash_size" not in ok_kw:
+            say(label, "(per-environment tables)")
     orc = _oracle_from_state(x, v, r, bodies, **ok_kw)
     sim.step(1)
     d = orc.step(detail=True)
@@ -168,6 +172,39 @@ def test_one_step_full_scoop_bed():
     assert d["n_pp"] > 2.5 * s.n
 
 
+def test_one_step_full_batched_beds():
+    # all 256 environments (9.7M grains) in the launch configuration the
+    # benchmark times, capsules lowered 1 cm into their beds
+    s = scenes.batched_scene(n_steps=1)
+    bodies = [dict(b) for b in s.bodies]
+    for b in bodies:
+        if b["shape"] == "capsule":
+            b["t"] = np.asarray(b["t"]) - np.array([0.0, 0.0, 0.01])
+    d = _compare_one_step(s.x, s.v, s.radius, bodies, "batched-256", env_offsets=s.env_offsets, dt=s.dt,
+                          alpha=s.alpha, mu=s.mu, n_iters=s.n_iters)
+    assert d["n_pb"] > 256 and d["n_pp"] > 2 * s.n
+
+
+def test_one_step_large_polydisperse_bed():
+    # 4,194,304 polydisperse grains, 64 sweeps, box and capsule tools pressed
+    # into the bed, from a state settled on the GPU (both sides start from the
+    # same binary32 state); the launch shape is the benchmark's
+    s = scenes.large_scene()
+    still = [dict(b, nu=np.zeros(3), omega=np.zeros(3)) for b in s.bodies]
+    sim = gg.Sim(s.x, s.v, s.radius, still, dt=s.dt, alpha=s.alpha, mu=s.mu, n_iters=20)
+    sim.step(150)
+    x, v = sim.read("pos"), sim.read("vel")
+    sim.close()
+    surface = float(np.percentile(x[:, 2] + s.radius, 99.5))
+    bodies = [dict(b) for b in s.bodies]
+    for b in bodies[-2:]:
+        low = b["params"][2] if b["shape"] == "box" else b["params"][0]
+        b["t"] = np.array([b["t"][0], b["t"][1], surface - 0.005 + low])
+    d = _compare_one_step(x, v, s.radius, bodies, "large-4M", dt=s.dt, alpha=s.alpha, mu=s.mu,
+                          n_iters=s.n_iters)
+    assert d["n_pp"] > s.n and d["n_pb"] > 1000
+
+
 # ------------------------------------------------------------------ multi-step
 
 def _stats(x, pairs, n):
@@ -192,6 +229,51 @@ def test_drop_100_steps_statistics():
     say("com gpu", sg["com"], "oracle", so["com"], "coord", sg["coord"], so["coord"])
     np.testing.assert_allclose(sg["com"], so["com"], rtol=0.01)
     assert abs(sg["coord"] - so["coord"]) <= 0.01 * so["coord"]
+
+
+def _bed_statistics(x, x0, r, pairs, n_pp, side, surface, c):
+    """Centre of mass, packing fraction of a central sub-box (3 cells from the
+    walls, the floor and the surface), mean coordination number (pair contacts
+    per grain) and the fraction of grains displaced by more than a radius."""
+    lo = np.array([3 * c, 3 * c, 3 * c])
+    hi = np.array([side - 3 * c, side - 3 * c, surface - 3 * c])
+    inside = np.all((x >= lo) & (x <= hi), axis=1)
+    vol = (4.0 / 3.0) * np.pi * np.sum(r[inside].astype(np.float64) ** 3)
+    deg = np.bincount(np.asarray(pairs[:n_pp]).ravel(), minlength=len(x))
+    moved = np.linalg.norm(x - x0, axis=1) > r
+    return {"com": x.mean(0), "phi": vol / np.prod(hi - lo), "coord": deg.mean(), "displaced": moved.mean()}
+
+
+def test_tool_in_bed_100_steps_statistics():
+    # the scoop bed's recipe at 20,000 grains with a box tool ploughing 2 cm
+    # into it: statistics after 100 chaotic steps within 1%
+    template = scenes.Scene("scoop", np.zeros((1, 3), np.float32), np.zeros((1, 3), np.float32),
+                            np.full(1, 0.002, np.float32))
+    base = scenes.scaled(template, 20000)
+    r = float(base.radius[0])
+    side = max(0.05, np.sqrt(base.n / 10.0) * 2 * r)      # the recipe's footprint
+    surface = scenes.surface_height(base.x, r)
+    tool = scenes.box_tool((0.05, side / 2, surface + 0.002 + 0.1), (0.025, 0.05, 0.1),
+                           nu=(0.3 * np.cos(np.pi / 4), 0.0, -0.3 * np.sin(np.pi / 4)))
+    bodies = base.bodies + [tool]
+    say("tool in bed 100 steps: n", base.n, "side", side)
+    sim = gg.Sim(base.x, base.v, base.radius, bodies)
+    sim.step(100)
+    orc = O.Oracle(base.x.astype(np.float64), base.v.astype(np.float64), base.radius, bodies)
+    for _ in range(99):
+        orc.step()
+    d = orc.step(detail=True)
+    c, _ = O.default_cell(base.radius)
+    x0 = base.x.astype(np.float64)
+    sg = _bed_statistics(sim.read("pos").astype(np.float64), x0, base.radius, sim.read("contacts"),
+                         sim.stats()["n_pp"], side, surface, c)
+    so = _bed_statistics(orc.x, x0, base.radius, d["pairs"], d["n_pp"], side, surface, c)
+    say("gpu", sg)
+    say("oracle", so)
+    np.testing.assert_allclose(sg["com"], so["com"], rtol=0.01)
+    for k in ("phi", "coord", "displaced"):
+        assert abs(sg[k] - so[k]) <= 0.01 * abs(so[k]), k
+    assert so["displaced"] > 0.02 and d["n_pb"] > 0
 
 
 def test_determinism_bitwise():
