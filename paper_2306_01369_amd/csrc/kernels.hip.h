@@ -754,8 +754,10 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // then bodies in body order, so results do not depend on the internal order or
 // on the path taken.  Also seeds the Jacobi iterate w = v + dt g and the split
 // inverse mass s_i = n_i / m_i.
+// (five waves per SIMD: the tile's LDS allows five workgroups per CU, and the
+// register budget that fits costs only a few bytes of spill)
 template <typename R, int TB>
-__global__ __launch_bounds__(TB) void k_detect(
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_detect(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
     float inv_c, int n_blk, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
@@ -855,24 +857,26 @@ __global__ __launch_bounds__(TB) void k_detect(
       }
       __syncthreads();
       if (active) {
+        // the three cells dx = -1, 0, 1 of a row are consecutive in the tile,
+        // and so are their staged members: one scan per row, skipping the
+        // other cells' members (sorted last within each cell), visits the
+        // partners in the same order as 27 cell scans
         for (int dz = -1; dz <= 1; ++dz)
-          for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              const int c = ((k2 + dz - ez) * Dy + (k1 + dy - ey)) * Dx + (k0 + dx - ex);
-              const int s0 = cell_off[c], s1 = cell_off[c + 1];
-              for (int q = s0; q < s1; ++q) {
-                const int j = st_j[q];
-                if (j < 0) break;          // members of other cells sort last
-                if (j == i) continue;
-                ++cand;
-                const V4<R> pj = st_x[q];
-                if (!pair_touch(p32, f32of(pj))) continue;
-                const int oj = st_o[q];
-                npp += oi < oj;
-                put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
-                ++cnt;
-              }
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int c = ((k2 + dz - ez) * Dy + (k1 + dy - ey)) * Dx + (k0 - 1 - ex);
+            const int s0 = cell_off[c], s1 = cell_off[c + 3];
+            for (int q = s0; q < s1; ++q) {
+              const int j = st_j[q];
+              if (j < 0 || j == i) continue;
+              ++cand;
+              const V4<R> pj = st_x[q];
+              if (!pair_touch(p32, f32of(pj))) continue;
+              const int oj = st_o[q];
+              npp += oi < oj;
+              put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
+              ++cnt;
             }
+          }
       }
     } else {
       fb += (threadIdx.x == 0);
