@@ -52,7 +52,7 @@ typedef enum {
   GG_ERR_UNSUPPORTED = 7  /* valid request that this build does not implement */
 } gg_status;
 
-typedef enum { GG_PLANE = 0, GG_BOX = 1, GG_CAPSULE = 2 } gg_shape;
+typedef enum { GG_PLANE = 0, GG_BOX = 1, GG_CAPSULE = 2, GG_GRID = 3 } gg_shape;
 typedef enum { GG_MEM_HOST = 0, GG_MEM_DEVICE = 1 } gg_mem;
 
 /* A kinematic rigid body (Sec. II: bodies are driven by time and receive no
@@ -61,6 +61,9 @@ typedef enum { GG_MEM_HOST = 0, GG_MEM_DEVICE = 1 } gg_mem;
  *   GG_BOX:     half extents params[0..2]
  *   GG_CAPSULE: radius params[0] around the body-frame segment
  *               (0,0,-params[1]) .. (0,0,+params[1])
+ *   GG_GRID:    SDF samples on a regular grid, trilinearly interpolated (the
+ *               pre-computed SDF of Sec. II-C for arbitrary geometry):
+ *               params[0] = index of a grid registered with gg_set_grids
  * pose = row-major [R | t] (3 x 4) mapping body to world, x_w = R p + t.
  * twist = (nu, omega): velocity of the body origin and angular velocity, both
  * in the world frame.  The pose given is the pose at the start of the next
@@ -73,6 +76,25 @@ typedef struct {
   float pose[12];
   float twist[6];
 } gg_body;
+
+/* A regular grid of SDF samples in a body's frame (Sec. II-C).  Knot (a, b, c),
+ * 0 <= a < nx, 0 <= b < ny, 0 <= c < nz, sits at the body-frame point
+ * origin + (a, b, c) / inv_spacing and holds values[offset + (c*ny + b)*nx + a].
+ * The SDF at a body-frame point p is the trilinear interpolant of the knots:
+ * per axis u = (p - origin) * inv_spacing, cell i = min(floor(u), n - 2),
+ * t = u - i; lerps a + t (b - a) along x, then y, then z.  Points with u
+ * outside [0, n - 1] on any axis are outside the geometry (no contact): the
+ * grid must contain the geometry with a margin of at least the largest
+ * particle radius.  The contact decision evaluates the interpolant in
+ * binary32 in that order without fused multiply-add; gaps and normals use the
+ * build's precision, the normal being the rotated interpolant gradient,
+ * normalised. */
+typedef struct {
+  int32_t nx, ny, nz;    /* knots per axis, each >= 2 */
+  float origin[3];       /* body-frame position of knot (0, 0, 0) */
+  float inv_spacing;     /* 1 / knot spacing (> 0) */
+  int64_t offset;        /* first value of this grid in the values array */
+} gg_grid;
 
 /* Flags for gg_params.flags */
 #define GG_FLAG_PROFILE 1u     /* time detection and projected-Jacobi phases with HIP events */
@@ -138,6 +160,16 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
  * Errors: GG_ERR_INVALID (unknown shape, bad env, non-positive extents,
  * non-finite pose or twist). */
 gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg_mem where);
+
+/* Register the grids that GG_GRID bodies refer to by index, replacing any
+ * registered before.  grids: n_grids descriptors (host memory); values:
+ * n_values floats in host or device memory (where), copied.  Each grid must
+ * lie inside the values array and every value must be finite; otherwise
+ * GG_ERR_INVALID and nothing changes.  gg_set_bodies checks grid indices
+ * against the grids registered at that time.  gg_step_backward does not
+ * differentiate grid bodies (GG_ERR_UNSUPPORTED when one is present). */
+gg_status gg_set_grids(gg_sim* sim, int32_t n_grids, const gg_grid* grids, int64_t n_values,
+                       const float* values, gg_mem where);
 
 /* Advance n_steps timesteps (>= 0).  twists: NULL keeps every body's current
  * twist, else n_steps x n_bodies x 6 floats, the twist of each body during

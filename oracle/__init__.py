@@ -18,13 +18,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-SHAPES = {"plane": 0, "box": 1, "capsule": 2}
+SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
 
 
 class Body(C.Structure):
     _fields_ = [("shape", C.c_int32), ("env", C.c_int32), ("params", C.c_float * 4),
                 ("R", C.c_double * 9), ("t", C.c_double * 3), ("nu", C.c_double * 3),
-                ("omega", C.c_double * 3)]
+                ("omega", C.c_double * 3), ("gv", C.c_void_p), ("gn", C.c_int32 * 3), ("go", C.c_float * 3),
+                ("gih", C.c_float), ("gpad", C.c_int32)]
 
 
 class BodyTan(C.Structure):
@@ -108,13 +109,29 @@ def default_cell(radius):
 
 
 def make_bodies(body_dicts):
+    """ctypes bodies from scenes-style dicts.  A "grid" body carries
+    b["grid"] = {"values": (nz, ny, nx), "origin", "inv_spacing"}; its values
+    are kept alive on the returned array (attribute ``keep``)."""
     arr = (Body * max(1, len(body_dicts)))()
+    keep = []
     for k, b in enumerate(body_dicts):
         B = arr[k]
         B.shape = SHAPES[b["shape"]]
         B.env = int(b.get("env", 0))
-        for q in range(4):
-            B.params[q] = float(np.float32(b["params"][q]))
+        if b["shape"] == "grid":
+            g = b["grid"]
+            vals = np.ascontiguousarray(g["values"], np.float32)
+            keep.append(vals)
+            B.gv = vals.ctypes.data
+            B.gn[0], B.gn[1], B.gn[2] = vals.shape[2], vals.shape[1], vals.shape[0]
+            for q in range(3):
+                B.go[q] = float(g["origin"][q])
+            B.gih = float(g["inv_spacing"])
+            for q in range(4):
+                B.params[q] = 0.0
+        else:
+            for q in range(4):
+                B.params[q] = float(np.float32(b["params"][q]))
         R = np.asarray(b["R"], dtype=np.float64).reshape(9)
         for q in range(9):
             B.R[q] = float(R[q])
@@ -122,6 +139,7 @@ def make_bodies(body_dicts):
             B.t[q] = float(b["t"][q])
             B.nu[q] = float(b["nu"][q])
             B.omega[q] = float(b["omega"][q])
+    arr.keep = keep
     return arr
 
 

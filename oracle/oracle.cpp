@@ -7,7 +7,8 @@
 //     (push-front into table[h] / next[i])                             (Sec. II-B)
 //   * the 3^3 neighbour-cell query and the sphere test ||xi-xj||^2 <= (ri+rj)^2
 //                                                                      (Sec. II-B, II-C)
-//   * particle-body contact through closed-form SDFs, psi = f_G(x) - r,
+//   * particle-body contact through closed-form SDFs, or SDF samples on a
+//     regular grid with trilinear interpolation, psi = f_G(x) - r,
 //     evaluated at the inverse body pose                               (Eq. (7), Sec. II-C)
 //   * contact frame (e1 = normal, e2/e3 any tangent basis)             (Fig. contact-frame)
 //   * projected Jacobi over the stored contact list (Alg. 1) for the NCP of
@@ -66,7 +67,7 @@ int64_t cell_coord(float x, float inv_c) {
 }
 
 // ---------------------------------------------------------------- bodies
-enum Shape { PLANE = 0, BOX = 1, CAPSULE = 2 };
+enum Shape { PLANE = 0, BOX = 1, CAPSULE = 2, GRID = 3 };
 
 struct Body {          // mirrored by the Python wrapper (ctypes)
   int32_t shape;
@@ -76,7 +77,79 @@ struct Body {          // mirrored by the Python wrapper (ctypes)
   double t[3];         // body origin in world
   double nu[3];        // linear velocity of the body origin (world)
   double omega[3];     // angular velocity (world)
+  const float* gv;     // GRID: knot values, x fastest ((c*ny + b)*nx + a)
+  int32_t gn[3];       // GRID: knots per axis
+  float go[3];         // GRID: body-frame position of knot (0, 0, 0)
+  float gih;           // GRID: 1 / knot spacing
+  int32_t gpad;
 };
+
+// Pre-computed SDF on a regular grid, trilinearly interpolated (Sec. II-C).
+// Per axis u = (p - origin) * inv_spacing; cell i = min(floor(u), n - 2),
+// t = u - i; the interpolant lerps a + t (b - a) along x, then y, then z.
+// In binary32 (the contact decision) a point with u outside [0, n - 1] on any
+// axis is outside the geometry; in FP64 u is clamped into the grid.
+const float kGridOutside = 3.0e38f;
+
+float grid_f32(const Body& b, const float p[3]) {
+  int i[3];
+  float t[3];
+  for (int a = 0; a < 3; ++a) {
+    volatile float d = p[a] - b.go[a];
+    volatile float u = d * b.gih;
+    if (!(u >= 0.0f && u <= (float)(b.gn[a] - 1))) return kGridOutside;
+    int k = (int)std::floor((float)u);
+    if (k > b.gn[a] - 2) k = b.gn[a] - 2;
+    i[a] = k;
+    t[a] = (float)u - (float)k;
+  }
+  auto V = [&](int a, int c, int e) {
+    return b.gv[((int64_t)(i[2] + e) * b.gn[1] + (i[1] + c)) * b.gn[0] + (i[0] + a)];
+  };
+  auto lerp = [](float x, float y, float t) {
+    volatile float d = y - x;
+    volatile float m = t * d;
+    return (float)(x + m);
+  };
+  float c00 = lerp(V(0, 0, 0), V(1, 0, 0), t[0]);
+  float c10 = lerp(V(0, 1, 0), V(1, 1, 0), t[0]);
+  float c01 = lerp(V(0, 0, 1), V(1, 0, 1), t[0]);
+  float c11 = lerp(V(0, 1, 1), V(1, 1, 1), t[0]);
+  float c0 = lerp(c00, c10, t[1]);
+  float c1 = lerp(c01, c11, t[1]);
+  return lerp(c0, c1, t[2]);
+}
+
+// FP64 value of the interpolant and its gradient with respect to p.
+double grid_f64(const Body& b, const double p[3], double grad[3]) {
+  int i[3];
+  double t[3];
+  for (int a = 0; a < 3; ++a) {
+    double u = (p[a] - (double)b.go[a]) * (double)b.gih;
+    u = std::min(std::max(u, 0.0), (double)(b.gn[a] - 1));
+    int k = std::min((int)std::floor(u), b.gn[a] - 2);
+    i[a] = k;
+    t[a] = u - (double)k;
+  }
+  auto V = [&](int a, int c, int e) -> double {
+    return b.gv[((int64_t)(i[2] + e) * b.gn[1] + (i[1] + c)) * b.gn[0] + (i[0] + a)];
+  };
+  // value: lerps along x, y, z
+  double c00 = V(0, 0, 0) + t[0] * (V(1, 0, 0) - V(0, 0, 0));
+  double c10 = V(0, 1, 0) + t[0] * (V(1, 1, 0) - V(0, 1, 0));
+  double c01 = V(0, 0, 1) + t[0] * (V(1, 0, 1) - V(0, 0, 1));
+  double c11 = V(0, 1, 1) + t[0] * (V(1, 1, 1) - V(0, 1, 1));
+  double c0 = c00 + t[1] * (c10 - c00);
+  double c1 = c01 + t[1] * (c11 - c01);
+  // partial derivatives of the interpolant with respect to t, times du/dp
+  double dx0 = (V(1, 0, 0) - V(0, 0, 0)) + t[1] * ((V(1, 1, 0) - V(0, 1, 0)) - (V(1, 0, 0) - V(0, 0, 0)));
+  double dx1 = (V(1, 0, 1) - V(0, 0, 1)) + t[1] * ((V(1, 1, 1) - V(0, 1, 1)) - (V(1, 0, 1) - V(0, 0, 1)));
+  double ih = (double)b.gih;
+  grad[0] = (dx0 + t[2] * (dx1 - dx0)) * ih;
+  grad[1] = ((c10 - c00) + t[2] * ((c11 - c01) - (c10 - c00))) * ih;
+  grad[2] = (c1 - c0) * ih;
+  return c0 + t[2] * (c1 - c0);
+}
 
 struct Params {
   double dt, alpha, mu, relax, density;
@@ -102,6 +175,7 @@ float sdf_f32(const Body& b, const float x[3]) {
     p[c] = s + a2;
   }
   if (b.shape == PLANE) return p[2];
+  if (b.shape == GRID) return grid_f32(b, p);
   if (b.shape == BOX) {
     float q[3], m[3];
     for (int c = 0; c < 3; ++c) {
@@ -153,6 +227,13 @@ double sdf_f64(const Body& b, const double p[3], double grad[3]) {
   if (b.shape == PLANE) {
     grad[0] = 0; grad[1] = 0; grad[2] = 1;
     return p[2];
+  }
+  if (b.shape == GRID) {
+    double f = grid_f64(b, p, grad);
+    if (!(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2] > 0)) {
+      grad[0] = 1; grad[1] = 0; grad[2] = 0;
+    }
+    return f;
   }
   if (b.shape == BOX) {
     double q[3], m[3];
@@ -616,7 +697,41 @@ struct DBody {
   int32_t shape;
   const float* params;
   Dual R[9], t[3], nu[3], om[3];
+  const Body* body;   // grid data (values, knots, origin, inv_spacing)
 };
+
+// grid_f64 on duals (the cell chosen on values).
+Dual grid_dual(const Body& b, const Dual p[3], Dual grad[3]) {
+  int i[3];
+  Dual t[3];
+  for (int a = 0; a < 3; ++a) {
+    Dual u = (p[a] - (double)b.go[a]) * (double)b.gih;
+    if (u.v < 0) u = mkd(0.0);
+    if (u.v > (double)(b.gn[a] - 1)) u = mkd((double)(b.gn[a] - 1));
+    int k = std::min((int)std::floor(u.v), b.gn[a] - 2);
+    i[a] = k;
+    t[a] = u - (double)k;
+  }
+  auto V = [&](int a, int c, int e) -> double {
+    return b.gv[((int64_t)(i[2] + e) * b.gn[1] + (i[1] + c)) * b.gn[0] + (i[0] + a)];
+  };
+  Dual c00 = V(0, 0, 0) + t[0] * (V(1, 0, 0) - V(0, 0, 0));
+  Dual c10 = V(0, 1, 0) + t[0] * (V(1, 1, 0) - V(0, 1, 0));
+  Dual c01 = V(0, 0, 1) + t[0] * (V(1, 0, 1) - V(0, 0, 1));
+  Dual c11 = V(0, 1, 1) + t[0] * (V(1, 1, 1) - V(0, 1, 1));
+  Dual c0 = c00 + t[1] * (c10 - c00);
+  Dual c1 = c01 + t[1] * (c11 - c01);
+  Dual dx0 = (V(1, 0, 0) - V(0, 0, 0)) + t[1] * ((V(1, 1, 0) - V(0, 1, 0)) - (V(1, 0, 0) - V(0, 0, 0)));
+  Dual dx1 = (V(1, 0, 1) - V(0, 0, 1)) + t[1] * ((V(1, 1, 1) - V(0, 1, 1)) - (V(1, 0, 1) - V(0, 0, 1)));
+  double ih = (double)b.gih;
+  grad[0] = (dx0 + t[2] * (dx1 - dx0)) * ih;
+  grad[1] = ((c10 - c00) + t[2] * ((c11 - c01) - (c10 - c00))) * ih;
+  grad[2] = (c1 - c0) * ih;
+  if (!(grad[0].v * grad[0].v + grad[1].v * grad[1].v + grad[2].v * grad[2].v > 0)) {
+    grad[0] = mkd(1.0); grad[1] = mkd(0.0); grad[2] = mkd(0.0);
+  }
+  return c0 + t[2] * (c1 - c0);
+}
 
 // sdf_f64 on duals (same branches, decided on values).
 Dual sdf_dual(const DBody& b, const Dual p[3], Dual grad[3]) {
@@ -625,6 +740,7 @@ Dual sdf_dual(const DBody& b, const Dual p[3], Dual grad[3]) {
     grad[0] = zero; grad[1] = zero; grad[2] = one;
     return p[2];
   }
+  if (b.shape == GRID) return grid_dual(*b.body, p, grad);
   if (b.shape == BOX) {
     Dual q[3], m[3];
     bool outside = false;
@@ -746,6 +862,7 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
   for (int b = 0; b < nb; ++b) {
     DB[b].shape = bodies[b].shape;
     DB[b].params = bodies[b].params;
+    DB[b].body = &bodies[b];
     for (int q = 0; q < 9; ++q) DB[b].R[q] = {bodies[b].R[q], dbodies[b].R[q]};
     for (int q = 0; q < 3; ++q) {
       DB[b].t[q] = {bodies[b].t[q], dbodies[b].t[q]};

@@ -25,6 +25,7 @@ struct HostBody {
   int32_t env, shape;
   float params[4];
   double R[9], t[3], nu[3], om[3];
+  int32_t grid = -1;  // GG_GRID: index of the registered grid
 };
 
 // Restores the caller's current device on scope exit.
@@ -123,8 +124,10 @@ void advance_pose(HostBody& B, double dt) {
   std::memcpy(B.R, Rn, sizeof(Rn));
 }
 
-ggk::DevBody to_dev(const HostBody& B) {
-  ggk::DevBody d;
+// grid: the registered grid of a GG_GRID body (else nullptr); values: the
+// device copy of all grids' values.
+ggk::DevBody to_dev(const HostBody& B, const gg_grid* grid, const float* values) {
+  ggk::DevBody d{};
   d.shape = B.shape;
   d.env = B.env;
   for (int q = 0; q < 4; ++q) d.params[q] = B.params[q];
@@ -139,6 +142,14 @@ ggk::DevBody to_dev(const HostBody& B) {
     d.td[q] = B.t[q];
     d.nud[q] = B.nu[q];
     d.omd[q] = B.om[q];
+  }
+  if (grid) {
+    d.gv = values + grid->offset;
+    d.gn[0] = grid->nx;
+    d.gn[1] = grid->ny;
+    d.gn[2] = grid->nz;
+    for (int q = 0; q < 3; ++q) d.go[q] = grid->origin[q];
+    d.gih = grid->inv_spacing;
   }
   return d;
 }
@@ -176,6 +187,8 @@ struct gg_sim {
 
   std::vector<HostBody> bodies;
   std::vector<int32_t> body_lo, body_hi;
+  std::vector<gg_grid> grids;       // registered SDF grids (gg_set_grids)
+  float* d_grid_values = nullptr;   // their values, device copy
 
   // device buffers.  Real-valued state is V4<R> / R of the build's precision
   // (fp64: double), so those buffers are untyped here.
@@ -344,7 +357,7 @@ void free_all(gg_sim* s) {
                   s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp, s->h6,
-                  s->d_env_tblk, s->d_env_toff};
+                  s->d_env_tblk, s->d_env_toff, s->d_grid_values};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (s->h_bodies) (void)hipHostFree(s->h_bodies);
@@ -909,7 +922,10 @@ gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_m
     if (B.env < 0 || B.env >= s->n_envs) return fail(GG_ERR_INVALID, "body env out of range");
     if (B.env < prev_env) return fail(GG_ERR_INVALID, "bodies must be grouped by env in non-decreasing order");
     prev_env = B.env;
-    if (B.shape < GG_PLANE || B.shape > GG_CAPSULE) return fail(GG_ERR_INVALID, "unknown body shape");
+    if (B.shape < GG_PLANE || B.shape > GG_GRID) return fail(GG_ERR_INVALID, "unknown body shape");
+    if (B.shape == GG_GRID &&
+        !(B.params[0] >= 0.0f && B.params[0] < (float)s->grids.size() && B.params[0] == std::floor(B.params[0])))
+      return fail(GG_ERR_INVALID, "grid body: params[0] must index a grid registered with gg_set_grids");
     for (int q = 0; q < 4; ++q)
       if (!std::isfinite(B.params[q])) return fail(GG_ERR_INVALID, "non-finite body parameter");
     if (B.shape == GG_BOX && !(B.params[0] > 0 && B.params[1] > 0 && B.params[2] > 0))
@@ -923,6 +939,7 @@ gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_m
     HostBody& H = nb[b];
     H.env = B.env;
     H.shape = B.shape;
+    H.grid = B.shape == GG_GRID ? (int32_t)B.params[0] : -1;
     for (int q = 0; q < 4; ++q) H.params[q] = B.params[q];
     for (int r = 0; r < 3; ++r) {
       for (int c = 0; c < 3; ++c) H.R[3 * r + c] = B.pose[4 * r + c];
@@ -938,6 +955,47 @@ gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_m
   gg_status st = upload_env_bodies(s);
   if (st != GG_OK) return st;
   return ensure_ell(s, compute_K(s));
+}
+
+gg_status gg_set_grids(gg_sim* s, int32_t n_grids, const gg_grid* grids, int64_t n_values, const float* values,
+                       gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (n_grids < 0 || n_grids > 4096) return fail(GG_ERR_INVALID, "n_grids must be in [0, 4096]");
+  if (n_values < 0) return fail(GG_ERR_INVALID, "n_values must be >= 0");
+  if (n_grids > 0 && !grids) return fail(GG_ERR_INVALID, "grids is NULL");
+  if (n_values > 0 && !values) return fail(GG_ERR_INVALID, "values is NULL");
+  std::vector<gg_grid> G(grids, grids + n_grids);
+  for (const gg_grid& g : G) {
+    if (g.nx < 2 || g.ny < 2 || g.nz < 2) return fail(GG_ERR_INVALID, "a grid needs at least 2 knots per axis");
+    if (!(g.inv_spacing > 0.0f) || !std::isfinite(g.inv_spacing) || !finite3(g.origin))
+      return fail(GG_ERR_INVALID, "grid origin and inv_spacing must be finite, inv_spacing > 0");
+    const int64_t m = (int64_t)g.nx * g.ny * g.nz;
+    if (g.offset < 0 || g.offset > n_values - m) return fail(GG_ERR_INVALID, "a grid lies outside the values array");
+  }
+  std::vector<float> hv((size_t)n_values);
+  DeviceGuard dg(s->dev);
+  if (!dg.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+  gg_status st = copy_in(values, (size_t)n_values * 4, where, hv.data());
+  if (st != GG_OK) return st;
+  for (float f : hv)
+    if (!std::isfinite(f)) return fail(GG_ERR_INVALID, "non-finite grid value");
+  float* d = nullptr;
+  if (n_values > 0) {
+    if (dev_alloc(&d, (size_t)n_values) != hipSuccess) return fail(GG_ERR_OOM, "grid allocation failed");
+    hipError_t e = hipMemcpy(d, hv.data(), (size_t)n_values * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(s, e, "grid upload");
+    }
+  }
+  if (s->stream) HIPCHK(s, hipStreamSynchronize(s->stream));  // no step still reads the old values
+  if (s->d_grid_values) HIPCHK(s, hipFree(s->d_grid_values));
+  s->d_grid_values = d;
+  s->grids = G;
+  return GG_OK;
 }
 
 gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where) {
@@ -957,6 +1015,9 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
     for (float f : tw)
       if (!std::isfinite(f)) return fail(GG_ERR_INVALID, "non-finite twist");
   }
+  for (const HostBody& b : s->bodies)
+    if (b.shape == GG_GRID && (b.grid < 0 || b.grid >= (int32_t)s->grids.size()))
+      return fail(GG_ERR_INVALID, "a grid body refers to a grid that is no longer registered");
   s->stats.steps_done = 0;
   s->stats.last_status = GG_OK;
   if (n_steps == 0) return GG_OK;
@@ -985,7 +1046,8 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
           cur[b].om[q] = t6[3 + q];
         }
       }
-      s->h_bodies[(size_t)st * nb + b] = to_dev(cur[b]);
+      const gg_grid* gr = cur[b].shape == GG_GRID ? &s->grids[cur[b].grid] : nullptr;
+      s->h_bodies[(size_t)st * nb + b] = to_dev(cur[b], gr, s->d_grid_values);
       s->pose_hist[(size_t)st * nb + b] = cur[b];
       advance_pose(cur[b], (double)s->p.dt);
     }
@@ -1153,6 +1215,8 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   if (!(s->p.flags & GG_FLAG_TAPE)) return fail(GG_ERR_NO_TAPE, "the simulation was created without GG_FLAG_TAPE");
   if (!s->tape_ok || s->tape_steps <= 0) return fail(GG_ERR_NO_TAPE, "no successful differentiable gg_step to reverse");
   if (s->n_envs != 1) return fail(GG_ERR_UNSUPPORTED, "the adjoint is built for one environment");
+  for (const HostBody& b : s->tape_poses)
+    if (b.shape == GG_GRID) return fail(GG_ERR_UNSUPPORTED, "the adjoint does not differentiate grid bodies");
   return s->fp64 ? backward_t<double>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where)
                  : backward_t<float>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where);
 }

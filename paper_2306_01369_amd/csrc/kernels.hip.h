@@ -46,7 +46,7 @@ constexpr int kDetBlock = 128;  // default detection workgroup (and work item) s
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
 
-struct DevBody {  // one body at one step; 240 bytes
+struct DevBody {  // one body at one step; 280 bytes
   int32_t shape, env;
   float params[4];
   float R[9];  // world <- body, row major
@@ -54,6 +54,11 @@ struct DevBody {  // one body at one step; 240 bytes
   float nu[3];
   float om[3];
   double Rd[9], td[3], nud[3], omd[3];  // the same pose and twist in double (FP64 build geometry)
+  const float* gv;                      // grid bodies: knot values, x fastest
+  int32_t gn[3];                        // knots per axis
+  float go[3];                          // body-frame position of knot (0, 0, 0)
+  float gih;                            // 1 / knot spacing
+  int32_t gpad;
 };
 
 // Four-vectors of the real type R.
@@ -185,6 +190,68 @@ __device__ __forceinline__ void to_body(const DevBody& B, R x0, R x1, R x2, R p[
   }
 }
 
+// ---------------------------------------------------------- grid SDF bodies
+// Trilinear interpolation of SDF samples on a regular grid (Sec. II-C).  The
+// binary32 form decides contact: u = (p - origin) * inv_spacing per axis (a
+// point with u outside [0, n - 1] is outside the geometry), cell
+// i = min(floor(u), n - 2), t = u - i, lerps a + t (b - a) along x, y, z.
+constexpr float kOutside = 3.0e38f;
+
+__device__ __forceinline__ float grid_sdf_f32(const DevBody& B, const float p[3]) {
+#pragma clang fp contract(off)
+  float t[3];
+  int i[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float d = p[a] - B.go[a];
+    const float u = d * B.gih;
+    if (!(u >= 0.0f && u <= (float)(B.gn[a] - 1))) return kOutside;
+    const int k = min((int)floorf(u), B.gn[a] - 2);
+    i[a] = k;
+    t[a] = u - (float)k;
+  }
+  const long long sy = B.gn[0], sz = (long long)B.gn[0] * B.gn[1];
+  const float* v = B.gv + ((long long)i[2] * sz + (long long)i[1] * sy + i[0]);
+  const float c00 = v[0] + t[0] * (v[1] - v[0]);
+  const float c10 = v[sy] + t[0] * (v[sy + 1] - v[sy]);
+  const float c01 = v[sz] + t[0] * (v[sz + 1] - v[sz]);
+  const float c11 = v[sz + sy] + t[0] * (v[sz + sy + 1] - v[sz + sy]);
+  const float c0 = c00 + t[1] * (c10 - c00);
+  const float c1 = c01 + t[1] * (c11 - c01);
+  return c0 + t[2] * (c1 - c0);
+}
+
+// The interpolant and its gradient (with respect to the body-frame point) in
+// precision Q, with u clamped into the grid (the point was inside when the
+// contact was detected).
+template <typename Q>
+__device__ __forceinline__ Q grid_sdf_grad(const DevBody& B, const Q p[3], Q g[3]) {
+  Q t[3];
+  int i[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Q u = (p[a] - (Q)B.go[a]) * (Q)B.gih;
+    u = fmin(fmax(u, Q(0)), (Q)(B.gn[a] - 1));
+    const int k = min((int)floor(u), B.gn[a] - 2);
+    i[a] = k;
+    t[a] = u - (Q)k;
+  }
+  const long long sy = B.gn[0], sz = (long long)B.gn[0] * B.gn[1];
+  const float* v = B.gv + ((long long)i[2] * sz + (long long)i[1] * sy + i[0]);
+  const Q v000 = v[0], v100 = v[1], v010 = v[sy], v110 = v[sy + 1];
+  const Q v001 = v[sz], v101 = v[sz + 1], v011 = v[sz + sy], v111 = v[sz + sy + 1];
+  const Q c00 = v000 + t[0] * (v100 - v000), c10 = v010 + t[0] * (v110 - v010);
+  const Q c01 = v001 + t[0] * (v101 - v001), c11 = v011 + t[0] * (v111 - v011);
+  const Q c0 = c00 + t[1] * (c10 - c00), c1 = c01 + t[1] * (c11 - c01);
+  const Q e0 = (v100 - v000) + t[1] * ((v110 - v010) - (v100 - v000));
+  const Q e1 = (v101 - v001) + t[1] * ((v111 - v011) - (v101 - v001));
+  const Q ih = (Q)B.gih;
+  g[0] = (e0 + t[2] * (e1 - e0)) * ih;
+  g[1] = ((c10 - c00) + t[2] * ((c11 - c01) - (c10 - c00))) * ih;
+  g[2] = (c1 - c0) * ih;
+  return c0 + t[2] * (c1 - c0);
+}
+
 // Closed-form SDFs (Sec. II-C) in binary32 with a fixed operation order: the
 // value that decides contact (psi = f - r <= 0, Eq. (7)).
 __device__ __forceinline__ float sdf_decide(const DevBody& B, float x0, float x1, float x2) {
@@ -192,6 +259,7 @@ __device__ __forceinline__ float sdf_decide(const DevBody& B, float x0, float x1
   float p[3];
   to_body<float>(B, x0, x1, x2, p);
   if (B.shape == 0) return p[2];
+  if (B.shape == 3) return grid_sdf_f32(B, p);
   if (B.shape == 1) {
     float q0 = fabsf(p[0]) - B.params[0];
     float q1 = fabsf(p[1]) - B.params[1];
@@ -258,6 +326,9 @@ __device__ __forceinline__ R body_gap(const DevBody& B, const V4<R> xi) {
   double f;
   if (B.shape == 0) {
     f = p[2];
+  } else if (B.shape == 3) {
+    double g[3];
+    f = grid_sdf_grad<double>(B, p, g);
   } else if (B.shape == 1) {
     double q0 = fabs(p[0]) - B.params[0], q1 = fabs(p[1]) - B.params[1], q2 = fabs(p[2]) - B.params[2];
     double m0 = fmax(q0, 0.0), m1 = fmax(q1, 0.0), m2 = fmax(q2, 0.0);
@@ -286,6 +357,11 @@ __device__ __forceinline__ void body_geometry(const DevBody& B, const V4<R> xi, 
   if (B.shape == 0) {
     g[0] = R(0); g[1] = R(0); g[2] = R(1);
     f = p[2];
+  } else if (B.shape == 3) {
+    f = grid_sdf_grad<R>(B, p, g);
+    if (!(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] > R(0))) {
+      g[0] = R(1); g[1] = R(0); g[2] = R(0);
+    }
   } else if (B.shape == 1) {
     R q[3], m[3];
     bool outside = false;

@@ -22,7 +22,7 @@ GG_MEM_HOST, GG_MEM_DEVICE = 0, 1
 GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS, GG_FLAG_TAPE, GG_FLAG_GRAPH = 1, 2, 4, 8
 FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "stats": 5, "dv": 6,
          "radius": 7}
-SHAPES = {"plane": 0, "box": 1, "capsule": 2}
+SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
 
 EXPORTS = ("gg_create", "gg_set_bodies", "gg_step", "gg_step_backward", "gg_read", "gg_destroy",
            "gg_status_string", "gg_error_detail")
@@ -41,6 +41,11 @@ class CapacityError(GGError):
 class Body(C.Structure):
     _fields_ = [("env", C.c_int32), ("shape", C.c_int32), ("params", C.c_float * 4),
                 ("pose", C.c_float * 12), ("twist", C.c_float * 6)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("origin", C.c_float * 3),
+                ("inv_spacing", C.c_float), ("offset", C.c_int64)]
 
 
 class Params(C.Structure):
@@ -92,6 +97,8 @@ def lib():
         L.gg_create.argtypes = [C.POINTER(Params), i32, vp, i64, vp, vp, vp, i32, C.POINTER(vp)]
         L.gg_set_bodies.restype = i32
         L.gg_set_bodies.argtypes = [vp, i32, vp, i32]
+        L.gg_set_grids.restype = i32
+        L.gg_set_grids.argtypes = [vp, i32, vp, i64, vp, i32]
         L.gg_step.restype = i32
         L.gg_step.argtypes = [vp, i32, vp, i32]
         L.gg_step_backward.restype = i32
@@ -225,9 +232,46 @@ class Sim:
             pass
 
     def set_bodies(self, bodies):
-        arr = (Body * max(1, len(bodies)))(*[make_body(b) if isinstance(b, dict) else b for b in bodies])
-        _check(lib().gg_set_bodies(self._h, len(bodies), arr, GG_MEM_HOST))
-        self.n_bodies = len(bodies)
+        """Bodies as scenes-style dicts (or gg_body records).  A "grid" body
+        carries its samples: d["grid"] = {"values": (nz, ny, nx) float32,
+        "origin": (3,), "inv_spacing": float}; the distinct grids are
+        registered (gg_set_grids) and indexed through params[0]."""
+        bodies = list(bodies)
+        grids, index, recs = [], {}, []
+        for b in bodies:
+            if isinstance(b, dict) and b.get("shape") == "grid":
+                g = b["grid"]
+                key = id(g["values"])
+                if key not in index:
+                    index[key] = len(grids)
+                    grids.append(g)
+                b = dict(b, params=[float(index[key]), 0.0, 0.0, 0.0])
+            recs.append(make_body(b) if isinstance(b, dict) else b)
+        if grids:
+            self.set_grids(grids)
+        arr = (Body * max(1, len(recs)))(*recs)
+        _check(lib().gg_set_bodies(self._h, len(recs), arr, GG_MEM_HOST))
+        self.n_bodies = len(recs)
+
+    def set_grids(self, grids):
+        """Register SDF grids: list of {"values": (nz, ny, nx), "origin", "inv_spacing"}."""
+        descs = (Grid * max(1, len(grids)))()
+        chunks, off = [], 0
+        for k, g in enumerate(grids):
+            vals = np.ascontiguousarray(g["values"], np.float32)
+            nz, ny, nx = vals.shape
+            d = descs[k]
+            d.nx, d.ny, d.nz = nx, ny, nz
+            for a in range(3):
+                d.origin[a] = float(g["origin"][a])
+            d.inv_spacing = float(g["inv_spacing"])
+            d.offset = off
+            chunks.append(vals.ravel())
+            off += vals.size
+        allv = np.concatenate(chunks) if chunks else np.zeros(1, np.float32)
+        _check(lib().gg_set_grids(self._h, len(grids), descs, int(off), allv.ctypes.data_as(C.c_void_p),
+                                  GG_MEM_HOST))
+        self._grids = list(grids)
 
     def step(self, n_steps=1, twists=None):
         pt, wt, kt = _arg(twists, np.float32)

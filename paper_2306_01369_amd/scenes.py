@@ -93,6 +93,57 @@ def capsule_tool(center, radius, half_length, nu=(0, 0, 0), omega=(0, 0, 0), R=N
             "omega": np.asarray(omega, float), "env": env}
 
 
+def sdf_grid(fn, lo, hi, inv_spacing):
+    """Samples of a distance field fn(points (m, 3) body frame) -> (m,) on the
+    regular grid with knots at lo + k / inv_spacing covering [lo, hi]: the
+    input format of grid bodies (values (nz, ny, nx), x fastest)."""
+    lo = np.asarray(lo, np.float32).astype(np.float64)   # the origin as the grid stores it
+    n = [int(np.ceil((hi[a] - lo[a]) * inv_spacing)) + 1 for a in range(3)]
+    ax = [lo[a] + np.arange(n[a]) / inv_spacing for a in range(3)]
+    zz, yy, xx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1)
+    vals = np.asarray(fn(pts), np.float64).reshape(n[2], n[1], n[0])
+    return {"values": vals.astype(np.float32), "origin": lo.astype(np.float32), "inv_spacing": float(inv_spacing)}
+
+
+def ball_grid(radius, margin, inv_spacing):
+    """Distance field of a ball of the given radius about the body origin."""
+    m = radius + margin
+    return sdf_grid(lambda p: np.linalg.norm(p, axis=1) - radius, (-m, -m, -m), (m, m, m), inv_spacing)
+
+
+def bowl_grid(radius, thickness, margin, inv_spacing):
+    """A scoop-like bowl: the lower half (z <= 0) of a spherical shell of
+    inner radius ``radius`` and the given thickness, about the body origin,
+    as the exact distance to that solid (shell distance, then the cut)."""
+    R0, R1 = radius, radius + thickness
+    m = R1 + margin
+
+    def fn(p):
+        r = np.linalg.norm(p, axis=1)
+        shell = np.maximum(r - R1, R0 - r)               # full spherical shell
+        # points above the cut plane: distance to the rim annulus in z = 0
+        rho = np.linalg.norm(p[:, :2], axis=1)
+        dr = np.maximum(np.maximum(R0 - rho, rho - R1), 0.0)
+        above = np.sqrt(dr * dr + p[:, 2] ** 2)
+        return np.where(p[:, 2] <= 0.0, shell, np.maximum(above, shell))
+
+    return sdf_grid(fn, (-m, -m, -m), (m, m, m / 2), inv_spacing)
+
+
+def affine_grid(normal, offset, lo, hi, inv_spacing):
+    """The affine field n . p - offset (a plane's distance for a unit n)."""
+    nrm = np.asarray(normal, np.float64)
+    return sdf_grid(lambda p: p @ nrm - offset, lo, hi, inv_spacing)
+
+
+def grid_tool(grid, center, nu=(0, 0, 0), omega=(0, 0, 0), R=None, env=0):
+    return {"shape": "grid", "params": [0.0, 0.0, 0.0, 0.0], "grid": grid,
+            "R": np.eye(3) if R is None else np.asarray(R, float),
+            "t": np.asarray(center, float), "nu": np.asarray(nu, float),
+            "omega": np.asarray(omega, float), "env": env}
+
+
 def walled_box(x0, x1, y0, y1, env=0, ground_z=0.0):
     """Ground plane plus four side walls of an open-top container."""
     return [

@@ -621,3 +621,73 @@ def test_fp64_build_multi_env_and_graph_replay():
         orc.step()
     sim.step(5)
     assert np.abs(sim.read("pos") - orc.x).max() <= 2e-8
+
+
+# ------------------------------------------------- grid SDF bodies
+
+def _bed_with_grid_tools(n=4000, seed=0):
+    s = scenes.column_scene(n=n, r=0.004, seed=seed)
+    top = scenes.surface_height(s.x, 0.004)
+    rng = np.random.default_rng(seed + 7)
+    bowl = scenes.grid_tool(scenes.bowl_grid(0.02, 0.004, 0.006, 512.0), (0.03, 0.03, top + 0.012),
+                            R=scenes.random_rotation(rng), nu=(0.1, 0.0, -0.2), omega=(0.5, -1.0, 0.3))
+    ball = scenes.grid_tool(scenes.ball_grid(0.01, 0.006, 512.0), (0.06, 0.05, top + 0.006),
+                            nu=(0.0, 0.05, -0.1))
+    return s, s.bodies + [bowl, ball]
+
+
+def test_one_step_bed_with_grid_tools():
+    s, bodies = _bed_with_grid_tools()
+    d = _compare_one_step(s.x, s.v, s.radius, bodies, "grid tools")
+    grid_contacts = int(np.sum(d["pairs"][d["n_pp"]:, 1] >= len(s.bodies)))
+    say("grid-body contacts", grid_contacts)
+    assert grid_contacts > 20
+
+
+def test_grid_tools_over_steps_follow_the_oracle():
+    # the double build tracks the oracle's contact sets and trajectory with
+    # moving and spinning grid tools
+    s, bodies = _bed_with_grid_tools(n=2500, seed=1)
+    kw = dict(dt=float(np.float32(1e-3)), alpha=float(np.float32(0.2)), gravity=(0.0, 0.0, float(np.float32(-9.81))))
+    say("grid tools, 25 steps, double build")
+    sim = gg.Sim(s.x, s.v, s.radius, bodies, precision=1, **kw)
+    orc = O.Oracle(s.x.astype(np.float64), s.v.astype(np.float64), s.radius, bodies, **kw)
+    n_grid = 0
+    for k in range(25):
+        sim.step(1)
+        d = orc.step(detail=True)
+        np.testing.assert_array_equal(sim.read("contacts"), d["pairs"], err_msg=f"step {k}")
+        n_grid += int(np.sum(d["pairs"][d["n_pp"]:, 1] >= len(s.bodies)))
+    assert n_grid > 100
+    assert np.abs(sim.read("pos") - orc.x).max() <= 2e-8
+
+
+def test_grid_registration_is_validated():
+    s, bodies = _bed_with_grid_tools(n=500)
+    sim = gg.Sim(s.x, s.v, s.radius, bodies)
+    good = bodies[-1]["grid"]
+    bad = [dict(good, inv_spacing=0.0), dict(good, inv_spacing=float("nan")),
+           dict(good, values=np.full((1, 4, 4), 0.1, np.float32)),
+           dict(good, values=np.where(np.arange(good["values"].size).reshape(good["values"].shape) == 5, np.inf,
+                                      good["values"]).astype(np.float32))]
+    for g in bad:
+        with pytest.raises(gg.GGError) as e:
+            sim.set_grids([g])
+        assert e.value.status == gg.GG_ERR_INVALID
+    # a body naming a grid index that is not registered
+    sim.set_grids([good])
+    with pytest.raises(gg.GGError) as e:
+        sim.set_bodies(s.bodies + [dict(bodies[-1], shape=3, params=[1.0, 0, 0, 0])])
+    assert e.value.status == gg.GG_ERR_INVALID
+    # the registered bodies still step
+    sim.set_bodies(bodies)
+    sim.step(2)
+
+
+def test_backward_does_not_differentiate_grid_bodies():
+    s, bodies = _bed_with_grid_tools(n=500)
+    sim = gg.Sim(s.x, s.v, s.radius, bodies, differentiable=True)
+    sim.step(2)
+    with pytest.raises(gg.GGError) as e:
+        sim.backward(np.zeros((s.n, 3)), None)
+    assert e.value.status == gg.GG_ERR_UNSUPPORTED

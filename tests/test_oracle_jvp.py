@@ -121,3 +121,23 @@ def test_dual_numbers_with_plain_masses_and_relaxation():
     fd, same = fd_directional(loss, x, v, r, bodies, tw, (dx, dv, dtw), h, **kw)
     assert same
     assert abs(jv - fd) <= 1e-5 * abs(fd), (jv, fd)
+
+
+def test_dual_numbers_with_a_grid_body():
+    # a spinning bowl sampled on a grid among colliding grains: the dual
+    # numbers through the trilinear interpolant and its gradient
+    x, v, r, bodies, tw, loss = _colliding(n=300, seed=13, steps=5)
+    side = 0.01 + 2.02 * 0.004 * 8
+    bowl = scenes.grid_tool(scenes.bowl_grid(0.012, 0.003, 0.006, 1024.0), (side / 2, side / 2, side / 2),
+                            R=scenes.random_rotation(np.random.default_rng(5)))
+    bodies = bodies[:-1] + [bowl]
+    rng = np.random.default_rng(14)
+    dx, dv = rng.normal(size=x.shape), rng.normal(size=v.shape)
+    dtw = np.zeros_like(tw)
+    dtw[:, -1, :] = rng.normal(size=(tw.shape[0], 6))
+    kw = dict(gravity=(0.0, 0.0, 0.0))
+    jv = jvp_directional(loss, x, v, r, bodies, tw, (dx, dv, dtw), **kw)
+    h = 1e-8 / max(np.abs(dx).max(), np.abs(dv).max(), np.abs(dtw).max())
+    fd, same = fd_directional(loss, x, v, r, bodies, tw, (dx, dv, dtw), h, **kw)
+    assert same
+    assert abs(jv - fd) <= 1e-5 * abs(fd), (jv, fd)
