@@ -166,8 +166,7 @@ gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg
  * n_values floats in host or device memory (where), copied.  Each grid must
  * lie inside the values array and every value must be finite; otherwise
  * GG_ERR_INVALID and nothing changes.  gg_set_bodies checks grid indices
- * against the grids registered at that time.  gg_step_backward does not
- * differentiate grid bodies (GG_ERR_UNSUPPORTED when one is present). */
+ * against the grids registered at that time. */
 gg_status gg_set_grids(gg_sim* sim, int32_t n_grids, const gg_grid* grids, int64_t n_values,
                        const float* values, gg_mem where);
 

@@ -240,6 +240,37 @@ __device__ __forceinline__ void sdf_hess_apply(const DevBody& B, const R p[3], c
   }
 }
 
+// Hessian of a grid body's trilinear interpolant (with respect to the
+// body-frame point) applied to w: zero on the diagonal inside a cell, the
+// mixed second differences lerped along the third axis off it, times
+// inv_spacing^2.
+template <typename R>
+__device__ __forceinline__ void grid_hess_apply(const DevBody& B, const R p[3], const R w[3], R out[3]) {
+  R t[3];
+  int i[3];
+  for (int a = 0; a < 3; ++a) {
+    R u = (p[a] - (R)B.go[a]) * (R)B.gih;
+    u = fmin(fmax(u, R(0)), (R)(B.gn[a] - 1));
+    const int k = min((int)floor(u), B.gn[a] - 2);
+    i[a] = k;
+    t[a] = u - (R)k;
+  }
+  const long long sy = B.gn[0], sz = (long long)B.gn[0] * B.gn[1];
+  const float* v = B.gv + ((long long)i[2] * sz + (long long)i[1] * sy + i[0]);
+  const R v000 = v[0], v100 = v[1], v010 = v[sy], v110 = v[sy + 1];
+  const R v001 = v[sz], v101 = v[sz + 1], v011 = v[sz + sy], v111 = v[sz + sy + 1];
+  const R Dz0 = v110 - v010 - v100 + v000, Dz1 = v111 - v011 - v101 + v001;   // d2f/dt0 dt1 at z0, z1
+  const R Ey0 = v101 - v001 - v100 + v000, Ey1 = v111 - v011 - v110 + v010;   // d2f/dt0 dt2 at y0, y1
+  const R Fx0 = v011 - v001 - v010 + v000, Fx1 = v111 - v101 - v110 + v100;   // d2f/dt1 dt2 at x0, x1
+  const R ih2 = (R)B.gih * (R)B.gih;
+  const R hxy = (Dz0 + t[2] * (Dz1 - Dz0)) * ih2;
+  const R hxz = (Ey0 + t[1] * (Ey1 - Ey0)) * ih2;
+  const R hyz = (Fx0 + t[0] * (Fx1 - Fx0)) * ih2;
+  out[0] = hxy * w[1] + hxz * w[2];
+  out[1] = hxy * w[0] + hyz * w[2];
+  out[2] = hxz * w[0] + hyz * w[1];
+}
+
 // Unit body-frame SDF gradient and value (same branches as the forward).
 template <typename R>
 __device__ __forceinline__ R sdf_grad(const DevBody& B, const R p[3], R g[3]) {
@@ -337,8 +368,23 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
           const R dd[3] = {xi.x - Bt[0], xi.y - Bt[1], xi.z - Bt[2]};
           for (int cc = 0; cc < 3; ++cc) pnt[cc] = BR[cc] * dd[0] + BR[3 + cc] * dd[1] + BR[6 + cc] * dd[2];
         }
-        R g[3];
-        sdf_grad(B, pnt, g);
+        R g[3], G[3], Gn = R(1);
+        if (B.shape == 3) {
+          // grid: the interpolant's gradient G is not unit length; the
+          // normal uses G / |G|
+          grid_sdf_grad<R>(B, pnt, G);
+          Gn = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+          if (Gn > R(0)) {
+            for (int q = 0; q < 3; ++q) g[q] = G[q] / Gn;
+          } else {
+            g[0] = R(1); g[1] = R(0); g[2] = R(0);
+            G[0] = G[1] = G[2] = R(0);
+            Gn = R(1);
+          }
+        } else {
+          sdf_grad(B, pnt, g);
+          for (int q = 0; q < 3; ++q) G[q] = g[q];
+        }
         R nr[3];
         for (int r = 0; r < 3; ++r) nr[r] = BR[3 * r] * g[0] + BR[3 * r + 1] * g[1] + BR[3 * r + 2] * g[2];
         const R psi = Psi[slot];
@@ -368,10 +414,17 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
         for (int q = 0; q < 3; ++q) gb[q] = BR[q] * ntot[0] + BR[3 + q] * ntot[1] + BR[6 + q] * ntot[2];
         for (int r = 0; r < 3; ++r)
           for (int q = 0; q < 3; ++q) Rb[3 * r + q] = ntot[r] * g[q];
-        // g = grad F(p), f = F(p)
+        // g = grad F(p) / |grad F(p)|, f = F(p)
         R pb[3];
-        sdf_hess_apply(B, pnt, g, gb, pb);
-        for (int q = 0; q < 3; ++q) pb[q] += fb * g[q];
+        if (B.shape == 3) {
+          const R gg = dot3f(g, gb);
+          R Gb[3];
+          for (int q = 0; q < 3; ++q) Gb[q] = (gb[q] - gg * g[q]) / Gn;
+          grid_hess_apply<R>(B, pnt, Gb, pb);
+        } else {
+          sdf_hess_apply(B, pnt, g, gb, pb);
+        }
+        for (int q = 0; q < 3; ++q) pb[q] += fb * G[q];
         // p = R^T (x - t)
         R Rp[3];
         for (int r = 0; r < 3; ++r) Rp[r] = BR[3 * r] * pb[0] + BR[3 * r + 1] * pb[1] + BR[3 * r + 2] * pb[2];

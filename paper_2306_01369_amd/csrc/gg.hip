@@ -1215,8 +1215,6 @@ gg_status gg_step_backward(gg_sim* s, const float* dL_dx, const float* dL_dv, fl
   if (!(s->p.flags & GG_FLAG_TAPE)) return fail(GG_ERR_NO_TAPE, "the simulation was created without GG_FLAG_TAPE");
   if (!s->tape_ok || s->tape_steps <= 0) return fail(GG_ERR_NO_TAPE, "no successful differentiable gg_step to reverse");
   if (s->n_envs != 1) return fail(GG_ERR_UNSUPPORTED, "the adjoint is built for one environment");
-  for (const HostBody& b : s->tape_poses)
-    if (b.shape == GG_GRID) return fail(GG_ERR_UNSUPPORTED, "the adjoint does not differentiate grid bodies");
   return s->fp64 ? backward_t<double>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where)
                  : backward_t<float>(s, dL_dx, dL_dv, dL_dx0, dL_dv0, dL_dtwists, where);
 }

@@ -317,3 +317,37 @@ def test_differentiable_bed_gradients_along_16_directions():
         assert abs(ref) > 0
     say("max rel err: fp64", max(errs[1]), "fp32", max(errs[0]))
     assert max(errs[1]) <= REL_TOL
+
+
+def test_adjoint_with_a_grid_tool_matches_dual_numbers():
+    # colliding grains around a spinning bowl sampled on a grid: the adjoint
+    # through the trilinear interpolant, its normalised gradient and its
+    # Hessian, against the oracle's dual numbers (both builds)
+    from gradcheck import jvp_directional
+    x, v, r, bodies, tw, loss = _dynamic_setup(n=1200, steps=6, seed=17)
+    side = 0.01 + 2.02 * 0.004 * 12
+    bowl = scenes.grid_tool(scenes.bowl_grid(0.015, 0.004, 0.006, 1024.0), (side / 2, side / 2, side / 2),
+                            R=scenes.random_rotation(np.random.default_rng(3)))
+    bodies = bodies[:-1] + [bowl]
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2))
+    g0 = (0.0, 0.0, 0.0)
+    say("grid-tool adjoint: n", len(x))
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    grads = {}
+    for prec in (0, 1):
+        grads[prec], st = _gpu_grads(x, v, r, bodies, tw, loss, gravity=g0, precision=prec, **kw)
+    assert st["n_pb"] > 10
+    rng = np.random.default_rng(8)
+    for kind in ("x0", "v0", "twist", "all"):
+        dx = rng.normal(size=x.shape) if kind in ("x0", "all") else np.zeros(x.shape)
+        dv = rng.normal(size=v.shape) if kind in ("v0", "all") else np.zeros(v.shape)
+        dt_ = np.zeros_like(tw)
+        if kind in ("twist", "all"):
+            dt_[:, -1, :] = rng.normal(size=(tw.shape[0], 6))
+        ref = jvp_directional(loss, x64, v64, r, bodies, tw, (dx, dv, dt_), gravity=g0, **kw)
+        for prec in (0, 1):
+            gx0, gv0, gtw = grads[prec]
+            an = np.sum(gx0 * dx) + np.sum(gv0 * dv) + np.sum(gtw * dt_)
+            err = abs(an - ref) / max(abs(ref), 1e-12)
+            say(kind, "precision", prec, "adjoint", an, "dual", ref, "rel err", err)
+            assert err <= REL_TOL, (kind, prec, err)

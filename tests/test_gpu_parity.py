@@ -682,12 +682,3 @@ def test_grid_registration_is_validated():
     # the registered bodies still step
     sim.set_bodies(bodies)
     sim.step(2)
-
-
-def test_backward_does_not_differentiate_grid_bodies():
-    s, bodies = _bed_with_grid_tools(n=500)
-    sim = gg.Sim(s.x, s.v, s.radius, bodies, differentiable=True)
-    sim.step(2)
-    with pytest.raises(gg.GGError) as e:
-        sim.backward(np.zeros((s.n, 3)), None)
-    assert e.value.status == gg.GG_ERR_UNSUPPORTED
