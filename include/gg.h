@@ -140,6 +140,10 @@ typedef struct {
   int32_t tile_threads;   /* detection workgroup size and work-item length: 64, 128 or
                              256; 0 -> 256 from 2^18 particles, else 128.
                              The tile parameters change speed only, never results. */
+  float cyclic_z[2]; /* (z_lo, z_hi): when z_hi > z_lo, a particle whose updated position
+                        falls below z_lo is moved up by z_hi - z_lo, velocity unchanged (the
+                        cyclic vertical boundary of the paper's gear-tower benchmark, Sec. IV);
+                        contact search does not wrap.  (0, 0): off */
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL */
 } gg_params;

@@ -38,7 +38,7 @@ class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
                 ("relax", C.c_double), ("density", C.c_double), ("g", C.c_double * 3),
                 ("n_iters", C.c_int32), ("mass_split", C.c_int32), ("inv_c", C.c_float),
-                ("pad", C.c_int32), ("n_h", C.c_int64)]
+                ("pad", C.c_int32), ("n_h", C.c_int64), ("cyc_lo", C.c_double), ("cyc_hi", C.c_double)]
 
 
 def lib():
@@ -241,7 +241,7 @@ class Oracle:
 
     def __init__(self, x, v, radius, bodies=(), *, dt=1e-3, alpha=0.2, mu=0.5, n_iters=20,
                  gravity=(0.0, 0.0, -9.81), relax=1.0, density=2500.0, mass_split=True,
-                 cell_size=None, hash_size=None, env=None):
+                 cell_size=None, hash_size=None, env=None, cyclic_z=None):
         self.x = np.array(x, dtype=np.float64, copy=True).reshape(-1, 3)
         self.v = np.array(v, dtype=np.float64, copy=True).reshape(-1, 3)
         self.r = _f32(radius)
@@ -262,6 +262,8 @@ class Oracle:
             inv_c = float(np.float32(1.0) / np.float32(cell_size))
         P.inv_c = inv_c
         P.n_h = int(hash_size) if hash_size else max(1, 2 * self.n)
+        if cyclic_z is not None:
+            P.cyc_lo, P.cyc_hi = float(cyclic_z[0]), float(cyclic_z[1])
         self.P = P
         self.cell_size = cell_size
         self.stats = np.zeros(4, np.int64)

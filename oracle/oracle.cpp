@@ -158,6 +158,7 @@ struct Params {
   float inv_c;
   int32_t pad;
   int64_t n_h;
+  double cyc_lo, cyc_hi;  // cyclic vertical boundary (off unless cyc_hi > cyc_lo)
 };
 
 // binary32 SDF with a fixed operation order (the contact decision).
@@ -629,10 +630,13 @@ int64_t ggo_step(const Params* P, int64_t n, double* x, double* v, const float* 
   if (dv)
     for (int64_t q = 0; q < 3 * n; ++q) dv[q] = w[q] - w0[q];
 
-  // ---- symplectic Euler (Eqs. (4)-(5)): velocity first, then position
+  // ---- symplectic Euler (Eqs. (4)-(5)): velocity first, then position; the
+  // tower benchmark's cyclic boundary moves a particle that falls below the
+  // bottom cap up by the tower height, velocity unchanged
   for (int64_t q = 0; q < 3 * n; ++q) {
     v[q] = w[q];
     x[q] = x[q] + P->dt * v[q];
+    if (q % 3 == 2 && P->cyc_hi > P->cyc_lo && x[q] < P->cyc_lo) x[q] += P->cyc_hi - P->cyc_lo;
   }
   if (advance_bodies) ggo_advance_bodies(nb, bodies, P->dt);
   return C;
@@ -992,6 +996,7 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
   for (int64_t q = 0; q < 3 * n; ++q) {
     V[q] = w[q];
     X[q] = X[q] + P->dt * V[q];
+    if (q % 3 == 2 && P->cyc_hi > P->cyc_lo && X[q].v < P->cyc_lo) X[q] = X[q] + (P->cyc_hi - P->cyc_lo);
     x[q] = X[q].v;
     dx[q] = X[q].d;
     v[q] = V[q].v;

@@ -126,7 +126,7 @@ void advance_pose(HostBody& B, double dt) {
 
 // grid: the registered grid of a GG_GRID body (else nullptr); values: the
 // device copy of all grids' values.
-ggk::DevBody to_dev(const HostBody& B, const gg_grid* grid, const float* values) {
+ggk::DevBody to_dev(const HostBody& B, const gg_grid* grid, const float* values, float r_max) {
   ggk::DevBody d{};
   d.shape = B.shape;
   d.env = B.env;
@@ -142,6 +142,47 @@ ggk::DevBody to_dev(const HostBody& B, const gg_grid* grid, const float* values)
     d.td[q] = B.t[q];
     d.nud[q] = B.nu[q];
     d.omd[q] = B.om[q];
+  }
+  // world box of the body's points, for the detection cull (planes are unbounded)
+  double blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+  bool bounded = true;
+  if (B.shape == GG_BOX) {
+    for (int r = 0; r < 3; ++r) {
+      double e = 0;
+      for (int c = 0; c < 3; ++c) e += std::fabs(B.R[3 * r + c]) * (double)B.params[c];
+      blo[r] = B.t[r] - e;
+      bhi[r] = B.t[r] + e;
+    }
+  } else if (B.shape == GG_CAPSULE) {
+    for (int r = 0; r < 3; ++r) {
+      const double e = std::fabs(B.R[3 * r + 2]) * (double)B.params[1] + (double)B.params[0];
+      blo[r] = B.t[r] - e;
+      bhi[r] = B.t[r] + e;
+    }
+  } else if (B.shape == GG_GRID && grid) {
+    const double ext[3] = {(grid->nx - 1) / (double)grid->inv_spacing, (grid->ny - 1) / (double)grid->inv_spacing,
+                           (grid->nz - 1) / (double)grid->inv_spacing};
+    for (int r = 0; r < 3; ++r) {
+      double c0 = B.t[r], e = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double mid = (double)grid->origin[c] + 0.5 * ext[c];
+        c0 += B.R[3 * r + c] * mid;
+        e += std::fabs(B.R[3 * r + c]) * 0.5 * ext[c];
+      }
+      blo[r] = c0 - e;
+      bhi[r] = c0 + e;
+    }
+  } else {
+    bounded = false;
+  }
+  if (bounded) {
+    d.cull = 1;
+    for (int r = 0; r < 3; ++r) {
+      // r_max plus a margin far above the rounding of the binary32 decision
+      const double m = (double)r_max + 1e-4 + 1e-5 * std::max(std::fabs(blo[r]), std::fabs(bhi[r]));
+      d.lo[r] = (float)(blo[r] - m);
+      d.hi[r] = (float)(bhi[r] + m);
+    }
   }
   if (grid) {
     d.gv = values + grid->offset;
@@ -294,6 +335,8 @@ gg_status check_params(const gg_params* p) {
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
+  if (!std::isfinite(p->cyclic_z[0]) || !std::isfinite(p->cyclic_z[1]))
+    return fail(GG_ERR_INVALID, "cyclic_z must be finite");
   if (p->tile_threads != 0 && p->tile_threads != 64 && p->tile_threads != 128 && p->tile_threads != 256)
     return fail(GG_ERR_INVALID, "tile_threads must be 0, 64, 128 or 256");
   if (p->device < 0) return fail(GG_ERR_INVALID, "device must be >= 0");
@@ -538,6 +581,16 @@ void launch_sweeps(gg_sim* s, const StepIO<R>& io, const ggk::DevBody* bod) {
   }
 }
 
+// The cyclic vertical boundary in the build's precision (span 0: off).
+template <typename R>
+R cyc_lo(const gg_sim* s) {
+  return (R)s->p.cyclic_z[0];
+}
+template <typename R>
+R cyc_span(const gg_sim* s) {
+  return s->p.cyclic_z[1] > s->p.cyclic_z[0] ? (R)s->p.cyclic_z[1] - (R)s->p.cyclic_z[0] : R(0);
+}
+
 // Enqueue the launches of n_steps steps on s->stream (eager or under capture).
 template <typename R>
 gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof) {
@@ -564,7 +617,8 @@ gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof)
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
     launch_sweeps<R>(s, io, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
-    ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, (V*)s->x, (const V*)s->v, dt, s->ctl);
+    ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, (V*)s->x, (const V*)s->v, dt, cyc_lo<R>(s), cyc_span<R>(s),
+                                                     s->ctl);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
   }
   return GG_OK;
@@ -1047,7 +1101,7 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
         }
       }
       const gg_grid* gr = cur[b].shape == GG_GRID ? &s->grids[cur[b].grid] : nullptr;
-      s->h_bodies[(size_t)st * nb + b] = to_dev(cur[b], gr, s->d_grid_values);
+      s->h_bodies[(size_t)st * nb + b] = to_dev(cur[b], gr, s->d_grid_values, s->r_max);
       s->pose_hist[(size_t)st * nb + b] = cur[b];
       advance_pose(cur[b], (double)s->p.dt);
     }
@@ -1367,7 +1421,7 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
         return fail(GG_ERR_HIP, "recomputed contacts differ from the recorded forward");
       }
       launch_sweeps<R>(s, io, bod);
-      ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, s->ctl);
+      ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, cyc_lo<R>(s), cyc_span<R>(s), s->ctl);
     }
     // reverse the segment
     for (int st = s1 - 1; st >= s0; --st) {

@@ -46,7 +46,7 @@ constexpr int kDetBlock = 128;  // default detection workgroup (and work item) s
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
 
-struct DevBody {  // one body at one step; 280 bytes
+struct DevBody {  // one body at one step; 312 bytes
   int32_t shape, env;
   float params[4];
   float R[9];  // world <- body, row major
@@ -58,7 +58,9 @@ struct DevBody {  // one body at one step; 280 bytes
   int32_t gn[3];                        // knots per axis
   float go[3];                          // body-frame position of knot (0, 0, 0)
   float gih;                            // 1 / knot spacing
-  int32_t gpad;
+  int32_t cull;                         // 1: particles outside [lo, hi] cannot touch the body
+  float lo[3], hi[3];                   // world box holding every point within r_max of the body
+  int32_t pad2;
 };
 
 // Four-vectors of the real type R.
@@ -996,7 +998,12 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     }
     if (active) {
       for (int b = b_lo; b < b_hi; ++b) {
-        if (body_touch(bodies[b], p32)) {
+        const DevBody& B = bodies[b];
+        // a particle outside the body's box is farther than r_max from it
+        if (B.cull && (p32.x < B.lo[0] || p32.x > B.hi[0] || p32.y < B.lo[1] || p32.y > B.hi[1] ||
+                       p32.z < B.lo[2] || p32.z > B.hi[2]))
+          continue;
+        if (body_touch(B, p32)) {
           put_contact(i, cnt, K, -1 - b, body_gap<R>(bodies[b], p), partner, Psi);
           ++cnt;
           ++npb;
@@ -1135,10 +1142,12 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
   }
 }
 
-// Positions from the new velocities (Eq. (5)), x' = x + dt v'.
+// Positions from the new velocities (Eq. (5)), x' = x + dt v'; with a cyclic
+// vertical boundary (zspan > 0) a particle below zlo moves up by zspan.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__ x,
-                                                      const V4<R>* __restrict__ v, R dt, Ctl* ctl) {
+                                                      const V4<R>* __restrict__ v, R dt, R zlo, R zspan,
+                                                      Ctl* ctl) {
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->steps_done, 1);
@@ -1146,6 +1155,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__
   V4<R> p = x[i];
   const V4<R> q = v[i];
   p.x += dt * q.x; p.y += dt * q.y; p.z += dt * q.z;
+  if (zspan > R(0) && p.z < zlo) p.z += zspan;
   x[i] = p;
 }
 

@@ -55,7 +55,8 @@ class Params(C.Structure):
                 ("max_contacts_per_particle", C.c_int32), ("precision", C.c_int32),
                 ("density", C.c_float), ("flags", C.c_uint32), ("reorder_every", C.c_int32),
                 ("tile_max_cells", C.c_int32), ("tile_max_stage", C.c_int32),
-                ("tile_node_shift", C.c_int32), ("tile_threads", C.c_int32), ("device", C.c_int32),
+                ("tile_node_shift", C.c_int32), ("tile_threads", C.c_int32), ("cyclic_z", C.c_float * 2),
+                ("device", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
@@ -173,7 +174,7 @@ class Sim:
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
                  profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
                  tile_max_stage=0, tile_node_shift=0, tile_threads=0, differentiable=False, checkpoint_every=0,
-                 graph=False, precision=0):
+                 graph=False, precision=0, cyclic_z=None):
         L = lib()
         P = Params()
         P.dt, P.alpha, P.mu = dt, alpha, mu
@@ -195,6 +196,8 @@ class Sim:
         P.tile_max_stage = int(tile_max_stage)
         P.tile_node_shift = int(tile_node_shift)
         P.tile_threads = int(tile_threads)
+        if cyclic_z is not None:
+            P.cyclic_z[0], P.cyclic_z[1] = float(cyclic_z[0]), float(cyclic_z[1])
         P.device = device
         P.stream = stream
         n = int(x.shape[0])

@@ -438,3 +438,76 @@ def scaled(scene: Scene, n: int, seed=0):
                  np.full(n, r, np.float32), walled_box(0.0, side, 0.0, side),
                  dt=scene.dt, n_iters=scene.n_iters, mu=scene.mu, alpha=scene.alpha,
                  n_steps=scene.n_steps)
+
+
+def gear_grid(outer=0.03, depth=0.006, teeth=12, thickness=0.02, helix=20.0, bore=0.008, inv_spacing=512.0):
+    """A helical gear sampled on a grid (body frame, axis z): a toothed disc of
+    outer radius ``outer`` whose tooth profile turns by ``helix`` rad/m along
+    the axis, with a central bore.  The field is a distance bound (radial gap
+    to the profile, intersected with the slab and the bore), exact enough to
+    stand in for a mesh's distance field."""
+    m = 0.006
+
+    def fn(p):
+        rho = np.linalg.norm(p[:, :2], axis=1)
+        th = np.arctan2(p[:, 1], p[:, 0])
+        prof = outer - depth * (0.5 - 0.5 * np.cos(teeth * (th - helix * p[:, 2])))
+        disc = np.maximum(rho - prof, np.abs(p[:, 2]) - 0.5 * thickness)
+        return np.maximum(disc, bore - rho)
+
+    lo = (-outer - m, -outer - m, -0.5 * thickness - m)
+    hi = (outer + m, outer + m, 0.5 * thickness + m)
+    return sdf_grid(fn, lo, hi, inv_spacing)
+
+
+def tower_grid(radius, z0, z1, inv_spacing=256.0):
+    """The wall of a vertical cylindrical tower of the given radius (solid
+    outside the cylinder), sampled on a grid over the tower's height."""
+    m = 0.01
+    return sdf_grid(lambda p: radius - np.linalg.norm(p[:, :2], axis=1), (-radius - m, -radius - m, z0 - m),
+                    (radius + m, radius + m, z1 + m), inv_spacing)
+
+
+def gear_tower(n=16384, n_gears=10, seed=0, r=0.002, radius=0.1, height=0.5, omega_max=6.0):
+    """The paper's many-body benchmark (helical gears spinning in a tall
+    cylindrical tower, particles recycled from the bottom to the top): n
+    spheres on a loose lattice inside the tower (random index order), n_gears
+    copies of one gear grid at random positions and axis orientations, each
+    spinning about its own axis at a uniformly random rate in
+    [-omega_max, omega_max] rad/s with its centre fixed.  Returns the scene
+    and the cyclic boundary (z_lo, z_hi) to pass to the simulator."""
+    rng = np.random.default_rng(seed)
+    tower = tower_grid(radius, 0.0, height)
+    gear = gear_grid()
+    bodies = [grid_tool(tower, (0.0, 0.0, 0.0))]
+    centres = []
+    for _ in range(n_gears):
+        for _try in range(200):
+            c = np.array([rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), rng.uniform(0.06, height - 0.06)])
+            if all(np.linalg.norm(c - q) > 0.075 for q in centres):
+                break
+        centres.append(c)
+        Rm = random_rotation(rng)
+        w = rng.uniform(-omega_max, omega_max)
+        bodies.append(grid_tool(gear, c, omega=w * Rm[:, 2], R=Rm))
+    # particles: a cubic lattice inside the tower, outside every gear's box
+    sp = 2.02 * r
+    k = int(np.ceil(2 * radius / sp)) + 1
+    g = np.arange(k) * sp - radius
+    nz = int(np.ceil(height / sp))
+    zz = 0.004 + np.arange(nz) * sp
+    X, Y, Z = np.meshgrid(g, g, zz, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    pts = pts[np.linalg.norm(pts[:, :2], axis=1) < radius - 1.5 * r]
+    keep = np.ones(len(pts), bool)
+    for c in centres:
+        keep &= np.linalg.norm(pts - c, axis=1) > 0.045
+    pts = pts[keep]
+    if len(pts) < n:
+        raise ValueError(f"the tower holds only {len(pts)} lattice sites")
+    pts = pts[np.sort(rng.choice(len(pts), n, replace=False))]
+    pts += rng.uniform(-0.05 * r, 0.05 * r, size=pts.shape)
+    pts = pts[rng.permutation(n)]
+    sc = Scene(f"gears-{n}-{n_gears}", _f32(pts), np.zeros((n, 3), np.float32), np.full(n, r, np.float32),
+               bodies, dt=1e-3, n_iters=20, mu=0.5, alpha=0.2, n_steps=100)
+    return sc, (0.0, float(height))

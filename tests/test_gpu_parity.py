@@ -38,7 +38,8 @@ def _compare_one_step(x, v, r, bodies, label, env_offsets=None, **kw):
     """Run one step on both sides from the same binary32 state and compare."""
     say(label, "n =", len(x), "bodies =", len(bodies))
     sim = _sim_from_state(x, v, r, bodies, diagnostics=True, env_offsets=env_offsets, **kw)
-    ok_kw = {k: kw[k] for k in ("dt", "alpha", "mu", "n_iters", "gravity", "mass_split", "hash_size", "cell_size")
+    ok_kw = {k: kw[k] for k in ("dt", "alpha", "mu", "n_iters", "gravity", "mass_split", "hash_size", "cell_size",
+                                "cyclic_z")
              if k in kw}
     if env_offsets is not None:
         ok_kw["env"] = np.repeat(np.arange(len(env_offsets) - 1), np.diff(env_offsets)).astype(np.int32)
@@ -682,3 +683,39 @@ def test_grid_registration_is_validated():
     # the registered bodies still step
     sim.set_bodies(bodies)
     sim.step(2)
+
+
+
+# ------------------------------------------------- many bodies, cyclic boundary
+
+def test_one_step_gear_tower():
+    # 16,384 grains flowing past 10 spinning grid gears in a grid tower: the
+    # body boxes cull most SDF tests, and the contact list must still equal
+    # the oracle's (which tests every body)
+    s, cyc = scenes.gear_tower(n=16384, n_gears=10, seed=2)
+    orc = O.Oracle(s.x.astype(np.float64), s.v.astype(np.float64), s.radius, s.bodies, cyclic_z=cyc)
+    for _ in range(150):                 # develop the flow on the oracle
+        orc.step()
+    x = orc.x.astype(np.float32)
+    v = orc.v.astype(np.float32)
+    d = _compare_one_step(x, v, s.radius, s.bodies, "gear-tower", cyclic_z=cyc)
+    per_body = np.bincount(d["pairs"][d["n_pp"]:, 1], minlength=len(s.bodies))
+    say("gear-tower contacts per body", per_body.tolist())
+    assert np.count_nonzero(per_body[1:]) >= 5
+
+
+def test_cyclic_boundary_over_steps_follows_the_oracle():
+    s, cyc = scenes.gear_tower(n=4096, n_gears=5, seed=3)
+    kw = dict(dt=float(np.float32(1e-3)), alpha=float(np.float32(0.2)), gravity=(0.0, 0.0, float(np.float32(-9.81))))
+    v0 = s.v.copy()
+    v0[:, 2] = -1.5                      # start falling so grains cross the bottom cap
+    say("cyclic boundary, double build")
+    sim = gg.Sim(s.x, v0, s.radius, s.bodies, precision=1, cyclic_z=cyc, **kw)
+    orc = O.Oracle(s.x.astype(np.float64), v0.astype(np.float64), s.radius, s.bodies, cyclic_z=cyc, **kw)
+    for k in range(30):
+        sim.step(1)
+        d = orc.step(detail=True)
+        np.testing.assert_array_equal(sim.read("contacts"), d["pairs"], err_msg=f"step {k}")
+    x = sim.read("pos")
+    assert np.abs(x - orc.x).max() <= 2e-8
+    assert np.sum(orc.x[:, 2] > s.x[:, 2] + 0.1) > 10      # grains that crossed the bottom re-entered at the top

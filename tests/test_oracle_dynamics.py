@@ -293,3 +293,22 @@ def test_body_point_velocity_of_rotating_tool():
                  n_iters=5, alpha=0.0)
     o.step()
     assert abs(o.v[0, 2] - float(np.float32(0.1))) < 1e-12   # body twist is handed over in binary32
+
+
+def test_cyclic_vertical_boundary_closed_form():
+    # no gravity, no contacts, downward velocities: with the tower's cyclic
+    # boundary the height is periodic, z_k = lo + ((z_0 + k dt v - lo) mod H)
+    # (floored modulus), velocities unchanged
+    n, dt, steps = 20, 1e-3, 400
+    rng = np.random.default_rng(4)
+    x = np.column_stack([np.arange(n) * 0.01, np.zeros(n), rng.uniform(0.05, 0.45, n)])
+    v = np.zeros((n, 3))
+    v[:, 2] = -rng.uniform(1.0, 3.0, n)
+    lo, hi = 0.0, 0.5
+    orc = O.Oracle(x, v, np.full(n, 0.001, np.float32), [], dt=dt, gravity=(0.0, 0.0, 0.0), cyclic_z=(lo, hi))
+    for _ in range(steps):
+        orc.step()
+    z = lo + np.mod(x[:, 2] + steps * dt * v[:, 2] - lo, hi - lo)
+    np.testing.assert_allclose(orc.x[:, 2], z, rtol=0, atol=1e-11)
+    np.testing.assert_array_equal(orc.v, v)
+    assert np.all(steps * dt * v[:, 2] < -(hi - lo) * 0.8)    # every grain wrapped at least once
