@@ -286,6 +286,43 @@ def bench_gears(args):
     }
 
 
+def bench_hash_sweep(args):
+    """The paper's hash-table-size ablation: a column of grains at rest (the
+    most collision candidates per grain), 1,024 .. 65,536 grains, table sizes
+    n/4 .. 16n; speedup over real time = dt / (seconds per step)."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    steps = args.steps if args.steps_given else 100
+    factors = (0.25, 0.5, 1, 2, 4, 8, 16)
+    table = []
+    for n in (1024, 4096, 16384, 65536):
+        sc = scenes.column_scene(n=n, r=0.004)
+        row = {"particles": n}
+        for f in factors:
+            sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
+                         n_iters=sc.n_iters, hash_size=max(1, int(f * n)), graph=True)
+            sim.step(steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            sim.close()
+            row[f"{f}n"] = sc.dt / t
+        table.append(row)
+        log(f"hash sweep n={n}: " + ", ".join(f"{k}={v:.1f}" for k, v in row.items() if k != "particles"))
+    last = table[-1]
+    return {
+        "metric": "speedup over real time vs hash table size (column at rest)",
+        "value": last["2n"], "unit": "x realtime (dt=1 ms)", "n_gpus": 1, "steps": steps, "warmup": steps,
+        "ms_per_step": sc.dt / last["2n"] * 1e3, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "column at rest: 1,024..65,536 spheres r=4 mm packed in an 8x8-grain walled column, "
+                               "20 PJA sweeps; table sizes n/4..16n (value: 65,536 grains at 2n)"},
+        "table": table,
+    }
+
+
 def bench_large(args):
     """4,194,304 polydisperse spheres, 64 sweeps, box + capsule tools: settle the
     layered start (untimed, 20 sweeps, tools still), time 80 forward steps, then a
@@ -369,7 +406,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears"], default="scoop")
+    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep"],
+                    default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
@@ -387,9 +425,9 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 200
-    if args.workload in ("batched", "large", "drop", "diff", "gears"):
+    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep"):
         out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop,
-               "diff": bench_diff, "gears": bench_gears}[args.workload](args)
+               "diff": bench_diff, "gears": bench_gears, "hashsweep": bench_hash_sweep}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
