@@ -88,12 +88,22 @@ def key_of(n, ppc, n_bodies):
     return f"{dev}|n2^{int(round(math.log2(max(n, 1))))}|ppc{ppc:.1f}|bodies{n_bodies}"
 
 
-def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=True, verbose=False):
+def cell_factors():
+    """Cell sizes tried by ``tune(..., tune_cell=True)``, as multiples of the
+    smallest admissible cell 2 r_max (1 + 2^-10)."""
+    return (1.0, 1.125, 1.25)
+
+
+def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=True, verbose=False,
+         tune_cell=False):
     """Return the fastest launch-shape parameters for this workload (a dict of
-    gg.Sim keyword arguments)."""
+    gg.Sim keyword arguments).  With tune_cell the cell size is tuned too:
+    a larger cell changes which cell, and so which list position, a partner
+    falls in, hence the summation order and the rounding of the impulses
+    (never the contact set); by default it stays at the smallest cell."""
     sim_kwargs = dict(sim_kwargs or {})
     ppc = particles_per_cell(x, radius)
-    key = key_of(len(x), ppc, len(bodies))
+    key = key_of(len(x), ppc, len(bodies)) + ("|cell" if tune_cell else "")
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -139,6 +149,15 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
         t = timed(cand)
         if t is not None and t < best_t:
             best, best_t = cand, t
+    if tune_cell:
+        c0 = 2.0 * float(np.max(radius)) * (1.0 + 2.0 ** -10)
+        for factor in cell_factors()[1:]:
+            # a larger cell holds more particles: rescale the LDS budget
+            cand = dict(best, cell_size=c0 * factor,
+                        tile_max_stage=min(2048, int(best.get("tile_max_stage", 768) * factor ** 3) + 1))
+            t = timed(cand)
+            if t is not None and t < best_t:
+                best, best_t = cand, t
     if use_cache:
         cache[key] = {"params": best, "ms_per_step": 1e3 * best_t}
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -40,3 +40,8 @@ def test_candidates_fit_the_lds_budget():
 def test_hash_sizes_tried_exclude_the_default_and_stay_positive():
     f = autotune.hash_factors()
     assert 2.0 not in f and all(x > 0 for x in f)
+
+
+def test_cell_sizes_tried_start_at_the_smallest_admissible_cell():
+    f = autotune.cell_factors()
+    assert f[0] == 1.0 and all(b > a for a, b in zip(f, f[1:]))

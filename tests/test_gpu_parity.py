@@ -467,6 +467,15 @@ def test_tile_and_per_particle_detection_agree_bitwise():
     assert tiled == per_particle
 
 
+def test_larger_cell_keeps_contacts_and_parity():
+    # the autotuner may grow the cell: same contact set, impulses within the
+    # one-step bar of the oracle (only the summation order changes)
+    s = scenes.column_scene(n=3000, r=0.004)
+    c, _ = O.default_cell(s.radius)
+    say("cell size x1.25")
+    _compare_one_step(s.x, s.v, s.radius, s.bodies, "cell-x1.25", cell_size=float(np.float32(1.25 * c)))
+
+
 @pytest.mark.parametrize("threads,shift", [(64, 5), (64, 6), (256, 7)])
 def test_detection_workgroup_size_keeps_results_bitwise(threads, shift):
     s = scenes.column_scene(n=5000, r=0.004)
