@@ -34,6 +34,16 @@ class BodyTan(C.Structure):
                 ("omega", C.c_double * 3)]
 
 
+class Camera(C.Structure):
+    """A depth camera: pose = row-major [R | t] (camera -> world), looking
+    along its +z axis; params = (p0, p1, far, 0)."""
+    _fields_ = [("env", C.c_int32), ("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("pose", C.c_float * 12), ("params", C.c_float * 4)]
+
+
+CAMERA_KINDS = {"ortho": 0, "perspective": 1}
+
+
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("alpha", C.c_double), ("mu", C.c_double),
                 ("relax", C.c_double), ("density", C.c_double), ("g", C.c_double * 3),
@@ -83,6 +93,12 @@ def lib():
         L.ggo_num_threads.restype = C.c_int32
         L.ggo_sizeof_body.restype = C.c_int32
         L.ggo_sizeof_params.restype = C.c_int32
+        L.ggo_render_depth.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                       P(Body), C.c_int32, P(Camera), C.c_void_p, C.c_int64, C.c_void_p]
+        L.ggo_goal_reward.argtypes = [C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+        L.ggo_sizeof_camera.restype = C.c_int32
+        assert L.ggo_sizeof_camera() == C.sizeof(Camera), "Camera layout mismatch"
         assert L.ggo_sizeof_body() == C.sizeof(Body), "Body layout mismatch"
         assert L.ggo_sizeof_params() == C.sizeof(Params), "Params layout mismatch"
         assert L.ggo_sizeof_body_tan() == C.sizeof(BodyTan), "BodyTan layout mismatch"
@@ -153,6 +169,71 @@ def bodies_to_f32_pose(arr, nb):
             arr[k].nu[q] = float(np.float32(arr[k].nu[q]))
             arr[k].omega[q] = float(np.float32(arr[k].omega[q]))
     return arr
+
+
+# ------------------------------------------------- observations (Sec. V-A)
+
+def make_cameras(cams):
+    """ctypes cameras from dicts {"env", "kind" ("ortho" | "perspective"),
+    "width", "height", "pose" (3 x 4), "params" (p0, p1, far[, 0])}."""
+    arr = (Camera * max(1, len(cams)))()
+    for k, c in enumerate(cams):
+        A = arr[k]
+        A.env = int(c.get("env", 0))
+        A.kind = CAMERA_KINDS[c["kind"]]
+        A.width, A.height = int(c["width"]), int(c["height"])
+        pose = np.asarray(c["pose"], np.float32).reshape(12)
+        for q in range(12):
+            A.pose[q] = float(pose[q])
+        prm = list(c["params"]) + [0.0] * (4 - len(c["params"]))
+        for q in range(4):
+            A.params[q] = float(np.float32(prm[q]))
+    return arr
+
+
+def _env_off(n, env_offsets):
+    if env_offsets is None:
+        return np.array([0, n], np.int64)
+    return np.ascontiguousarray(env_offsets, np.int64)
+
+
+def render_depth(x, radius, cams, bodies=(), env_offsets=None, pixels=None):
+    """Depth images (Sec. V-A observations) of the binary32 positions x
+    (n x 3) with radii `radius`: a list of (height, width) float32 arrays, or,
+    when `pixels` (indices into the concatenated images) is given, the depths
+    of those pixels only.  Plane bodies of each camera's environment are
+    drawn; body poses are rounded to binary32 as the step sees them."""
+    x = _f32(x, (-1, 3))
+    r = _f32(radius)
+    off = _env_off(len(x), env_offsets)
+    A = make_cameras(cams)
+    B = bodies_to_f32_pose(make_bodies(bodies), len(bodies))
+    sizes = [int(c["width"]) * int(c["height"]) for c in cams]
+    out = np.full(sum(sizes), np.nan, np.float32)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    lib().ggo_render_depth(len(x), _ptr(x), _ptr(r), len(off) - 1, _ptr(off), len(bodies), B, len(cams), A,
+                           _ptr(out), 0 if pix is None else len(pix), _ptr(pix))
+    if pix is not None:
+        return out[pix]
+    imgs, at = [], 0
+    for c, m in zip(cams, sizes):
+        imgs.append(out[at:at + m].reshape(int(c["height"]), int(c["width"])))
+        at += m
+    return imgs
+
+
+def goal_reward(x, boxes, env_offsets=None):
+    """Goal-box reward per environment (Sec. V-A) and the particles inside:
+    boxes = n_envs x (lo xyz, hi xyz)."""
+    x = _f32(x, (-1, 3))
+    off = _env_off(len(x), env_offsets)
+    bx = _f32(boxes, (-1, 6))
+    ne = len(off) - 1
+    assert bx.shape[0] == ne
+    rew = np.zeros(ne, np.float64)
+    ins = np.zeros(ne, np.int64)
+    lib().ggo_goal_reward(len(x), _ptr(x), ne, _ptr(off), _ptr(bx), _ptr(rew), _ptr(ins))
+    return rew, ins
 
 
 # ---------------------------------------------------------------- Eq. (6)

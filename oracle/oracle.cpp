@@ -1020,3 +1020,196 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
 int32_t ggo_sizeof_body_tan() { return (int32_t)sizeof(BodyTan); }
 
 }  // extern "C"
+
+// ======================================================= observations
+// The Gym-style environment of Sec. V-A ("Bulldozing") observes the scene
+// through two depth cameras computed on the simulating device -- a
+// perspective camera riding on the tool and an orthographic camera looking
+// down on the whole bed -- and rewards material inside a goal box.  The paper
+// gives no camera model; the readings taken here:
+//   - a camera has a pose [R | t] (camera -> world) and looks along its +z
+//     axis; pixel (u, v) of a W x H image has the centre coordinates
+//     g_u = (u + 1/2) * fl32(2/W) - 1 and g_v likewise, in binary32;
+//   - orthographic: the ray of pixel (u, v) starts at (p0 g_u, p1 g_v, 0) and
+//     runs along (0, 0, 1); perspective: it starts at the camera origin and
+//     runs along (p0 g_u, p1 g_v, 1) (p0, p1 = tangents of the half angles);
+//   - depth = camera-frame z of the first surface the ray meets (the ray
+//     parameter along those directions), at most `far` (= p2); `far` when the
+//     ray meets nothing;
+//   - surfaces drawn: the particles of the camera's environment (spheres) and
+//     its plane bodies (the solid half space below the body-frame xy plane);
+//     tool bodies are not drawn;
+//   - whether a ray meets a sphere is decided in binary32 with a fixed
+//     operation order and no fused multiply-add (the camera-frame centre
+//     c = R^T (x - t) summed as the SDF transform is; orthographic:
+//     c_z > 0 and (o_x - c_x)^2 + (o_y - c_y)^2 <= r^2; perspective: c_z > 0,
+//     E = |c|^2 - r^2 > 0 (the camera is outside the sphere), D = d.c > 0 and
+//     |d|^2 E <= D^2); the depth itself is FP64 from those binary32 values;
+//   - a plane is met when the ray runs into its solid side (n.d < 0) at a
+//     non-negative parameter.
+struct Camera {        // mirrored by the Python wrapper (ctypes)
+  int32_t env, kind;   // kind 0: orthographic, 1: perspective
+  int32_t width, height;
+  float pose[12];      // row-major [R | t], camera -> world
+  float params[4];     // p0, p1 (see above), far, unused
+};
+
+float pixel_centre(int idx, int size) {
+  const float s = (float)(2.0 / size);
+  float a = (float)idx + 0.5f;
+  float b = a * s;
+  return b - 1.0f;
+}
+
+// Depth of one pixel: every particle of the environment and every plane body
+// of it, smallest parameter wins.
+double pixel_depth(const Camera& C, int u, int v, const float* x, const float* r, int64_t i0, int64_t i1,
+                   int32_t nb, const Body* bodies) {
+  const float gu = pixel_centre(u, C.width), gv = pixel_centre(v, C.height);
+  const float a = C.params[0] * gu, b = C.params[1] * gv;
+  const bool ortho = C.kind == 0;
+  const float Rc[9] = {C.pose[0], C.pose[1], C.pose[2], C.pose[4], C.pose[5],
+                       C.pose[6], C.pose[8], C.pose[9], C.pose[10]};
+  const float tc[3] = {C.pose[3], C.pose[7], C.pose[11]};
+  double best = C.params[2];
+  for (int64_t i = i0; i < i1; ++i) {
+    // camera-frame centre, binary32
+    float d0 = x[3 * i] - tc[0], d1 = x[3 * i + 1] - tc[1], d2 = x[3 * i + 2] - tc[2];
+    float c[3];
+    for (int k = 0; k < 3; ++k) {
+      float s0 = Rc[0 * 3 + k] * d0;
+      float s1 = Rc[1 * 3 + k] * d1;
+      float s2 = Rc[2 * 3 + k] * d2;
+      float s = s0 + s1;
+      c[k] = s + s2;
+    }
+    if (!(c[2] > 0.0f)) continue;
+    const float ri = r[i];
+    const float r2 = ri * ri;
+    double tau;
+    if (ortho) {
+      float ex = a - c[0], ey = b - c[1];
+      float q0 = ex * ex;
+      float q1 = ey * ey;
+      float q = q0 + q1;
+      if (!(q <= r2)) continue;
+      const double ex64 = (double)a - c[0], ey64 = (double)b - c[1];
+      const double h = (double)ri * ri - (ex64 * ex64 + ey64 * ey64);
+      tau = (double)c[2] - std::sqrt(std::max(h, 0.0));
+      tau = std::max(tau, 0.0);
+    } else {
+      float aa = a * a;
+      float bb = b * b;
+      float A = aa + bb;
+      A = A + 1.0f;
+      float c00 = c[0] * c[0];
+      float c11 = c[1] * c[1];
+      float c22 = c[2] * c[2];
+      float B = c00 + c11;
+      B = B + c22;
+      float ac = a * c[0];
+      float bc = b * c[1];
+      float D = ac + bc;
+      D = D + c[2];
+      float E = B - r2;
+      if (!(E > 0.0f) || !(D > 0.0f)) continue;
+      float lhs = A * E;
+      float rhs = D * D;
+      if (!(lhs <= rhs)) continue;
+      // |t d - c|^2 = r^2, nearer root, written without cancellation
+      const double A6 = (double)a * a + (double)b * b + 1.0;
+      const double B6 = (double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2];
+      const double D6 = (double)a * c[0] + (double)b * c[1] + (double)c[2];
+      const double E6 = B6 - (double)ri * ri;
+      const double disc = std::max(D6 * D6 - A6 * E6, 0.0);
+      tau = E6 / (D6 + std::sqrt(disc));
+    }
+    best = std::min(best, tau);
+  }
+  // planes, in FP64
+  double o[3] = {0, 0, 0}, d[3] = {0, 0, 1};
+  if (ortho) {
+    o[0] = a; o[1] = b;
+  } else {
+    d[0] = a; d[1] = b;
+  }
+  double ow[3], dw[3];
+  for (int k = 0; k < 3; ++k) {
+    ow[k] = tc[k] + ((double)Rc[3 * k] * o[0] + (double)Rc[3 * k + 1] * o[1] + (double)Rc[3 * k + 2] * o[2]);
+    dw[k] = (double)Rc[3 * k] * d[0] + (double)Rc[3 * k + 1] * d[1] + (double)Rc[3 * k + 2] * d[2];
+  }
+  for (int q = 0; q < nb; ++q) {
+    const Body& B = bodies[q];
+    if (B.shape != PLANE || B.env != C.env) continue;
+    const double nrm[3] = {B.R[2], B.R[5], B.R[8]};
+    const double den = dot3(nrm, dw);
+    if (!(den < 0)) continue;
+    const double rel[3] = {B.t[0] - ow[0], B.t[1] - ow[1], B.t[2] - ow[2]};
+    const double tau = dot3(nrm, rel) / den;
+    if (tau >= 0) best = std::min(best, tau);
+  }
+  return best;
+}
+
+extern "C" {
+
+int32_t ggo_sizeof_camera() { return (int32_t)sizeof(Camera); }
+
+// Depth images of n_cams cameras, concatenated (camera k: height x width,
+// row v, column u at v*width + u), rounded to binary32.  env_off: n_envs + 1
+// particle offsets.  pixels: NULL for every pixel, else n_pix indices into the
+// concatenated output; only those entries are written.
+void ggo_render_depth(int64_t n, const float* x, const float* r, int32_t n_envs, const int64_t* env_off,
+                      int32_t nb, const Body* bodies, int32_t n_cams, const Camera* cams, float* out,
+                      int64_t n_pix, const int64_t* pixels) {
+  std::vector<int64_t> base(n_cams + 1, 0);
+  for (int k = 0; k < n_cams; ++k) base[k + 1] = base[k] + (int64_t)cams[k].width * cams[k].height;
+  const int64_t total = pixels ? n_pix : base[n_cams];
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < total; ++q) {
+    const int64_t p = pixels ? pixels[q] : q;
+    const int k = (int)(std::upper_bound(base.begin(), base.end(), p) - base.begin()) - 1;
+    const Camera& C = cams[k];
+    const int64_t loc = p - base[k];
+    const int u = (int)(loc % C.width), v = (int)(loc / C.width);
+    const int e = C.env;
+    const int64_t i0 = (e >= 0 && e < n_envs) ? env_off[e] : 0, i1 = (e >= 0 && e < n_envs) ? env_off[e + 1] : 0;
+    out[p] = (float)pixel_depth(C, u, v, x, r, i0, i1, nb, bodies);
+  }
+  (void)n;
+}
+
+// Goal-box reward (Sec. V-A): per environment, 100/n_e for every particle in
+// the closed box [lo, hi] (binary32 comparisons of the binary32 positions)
+// and -d/n_e for every other, d = FP64 distance to the nearest point of the
+// box.  boxes: n_envs x 6 (lo xyz, hi xyz).  reward: n_envs; inside: n_envs
+// (may be NULL).  An empty environment has reward 0.
+void ggo_goal_reward(int64_t n, const float* x, int32_t n_envs, const int64_t* env_off, const float* boxes,
+                     double* reward, int64_t* inside) {
+  for (int e = 0; e < n_envs; ++e) {
+    const float* lo = boxes + 6 * e;
+    const float* hi = lo + 3;
+    int64_t cnt = 0;
+    double dist = 0;
+    for (int64_t i = env_off[e]; i < env_off[e + 1]; ++i) {
+      const float* p = x + 3 * i;
+      bool in = true;
+      double s = 0;
+      for (int k = 0; k < 3; ++k) {
+        in = in && lo[k] <= p[k] && p[k] <= hi[k];
+        const double q = std::min(std::max((double)p[k], (double)lo[k]), (double)hi[k]);
+        s += ((double)p[k] - q) * ((double)p[k] - q);
+      }
+      if (in)
+        ++cnt;
+      else
+        dist += std::sqrt(s);
+    }
+    const int64_t ne = env_off[e + 1] - env_off[e];
+    reward[e] = ne > 0 ? (100.0 * (double)cnt - dist) / (double)ne : 0.0;
+    if (inside) inside[e] = cnt;
+  }
+  (void)n;
+}
+
+}  // extern "C"

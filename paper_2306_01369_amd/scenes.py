@@ -144,6 +144,41 @@ def grid_tool(grid, center, nu=(0, 0, 0), omega=(0, 0, 0), R=None, env=0):
             "omega": np.asarray(omega, float), "env": env}
 
 
+# ----------------------------------------------------------------------------
+# cameras (observations of the Gym-style environment, Sec. V-A)
+# ----------------------------------------------------------------------------
+
+def camera_pose(eye, target, up=(0.0, 0.0, 1.0)):
+    """Row-major [R | t] (camera -> world) of a camera at ``eye`` whose +z axis
+    points at ``target``; image x (columns) to the right, y (rows) downward."""
+    eye = np.asarray(eye, np.float64)
+    f = np.asarray(target, np.float64) - eye
+    f /= np.linalg.norm(f)
+    xa = np.cross(f, np.asarray(up, np.float64))
+    xa /= np.linalg.norm(xa)
+    ya = np.cross(f, xa)
+    R = np.stack([xa, ya, f], axis=1)
+    return np.concatenate([R, eye[:, None]], axis=1)
+
+
+def sky_camera(x0, x1, y0, y1, height, width, rows, far=None, env=0):
+    """Orthographic camera looking straight down on [x0, x1] x [y0, y1] from
+    ``height``; far defaults to the height (the depth of the plane z = 0)."""
+    pose = np.array([[1.0, 0.0, 0.0, 0.5 * (x0 + x1)],
+                     [0.0, -1.0, 0.0, 0.5 * (y0 + y1)],
+                     [0.0, 0.0, -1.0, height]])
+    return {"env": env, "kind": "ortho", "width": int(width), "height": int(rows), "pose": pose,
+            "params": (0.5 * (x1 - x0), 0.5 * (y1 - y0), height if far is None else far, 0.0)}
+
+
+def perspective_camera(eye, target, fov_x_deg, width, rows, far, up=(0.0, 0.0, 1.0), env=0):
+    """Perspective camera at ``eye`` looking at ``target`` with a horizontal
+    field of view of ``fov_x_deg`` degrees and square pixels."""
+    tx = float(np.tan(np.radians(fov_x_deg) / 2))
+    return {"env": env, "kind": "perspective", "width": int(width), "height": int(rows),
+            "pose": camera_pose(eye, target, up), "params": (tx, tx * rows / width, far, 0.0)}
+
+
 def walled_box(x0, x1, y0, y1, env=0, ground_z=0.0):
     """Ground plane plus four side walls of an open-top container."""
     return [
