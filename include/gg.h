@@ -263,6 +263,58 @@ typedef struct {
 gg_status gg_read(gg_sim* sim, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written,
                   gg_mem where);
 
+/* ---- Observations of the Gym-style environment (Sec. V-A, "Bulldozing"):
+ * depth images computed on the simulating device and the goal-box reward. */
+typedef enum { GG_CAM_ORTHO = 0, GG_CAM_PERSPECTIVE = 1 } gg_camera_kind;
+
+/* A depth camera.  pose = row-major [R | t] (3 x 4) mapping camera to world;
+ * the camera looks along its +z axis, image columns run along +x, rows along
+ * +y.  Pixel (u, v) has the binary32 centre coordinates
+ * g_u = (u + 1/2) * fl32(2 / width) - 1 and g_v likewise (in [-1, 1]).
+ *   GG_CAM_ORTHO:       the pixel's ray starts at camera-frame point
+ *                       (params[0] g_u, params[1] g_v, 0) and runs along +z
+ *                       (params[0], params[1]: half width and half height, m);
+ *   GG_CAM_PERSPECTIVE: it starts at the camera origin and runs along
+ *                       (params[0] g_u, params[1] g_v, 1) (the tangents of the
+ *                       half angles of view).
+ * A pixel's depth is the camera-frame z of the first surface its ray meets,
+ * at most params[2] (far), and far when it meets none.  Drawn: the particles
+ * of environment `env` (spheres) and its GG_PLANE bodies at their current
+ * pose (a plane is met where the ray enters its solid side); other bodies
+ * are not drawn.  Whether a ray meets a sphere is decided in binary32 without
+ * fused multiply-add (camera-frame centre c = R^T (x - t) summed as the SDF
+ * transform; orthographic: c_z > 0 and (o_x - c_x)^2 + (o_y - c_y)^2 <= r^2;
+ * perspective: c_z > 0, E = |c|^2 - r^2 > 0 -- a sphere holding the camera is
+ * skipped --, D = d.c > 0 and |d|^2 E <= D^2); depths are computed in double
+ * from those binary32 values and rounded once.  Images are deterministic. */
+typedef struct {
+  int32_t env;            /* environment drawn (0 .. n_envs-1) */
+  int32_t kind;           /* gg_camera_kind */
+  int32_t width, height;  /* pixels, 1 .. 8192 each */
+  float pose[12];
+  float params[4];        /* p0, p1, far (each finite and > 0), unused */
+} gg_camera;
+
+/* Render n_cams (0 .. 65535) cameras of the current state into dst: the
+ * cameras' images one after another, each height x width row-major
+ * (pixel (u, v) at v * width + u), binary32.  capacity_bytes must be at least
+ * 4 x the total pixel count.  cams is host memory; dst is host or device
+ * memory as `where` says.  The state is not changed.  Returns after the images
+ * are written.  Errors: GG_ERR_INVALID (bad camera, env, size or capacity;
+ * nothing written), GG_ERR_OOM, GG_ERR_HIP. */
+gg_status gg_render_depth(gg_sim* sim, int32_t n_cams, const gg_camera* cams, float* dst,
+                          int64_t capacity_bytes, gg_mem where);
+
+/* Goal-box reward per environment (Sec. V-A): 100 / n_e for every particle of
+ * environment e inside the closed box [lo, hi] (binary32 comparisons of the
+ * binary32 positions), and -d / n_e for every other, d = its distance to the
+ * nearest point of the box (double).  boxes: host, n_envs x 6 (lo xyz, hi xyz,
+ * finite, lo <= hi).  reward: n_envs doubles; inside: n_envs int64 particle
+ * counts, or NULL; both host or device memory as `where` says.  An empty
+ * environment scores 0.  Sums run in a fixed order (bitwise reproducible).
+ * Errors: GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP. */
+gg_status gg_goal_reward(gg_sim* sim, const float* boxes, double* reward, int64_t* inside, gg_mem where);
+
 /* Release every resource of the handle (NULL is ignored). */
 void gg_destroy(gg_sim* sim);
 

@@ -3,6 +3,7 @@
 #include "gg.h"
 #include "kernels.hip.h"
 #include "adjoint.hip.h"
+#include "observe.hip.h"
 
 #include <hip/hip_runtime.h>
 
@@ -292,6 +293,19 @@ struct gg_sim {
   uint64_t epoch = 1;  // bumped whenever a buffer a captured launch names is reallocated
   uint64_t graph_clock = 0;
   hipStream_t cap_stream = nullptr;
+  // observations (gg_render_depth, gg_goal_reward); sized on first use
+  ggk::DevCamera* d_cams = nullptr;
+  int64_t d_cams_cap = 0;
+  ggk::DevPlane* d_planes = nullptr;
+  int64_t d_planes_cap = 0;
+  float* obs_img = nullptr;           // depth staging for host destinations
+  int64_t obs_img_cap = 0;
+  int32_t *d_chunks = nullptr, *d_env_chunk = nullptr, *d_env_count = nullptr, *d_part_n = nullptr;
+  double* d_part_d = nullptr;
+  float* d_boxes = nullptr;
+  double* d_reward = nullptr;
+  int64_t* d_inside = nullptr;
+  int32_t n_chunks = 0;
 };
 
 namespace {
@@ -400,7 +414,9 @@ void free_all(gg_sim* s) {
                   s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp, s->h6,
-                  s->d_env_tblk, s->d_env_toff, s->d_grid_values};
+                  s->d_env_tblk, s->d_env_toff, s->d_grid_values, s->d_cams, s->d_planes, s->obs_img,
+                  s->d_chunks, s->d_env_chunk, s->d_env_count, s->d_part_n, s->d_part_d, s->d_boxes,
+                  s->d_reward, s->d_inside};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (s->h_bodies) (void)hipHostFree(s->h_bodies);
@@ -1650,6 +1666,162 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
   } else {
     HIPCHK(s, hipMemcpy(dst, src, (size_t)need, hipMemcpyHostToDevice));
   }
+  return GG_OK;
+}
+
+gg_status gg_render_depth(gg_sim* s, int32_t n_cams, const gg_camera* cams, float* depth, int64_t capacity_bytes,
+                          gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (n_cams < 0 || n_cams > 65535) return fail(GG_ERR_INVALID, "n_cams must be in 0 .. 65535");
+  if (n_cams > 0 && !cams) return fail(GG_ERR_INVALID, "cams is NULL");
+  std::vector<ggk::DevCamera> hc(n_cams);
+  std::vector<ggk::DevPlane> hp;
+  int64_t total = 0;
+  int max_px = 0, max_n = 0;
+  for (int k = 0; k < n_cams; ++k) {
+    const gg_camera& c = cams[k];
+    if (c.kind != GG_CAM_ORTHO && c.kind != GG_CAM_PERSPECTIVE) return fail(GG_ERR_INVALID, "unknown camera kind");
+    if (c.width < 1 || c.width > 8192 || c.height < 1 || c.height > 8192)
+      return fail(GG_ERR_INVALID, "camera width and height must be in 1 .. 8192");
+    if (c.env < 0 || c.env >= s->n_envs) return fail(GG_ERR_INVALID, "camera env out of range");
+    for (int q = 0; q < 12; ++q)
+      if (!std::isfinite(c.pose[q])) return fail(GG_ERR_INVALID, "camera pose must be finite");
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(c.params[q]) || !(c.params[q] > 0.0f))
+        return fail(GG_ERR_INVALID, "camera params[0..2] must be finite and positive");
+    ggk::DevCamera& d = hc[k];
+    d.kind = c.kind;
+    d.width = c.width;
+    d.height = c.height;
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) d.R[3 * r + q] = c.pose[4 * r + q];
+      d.t[r] = c.pose[4 * r + 3];
+    }
+    d.p0 = c.params[0];
+    d.p1 = c.params[1];
+    d.far = c.params[2];
+    d.su = (float)(2.0 / c.width);
+    d.sv = (float)(2.0 / c.height);
+    d.i0 = (int32_t)s->env_off[c.env];
+    d.i1 = (int32_t)s->env_off[c.env + 1];
+    d.q0 = (int32_t)hp.size();
+    for (const HostBody& b : s->bodies) {
+      if (b.shape != GG_PLANE || b.env != c.env) continue;
+      ggk::DevPlane pl;
+      for (int q = 0; q < 3; ++q) {
+        pl.n[q] = (float)b.R[3 * q + 2];
+        pl.t[q] = (float)b.t[q];
+      }
+      hp.push_back(pl);
+    }
+    d.q1 = (int32_t)hp.size();
+    d.base = total;
+    total += (int64_t)c.width * c.height;
+    max_px = std::max(max_px, c.width * c.height);
+    max_n = std::max(max_n, d.i1 - d.i0);
+  }
+  if (total > 0 && !depth) return fail(GG_ERR_INVALID, "depth is NULL");
+  if (capacity_bytes < total * 4) return fail(GG_ERR_INVALID, "destination too small");
+  if (total == 0) return GG_OK;
+  DeviceGuard g(s->dev);
+  auto grow = [&](void** buf, int64_t& cap, int64_t need_bytes) -> gg_status {
+    if (need_bytes <= cap) return GG_OK;
+    if (*buf) HIPCHK(s, hipFree(*buf));
+    *buf = nullptr;
+    cap = 0;
+    if (hipMalloc(buf, (size_t)need_bytes) != hipSuccess) return fail(GG_ERR_OOM, "observation buffer allocation failed");
+    cap = need_bytes;
+    return GG_OK;
+  };
+  gg_status st = grow((void**)&s->d_cams, s->d_cams_cap, (int64_t)(n_cams * sizeof(ggk::DevCamera)));
+  if (st == GG_OK) st = grow((void**)&s->d_planes, s->d_planes_cap, (int64_t)(std::max<size_t>(1, hp.size()) * sizeof(ggk::DevPlane)));
+  if (st == GG_OK && where == GG_MEM_HOST) st = grow((void**)&s->obs_img, s->obs_img_cap, total * 4);
+  if (st != GG_OK) return st;
+  HIPCHK(s, hipMemcpyAsync(s->d_cams, hc.data(), n_cams * sizeof(ggk::DevCamera), hipMemcpyHostToDevice, s->stream));
+  if (!hp.empty())
+    HIPCHK(s, hipMemcpyAsync(s->d_planes, hp.data(), hp.size() * sizeof(ggk::DevPlane), hipMemcpyHostToDevice, s->stream));
+  float* out = where == GG_MEM_DEVICE ? depth : s->obs_img;
+  const int gx = std::max(1, std::min((max_px + ggk::kBlock - 1) / ggk::kBlock, 1024));
+  ggk::k_depth_planes<<<dim3(gx, n_cams), ggk::kBlock, 0, s->stream>>>(s->d_cams, s->d_planes, out);
+  HIPCHK(s, hipGetLastError());
+  if (max_n > 0) {
+    const int gs = std::max(1, std::min((max_n + ggk::kBlock - 1) / ggk::kBlock, 4096));
+    if (s->fp64)
+      ggk::k_depth_spheres<double><<<dim3(gs, n_cams), ggk::kBlock, 0, s->stream>>>(s->d_cams, (const double4*)s->x, out);
+    else
+      ggk::k_depth_spheres<float><<<dim3(gs, n_cams), ggk::kBlock, 0, s->stream>>>(s->d_cams, (const float4*)s->x, out);
+    HIPCHK(s, hipGetLastError());
+  }
+  if (where == GG_MEM_HOST)
+    HIPCHK(s, hipMemcpyAsync(depth, s->obs_img, (size_t)total * 4, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return GG_OK;
+}
+
+gg_status gg_goal_reward(gg_sim* s, const float* boxes, double* reward, int64_t* inside, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (!boxes || !reward) return fail(GG_ERR_INVALID, "boxes and reward are required");
+  const int ne = s->n_envs;
+  for (int e = 0; e < ne; ++e)
+    for (int q = 0; q < 3; ++q) {
+      const float lo = boxes[6 * e + q], hi = boxes[6 * e + 3 + q];
+      if (!std::isfinite(lo) || !std::isfinite(hi) || lo > hi)
+        return fail(GG_ERR_INVALID, "goal boxes must be finite with lo <= hi");
+    }
+  DeviceGuard g(s->dev);
+  if (!s->d_chunks) {
+    // chunks of at most kRewardChunk particles, none spanning two environments
+    std::vector<int32_t> ch, ec(ne + 1, 0), cnt(ne);
+    for (int e = 0; e < ne; ++e) {
+      ec[e] = (int32_t)(ch.size() / 3);
+      cnt[e] = (int32_t)(s->env_off[e + 1] - s->env_off[e]);
+      for (int64_t b = s->env_off[e]; b < s->env_off[e + 1]; b += ggk::kRewardChunk) {
+        ch.push_back(e);
+        ch.push_back((int32_t)b);
+        ch.push_back((int32_t)std::min<int64_t>(b + ggk::kRewardChunk, s->env_off[e + 1]));
+      }
+    }
+    ec[ne] = (int32_t)(ch.size() / 3);
+    const int nc = ec[ne];
+    bool ok = dev_alloc(&s->d_chunks, (size_t)std::max(1, nc) * 3) == hipSuccess &&
+              dev_alloc(&s->d_env_chunk, (size_t)ne + 1) == hipSuccess &&
+              dev_alloc(&s->d_env_count, (size_t)ne) == hipSuccess &&
+              dev_alloc(&s->d_part_n, (size_t)std::max(1, nc)) == hipSuccess &&
+              dev_alloc(&s->d_part_d, (size_t)std::max(1, nc)) == hipSuccess &&
+              dev_alloc(&s->d_boxes, (size_t)ne * 6) == hipSuccess && dev_alloc(&s->d_reward, (size_t)ne) == hipSuccess &&
+              dev_alloc(&s->d_inside, (size_t)ne) == hipSuccess;
+    if (!ok) return fail(GG_ERR_OOM, "reward buffer allocation failed");
+    if (nc > 0) HIPCHK(s, hipMemcpy(s->d_chunks, ch.data(), ch.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(s->d_env_chunk, ec.data(), ec.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(s->d_env_count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
+    s->n_chunks = nc;
+  }
+  HIPCHK(s, hipMemcpyAsync(s->d_boxes, boxes, (size_t)ne * 24, hipMemcpyHostToDevice, s->stream));
+  if (s->n_chunks > 0) {
+    if (s->fp64)
+      ggk::k_reward_chunks<double><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const double4*)s->x, s->d_chunks,
+                                                                            s->d_boxes, s->d_part_d, s->d_part_n);
+    else
+      ggk::k_reward_chunks<float><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const float4*)s->x, s->d_chunks,
+                                                                           s->d_boxes, s->d_part_d, s->d_part_n);
+    HIPCHK(s, hipGetLastError());
+  }
+  double* rw = where == GG_MEM_DEVICE ? reward : s->d_reward;
+  int64_t* in = where == GG_MEM_DEVICE ? inside : (inside ? s->d_inside : nullptr);
+  ggk::k_reward_envs<<<(ne + 255) / 256, 256, 0, s->stream>>>(ne, s->d_env_chunk, s->d_env_count, s->d_part_d,
+                                                               s->d_part_n, rw, in);
+  HIPCHK(s, hipGetLastError());
+  if (where == GG_MEM_HOST) {
+    HIPCHK(s, hipMemcpyAsync(reward, s->d_reward, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
+    if (inside) HIPCHK(s, hipMemcpyAsync(inside, s->d_inside, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
   return GG_OK;
 }
 

@@ -24,7 +24,8 @@ FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "sta
          "radius": 7}
 SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
 
-EXPORTS = ("gg_create", "gg_set_bodies", "gg_step", "gg_step_backward", "gg_read", "gg_destroy",
+EXPORTS = ("gg_create", "gg_set_bodies", "gg_set_grids", "gg_step", "gg_step_backward", "gg_read",
+           "gg_render_depth", "gg_goal_reward", "gg_destroy",
            "gg_status_string", "gg_error_detail")
 
 
@@ -46,6 +47,32 @@ class Body(C.Structure):
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("origin", C.c_float * 3),
                 ("inv_spacing", C.c_float), ("offset", C.c_int64)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("env", C.c_int32), ("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("pose", C.c_float * 12), ("params", C.c_float * 4)]
+
+
+CAMERA_KINDS = {"ortho": 0, "perspective": 1}
+
+
+def make_cameras(cams):
+    """gg_camera array from dicts {"env", "kind" ("ortho" | "perspective"),
+    "width", "height", "pose" (3 x 4, camera -> world), "params" (p0, p1, far)}."""
+    arr = (Camera * max(1, len(cams)))()
+    for k, c in enumerate(cams):
+        A = arr[k]
+        A.env = int(c.get("env", 0))
+        A.kind = CAMERA_KINDS[c["kind"]] if isinstance(c["kind"], str) else int(c["kind"])
+        A.width, A.height = int(c["width"]), int(c["height"])
+        pose = np.asarray(c["pose"], np.float64).reshape(12)
+        for q in range(12):
+            A.pose[q] = float(pose[q])
+        prm = list(c["params"]) + [0.0] * (4 - len(c["params"]))
+        for q in range(4):
+            A.params[q] = float(prm[q])
+    return arr
 
 
 class Params(C.Structure):
@@ -106,6 +133,10 @@ def lib():
         L.gg_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, i32]
         L.gg_read.restype = i32
         L.gg_read.argtypes = [vp, i32, vp, i64, C.POINTER(i64), i32]
+        L.gg_render_depth.restype = i32
+        L.gg_render_depth.argtypes = [vp, i32, vp, vp, i64, i32]
+        L.gg_goal_reward.restype = i32
+        L.gg_goal_reward.argtypes = [vp, vp, vp, vp, i32]
         L.gg_destroy.restype = None
         L.gg_destroy.argtypes = [vp]
         L.gg_status_string.restype = C.c_char_p
@@ -314,6 +345,52 @@ class Sim:
 
     def stats(self):
         return self.read("stats")
+
+    def render_depth(self, cams, out=None):
+        """Depth images of the current state (Sec. V-A observations): a list of
+        (height, width) float32 arrays, or, with ``out`` (a device tensor of at
+        least the total pixel count), the concatenated images written there."""
+        A = make_cameras(cams)
+        sizes = [int(c["width"]) * int(c["height"]) for c in cams]
+        total = sum(sizes)
+        if out is not None:
+            _check(lib().gg_render_depth(self._h, len(cams), C.byref(A), C.c_void_p(out.data_ptr()),
+                                         out.numel() * out.element_size(),
+                                         GG_MEM_DEVICE if out.is_cuda else GG_MEM_HOST))
+            return out
+        buf = np.empty(total, np.float32)
+        _check(lib().gg_render_depth(self._h, len(cams), C.byref(A), buf.ctypes.data_as(C.c_void_p), total * 4,
+                                     GG_MEM_HOST))
+        imgs, at = [], 0
+        for c, m in zip(cams, sizes):
+            imgs.append(buf[at:at + m].reshape(int(c["height"]), int(c["width"])))
+            at += m
+        return imgs
+
+    def render_cameras(self, cam_array, n_cams, out):
+        """Render a prepared gg_camera array (``make_cameras``) into ``out``, a
+        float32 NumPy array or torch tensor (host or device) holding at least
+        the total pixel count."""
+        if _is_torch(out):
+            ptr, nbytes = C.c_void_p(out.data_ptr()), out.numel() * out.element_size()
+            where = GG_MEM_DEVICE if out.is_cuda else GG_MEM_HOST
+        else:
+            assert out.dtype == np.float32 and out.flags.c_contiguous
+            ptr, nbytes, where = out.ctypes.data_as(C.c_void_p), out.nbytes, GG_MEM_HOST
+        _check(lib().gg_render_depth(self._h, int(n_cams), C.byref(cam_array), ptr, nbytes, where))
+        return out
+
+    def goal_reward(self, boxes):
+        """(reward, inside) per environment for goal boxes n_envs x (lo, hi)."""
+        bx = np.ascontiguousarray(boxes, np.float32).reshape(-1, 6)
+        ne = bx.shape[0]
+        if ne != self.n_envs:
+            raise ValueError(f"need one goal box per environment ({self.n_envs}), got {ne}")
+        rew = np.zeros(ne, np.float64)
+        ins = np.zeros(ne, np.int64)
+        _check(lib().gg_goal_reward(self._h, bx.ctypes.data_as(C.c_void_p), rew.ctypes.data_as(C.c_void_p),
+                                    ins.ctypes.data_as(C.c_void_p), GG_MEM_HOST))
+        return rew, ins
 
     def backward(self, dL_dx=None, dL_dv=None, n_steps=None):
         """Gradients of the last (differentiable) step call: returns

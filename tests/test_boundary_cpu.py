@@ -40,6 +40,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(gg_params, hash_size), offsetof(gg_params, flags),
          offsetof(gg_params, stream), offsetof(gg_body, twist));
   printf("%zu %zu\n", offsetof(gg_stats, ms_detect), offsetof(gg_stats, pja_launches));
+  printf("%zu %zu %zu\n", sizeof(gg_camera), offsetof(gg_camera, pose), offsetof(gg_camera, params));
   return 0;
 }
 """
@@ -57,6 +58,7 @@ int main(void) {
     assert vals[6] == gg.Body.twist.offset
     assert vals[7] == gg.Stats.ms_detect.offset
     assert vals[8] == gg.Stats.pja_launches.offset
+    assert vals[9:12] == [C.sizeof(gg.Camera), gg.Camera.pose.offset, gg.Camera.params.offset]
 
 
 def test_status_strings():
@@ -121,6 +123,8 @@ def test_null_handle_calls_are_rejected():
     w = C.c_int64(0)
     assert L.gg_read(None, 0, None, 0, C.byref(w), 0) == gg.GG_ERR_INVALID
     assert L.gg_step_backward(None, None, None, None, None, None, 0) == gg.GG_ERR_INVALID
+    assert L.gg_render_depth(None, 0, None, None, 0, 0) == gg.GG_ERR_INVALID
+    assert L.gg_goal_reward(None, None, None, None, 0) == gg.GG_ERR_INVALID
     L.gg_destroy(None)
     assert b"NULL" in L.gg_error_detail() or L.gg_error_detail() == b"sim is NULL"
 

@@ -1,0 +1,72 @@
+"""The Gym-style bulldozing environment (Sec. V-A) on the device: its
+observations and rewards against the FP64 oracle on the state read back, and
+the blade pushing grains into the goal box."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_01369_amd.bulldozer import BulldozerEnv
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _check_obs(env, obs, reward, label):
+    x = env.sim.read("pos")
+    r = env.sim.read("radius")
+    cams = env.cameras()
+    want = O.render_depth(x, r, cams, env.bodies, env_offsets=env.offsets)
+    for e in range(env.n_envs):
+        for got, w in ((obs["ego"][e], want[2 * e]), (obs["sky"][e], want[2 * e + 1])):
+            got = np.asarray(got)
+            ulp = np.spacing(np.abs(w)).astype(np.float64)
+            assert np.all(np.abs(got.astype(np.float64) - w) <= 2 * ulp), (label, e)
+    if reward is not None:
+        rw, iw = O.goal_reward(x, env.boxes, env_offsets=env.offsets)
+        assert np.all(np.abs(reward - rw) <= 1e-12 * 100 + 1e-12 * np.abs(rw)), (label, reward, rw)
+        say(label, "reward", np.round(reward, 4), "inside", iw)
+        return iw
+    return None
+
+
+def test_observations_and_rewards_match_the_oracle_while_pushing():
+    env = BulldozerEnv(n_envs=3, n_particles=3000, substeps=5, v_max=0.25)
+    obs = env.reset()
+    say("bulldozer 3 envs x 3000 grains")
+    _check_obs(env, obs, None, "reset")
+    inside = None
+    acts = np.array([[1.0, 0.0], [1.0, 0.15], [0.6, -0.1]])
+    for t in range(36):
+        obs, rew, done, info = env.step(acts)
+        if t in (0, 9, 35):
+            inside = _check_obs(env, obs, rew, f"step {t + 1}")
+    assert not done.any()
+    # driving at full speed for 36 x 5 x 10 ms, the first blade has crossed
+    # the arena and pushed grains into the goal box
+    assert inside[0] > 0, inside
+    pose = obs["pose"]
+    assert pose[0, 0] > 0.4 and abs(pose[0, 2]) < 1e-12
+    assert pose[1, 2] > 0.2
+    env.close()
+
+
+def test_device_observations_equal_host_observations():
+    torch = pytest.importorskip("torch")
+    a = BulldozerEnv(n_envs=2, n_particles=2000, device_obs=True)
+    b = BulldozerEnv(n_envs=2, n_particles=2000, device_obs=False)
+    oa, ob = a.reset(), b.reset()
+    for _ in range(3):
+        oa, ra, _, _ = a.step(np.array([[1.0, 0.3], [0.5, -0.5]]))
+        ob, rb, _, _ = b.step(np.array([[1.0, 0.3], [0.5, -0.5]]))
+    torch.cuda.synchronize()
+    assert oa["ego"].is_cuda
+    assert np.array_equal(oa["ego"].cpu().numpy(), ob["ego"]) and np.array_equal(oa["sky"].cpu().numpy(), ob["sky"])
+    assert np.array_equal(ra, rb)
+    a.close()
+    b.close()
