@@ -323,6 +323,67 @@ def bench_hash_sweep(args):
     }
 
 
+def bench_gym(args):
+    """The Gym-style bulldozing environment (Sec. V-A): 128 arenas of 8,192
+    grains (1,048,576 in all), each action held for 5 steps of 10 ms, ego
+    (64x48, perspective) and sky (64x64, orthographic) depth images and the
+    goal-box reward after every environment step, uniform random actions."""
+    from paper_2306_01369_amd.bulldozer import BulldozerEnv
+    import torch
+    steps = args.steps if args.steps_given else 40
+    n_envs, per = 128, 8192
+    env = BulldozerEnv(n_envs=n_envs, n_particles=per, device_obs=True)
+    rng = np.random.default_rng(0)
+    env.reset()
+    log("gym: warm-up (graph capture)")
+    for _ in range(5):
+        env.step(rng.uniform(-1, 1, (n_envs, 2)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        obs, rew, done, info = env.step(rng.uniform(-1, 1, (n_envs, 2)))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    # phase split (each phase synchronised, so the sum exceeds the loop above)
+    ph = {"sim_steps": 0.0, "render": 0.0, "reward": 0.0, "host_control": 0.0}
+    k_ph = max(5, steps // 4)
+    for _ in range(k_ph):
+        ta = time.perf_counter()
+        tw = env._twists(rng.uniform(-1, 1, (n_envs, 2)))
+        tb = time.perf_counter()
+        env.sim.step(env.substeps, tw)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        env.observe()
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        env.sim.goal_reward(env.boxes)
+        te = time.perf_counter()
+        ph["host_control"] += tb - ta
+        ph["sim_steps"] += tc - tb
+        ph["render"] += td - tc
+        ph["reward"] += te - td
+    ph = {k: 1e3 * v / k_ph for k, v in ph.items()}
+    st = env.sim.stats()
+    env.close()
+    n = n_envs * per
+    log(f"gym: {1e3 * total / steps:.2f} ms per environment step; phases {ph}")
+    return {
+        "metric": "bulldozing environment steps/s (128 arenas, 5 x 10 ms sim steps + depth images + reward)",
+        "value": n_envs * steps / total, "unit": "env-steps/s", "n_gpus": 1, "steps": steps, "warmup": 5,
+        "ms_per_step": 1e3 * total / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bulldozing: 128 walled 0.7 m arenas, each a 0.4 m pile of 8,192 spheres r=4 mm, a "
+                               "goal box along the far side and a box blade under track steering; action held 5 "
+                               "steps of 10 ms, 20 PJA sweeps; ego 64x48 + sky 64x64 depth images and goal-box "
+                               "reward per environment step, uniform random actions",
+                   "n": n, "n_envs": n_envs, "substeps": env.substeps},
+        "particle_steps_per_s": n * env.substeps * steps / total,
+        "phases_ms_per_env_step": ph,
+        "contacts_last_step": st["n_pp"] + st["n_pb"],
+    }
+
+
 def bench_large(args):
     """4,194,304 polydisperse spheres, 64 sweeps, box + capsule tools: settle the
     layered start (untimed, 20 sweeps, tools still), time 80 forward steps, then a
@@ -406,7 +467,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep"],
+    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep", "gym"],
                     default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150)
     ap.add_argument("--plain-steps", type=int, default=5)
@@ -425,9 +486,9 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 200
-    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep"):
-        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop,
-               "diff": bench_diff, "gears": bench_gears, "hashsweep": bench_hash_sweep}[args.workload](args)
+    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep", "gym"):
+        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop, "diff": bench_diff,
+               "gears": bench_gears, "hashsweep": bench_hash_sweep, "gym": bench_gym}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -17,7 +17,14 @@ grain outside it at distance d).
 
 The paper's arena, vehicle model, camera placement and control period are not
 given; the values here are choices of this environment, stated in the
-constructor's arguments.
+constructor's arguments.  The default pile is about four grains deep: at the
+coarse 10 ms step, 20 projected-Jacobi sweeps cannot hold up much taller
+stacks, which then sink into themselves (the collapse of tall stacks the paper
+reports for this step size) until contacts exceed their capacity.  For the
+same reason grains that the kinematic blade drives into the pile overlap
+their neighbours deeply -- more neighbours than a sphere can touch without
+overlap, and some sink into the floor -- so the contact capacity defaults to
+64 per grain rather than the packing bound.
 """
 from __future__ import annotations
 
@@ -37,17 +44,18 @@ class BulldozerEnv:
     With device_obs=True the depth images are torch tensors on the device the
     simulation runs on (no host copy)."""
 
-    def __init__(self, n_envs=4, n_particles=8192, seed=0, r=0.004, arena=0.6, pile=0.3, dt=0.01,
-                 substeps=5, n_iters=20, mu=0.5, alpha=0.2, horizon=100, v_max=0.25, yaw_max=1.5,
-                 blade=(0.015, 0.1, 0.04), ego=(64, 48), sky=(64, 64), ego_fov=70.0, graph=True,
-                 precision=0, device_obs=False):
+    def __init__(self, n_envs=4, n_particles=8192, seed=0, r=0.004, arena=0.7, pile=0.4, dt=0.01,
+                 substeps=5, n_iters=20, mu=0.5, alpha=0.2, horizon=100, v_max=0.15, yaw_max=1.0,
+                 blade=(0.015, 0.1, 0.05), ego=(64, 48), sky=(64, 64), ego_fov=70.0, graph=True,
+                 precision=0, device_obs=False, max_contacts=64):
         self.n_envs, self.n_particles, self.r = int(n_envs), int(n_particles), float(r)
         self.arena, self.pile = float(arena), float(pile)
         self.dt, self.substeps, self.horizon = float(dt), int(substeps), int(horizon)
         self.v_max, self.yaw_max = float(v_max), float(yaw_max)
         self.blade = tuple(float(b) for b in blade)
         self.ego_size, self.sky_size, self.ego_fov = tuple(ego), tuple(sky), float(ego_fov)
-        self.sim_kw = dict(dt=dt, n_iters=n_iters, mu=mu, alpha=alpha, graph=graph, precision=precision)
+        self.sim_kw = dict(dt=dt, n_iters=n_iters, mu=mu, alpha=alpha, graph=graph, precision=precision,
+                           max_contacts=max_contacts)
         self.device_obs = bool(device_obs)
         self.seed = seed
         self.sim = None
@@ -64,7 +72,7 @@ class BulldozerEnv:
     def goal_box(self, e):
         gx, gy = self.origin(e)
         a = self.arena
-        return np.array([gx + 0.75 * a, gy, 0.0, gx + a, gy + a, 0.2], np.float32)
+        return np.array([gx + 0.8 * a, gy, 0.0, gx + a, gy + a, 0.2], np.float32)
 
     def _build(self, seed):
         rng = np.random.default_rng(seed)
@@ -73,10 +81,13 @@ class BulldozerEnv:
         for e in range(self.n_envs):
             gx, gy = self.origin(e)
             y0 = gy + 0.5 * (a - p)
-            xs.append(scenes.packed_bed(self.n_particles, self.r, gx + 0.2 * a, gx + 0.2 * a + p, y0, y0 + p, rng))
+            xs.append(scenes.packed_bed(self.n_particles, self.r, gx + 0.1 * a, gx + 0.1 * a + p, y0, y0 + p, rng))
             bodies += scenes.walled_box(gx, gx + a, gy, gy + a, env=e)
             self.blade_index.append(len(bodies))
-            bodies.append(scenes.box_tool((gx + 0.06, gy + 0.5 * a, self.blade[2] + 0.002), self.blade, env=e))
+            # the blade reaches 2 cm below the floor: no grain can be caught under
+            # it, and a grain pressed into its face stays nearer that face than
+            # the bottom face (whose normal would push it into the floor)
+            bodies.append(scenes.box_tool((gx + 0.035, gy + 0.5 * a, self.blade[2] - 0.02), self.blade, env=e))
         self.x0 = np.ascontiguousarray(np.concatenate(xs), np.float32)
         self.radius = np.full(len(self.x0), self.r, np.float32)
         self.offsets = np.arange(self.n_envs + 1, dtype=np.int64) * self.n_particles
@@ -91,33 +102,54 @@ class BulldozerEnv:
             cams.append(scenes.sky_camera(gx, gx + a, gy, gy + a, 0.4, self.sky_size[0], self.sky_size[1], env=e))
         self.cams = cams
         self.cam_array = gg.make_cameras(cams)
+        self.cam_view = np.ctypeslib.as_array(self.cam_array)   # writes go to the camera array
+        self.corners = np.array([self.origin(e) for e in range(self.n_envs)], np.float64)
         self.ego_px = self.ego_size[0] * self.ego_size[1]
         self.sky_px = self.sky_size[0] * self.sky_size[1]
 
     # ---------------------------------------------------------------- control
-    def _ego_pose(self, e):
-        x, y, th = self.state[e]
-        c, s = math.cos(th), math.sin(th)
-        z = self.blade[2] + 0.002
-        eye = (x - 0.06 * c, y - 0.06 * s, z + 0.10)
-        tgt = (x + 0.25 * c, y + 0.25 * s, 0.0)
-        return scenes.camera_pose(eye, tgt)
+    def _ego_poses(self):
+        """Ego camera poses (n_envs, 3, 4): 6 cm behind and 10 cm above the
+        blade's top, looking at the floor 25 cm ahead of it."""
+        x, y, th = self.state[:, 0], self.state[:, 1], self.state[:, 2]
+        c, s = np.cos(th), np.sin(th)
+        z = self.blade[2] - 0.02
+        eye = np.stack([x - 0.06 * c, y - 0.06 * s, np.full_like(x, z + 0.10)], axis=1)
+        tgt = np.stack([x + 0.25 * c, y + 0.25 * s, np.zeros_like(x)], axis=1)
+        f = tgt - eye
+        f /= np.linalg.norm(f, axis=1, keepdims=True)
+        xa = np.cross(f, np.array([0.0, 0.0, 1.0]))
+        xa /= np.linalg.norm(xa, axis=1, keepdims=True)
+        ya = np.cross(f, xa)
+        return np.concatenate([np.stack([xa, ya, f], axis=2), eye[:, :, None]], axis=2)
 
     def _twists(self, actions):
         """Per-substep body twists (substeps, n_bodies, 6) and the blade poses
-        they lead to (the library advances t += dt nu, yaw += dt omega)."""
+        they lead to (the library advances t += dt nu, yaw += dt omega).  The
+        vehicle stops where a step would bring the blade's centre closer to a
+        wall than its half width plus 2 cm (it may still turn there, and move
+        away from the wall), so the blade never crushes grains against the
+        walls."""
         act = np.clip(np.asarray(actions, np.float64).reshape(self.n_envs, 2), -1.0, 1.0)
         tw = np.zeros((self.substeps, len(self.bodies), 6), np.float32)
+        m = math.hypot(self.blade[0], self.blade[1]) + 0.02
+        lo = self.corners + m
+        hi = self.corners + self.arena - m
+
+        def out(p):
+            return (np.maximum(np.maximum(lo - p, p - hi), 0.0)).sum(axis=1)
+        v0, w = self.v_max * act[:, 0], self.yaw_max * act[:, 1]
+        b = np.asarray(self.blade_index)
         for k in range(self.substeps):
-            for e in range(self.n_envs):
-                x, y, th = self.state[e]
-                v, w = self.v_max * act[e, 0], self.yaw_max * act[e, 1]
-                nu = np.float32([v * math.cos(th), v * math.sin(th), 0.0])
-                om = np.float32(w)
-                b = self.blade_index[e]
-                tw[k, b, 0:3] = nu
-                tw[k, b, 5] = om
-                self.state[e] = (x + self.dt * float(nu[0]), y + self.dt * float(nu[1]), th + self.dt * float(om))
+            xy, th = self.state[:, :2], self.state[:, 2]
+            head = np.stack([np.cos(th), np.sin(th)], axis=1)
+            v = np.where(out(xy + self.dt * v0[:, None] * head) > out(xy), 0.0, v0)
+            nu = (v[:, None] * head).astype(np.float32)
+            om = w.astype(np.float32)
+            tw[k, b, 0:2] = nu
+            tw[k, b, 5] = om
+            self.state[:, 0:2] += self.dt * nu.astype(np.float64)
+            self.state[:, 2] += self.dt * om.astype(np.float64)
         return tw
 
     # ---------------------------------------------------------------- Gym API
@@ -129,19 +161,18 @@ class BulldozerEnv:
             self.sim.close()
         self.sim = gg.Sim(self.x0, np.zeros_like(self.x0), self.radius, self.bodies, env_offsets=self.offsets,
                           **self.sim_kw)
-        self.state = []
-        for e in range(self.n_envs):
-            t = self.bodies[self.blade_index[e]]["t"]
-            self.state.append((float(np.float32(t[0])), float(np.float32(t[1])), 0.0))
+        self.state = self.initial_state()
         self.t = 0
         return self.observe()
 
+    def initial_state(self):
+        """Blade (x, y, yaw) per environment at reset, x and y as the library
+        holds them (binary32)."""
+        t = np.array([self.bodies[b]["t"][:2] for b in self.blade_index], np.float32).astype(np.float64)
+        return np.concatenate([t, np.zeros((self.n_envs, 1))], axis=1)
+
     def observe(self):
-        for e in range(self.n_envs):
-            pose = np.asarray(self._ego_pose(e), np.float32).reshape(12)
-            A = self.cam_array[2 * e]
-            for q in range(12):
-                A.pose[q] = float(pose[q])
+        self.cam_view["pose"][0::2] = self._ego_poses().reshape(self.n_envs, 12)
         total = self.n_envs * (self.ego_px + self.sky_px)
         per = self.ego_px + self.sky_px
         if self.device_obs:
@@ -155,8 +186,8 @@ class BulldozerEnv:
             view = buf.reshape(self.n_envs, per)
         ego = view[:, :self.ego_px].reshape(self.n_envs, self.ego_size[1], self.ego_size[0])
         sky = view[:, self.ego_px:].reshape(self.n_envs, self.sky_size[1], self.sky_size[0])
-        pose = np.array([(x - self.origin(e)[0], y - self.origin(e)[1], th)
-                         for e, (x, y, th) in enumerate(self.state)])
+        pose = self.state.copy()
+        pose[:, :2] -= self.corners
         return {"ego": ego, "sky": sky, "pose": pose}
 
     def step(self, actions):

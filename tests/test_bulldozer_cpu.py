@@ -9,7 +9,7 @@ from paper_2306_01369_amd.bulldozer import BulldozerEnv
 
 def _env(**kw):
     e = BulldozerEnv(n_envs=3, n_particles=500, **kw)
-    e.state = [(e.bodies[e.blade_index[k]]["t"][0], e.bodies[e.blade_index[k]]["t"][1], 0.0) for k in range(3)]
+    e.state = e.initial_state()
     return e
 
 
@@ -32,7 +32,7 @@ def test_layout_keeps_piles_blades_and_goals_apart():
 
 def test_track_steering_twists():
     e = _env(substeps=4, dt=0.01, v_max=0.2, yaw_max=1.0)
-    x0 = [s for s in e.state]
+    x0 = e.state.copy()
     tw = e._twists(np.array([[1.0, 0.0], [0.0, 1.0], [5.0, -5.0]]))
     assert tw.shape == (4, len(e.bodies), 6)
     blades = set(e.blade_index)
@@ -42,7 +42,7 @@ def test_track_steering_twists():
     # env 0: straight ahead along +x; env 1: turn in place; env 2: clipped to (1, -1)
     assert e.state[0][0] - x0[0][0] == pytest_approx(4 * 0.01 * 0.2)
     assert e.state[0][2] == 0.0
-    assert e.state[1][:2] == x0[1][:2] and e.state[1][2] == pytest_approx(4 * 0.01 * 1.0)
+    assert np.array_equal(e.state[1][:2], x0[1][:2]) and e.state[1][2] == pytest_approx(4 * 0.01 * 1.0)
     assert e.state[2][2] == pytest_approx(-4 * 0.01 * 1.0)
     b2 = e.blade_index[2]
     np.testing.assert_allclose(np.linalg.norm(tw[:, b2, :3], axis=1), 0.2, rtol=1e-6)
@@ -55,8 +55,8 @@ def test_track_steering_twists():
 
 def test_ego_camera_rides_on_the_blade():
     e = _env()
-    e.state[0] = (e.state[0][0], e.state[0][1], math.pi / 2)
-    pose = e._ego_pose(0)
+    e.state[0, 2] = math.pi / 2
+    pose = e._ego_poses()[0]
     R, t = pose[:, :3], pose[:, 3]
     np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
     fwd = R[:, 2]
@@ -67,3 +67,18 @@ def test_ego_camera_rides_on_the_blade():
 def pytest_approx(v):
     import pytest
     return pytest.approx(v, rel=1e-6, abs=1e-12)   # twists are binary32
+
+
+def test_blade_stops_short_of_the_walls_but_may_turn_and_back_off():
+    e = _env(substeps=3, dt=0.01, v_max=0.2, yaw_max=1.0)
+    m = math.hypot(e.blade[0], e.blade[1]) + 0.02
+    gx, gy = e.origin(1)
+    e.state[1] = (gx + e.arena - m - 1e-4, gy + 0.3, 0.0)   # facing the far wall, almost at the limit
+    x_before = e.state[1, 0]
+    tw = e._twists(np.array([[0.0, 0.0], [1.0, 0.5], [0.0, 0.0]]))
+    b = e.blade_index[1]
+    assert np.all(tw[:, b, 0] == 0.0) and np.all(tw[:, b, 5] == np.float32(0.5))   # turns, does not advance
+    assert e.state[1, 0] == x_before
+    e.state[1, 2] = 0.0
+    tw = e._twists(np.array([[0.0, 0.0], [-1.0, 0.0], [0.0, 0.0]]))
+    assert np.all(tw[:, b, 0] < 0)                                                  # backing off is allowed

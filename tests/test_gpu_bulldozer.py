@@ -36,22 +36,23 @@ def _check_obs(env, obs, reward, label):
 
 
 def test_observations_and_rewards_match_the_oracle_while_pushing():
-    env = BulldozerEnv(n_envs=3, n_particles=3000, substeps=5, v_max=0.25)
+    env = BulldozerEnv(n_envs=3, n_particles=3000, substeps=5, v_max=0.25, yaw_max=1.5)
     obs = env.reset()
     say("bulldozer 3 envs x 3000 grains")
     _check_obs(env, obs, None, "reset")
     inside = None
     acts = np.array([[1.0, 0.0], [1.0, 0.15], [0.6, -0.1]])
-    for t in range(36):
+    for t in range(50):
         obs, rew, done, info = env.step(acts)
-        if t in (0, 9, 35):
+        if t in (0, 9, 49):
             inside = _check_obs(env, obs, rew, f"step {t + 1}")
     assert not done.any()
-    # driving at full speed for 36 x 5 x 10 ms, the first blade has crossed
-    # the arena and pushed grains into the goal box
+    # driving at full speed for 50 x 5 x 10 ms, the first blade has crossed
+    # the arena and pushed grains into the goal box,
     assert inside[0] > 0, inside
     pose = obs["pose"]
-    assert pose[0, 0] > 0.4 and abs(pose[0, 2]) < 1e-12
+    # ... and stopped short of the far wall (centre at most 0.7 - 0.121 m)
+    assert 0.55 < pose[0, 0] <= 0.7 - np.hypot(0.015, 0.1) - 0.02 + 1e-9 and abs(pose[0, 2]) < 1e-12
     assert pose[1, 2] > 0.2
     env.close()
 
