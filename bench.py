@@ -323,6 +323,49 @@ def bench_hash_sweep(args):
     }
 
 
+def bench_passes(args):
+    """The paper's kernel-order ablation on MI355X: detection and the impulse
+    sweeps split across launches (the production path; also replayed from a
+    captured graph) against one cooperative launch per step with grid-wide
+    barriers (GG_FLAG_FUSED), on a column of grains at rest (1,024 .. 65,536
+    grains) and on the 1M scoop bed; speedup over real time = dt / (s per step)."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    # step counts are multiples of the re-sort interval (8), so the timed call
+    # replays the graph the warm-up call captured (same re-sort phase)
+    steps = 8 * max(1, (args.steps if args.steps_given else 96) // 8)
+    modes = (("split", {}), ("split+graph", {"graph": True}), ("fused", {"fused": True}))
+    cases = [(f"column-{n}", scenes.column_scene(n=n, r=0.004)) for n in (1024, 4096, 16384, 65536)]
+    cases.append(("scoop-1M", scenes.scoop_scene()))
+    table = []
+    for name, sc in cases:
+        row = {"case": name, "particles": sc.n}
+        for mode, kw in modes:
+            sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
+                         n_iters=sc.n_iters, **kw)
+            k = steps if sc.n < 500000 else max(8, 8 * (steps // 40))
+            sim.step(k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(k)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / k
+            sim.close()
+            row[mode] = {"us_per_step": 1e6 * t, "x_realtime": sc.dt / t}
+        table.append(row)
+        log(f"passes {name}: " + ", ".join(f"{m}={row[m]['us_per_step']:.0f} us" for m, _ in modes))
+    last = table[-1]
+    return {
+        "metric": "kernel-order ablation: us/step, split launches vs one fused cooperative launch",
+        "value": last["fused"]["us_per_step"] / last["split"]["us_per_step"], "unit": "fused/split time ratio (1M)",
+        "n_gpus": 1, "steps": steps, "warmup": steps, "ms_per_step": last["fused"]["us_per_step"] / 1e3,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "column at rest (1,024..65,536 spheres r=4 mm, 8x8 grains per layer, walled) and "
+                               "the 1M scoop bed; 20 PJA sweeps; split launches (direct, graph) vs GG_FLAG_FUSED"},
+        "table": table,
+    }
+
+
 def bench_gym(args):
     """The Gym-style bulldozing environment (Sec. V-A): 128 arenas of 8,192
     grains (1,048,576 in all), each action held for 5 steps of 10 ms, ego
@@ -467,7 +510,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep", "gym"],
+    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep", "gym", "passes"],
                     default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150)
     ap.add_argument("--plain-steps", type=int, default=5)
@@ -486,9 +529,10 @@ def main():
     args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = 200
-    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep", "gym"):
+    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep", "gym", "passes"):
         out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop, "diff": bench_diff,
-               "gears": bench_gears, "hashsweep": bench_hash_sweep, "gym": bench_gym}[args.workload](args)
+               "gears": bench_gears, "hashsweep": bench_hash_sweep, "gym": bench_gym,
+               "passes": bench_passes}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -107,6 +107,17 @@ typedef struct {
                                   of direct launches.  Ignored with GG_FLAG_PROFILE or
                                   GG_FLAG_TAPE. */
 
+#define GG_FLAG_FUSED 16u       /* run each step's detection, projected-Jacobi sweeps and position
+                                  update as one cooperative kernel launch with grid-wide
+                                  barriers between the phases (the fused kernel order of the
+                                  Sec. II-D ablation; the split launches are the default).
+                                  Results equal the split launches' to rounding (the
+                                  compiler may fuse multiply-adds differently; contact
+                                  decisions are unaffected).  Not with
+                                  GG_FLAG_TAPE; GG_FLAG_GRAPH is ignored; with
+                                  GG_FLAG_PROFILE the detection is timed in ms_pja.  Needs a
+                                  device with cooperative launches (else GG_ERR_UNSUPPORTED). */
+
 /* Simulation parameters.  Zero selects the stated default. */
 typedef struct {
   float dt;          /* timestep (> 0) */

@@ -4,6 +4,7 @@
 #include "kernels.hip.h"
 #include "adjoint.hip.h"
 #include "observe.hip.h"
+#include "fused.hip.h"
 
 #include <hip/hip_runtime.h>
 
@@ -244,6 +245,7 @@ struct gg_sim {
   int32_t *rs_hist = nullptr, *rs_bsum = nullptr;      // radix histograms and their scan
   int rs_nb = 0, rs_passes = 0;
   int det_grid = 2048;  // detection workgroups: what the device holds at once (occupancy API)
+  int fused_grid = 0;   // GG_FLAG_FUSED: workgroups of the cooperative step kernel (all resident)
   void* xs = nullptr;                                  // bucket-ordered positions
   int32_t* os = nullptr;                               // bucket-ordered original indices
   int32_t *it_f = nullptr, *it_e = nullptr, *it_first = nullptr, *it_g = nullptr, *it_h = nullptr;
@@ -344,8 +346,10 @@ gg_status check_params(const gg_params* p) {
     return fail(GG_ERR_INVALID, "max_contacts_per_particle must be in [0, 256]");
   if (p->precision != 0 && p->precision != 1) return fail(GG_ERR_INVALID, "precision must be 0 or 1");
   if (!(p->density >= 0.0f) || !std::isfinite(p->density)) return fail(GG_ERR_INVALID, "density must be finite and >= 0");
-  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS | GG_FLAG_TAPE | GG_FLAG_GRAPH))
+  if (p->flags & ~(GG_FLAG_PROFILE | GG_FLAG_DIAGNOSTICS | GG_FLAG_TAPE | GG_FLAG_GRAPH | GG_FLAG_FUSED))
     return fail(GG_ERR_INVALID, "unknown flag bits");
+  if ((p->flags & GG_FLAG_FUSED) && (p->flags & GG_FLAG_TAPE))
+    return fail(GG_ERR_INVALID, "GG_FLAG_FUSED does not record the sweeps for GG_FLAG_TAPE");
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
@@ -554,7 +558,7 @@ void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
 
 // Bucket table and contact detection of one step.
 template <typename R>
-void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod) {
+void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, bool with_detect = true) {
   using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
@@ -573,6 +577,7 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
   ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
                                                  s->os);
+  if (!with_detect) return;
   switch (s->p.tile_threads) {
     case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et); break;
     case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et); break;
@@ -598,6 +603,73 @@ void launch_sweeps(gg_sim* s, const StepIO<R>& io, const ggk::DevBody* bod) {
 }
 
 // The cyclic vertical boundary in the build's precision (span 0: off).
+template <typename R>
+R cyc_lo(const gg_sim* s);
+template <typename R>
+R cyc_span(const gg_sim* s);
+
+// Detection, sweeps and position update of one step as one cooperative launch
+// (GG_FLAG_FUSED); the bucket table is built by the preceding launches.
+template <typename R, int TB>
+hipError_t fused_kernel(gg_sim* s, ggk::FusedArgs<R>& a) {
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)ggk::k_step_fused<R, TB>, dim3(s->fused_grid), dim3(TB), args,
+                                    (unsigned)detect_lds_bytes(s), s->stream);
+}
+
+template <typename R>
+gg_status launch_fused(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod) {
+  ggk::FusedArgs<R> a;
+  a.n = (int)s->n;
+  a.K = s->K;
+  a.x = io.x;
+  a.v = io.v;
+  a.orig = s->orig;
+  a.inv_c = s->inv_c;
+  a.n_blk = s->env_tblk[0];
+  a.env = env_tables(s);
+  a.start = s->bstart;
+  a.sidx = s->sidx;
+  a.xs = (const ggk::V4<R>*)s->xs;
+  a.os = s->os;
+  a.item_start = s->item_start;
+  a.n_items = &s->ctl->items;
+  a.bodies = bod;
+  a.n_bodies = (int)s->bodies.size();
+  a.mass_split = s->p.mass_split;
+  a.max_cells = s->p.tile_max_cells;
+  a.max_stage = s->p.tile_max_stage;
+  a.iters = s->p.n_iters;
+  a.gx = (R)s->p.gravity[0];
+  a.gy = (R)s->p.gravity[1];
+  a.gz = (R)s->p.gravity[2];
+  a.dt = (R)s->p.dt;
+  a.alpha_dt = (R)s->p.alpha / (R)s->p.dt;
+  a.mu = (R)s->p.mu;
+  a.relax = (R)s->p.relax;
+  a.zlo = cyc_lo<R>(s);
+  a.zspan = cyc_span<R>(s);
+  a.ncon = io.ncon;
+  a.partner = io.partner;
+  a.Psi = io.Psi;
+  a.wa = io.w[0];
+  a.wb = io.w[1];
+  a.Px = io.Px[0];
+  a.Py = io.Py[0];
+  a.Pz = io.Pz[0];
+  a.dv = io.dv;
+  a.ctl = s->ctl;
+  a.step = st;
+  hipError_t e;
+  switch (s->p.tile_threads) {
+    case 64: e = fused_kernel<R, 64>(s, a); break;
+    case 256: e = fused_kernel<R, 256>(s, a); break;
+    default: e = fused_kernel<R, 128>(s, a); break;
+  }
+  HIPCHK(s, e);
+  return GG_OK;
+}
+
 template <typename R>
 R cyc_lo(const gg_sim* s) {
   return (R)s->p.cyclic_z[0];
@@ -628,6 +700,15 @@ gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof)
       HIPCHK(s, hipMemcpyAsync(ckx + n, s->v, (size_t)n * sizeof(V), hipMemcpyDeviceToDevice, S));
     }
     const StepIO<R> io = plain_io<R>(s);
+    if (s->p.flags & GG_FLAG_FUSED) {  // (never taped: rejected at creation)
+      launch_detect<R>(s, io, st, bod, false);
+      if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
+      gg_status fs = launch_fused<R>(s, io, st, bod);
+      if (fs != GG_OK) return fs;
+      if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
+      if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
+      continue;
+    }
     launch_detect<R>(s, io, st, bod);
     if (taped) ggk::k_record_counts<<<1, 64, 0, S>>>(s->ctl, s->d_counts + 2 * (size_t)st);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
@@ -956,6 +1037,25 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (oe == hipSuccess) oe = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->dev);
     if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "occupancy query"));
     s->det_grid = std::max(1, per_cu * n_cu);
+    if (s->p.flags & GG_FLAG_FUSED) {
+      int coop = 0;
+      oe = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->dev);
+      if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "cooperative launch query"));
+      if (!coop) return bail(fail(GG_ERR_UNSUPPORTED, "GG_FLAG_FUSED needs cooperative launches"));
+      int fpc = 0;
+      if (s->fp64)
+        oe = tb == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<double, 64>, tb, dlds)
+             : tb == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<double, 256>, tb, dlds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<double, 128>, tb, dlds);
+      else
+        oe = tb == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<float, 64>, tb, dlds)
+             : tb == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<float, 256>, tb, dlds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&fpc, ggk::k_step_fused<float, 128>, tb, dlds);
+      if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "occupancy query"));
+      if (fpc < 1) return bail(fail(GG_ERR_UNSUPPORTED, "the fused step kernel does not fit a compute unit"));
+      // resident at once, and no more workgroups than particles call for
+      s->fused_grid = std::max(1, std::min(fpc * n_cu, (int)((s->n + tb - 1) / tb)));
+    }
   }
   s->stats.tile_threads = s->p.tile_threads;
   s->stats.tile_node_shift = s->p.tile_node_shift;
@@ -1163,7 +1263,7 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
       s->d_counts_cap = (size_t)n_steps * 2;
     }
   }
-  const bool graphed = (s->p.flags & GG_FLAG_GRAPH) && !prof && !taped && n > 0;
+  const bool graphed = (s->p.flags & GG_FLAG_GRAPH) && !(s->p.flags & GG_FLAG_FUSED) && !prof && !taped && n > 0;
   if (graphed) {
     gg_status gs = launch_graphed(s, n_steps, nb);
     if (gs != GG_OK) return gs;

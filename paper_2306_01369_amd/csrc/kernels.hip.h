@@ -834,18 +834,19 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // inverse mass s_i = n_i / m_i.
 // (five waves per SIMD: the tile's LDS allows five workgroups per CU, and the
 // register budget that fits costs only a few bytes of spill)
+// (the work of workgroup `blk` of `nblk`; k_detect and the fused step call it)
 template <typename R, int TB>
-__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_detect(
+__device__ __forceinline__ void detect_items(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
     float inv_c, int n_blk, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
-    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step) {
+    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step, int blk,
+    int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[TB / 64][8];
   __shared__ int red[TB / 64];
-  if (ctl->err) return;
   int* cell_off = (int*)smem;                                  // max_cells + 1
   int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
   V4<R>* st_x = (V4<R>*)(smem + ((((2 * max_cells + 1) * 4) + 31) & ~31));  // max_stage
@@ -853,8 +854,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   int* st_o = st_j + max_stage;                                // max_stage
 
   const int n_items = *n_items_ptr;
-  const int per = (n_items + gridDim.x - 1) / gridDim.x;
-  const int blk = xcd_block();
+  const int per = (n_items + nblk - 1) / nblk;
   const int it0 = min(blk * per, n_items), it1 = min(it0 + per, n_items);
   int cand = 0, npp = 0, npb = 0, mx = 0, fb = 0;
   const int BIG = 0x3fffffff;
@@ -1033,6 +1033,20 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   }
 }
 
+template <typename R, int TB>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_detect(
+    int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
+    float inv_c, int n_blk, EnvTables env, const int32_t* __restrict__ start, const int32_t* __restrict__ sidx,
+    const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
+    const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
+    R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
+    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step) {
+  if (ctl->err) return;
+  detect_items<R, TB>(n, K, x, v, orig, inv_c, n_blk, env, start, sidx, xs, os, item_start, n_items_ptr, bodies,
+                      n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, ctl, step,
+                      xcd_block(), gridDim.x);
+}
+
 // ------------------------------------------------------ projected Jacobi
 // One sweep (Alg. 1).  Every contact reads the iterate of the previous sweep
 // (w_in) and its own accumulated world impulse P (on the member with the lower
@@ -1050,20 +1064,17 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
 // indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
+// (one particle's part of a sweep; k_pja and the fused step call it)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __restrict__ x,
-                                                V4<R>* __restrict__ v, const V4<R>* __restrict__ w_in,
-                                                V4<R>* __restrict__ w_out, const int32_t* __restrict__ ncon,
-                                                const int32_t* __restrict__ partner,
-                                                const R* __restrict__ Psi, const R* Pix,
-                                                const R* Piy, const R* Piz, R* Px, R* Py,
-                                                R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
-                                                R gz, R dt, R alpha_dt, R mu, R relax,
-                                                int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
-                                                const Ctl* ctl) {
-  if (ctl->err) return;
-  const int i = xcd_block() * kBlock + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restrict__ x,
+                                             V4<R>* __restrict__ v, const V4<R>* __restrict__ w_in,
+                                             V4<R>* __restrict__ w_out, const int32_t* __restrict__ ncon,
+                                             const int32_t* __restrict__ partner,
+                                             const R* __restrict__ Psi, const R* Pix,
+                                             const R* Piy, const R* Piz, R* Px, R* Py,
+                                             R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
+                                             R gz, R dt, R alpha_dt, R mu, R relax,
+                                             int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs) {
   const bool first = mode & 1, last = mode & 2;
   const int pbase = pofs ? pofs[i] : 0;
   const V4<R> xi = x[i];
@@ -1142,8 +1153,36 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __restrict__ x,
+                                                V4<R>* __restrict__ v, const V4<R>* __restrict__ w_in,
+                                                V4<R>* __restrict__ w_out, const int32_t* __restrict__ ncon,
+                                                const int32_t* __restrict__ partner,
+                                                const R* __restrict__ Psi, const R* Pix,
+                                                const R* Piy, const R* Piz, R* Px, R* Py,
+                                                R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
+                                                R gz, R dt, R alpha_dt, R mu, R relax,
+                                                int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
+                                                const Ctl* ctl) {
+  if (ctl->err) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  pja_particle<R>(i, K, x, v, w_in, w_out, ncon, partner, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies, gx, gy, gz, dt,
+                  alpha_dt, mu, relax, mode, dv, pofs);
+}
+
 // Positions from the new velocities (Eq. (5)), x' = x + dt v'; with a cyclic
 // vertical boundary (zspan > 0) a particle below zlo moves up by zspan.
+template <typename R>
+__device__ __forceinline__ void integrate_particle(int i, V4<R>* __restrict__ x, const V4<R>* __restrict__ v, R dt,
+                                                   R zlo, R zspan) {
+  V4<R> p = x[i];
+  const V4<R> q = v[i];
+  p.x += dt * q.x; p.y += dt * q.y; p.z += dt * q.z;
+  if (zspan > R(0) && p.z < zlo) p.z += zspan;
+  x[i] = p;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__ x,
                                                       const V4<R>* __restrict__ v, R dt, R zlo, R zspan,
@@ -1152,11 +1191,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->steps_done, 1);
   if (i >= n) return;
-  V4<R> p = x[i];
-  const V4<R> q = v[i];
-  p.x += dt * q.x; p.y += dt * q.y; p.z += dt * q.z;
-  if (zspan > R(0) && p.z < zlo) p.z += zspan;
-  x[i] = p;
+  integrate_particle<R>(i, x, v, dt, zlo, zspan);
 }
 
 // ---------------------------------------------------------------- readout

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgg.so")
 GG_OK, GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP, GG_ERR_CAPACITY, GG_ERR_NONFINITE, GG_ERR_NO_TAPE, \
     GG_ERR_UNSUPPORTED = range(8)
 GG_MEM_HOST, GG_MEM_DEVICE = 0, 1
-GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS, GG_FLAG_TAPE, GG_FLAG_GRAPH = 1, 2, 4, 8
+GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS, GG_FLAG_TAPE, GG_FLAG_GRAPH, GG_FLAG_FUSED = 1, 2, 4, 8, 16
 FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "stats": 5, "dv": 6,
          "radius": 7}
 SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
@@ -205,7 +205,7 @@ class Sim:
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
                  profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
                  tile_max_stage=0, tile_node_shift=0, tile_threads=0, differentiable=False, checkpoint_every=0,
-                 graph=False, precision=0, cyclic_z=None):
+                 graph=False, precision=0, cyclic_z=None, fused=False):
         L = lib()
         P = Params()
         P.dt, P.alpha, P.mu = dt, alpha, mu
@@ -219,7 +219,8 @@ class Sim:
         P.max_contacts_per_particle = int(max_contacts)
         P.density = density
         P.flags = (GG_FLAG_PROFILE if profile else 0) | (GG_FLAG_DIAGNOSTICS if diagnostics else 0) | \
-            (GG_FLAG_TAPE if differentiable else 0) | (GG_FLAG_GRAPH if graph else 0)
+            (GG_FLAG_TAPE if differentiable else 0) | (GG_FLAG_GRAPH if graph else 0) | \
+            (GG_FLAG_FUSED if fused else 0)
         P.checkpoint_every = int(checkpoint_every)
         P.precision = int(precision)
         P.reorder_every = int(reorder_every)

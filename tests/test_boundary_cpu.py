@@ -95,6 +95,7 @@ def _create(**kw):
     ({"env_offsets": [0, 3, 2, 8]}, gg.GG_ERR_INVALID),
     ({"env_offsets": [0, 3, 9]}, gg.GG_ERR_INVALID),
     ({"env_offsets": [1, 8]}, gg.GG_ERR_INVALID),
+    ({"fused": True, "differentiable": True}, gg.GG_ERR_INVALID),   # the fused step keeps no tape
 ])
 def test_create_rejects_bad_arguments_on_host(kw, status):
     with pytest.raises(gg.GGError) as e:
