@@ -367,7 +367,7 @@ def bench_passes(args):
 
 
 def bench_gym(args):
-    """The Gym-style bulldozing environment (Sec. V-A): 128 arenas of 8,192
+    """The Gym-style bulldozing environment (Sec. III-A): 128 arenas of 8,192
     grains (1,048,576 in all), each action held for 5 steps of 10 ms, ego
     (64x48, perspective) and sky (64x64, orthographic) depth images and the
     goal-box reward after every environment step, uniform random actions."""

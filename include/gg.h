@@ -153,7 +153,7 @@ typedef struct {
                              The tile parameters change speed only, never results. */
   float cyclic_z[2]; /* (z_lo, z_hi): when z_hi > z_lo, a particle whose updated position
                         falls below z_lo is moved up by z_hi - z_lo, velocity unchanged (the
-                        cyclic vertical boundary of the paper's gear-tower benchmark, Sec. IV);
+                        cyclic vertical boundary of the paper's gear-tower benchmark, Sec. III-B);
                         contact search does not wrap.  (0, 0): off */
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL */
@@ -274,7 +274,7 @@ typedef struct {
 gg_status gg_read(gg_sim* sim, int32_t field, void* dst, int64_t capacity_bytes, int64_t* written,
                   gg_mem where);
 
-/* ---- Observations of the Gym-style environment (Sec. V-A, "Bulldozing"):
+/* ---- Observations of the Gym-style environment (Sec. III-A, "Bulldozing"):
  * depth images computed on the simulating device and the goal-box reward. */
 typedef enum { GG_CAM_ORTHO = 0, GG_CAM_PERSPECTIVE = 1 } gg_camera_kind;
 
@@ -316,7 +316,7 @@ typedef struct {
 gg_status gg_render_depth(gg_sim* sim, int32_t n_cams, const gg_camera* cams, float* dst,
                           int64_t capacity_bytes, gg_mem where);
 
-/* Goal-box reward per environment (Sec. V-A): 100 / n_e for every particle of
+/* Goal-box reward per environment (Sec. III-A): 100 / n_e for every particle of
  * environment e inside the closed box [lo, hi] (binary32 comparisons of the
  * binary32 positions), and -d / n_e for every other, d = its distance to the
  * nearest point of the box (double).  boxes: host, n_envs x 6 (lo xyz, hi xyz,

@@ -171,7 +171,7 @@ def bodies_to_f32_pose(arr, nb):
     return arr
 
 
-# ------------------------------------------------- observations (Sec. V-A)
+# ------------------------------------------------- observations (Sec. III-A)
 
 def make_cameras(cams):
     """ctypes cameras from dicts {"env", "kind" ("ortho" | "perspective"),
@@ -198,7 +198,7 @@ def _env_off(n, env_offsets):
 
 
 def render_depth(x, radius, cams, bodies=(), env_offsets=None, pixels=None):
-    """Depth images (Sec. V-A observations) of the binary32 positions x
+    """Depth images (Sec. III-A observations) of the binary32 positions x
     (n x 3) with radii `radius`: a list of (height, width) float32 arrays, or,
     when `pixels` (indices into the concatenated images) is given, the depths
     of those pixels only.  Plane bodies of each camera's environment are
@@ -223,7 +223,7 @@ def render_depth(x, radius, cams, bodies=(), env_offsets=None, pixels=None):
 
 
 def goal_reward(x, boxes, env_offsets=None):
-    """Goal-box reward per environment (Sec. V-A) and the particles inside:
+    """Goal-box reward per environment (Sec. III-A) and the particles inside:
     boxes = n_envs x (lo xyz, hi xyz)."""
     x = _f32(x, (-1, 3))
     off = _env_off(len(x), env_offsets)

@@ -1022,7 +1022,7 @@ int32_t ggo_sizeof_body_tan() { return (int32_t)sizeof(BodyTan); }
 }  // extern "C"
 
 // ======================================================= observations
-// The Gym-style environment of Sec. V-A ("Bulldozing") observes the scene
+// The Gym-style environment of Sec. III-A ("Bulldozing") observes the scene
 // through two depth cameras computed on the simulating device -- a
 // perspective camera riding on the tool and an orthographic camera looking
 // down on the whole bed -- and rewards material inside a goal box.  The paper
@@ -1179,7 +1179,7 @@ void ggo_render_depth(int64_t n, const float* x, const float* r, int32_t n_envs,
   (void)n;
 }
 
-// Goal-box reward (Sec. V-A): per environment, 100/n_e for every particle in
+// Goal-box reward (Sec. III-A): per environment, 100/n_e for every particle in
 // the closed box [lo, hi] (binary32 comparisons of the binary32 positions)
 // and -d/n_e for every other, d = FP64 distance to the nearest point of the
 // box.  boxes: n_envs x 6 (lo xyz, hi xyz).  reward: n_envs; inside: n_envs

@@ -1,5 +1,5 @@
 """Gym-style bulldozing environment around the simulator (arXiv 2306.01369,
-Sec. V-A, "Bulldozing").
+Sec. III-A, "Bulldozing").
 
 A batch of independent environments in one simulation (the batched form: one
 particle segment and one set of bodies per environment).  Each environment is

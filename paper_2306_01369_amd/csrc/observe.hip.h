@@ -1,4 +1,4 @@
-// Observations of the Gym-style environment (arXiv 2306.01369, Sec. V-A,
+// Observations of the Gym-style environment (arXiv 2306.01369, Sec. III-A,
 // "Bulldozing"): depth images from cameras, computed on the device that holds
 // the particles, and the goal-box reward.
 //

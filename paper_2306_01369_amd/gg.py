@@ -348,7 +348,7 @@ class Sim:
         return self.read("stats")
 
     def render_depth(self, cams, out=None):
-        """Depth images of the current state (Sec. V-A observations): a list of
+        """Depth images of the current state (Sec. III-A observations): a list of
         (height, width) float32 arrays, or, with ``out`` (a device tensor of at
         least the total pixel count), the concatenated images written there."""
         A = make_cameras(cams)

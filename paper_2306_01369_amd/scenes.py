@@ -145,7 +145,7 @@ def grid_tool(grid, center, nu=(0, 0, 0), omega=(0, 0, 0), R=None, env=0):
 
 
 # ----------------------------------------------------------------------------
-# cameras (observations of the Gym-style environment, Sec. V-A)
+# cameras (observations of the Gym-style environment, Sec. III-A)
 # ----------------------------------------------------------------------------
 
 def camera_pose(eye, target, up=(0.0, 0.0, 1.0)):
@@ -504,7 +504,7 @@ def tower_grid(radius, z0, z1, inv_spacing=256.0):
 
 
 def gear_tower(n=16384, n_gears=10, seed=0, r=0.002, radius=0.1, height=0.5, omega_max=6.0):
-    """The paper's many-body benchmark (helical gears spinning in a tall
+    """The many-body benchmark of Sec. III-B (helical gears spinning in a tall
     cylindrical tower, particles recycled from the bottom to the top): n
     spheres on a loose lattice inside the tower (random index order), n_gears
     copies of one gear grid at random positions and axis orientations, each

@@ -1,4 +1,4 @@
-"""Host-side logic of the Gym-style bulldozing environment (Sec. V-A): arena
+"""Host-side logic of the Gym-style bulldozing environment (Sec. III-A): arena
 layout, track steering and camera placement, without a device."""
 import math
 

@@ -1,4 +1,4 @@
-"""The Gym-style bulldozing environment (Sec. V-A) on the device: its
+"""The Gym-style bulldozing environment (Sec. III-A) on the device: its
 observations and rewards against the FP64 oracle on the state read back, and
 the blade pushing grains into the goal box."""
 import sys

@@ -1,4 +1,4 @@
-"""GPU parity of the observations of the Gym-style environment (Sec. V-A):
+"""GPU parity of the observations of the Gym-style environment (Sec. III-A):
 depth cameras and the goal-box reward through the C ABI, against the FP64
 oracle on the state read back from the device.
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's observation functions (Sec. V-A, "Bulldozing"): depth
+"""Pins of the oracle's observation functions (Sec. III-A, "Bulldozing"): depth
 cameras and the goal-box reward.  Each check rests on geometry worked out
 independently of the oracle's camera-frame arithmetic: closed forms for a
 sphere seen along the optical axis or from above, constant depth of a plane
