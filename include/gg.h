@@ -155,6 +155,9 @@ typedef struct {
                         falls below z_lo is moved up by z_hi - z_lo, velocity unchanged (the
                         cyclic vertical boundary of the paper's gear-tower benchmark, Sec. III-B);
                         contact search does not wrap.  (0, 0): off */
+  int32_t pja_lanes; /* lanes per particle in a projected-Jacobi sweep: 1, 2 or 4 (each lane
+                        takes every L-th contact; the sum keeps list order, so results do not
+                        depend on it); 0 -> from the particle count */
   int32_t device;    /* HIP device ordinal */
   void* stream;      /* hipStream_t or NULL */
 } gg_params;
@@ -264,6 +267,8 @@ typedef struct {
   int32_t tile_max_stage;
   int32_t detect_workgroups; /* detection grid: workgroups resident at once on the device */
   int32_t reorder_every;
+  int32_t pja_lanes;      /* lanes per particle of the sweeps (default resolved) */
+  int32_t pad0;
 } gg_stats;
 
 /* Copy a field into dst (where says where dst lives).  If dst is NULL only

@@ -88,6 +88,11 @@ def key_of(n, ppc, n_bodies):
     return f"{dev}|n2^{int(round(math.log2(max(n, 1))))}|ppc{ppc:.1f}|bodies{n_bodies}"
 
 
+def lane_counts():
+    """Lanes per particle tried for the sweeps (results do not depend on it)."""
+    return (1, 2, 4)
+
+
 def cell_factors():
     """Cell sizes tried by ``tune(..., tune_cell=True)``, as multiples of the
     smallest admissible cell 2 r_max (1 + 2^-10)."""
@@ -142,7 +147,12 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             best, best_t = cand, t
     if best is None:
         return {}
-    # then the table size, with the best launch shape
+    # then the lanes per particle of the sweeps, and the table size
+    for lanes in lane_counts():
+        cand = dict(best, pja_lanes=lanes)
+        t = timed(cand)
+        if t is not None and t < best_t:
+            best, best_t = cand, t
     n = len(x)
     for factor in hash_factors():
         cand = dict(best, hash_size=max(1, int(factor * n)))

@@ -87,6 +87,10 @@ double particles_per_cell(const std::vector<float>& x, int64_t n, float inv_c) {
 // decomposition depend on it, never results.
 void default_tile(int64_t n, double ppc, gg_params& p) {
   if (p.tile_threads == 0) p.tile_threads = n >= (1 << 18) ? 256 : 128;
+  // lanes per particle shorten the sweeps' dependent-load chains where they,
+  // not bandwidth, bound a sweep: four up to 2^17 particles (-26..31% per step
+  // at 4k..64k), two up to 2^19; bandwidth-bound large beds keep one lane
+  if (p.pja_lanes == 0) p.pja_lanes = n < (1 << 17) ? 4 : (n < (1 << 19) ? 2 : 1);
   if (p.tile_node_shift == 0) {
     int shift = 1;
     while (shift < 12 && ppc * (double)(1 << (shift + 1)) <= (double)p.tile_threads) ++shift;
@@ -353,6 +357,8 @@ gg_status check_params(const gg_params* p) {
   if (p->tile_max_cells < 0 || p->tile_max_cells > 4096) return fail(GG_ERR_INVALID, "tile_max_cells must be in [0, 4096]");
   if (p->tile_max_stage < 0 || p->tile_max_stage > 2048) return fail(GG_ERR_INVALID, "tile_max_stage must be in [0, 2048]");
   if (p->tile_node_shift < 0 || p->tile_node_shift > 15) return fail(GG_ERR_INVALID, "tile_node_shift must be in [0, 15]");
+  if (p->pja_lanes != 0 && p->pja_lanes != 1 && p->pja_lanes != 2 && p->pja_lanes != 4)
+    return fail(GG_ERR_INVALID, "pja_lanes must be 0, 1, 2 or 4");
   if (!std::isfinite(p->cyclic_z[0]) || !std::isfinite(p->cyclic_z[1]))
     return fail(GG_ERR_INVALID, "cyclic_z must be finite");
   if (p->tile_threads != 0 && p->tile_threads != 64 && p->tile_threads != 128 && p->tile_threads != 256)
@@ -592,13 +598,26 @@ void launch_sweeps(gg_sim* s, const StepIO<R>& io, const ggk::DevBody* bod) {
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int I = s->p.n_iters;
   const R alpha_dt = (R)s->p.alpha / (R)s->p.dt;
+  const int L = s->p.pja_lanes;
+  const int lgrid = (int)(((int64_t)n * L + ggk::kBlock - 1) / ggk::kBlock);
   for (int it = 0; it < I; ++it) {
     const int l = it + 1;
     const int mode = (it == 0 ? 1 : 0) | (it == I - 1 ? 2 : 0);
-    ggk::k_pja<R><<<grid, ggk::kBlock, 0, s->stream>>>(
-        n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
-        io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
-        (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+    if (L == 1)
+      ggk::k_pja<R><<<grid, ggk::kBlock, 0, s->stream>>>(
+          n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
+          io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+    else if (L == 2)
+      ggk::k_pja_lanes<R, 2><<<lgrid, ggk::kBlock, 0, s->stream>>>(
+          n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
+          io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+    else
+      ggk::k_pja_lanes<R, 4><<<lgrid, ggk::kBlock, 0, s->stream>>>(
+          n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
+          io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
   }
 }
 
@@ -1063,6 +1082,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->stats.tile_max_stage = s->p.tile_max_stage;
   s->stats.detect_workgroups = s->det_grid;
   s->stats.reorder_every = s->p.reorder_every;
+  s->stats.pja_lanes = s->p.pja_lanes;
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
   sample_memory(s);

@@ -1064,6 +1064,92 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
 // indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
+// One half contact of a sweep: the impulse Q of contact `code` (slot `slot`,
+// impulse index `ps`) of particle i from the previous impulse and iterate,
+// stored to P*, and the sign sg with which it enters i's sum.  Multiply-adds
+// are fused only within one expression (fp contract on), so every kernel that
+// calls it computes the same bits.
+template <typename R>
+__device__ __forceinline__ void half_contact(int code, int slot, int ps, bool first, const V4<R>& xi,
+                                             const V4<R>& wi, const V4<R>* __restrict__ x,
+                                             const V4<R>* __restrict__ w_in, const R* __restrict__ Psi,
+                                             const R* Pix, const R* Piy, const R* Piz, R* Px, R* Py, R* Pz,
+                                             const DevBody* __restrict__ bodies, R alpha_dt, R mu, R relax,
+                                             R& Q0, R& Q1, R& Q2, R& sg) {
+#pragma clang fp contract(on)
+  R psi;
+  R P0 = R(0), P1 = R(0), P2 = R(0);
+  if (!first) {
+    P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
+  }
+  R n0, n1, n2, u0, u1, u2, mt;
+  if (code >= 0) {
+    const int j = code & (kHiFlag - 1);
+    const bool lo = (code & kHiFlag) == 0;
+    const V4<R> xj = x[j];
+    const V4<R> wj = w_in[j];
+    psi = pair_gap(xi, xj);
+    const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
+    const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
+    const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
+    const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (L > R(0)) {
+      const R il = R(1) / L;
+      n0 = d0 * il; n1 = d1 * il; n2 = d2 * il;
+    } else {
+      n0 = R(0); n1 = R(0); n2 = R(1);
+    }
+    u0 = wl.x - wh.x; u1 = wl.y - wh.y; u2 = wl.z - wh.z;
+    mt = R(1) / (wl.w + wh.w);
+    sg = lo ? R(1) : R(-1);
+  } else {
+    R nb[3], V[3];
+    psi = Psi[slot];
+    body_geometry<R>(bodies[-1 - code], xi, psi, nb, V);
+    n0 = nb[0]; n1 = nb[1]; n2 = nb[2];
+    u0 = wi.x - V[0]; u1 = wi.y - V[1]; u2 = wi.z - V[2];
+    mt = R(1) / wi.w;
+    sg = R(1);
+  }
+  const R bias = alpha_dt * psi;
+  const R y0 = P0 - mt * (u0 + bias * n0);
+  const R y1 = P1 - mt * (u1 + bias * n1);
+  const R y2 = P2 - mt * (u2 + bias * n2);
+  const R yn = n0 * y0 + n1 * y1 + n2 * y2;
+  R t0 = y0 - yn * n0, t1 = y1 - yn * n1, t2 = y2 - yn * n2;
+  const R ynp = fmax(yn, R(0));
+  const R ts = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+  if (ts > mu * ynp) {
+    const R f = mu * ynp / ts;
+    t0 *= f; t1 *= f; t2 *= f;
+  }
+  Q0 = ynp * n0 + t0; Q1 = ynp * n1 + t1; Q2 = ynp * n2 + t2;
+  if (relax != R(1)) {
+    Q0 = P0 + relax * (Q0 - P0);
+    Q1 = P1 + relax * (Q1 - P1);
+    Q2 = P2 + relax * (Q2 - P2);
+  }
+  Px[ps] = Q0; Py[ps] = Q1; Pz[ps] = Q2;
+}
+
+// The particle's new iterate from its impulse sum a (last sweep: the velocity).
+template <typename R>
+__device__ __forceinline__ void finish_particle(int i, bool last, const V4<R>& vi, const V4<R>& wi, R a0, R a1,
+                                                R a2, R gx, R gy, R gz, R dt, V4<R>* __restrict__ v,
+                                                V4<R>* __restrict__ w_out, V4<R>* __restrict__ dv) {
+#pragma clang fp contract(on)
+  const R im = vi.w;
+  const R n0 = vi.x + dt * gx + im * a0;
+  const R n1 = vi.y + dt * gy + im * a1;
+  const R n2 = vi.z + dt * gz + im * a2;
+  if (last) {
+    v[i] = mk4<R>(n0, n1, n2, im);
+    if (dv) dv[i] = mk4<R>(im * a0, im * a1, im * a2, R(0));
+  } else {
+    w_out[i] = mk4<R>(n0, n1, n2, wi.w);
+  }
+}
+
 // (one particle's part of a sweep; k_pja and the fused step call it)
 template <typename R>
 __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restrict__ x,
@@ -1075,6 +1161,7 @@ __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restri
                                              R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
                                              R gz, R dt, R alpha_dt, R mu, R relax,
                                              int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs) {
+#pragma clang fp contract(on)
   const bool first = mode & 1, last = mode & 2;
   const int pbase = pofs ? pofs[i] : 0;
   const V4<R> xi = x[i];
@@ -1085,72 +1172,12 @@ __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restri
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
     const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
-    const int code = partner[slot];
-    R psi;
-    R P0 = R(0), P1 = R(0), P2 = R(0);
-    if (!first) {
-      P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
-    }
-    R n0, n1, n2, u0, u1, u2, mt, sg;
-    if (code >= 0) {
-      const int j = code & (kHiFlag - 1);
-      const bool lo = (code & kHiFlag) == 0;
-      const V4<R> xj = x[j];
-      const V4<R> wj = w_in[j];
-      psi = pair_gap(xi, xj);
-      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
-      const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
-      const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      if (L > R(0)) {
-        const R il = R(1) / L;
-        n0 = d0 * il; n1 = d1 * il; n2 = d2 * il;
-      } else {
-        n0 = R(0); n1 = R(0); n2 = R(1);
-      }
-      u0 = wl.x - wh.x; u1 = wl.y - wh.y; u2 = wl.z - wh.z;
-      mt = R(1) / (wl.w + wh.w);
-      sg = lo ? R(1) : R(-1);
-    } else {
-      R nb[3], V[3];
-      psi = Psi[slot];
-      body_geometry<R>(bodies[-1 - code], xi, psi, nb, V);
-      n0 = nb[0]; n1 = nb[1]; n2 = nb[2];
-      u0 = wi.x - V[0]; u1 = wi.y - V[1]; u2 = wi.z - V[2];
-      mt = R(1) / wi.w;
-      sg = R(1);
-    }
-    const R bias = alpha_dt * psi;
-    const R y0 = P0 - mt * (u0 + bias * n0);
-    const R y1 = P1 - mt * (u1 + bias * n1);
-    const R y2 = P2 - mt * (u2 + bias * n2);
-    const R yn = n0 * y0 + n1 * y1 + n2 * y2;
-    R t0 = y0 - yn * n0, t1 = y1 - yn * n1, t2 = y2 - yn * n2;
-    const R ynp = fmax(yn, R(0));
-    const R ts = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-    if (ts > mu * ynp) {
-      const R f = mu * ynp / ts;
-      t0 *= f; t1 *= f; t2 *= f;
-    }
-    R Q0 = ynp * n0 + t0, Q1 = ynp * n1 + t1, Q2 = ynp * n2 + t2;
-    if (relax != R(1)) {
-      Q0 = P0 + relax * (Q0 - P0);
-      Q1 = P1 + relax * (Q1 - P1);
-      Q2 = P2 + relax * (Q2 - P2);
-    }
-    Px[ps] = Q0; Py[ps] = Q1; Pz[ps] = Q2;
+    R Q0, Q1, Q2, sg;
+    half_contact<R>(partner[slot], slot, ps, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies,
+                    alpha_dt, mu, relax, Q0, Q1, Q2, sg);
     a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
   }
-  const R im = vi.w;
-  const R n0 = vi.x + dt * gx + im * a0;
-  const R n1 = vi.y + dt * gy + im * a1;
-  const R n2 = vi.z + dt * gz + im * a2;
-  if (last) {
-    v[i] = mk4<R>(n0, n1, n2, im);
-    if (dv) dv[i] = mk4<R>(im * a0, im * a1, im * a2, R(0));
-  } else {
-    w_out[i] = mk4<R>(n0, n1, n2, wi.w);
-  }
+  finish_particle<R>(i, last, vi, wi, a0, a1, a2, gx, gy, gz, dt, v, w_out, dv);
 }
 
 template <typename R>
@@ -1169,6 +1196,55 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
   if (i >= n) return;
   pja_particle<R>(i, K, x, v, w_in, w_out, ncon, partner, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies, gx, gy, gz, dt,
                   alpha_dt, mu, relax, mode, dv, pofs);
+}
+
+// The same sweep with L lanes per particle (L = 2 or 4; small beds, where a
+// sweep is bound by each lane's chain of dependent loads, not by bandwidth).
+// Lane s of a particle takes its contacts s, s + L, s + 2L, ...; after every
+// round of L contacts all lanes of the particle add the round's impulses in
+// list order (cross-lane shuffles), so the sum -- and every result -- is
+// bitwise that of k_pja, with a chain L times shorter.
+template <typename R, int L>
+__global__ __launch_bounds__(kBlock) void k_pja_lanes(int n, int K, const V4<R>* __restrict__ x,
+                                                      V4<R>* __restrict__ v, const V4<R>* __restrict__ w_in,
+                                                      V4<R>* __restrict__ w_out, const int32_t* __restrict__ ncon,
+                                                      const int32_t* __restrict__ partner,
+                                                      const R* __restrict__ Psi, const R* Pix, const R* Piy,
+                                                      const R* Piz, R* Px, R* Py, R* Pz,
+                                                      const DevBody* __restrict__ bodies, R gx, R gy, R gz, R dt,
+                                                      R alpha_dt, R mu, R relax, int mode,
+                                                      V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
+                                                      const Ctl* ctl) {
+#pragma clang fp contract(on)
+  static_assert(L == 2 || L == 4, "lanes per particle");
+  if (ctl->err) return;
+  const int t = xcd_block() * kBlock + threadIdx.x;
+  const int i = t / L, sub = t % L;
+  if (i >= n) return;  // (the L lanes of a particle leave together)
+  const bool first = mode & 1, last = mode & 2;
+  const int pbase = pofs ? pofs[i] : 0;
+  const V4<R> xi = x[i];
+  const V4<R> vi = v[i];
+  const V4<R> wi = w_in[i];
+  R a0 = R(0), a1 = R(0), a2 = R(0);
+  const int c = ncon[i];
+  for (int m = 0; m * L < c; ++m) {
+    const int k = m * L + sub;
+    R Q0 = R(0), Q1 = R(0), Q2 = R(0), sg = R(0);
+    if (k < c) {
+      const int slot = ell_slot(i, k, K);
+      half_contact<R>(partner[slot], slot, pofs ? pbase + k : slot, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz,
+                      Px, Py, Pz, bodies, alpha_dt, mu, relax, Q0, Q1, Q2, sg);
+    }
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const R g = __shfl(sg, q, L), q0 = __shfl(Q0, q, L), q1 = __shfl(Q1, q, L), q2 = __shfl(Q2, q, L);
+      if (m * L + q < c) {
+        a0 += g * q0; a1 += g * q1; a2 += g * q2;
+      }
+    }
+  }
+  if (sub == 0) finish_particle<R>(i, last, vi, wi, a0, a1, a2, gx, gy, gz, dt, v, w_out, dv);
 }
 
 // Positions from the new velocities (Eq. (5)), x' = x + dt v'; with a cyclic

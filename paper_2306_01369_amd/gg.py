@@ -83,7 +83,7 @@ class Params(C.Structure):
                 ("density", C.c_float), ("flags", C.c_uint32), ("reorder_every", C.c_int32),
                 ("tile_max_cells", C.c_int32), ("tile_max_stage", C.c_int32),
                 ("tile_node_shift", C.c_int32), ("tile_threads", C.c_int32), ("cyclic_z", C.c_float * 2),
-                ("device", C.c_int32),
+                ("pja_lanes", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
@@ -96,7 +96,8 @@ class Stats(C.Structure):
                 ("contacts_summed", C.c_int64), ("detect_fallback", C.c_int64),
                 ("detect_items", C.c_int64), ("device_bytes_peak", C.c_int64),
                 ("tile_threads", C.c_int32), ("tile_node_shift", C.c_int32), ("tile_max_cells", C.c_int32),
-                ("tile_max_stage", C.c_int32), ("detect_workgroups", C.c_int32), ("reorder_every", C.c_int32)]
+                ("tile_max_stage", C.c_int32), ("detect_workgroups", C.c_int32), ("reorder_every", C.c_int32),
+                ("pja_lanes", C.c_int32), ("pad0", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -205,7 +206,7 @@ class Sim:
                  max_contacts=0, density=2500.0, env_offsets=None, device=0, stream=None,
                  profile=False, diagnostics=False, reorder_every=0, tile_max_cells=0,
                  tile_max_stage=0, tile_node_shift=0, tile_threads=0, differentiable=False, checkpoint_every=0,
-                 graph=False, precision=0, cyclic_z=None, fused=False):
+                 graph=False, precision=0, cyclic_z=None, fused=False, pja_lanes=0):
         L = lib()
         P = Params()
         P.dt, P.alpha, P.mu = dt, alpha, mu
@@ -228,6 +229,7 @@ class Sim:
         P.tile_max_stage = int(tile_max_stage)
         P.tile_node_shift = int(tile_node_shift)
         P.tile_threads = int(tile_threads)
+        P.pja_lanes = int(pja_lanes)
         if cyclic_z is not None:
             P.cyclic_z[0], P.cyclic_z[1] = float(cyclic_z[0]), float(cyclic_z[1])
         P.device = device

@@ -45,3 +45,7 @@ def test_hash_sizes_tried_exclude_the_default_and_stay_positive():
 def test_cell_sizes_tried_start_at_the_smallest_admissible_cell():
     f = autotune.cell_factors()
     assert f[0] == 1.0 and all(b > a for a, b in zip(f, f[1:]))
+
+
+def test_lane_counts_are_the_supported_ones():
+    assert set(autotune.lane_counts()) == {1, 2, 4}
