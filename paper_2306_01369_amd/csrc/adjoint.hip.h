@@ -75,6 +75,86 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
   }
 }
 
+// One half contact of a reverse sweep: recomputes y of sweep l for contact
+// `code` of particle i from the recorded impulse P^(l-1) and iterate w^(l-1),
+// updates the contact's adjoint state (index q) and returns ub (the adjoint of
+// its velocity residual) with the sign sg it takes in i's sum.  Multiply-adds
+// are fused only within an expression (fp contract on), so every kernel that
+// calls it computes the same bits.
+template <typename R>
+__device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool first_sweep, const V4<R>& xi,
+                                                 const V4<R>& vi, const V4<R>& wi, const V4<R>& bi,
+                                                 const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
+                                                 const V4<R>* __restrict__ w_prev,
+                                                 const V4<R>* __restrict__ wbar_in, const R* __restrict__ Psi,
+                                                 const R* __restrict__ Ppx, const R* __restrict__ Ppy,
+                                                 const R* __restrict__ Ppz, AdjSlots<R>& A,
+                                                 const DevBody* __restrict__ bodies, R alpha_dt, R mu, R relax,
+                                                 R ub[3], R& sg) {
+#pragma clang fp contract(on)
+  const R psi = Psi[slot];
+  R P[3] = {R(0), R(0), R(0)};
+  if (!first_sweep) {
+    P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
+  }
+  R nrm[3], u[3], mt, Pb[3];
+  const R carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
+  bool lo = true, body = code < 0;
+  if (!body) {
+    const int j = code & (kHiFlag - 1);
+    lo = (code & kHiFlag) == 0;
+    const V4<R> xj = x[j];
+    const V4<R> wj = w_prev[j];
+    const V4<R> bj = wbar_in[j];
+    const R imj = v[j].w;
+    const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
+    const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
+    const V4<R> bl = lo ? bi : bj, bh = lo ? bj : bi;
+    const R iml = lo ? vi.w : imj, imh = lo ? imj : vi.w;
+    const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
+    const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (L > R(0)) {
+      const R il = R(1) / L;
+      nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
+    } else {
+      nrm[0] = R(0); nrm[1] = R(0); nrm[2] = R(1);
+    }
+    u[0] = wl.x - wh.x; u[1] = wl.y - wh.y; u[2] = wl.z - wh.z;
+    mt = R(1) / (wl.w + wh.w);
+    Pb[0] = carry[0] + iml * bl.x - imh * bh.x;
+    Pb[1] = carry[1] + iml * bl.y - imh * bh.y;
+    Pb[2] = carry[2] + iml * bl.z - imh * bh.z;
+  } else {
+    R V[3];
+    body_geometry<R>(bodies[-1 - code], xi, psi, nrm, V);
+    u[0] = wi.x - V[0]; u[1] = wi.y - V[1]; u[2] = wi.z - V[2];
+    mt = R(1) / wi.w;
+    Pb[0] = carry[0] + vi.w * bi.x;
+    Pb[1] = carry[1] + vi.w * bi.y;
+    Pb[2] = carry[2] + vi.w * bi.z;
+  }
+  const R bias = alpha_dt * psi;
+  R y[3];
+  for (int a = 0; a < 3; ++a) y[a] = P[a] - mt * (u[a] + bias * nrm[a]);
+  const R Qb[3] = {relax * Pb[0], relax * Pb[1], relax * Pb[2]};
+  R yb[3], nb[3] = {R(0), R(0), R(0)};
+  proj_adjoint(y, nrm, mu, Qb, yb, nb);
+  const R keep = R(1) - relax;
+  A.cx[q] = yb[0] + keep * Pb[0];
+  A.cy[q] = yb[1] + keep * Pb[1];
+  A.cz[q] = yb[2] + keep * Pb[2];
+  ub[0] = -mt * yb[0]; ub[1] = -mt * yb[1]; ub[2] = -mt * yb[2];
+  const R bb = -mt * dot3f(yb, nrm);
+  A.nx[q] += nb[0] - mt * bias * yb[0];
+  A.ny[q] += nb[1] - mt * bias * yb[1];
+  A.nz[q] += nb[2] - mt * bias * yb[2];
+  A.ps[q] += alpha_dt * bb;
+  if (body) {
+    A.vx[q] -= ub[0]; A.vy[q] -= ub[1]; A.vz[q] -= ub[2];
+  }
+  sg = lo ? R(1) : R(-1);
+}
+
 // One reverse sweep: from wbar_in (adjoint of iterate l) to wbar_out (adjoint of
 // iterate l-1).  Recomputes y of sweep l from the recorded impulses P^(l-1) and
 // iterate w^(l-1).  Also accumulates wbar_in into the adjoint of w0.
@@ -86,6 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
     const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
     R relax, int first_sweep, const int32_t* __restrict__ pofs) {
+#pragma clang fp contract(on)
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int pbase = pofs[i];
@@ -97,75 +178,63 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
-    const int q = pbase + k;   // compact index of the recorded impulse and adjoint state
-    const int code = partner[slot];
-    const R psi = Psi[slot];
-    R P[3] = {R(0), R(0), R(0)};
-    if (!first_sweep) {
-      P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
-    }
-    R nrm[3], u[3], mt, Pb[3];
-    const R carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
-    bool lo = true, body = code < 0;
-    if (!body) {
-      const int j = code & (kHiFlag - 1);
-      lo = (code & kHiFlag) == 0;
-      const V4<R> xj = x[j];
-      const V4<R> wj = w_prev[j];
-      const V4<R> bj = wbar_in[j];
-      const R imj = v[j].w;
-      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
-      const V4<R> bl = lo ? bi : bj, bh = lo ? bj : bi;
-      const R iml = lo ? vi.w : imj, imh = lo ? imj : vi.w;
-      const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
-      const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      if (L > R(0)) {
-        const R il = R(1) / L;
-        nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
-      } else {
-        nrm[0] = R(0); nrm[1] = R(0); nrm[2] = R(1);
-      }
-      u[0] = wl.x - wh.x; u[1] = wl.y - wh.y; u[2] = wl.z - wh.z;
-      mt = R(1) / (wl.w + wh.w);
-      Pb[0] = carry[0] + iml * bl.x - imh * bh.x;
-      Pb[1] = carry[1] + iml * bl.y - imh * bh.y;
-      Pb[2] = carry[2] + iml * bl.z - imh * bh.z;
-    } else {
-      R V[3];
-      body_geometry<R>(bodies[-1 - code], xi, psi, nrm, V);
-      u[0] = wi.x - V[0]; u[1] = wi.y - V[1]; u[2] = wi.z - V[2];
-      mt = R(1) / wi.w;
-      Pb[0] = carry[0] + vi.w * bi.x;
-      Pb[1] = carry[1] + vi.w * bi.y;
-      Pb[2] = carry[2] + vi.w * bi.z;
-    }
-    const R bias = alpha_dt * psi;
-    R y[3];
-    for (int a = 0; a < 3; ++a) y[a] = P[a] - mt * (u[a] + bias * nrm[a]);
-    const R Qb[3] = {relax * Pb[0], relax * Pb[1], relax * Pb[2]};
-    R yb[3], nb[3] = {R(0), R(0), R(0)};
-    proj_adjoint(y, nrm, mu, Qb, yb, nb);
-    const R keep = R(1) - relax;
-    A.cx[q] = yb[0] + keep * Pb[0];
-    A.cy[q] = yb[1] + keep * Pb[1];
-    A.cz[q] = yb[2] + keep * Pb[2];
-    const R ub[3] = {-mt * yb[0], -mt * yb[1], -mt * yb[2]};
-    const R bb = -mt * dot3f(yb, nrm);
-    A.nx[q] += nb[0] - mt * bias * yb[0];
-    A.ny[q] += nb[1] - mt * bias * yb[1];
-    A.nz[q] += nb[2] - mt * bias * yb[2];
-    A.ps[q] += alpha_dt * bb;
-    if (body) {
-      A.vx[q] -= ub[0]; A.vy[q] -= ub[1]; A.vz[q] -= ub[2];
-    }
-    const R sg = lo ? R(1) : R(-1);
+    R ub[3], sg;
+    half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, xi, vi, wi, bi, x, v, w_prev, wbar_in,
+                        Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
     acc[0] += sg * ub[0]; acc[1] += sg * ub[1]; acc[2] += sg * ub[2];
   }
   wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], R(0));
   V4<R> z = w0bar[i];
   z.x += bi.x; z.y += bi.y; z.z += bi.z;
   w0bar[i] = z;
+}
+
+// The same reverse sweep with L lanes per particle (L = 2 or 4): lane s takes
+// contacts s, s + L, ...; the sum over contacts keeps list order (cross-lane
+// shuffles after every round), so results are bitwise those of k_pja_adj.
+template <typename R, int L>
+__global__ __launch_bounds__(kBlock) void k_pja_adj_lanes(
+    int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
+    const V4<R>* __restrict__ w_prev, const V4<R>* __restrict__ wbar_in, V4<R>* __restrict__ wbar_out,
+    V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
+    const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
+    const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
+    R relax, int first_sweep, const int32_t* __restrict__ pofs) {
+#pragma clang fp contract(on)
+  static_assert(L == 2 || L == 4, "lanes per particle");
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = t / L, sub = t % L;
+  if (i >= n) return;  // (the L lanes of a particle leave together)
+  const int pbase = pofs[i];
+  const V4<R> xi = x[i];
+  const V4<R> vi = v[i];
+  const V4<R> wi = w_prev[i];
+  const V4<R> bi = wbar_in[i];
+  R acc[3] = {R(0), R(0), R(0)};
+  const int c = ncon[i];
+  for (int m = 0; m * L < c; ++m) {
+    const int k = m * L + sub;
+    R ub[3] = {R(0), R(0), R(0)}, sg = R(0);
+    if (k < c) {
+      const int slot = ell_slot(i, k, K);
+      half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, xi, vi, wi, bi, x, v, w_prev,
+                          wbar_in, Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
+    }
+#pragma unroll
+    for (int qq = 0; qq < L; ++qq) {
+      const R g = __shfl(sg, qq, L), u0 = __shfl(ub[0], qq, L), u1 = __shfl(ub[1], qq, L),
+              u2 = __shfl(ub[2], qq, L);
+      if (m * L + qq < c) {
+        acc[0] += g * u0; acc[1] += g * u1; acc[2] += g * u2;
+      }
+    }
+  }
+  if (sub == 0) {
+    wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], R(0));
+    V4<R> z = w0bar[i];
+    z.x += bi.x; z.y += bi.y; z.z += bi.z;
+    w0bar[i] = z;
+  }
 }
 
 // Start of the reverse of one step: xbar^k = xbar^{k+1} (positions pass through),

@@ -1576,9 +1576,21 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       for (int l = I; l >= 1; --l) {
         const V* wprev = tw + ((size_t)r * I + (l - 1)) * n;
         const R* Pp = (l >= 2) ? tP + pstart[r] + (size_t)(l - 2) * 3 * hc[st] : nullptr;
-        ggk::k_pja_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
-                                                    Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr, A,
-                                                    bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
+        const int Ln = s->p.pja_lanes;
+        const int lg = (int)(((int64_t)n * Ln + ggk::kBlock - 1) / ggk::kBlock);
+        if (Ln == 1)
+          ggk::k_pja_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
+                                                      Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr,
+                                                      A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
+                                                      po);
+        else if (Ln == 2)
+          ggk::k_pja_adj_lanes<R, 2><<<lg, ggk::kBlock, 0, S>>>(
+              n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
+              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
+        else
+          ggk::k_pja_adj_lanes<R, 4><<<lg, ggk::kBlock, 0, S>>>(
+              n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
+              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
         std::swap(win, wout);
       }
       ggk::k_adj_vbar<R><<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);

@@ -71,3 +71,25 @@ def test_four_lanes_one_step_against_the_oracle():
     say("four lanes vs oracle: impulses", err, "dv", errv)
     assert err <= 1e-5 and errv <= 1e-5
     sim.close()
+
+
+def test_lanes_give_the_same_gradients():
+    sc = scenes.diff_scene(n=4096)
+    rng = np.random.default_rng(4)
+    steps = 6
+    tw = np.zeros((steps, len(sc.bodies), 6), np.float32)
+    tw[:, -1, :3] = (0.2, 0.0, -0.1)
+    gx = rng.normal(size=(sc.n, 3)).astype(np.float32)
+    gv = rng.normal(size=(sc.n, 3)).astype(np.float32)
+    out = []
+    for lanes in (1, 2, 4):
+        sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters,
+                     differentiable=True, checkpoint_every=3, pja_lanes=lanes)
+        sim.step(steps, twists=tw)
+        res = (sim.read("pos"),) + tuple(sim.backward(gx, gv))
+        sim.close()
+        out.append(res)
+    for lanes, res in zip((2, 4), out[1:]):
+        say("gradients, lanes", lanes, "max |d dL/dx0|", float(np.abs(res[1] - out[0][1]).max()))
+        for a, b in zip(res, out[0]):
+            assert np.array_equal(a, b), lanes
