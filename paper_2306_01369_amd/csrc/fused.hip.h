@@ -50,6 +50,7 @@ struct FusedArgs {
   R* Py;
   R* Pz;
   V4<R>* dv;
+  R* imass;
   Ctl* ctl;
   int step;
 };
@@ -71,7 +72,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   if (err0 == 0)
     detect_items<R, TB>(a.n, a.K, a.x, a.v, a.orig, a.inv_c, a.n_blk, a.env, a.start, a.sidx, a.xs, a.os,
                         a.item_start, a.n_items, a.bodies, a.n_bodies, a.gx, a.gy, a.gz, a.dt, a.mass_split,
-                        a.max_cells, a.max_stage, a.ncon, a.partner, a.Psi, a.wa, a.ctl, a.step, blk, nblk);
+                        a.max_cells, a.max_stage, a.ncon, a.partner, a.Psi, a.wa, a.imass, a.ctl, a.step, blk,
+                        nblk);
   grid.sync();
   // nothing writes the error word after detection: every thread reads the same value
   const bool run = __hip_atomic_load(&a.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
@@ -85,7 +87,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
         const int i = base + (int)threadIdx.x;
         if (i < a.n)
           pja_particle<R>(i, a.K, a.x, a.v, w_in, w_out, a.ncon, a.partner, a.Psi, a.Px, a.Py, a.Pz, a.Px, a.Py,
-                          a.Pz, a.bodies, a.gx, a.gy, a.gz, a.dt, a.alpha_dt, a.mu, a.relax, mode, a.dv, nullptr);
+                          a.Pz, a.bodies, a.gx, a.gy, a.gz, a.dt, a.alpha_dt, a.mu, a.relax, mode, a.dv, nullptr,
+                          a.imass);
       }
     grid.sync();
   }

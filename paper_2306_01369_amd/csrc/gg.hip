@@ -257,6 +257,7 @@ struct gg_sim {
   int64_t steps_global = 0;
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
+  void* imass = nullptr;  // 1/m_i in the internal order (written by detection, R)
   void *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
   int32_t* h6 = nullptr;  // Eq. (6) cell index of each particle at the last detection
   int32_t *d_env_tblk = nullptr, *d_env_toff = nullptr;
@@ -422,7 +423,7 @@ void free_all(gg_sim* s) {
   void* bufs[] = {s->x, s->v, s->wa, s->wb, s->dv, s->x2, s->v2, s->orig, s->orig2, s->mk[0], s->mk[1],
                   s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
                   s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
-                  s->sidx, s->ncon, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
+                  s->sidx, s->ncon, s->imass, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
                   s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp, s->h6,
                   s->d_env_tblk, s->d_env_toff, s->d_grid_values, s->d_cams, s->d_planes, s->obs_img,
                   s->d_chunks, s->d_env_chunk, s->d_env_count, s->d_part_n, s->d_part_d, s->d_boxes,
@@ -478,6 +479,7 @@ struct StepIO {
   ggk::V4<R>* x;
   ggk::V4<R>* v;
   int32_t* ncon;
+  R* imass;
   int32_t* partner;
   R* Psi;
   std::vector<ggk::V4<R>*> w;
@@ -492,6 +494,7 @@ StepIO<R> plain_io(gg_sim* s) {
   io.x = (ggk::V4<R>*)s->x;
   io.v = (ggk::V4<R>*)s->v;
   io.ncon = s->ncon;
+  io.imass = (R*)s->imass;
   io.partner = s->partner;
   io.Psi = (R*)s->Psi;
   const int I = s->p.n_iters;
@@ -559,7 +562,7 @@ void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
       (int)s->n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os,
       s->item_start, &s->ctl->items, bod, (int)s->bodies.size(), (R)s->p.gravity[0], (R)s->p.gravity[1],
       (R)s->p.gravity[2], (R)s->p.dt, s->p.mass_split, s->p.tile_max_cells, s->p.tile_max_stage, io.ncon,
-      io.partner, io.Psi, io.w[0], s->ctl, st);
+      io.partner, io.Psi, io.w[0], io.imass, s->ctl, st);
 }
 
 // Bucket table and contact detection of one step.
@@ -607,17 +610,20 @@ void launch_sweeps(gg_sim* s, const StepIO<R>& io, const ggk::DevBody* bod) {
       ggk::k_pja<R><<<grid, ggk::kBlock, 0, s->stream>>>(
           n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
           io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
-          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, io.imass,
+          s->ctl);
     else if (L == 2)
       ggk::k_pja_lanes<R, 2><<<lgrid, ggk::kBlock, 0, s->stream>>>(
           n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
           io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
-          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, io.imass,
+          s->ctl);
     else
       ggk::k_pja_lanes<R, 4><<<lgrid, ggk::kBlock, 0, s->stream>>>(
           n, s->K, io.x, io.v, io.w[l - 1], io.w[l], io.ncon, io.partner, io.Psi, io.Px[l - 1], io.Py[l - 1],
           io.Pz[l - 1], io.Px[l], io.Py[l], io.Pz[l], bod, (R)s->p.gravity[0], (R)s->p.gravity[1],
-          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, s->ctl);
+          (R)s->p.gravity[2], (R)s->p.dt, alpha_dt, (R)s->p.mu, (R)s->p.relax, mode, io.dv, io.pofs, io.imass,
+          s->ctl);
   }
 }
 
@@ -677,6 +683,7 @@ gg_status launch_fused(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBod
   a.Py = io.Py[0];
   a.Pz = io.Pz[0];
   a.dv = io.dv;
+  a.imass = io.imass;
   a.ctl = s->ctl;
   a.step = st;
   hipError_t e;
@@ -968,6 +975,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
             dev_alloc(&s->bstart, (size_t)total_tab + 1) == hipSuccess &&
             dev_alloc(&s->bsum, (size_t)(total_tab + ggk::kScanTile - 1) / ggk::kScanTile + 1) == hipSuccess &&
             dev_alloc(&s->sidx, N) == hipSuccess && dev_alloc(&s->ncon, N) == hipSuccess &&
+            dev_alloc_bytes(&s->imass, N * s->es) == hipSuccess &&
             dev_alloc(&s->ctl, 1) == hipSuccess && dev_alloc_bytes(&s->x2, N4) == hipSuccess &&
             dev_alloc_bytes(&s->v2, N4) == hipSuccess && dev_alloc(&s->orig, N) == hipSuccess &&
             dev_alloc(&s->orig2, N) == hipSuccess && dev_alloc(&s->mk[0], N) == hipSuccess &&
@@ -1530,6 +1538,7 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       io.x = xw;
       io.v = vw;
       io.ncon = tncon + (size_t)r * n;
+      io.imass = (R*)s->imass;
       io.partner = tpart + slots * r;
       io.Psi = tpsi + slots * r;
       io.w.resize(I + 1);

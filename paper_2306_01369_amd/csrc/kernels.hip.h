@@ -842,8 +842,8 @@ __device__ __forceinline__ void detect_items(
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
-    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step, int blk,
-    int nblk) {
+    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
+    int step, int blk, int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[TB / 64][8];
   __shared__ int red[TB / 64];
@@ -1015,6 +1015,7 @@ __device__ __forceinline__ void detect_items(
       const V4<R> vi = v[i];
       const R s_i = mass_split ? (R)cnt * vi.w : vi.w;
       w[i] = mk4<R>(vi.x + dt * gx, vi.y + dt * gy, vi.z + dt * gz, s_i);
+      imass[i] = vi.w;
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -1040,11 +1041,12 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const V4<R>* __restrict__ xs, const int32_t* __restrict__ os, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
-    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, Ctl* ctl, int step) {
+    int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
+    int step) {
   if (ctl->err) return;
   detect_items<R, TB>(n, K, x, v, orig, inv_c, n_blk, env, start, sidx, xs, os, item_start, n_items_ptr, bodies,
-                      n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, ctl, step,
-                      xcd_block(), gridDim.x);
+                      n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, imass, ctl,
+                      step, xcd_block(), gridDim.x);
 }
 
 // ------------------------------------------------------ projected Jacobi
@@ -1065,8 +1067,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
 // indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
 // One half contact of a sweep: the impulse Q of contact `code` (slot `slot`,
-// impulse index `ps`) of particle i from the previous impulse and iterate,
-// stored to P*, and the sign sg with which it enters i's sum.  Multiply-adds
+// impulse index `ps`) of particle i from the previous impulse P and iterate,
+// stored to P*, P itself, and the sign sg with which it enters i's sum.  Multiply-adds
 // are fused only within one expression (fp contract on), so every kernel that
 // calls it computes the same bits.
 template <typename R>
@@ -1075,10 +1077,10 @@ __device__ __forceinline__ void half_contact(int code, int slot, int ps, bool fi
                                              const V4<R>* __restrict__ w_in, const R* __restrict__ Psi,
                                              const R* Pix, const R* Piy, const R* Piz, R* Px, R* Py, R* Pz,
                                              const DevBody* __restrict__ bodies, R alpha_dt, R mu, R relax,
-                                             R& Q0, R& Q1, R& Q2, R& sg) {
+                                             R& Q0, R& Q1, R& Q2, R& P0, R& P1, R& P2, R& sg) {
 #pragma clang fp contract(on)
   R psi;
-  R P0 = R(0), P1 = R(0), P2 = R(0);
+  P0 = R(0); P1 = R(0); P2 = R(0);
   if (!first) {
     P0 = Pix[ps]; P1 = Piy[ps]; P2 = Piz[ps];
   }
@@ -1132,16 +1134,19 @@ __device__ __forceinline__ void half_contact(int code, int slot, int ps, bool fi
   Px[ps] = Q0; Py[ps] = Q1; Pz[ps] = Q2;
 }
 
-// The particle's new iterate from its impulse sum a (last sweep: the velocity).
+// The particle's new iterate.  Jacobi: w = w0 + im sum sigma Q; it is formed
+// from the previous iterate as w = w_prev + im sum sigma (Q - P), which is the
+// same in exact arithmetic and spares reading v (w0 = v + dt g) every sweep.
+// d = sum sigma (Q - P); a = sum sigma Q (only for the velocity change dv).
+// The last sweep writes the velocity.
 template <typename R>
-__device__ __forceinline__ void finish_particle(int i, bool last, const V4<R>& vi, const V4<R>& wi, R a0, R a1,
-                                                R a2, R gx, R gy, R gz, R dt, V4<R>* __restrict__ v,
-                                                V4<R>* __restrict__ w_out, V4<R>* __restrict__ dv) {
+__device__ __forceinline__ void finish_particle(int i, bool last, R im, const V4<R>& wi, R d0, R d1, R d2, R a0,
+                                                R a1, R a2, V4<R>* __restrict__ v, V4<R>* __restrict__ w_out,
+                                                V4<R>* __restrict__ dv) {
 #pragma clang fp contract(on)
-  const R im = vi.w;
-  const R n0 = vi.x + dt * gx + im * a0;
-  const R n1 = vi.y + dt * gy + im * a1;
-  const R n2 = vi.z + dt * gz + im * a2;
+  const R n0 = wi.x + im * d0;
+  const R n1 = wi.y + im * d1;
+  const R n2 = wi.z + im * d2;
   if (last) {
     v[i] = mk4<R>(n0, n1, n2, im);
     if (dv) dv[i] = mk4<R>(im * a0, im * a1, im * a2, R(0));
@@ -1160,24 +1165,29 @@ __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restri
                                              const R* Piy, const R* Piz, R* Px, R* Py,
                                              R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
                                              R gz, R dt, R alpha_dt, R mu, R relax,
-                                             int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs) {
+                                             int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
+                                             const R* __restrict__ imass) {
 #pragma clang fp contract(on)
   const bool first = mode & 1, last = mode & 2;
   const int pbase = pofs ? pofs[i] : 0;
   const V4<R> xi = x[i];
-  const V4<R> vi = v[i];
   const V4<R> wi = w_in[i];
-  R a0 = R(0), a1 = R(0), a2 = R(0);
+  const R im = imass[i];
+  R d0 = R(0), d1 = R(0), d2 = R(0), a0 = R(0), a1 = R(0), a2 = R(0);
   const int c = ncon[i];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
     const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
-    R Q0, Q1, Q2, sg;
+    R Q0, Q1, Q2, P0, P1, P2, sg;
     half_contact<R>(partner[slot], slot, ps, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies,
-                    alpha_dt, mu, relax, Q0, Q1, Q2, sg);
-    a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
+                    alpha_dt, mu, relax, Q0, Q1, Q2, P0, P1, P2, sg);
+    const R D0 = Q0 - P0, D1 = Q1 - P1, D2 = Q2 - P2;
+    d0 += sg * D0; d1 += sg * D1; d2 += sg * D2;
+    if (last && dv) {
+      a0 += sg * Q0; a1 += sg * Q1; a2 += sg * Q2;
+    }
   }
-  finish_particle<R>(i, last, vi, wi, a0, a1, a2, gx, gy, gz, dt, v, w_out, dv);
+  finish_particle<R>(i, last, im, wi, d0, d1, d2, a0, a1, a2, v, w_out, dv);
 }
 
 template <typename R>
@@ -1190,12 +1200,12 @@ __global__ __launch_bounds__(kBlock) void k_pja(int n, int K, const V4<R>* __res
                                                 R* Pz, const DevBody* __restrict__ bodies, R gx, R gy,
                                                 R gz, R dt, R alpha_dt, R mu, R relax,
                                                 int mode, V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
-                                                const Ctl* ctl) {
+                                                const R* __restrict__ imass, const Ctl* ctl) {
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   pja_particle<R>(i, K, x, v, w_in, w_out, ncon, partner, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies, gx, gy, gz, dt,
-                  alpha_dt, mu, relax, mode, dv, pofs);
+                  alpha_dt, mu, relax, mode, dv, pofs, imass);
 }
 
 // The same sweep with L lanes per particle (L = 2 or 4; small beds, where a
@@ -1214,7 +1224,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_lanes(int n, int K, const V4<R>*
                                                       const DevBody* __restrict__ bodies, R gx, R gy, R gz, R dt,
                                                       R alpha_dt, R mu, R relax, int mode,
                                                       V4<R>* __restrict__ dv, const int32_t* __restrict__ pofs,
-                                                      const Ctl* ctl) {
+                                                      const R* __restrict__ imass, const Ctl* ctl) {
 #pragma clang fp contract(on)
   static_assert(L == 2 || L == 4, "lanes per particle");
   if (ctl->err) return;
@@ -1224,27 +1234,34 @@ __global__ __launch_bounds__(kBlock) void k_pja_lanes(int n, int K, const V4<R>*
   const bool first = mode & 1, last = mode & 2;
   const int pbase = pofs ? pofs[i] : 0;
   const V4<R> xi = x[i];
-  const V4<R> vi = v[i];
   const V4<R> wi = w_in[i];
-  R a0 = R(0), a1 = R(0), a2 = R(0);
+  const R im = imass[i];
+  R d0 = R(0), d1 = R(0), d2 = R(0), a0 = R(0), a1 = R(0), a2 = R(0);
   const int c = ncon[i];
   for (int m = 0; m * L < c; ++m) {
     const int k = m * L + sub;
-    R Q0 = R(0), Q1 = R(0), Q2 = R(0), sg = R(0);
+    R Q0 = R(0), Q1 = R(0), Q2 = R(0), P0 = R(0), P1 = R(0), P2 = R(0), sg = R(0);
     if (k < c) {
       const int slot = ell_slot(i, k, K);
       half_contact<R>(partner[slot], slot, pofs ? pbase + k : slot, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz,
-                      Px, Py, Pz, bodies, alpha_dt, mu, relax, Q0, Q1, Q2, sg);
+                      Px, Py, Pz, bodies, alpha_dt, mu, relax, Q0, Q1, Q2, P0, P1, P2, sg);
     }
+    const R D0 = Q0 - P0, D1 = Q1 - P1, D2 = Q2 - P2;
 #pragma unroll
     for (int q = 0; q < L; ++q) {
-      const R g = __shfl(sg, q, L), q0 = __shfl(Q0, q, L), q1 = __shfl(Q1, q, L), q2 = __shfl(Q2, q, L);
+      const R g = __shfl(sg, q, L), e0 = __shfl(D0, q, L), e1 = __shfl(D1, q, L), e2 = __shfl(D2, q, L);
       if (m * L + q < c) {
-        a0 += g * q0; a1 += g * q1; a2 += g * q2;
+        d0 += g * e0; d1 += g * e1; d2 += g * e2;
+      }
+      if (last && dv) {   // (the same for every lane of the launch)
+        const R q0 = __shfl(Q0, q, L), q1 = __shfl(Q1, q, L), q2 = __shfl(Q2, q, L);
+        if (m * L + q < c) {
+          a0 += g * q0; a1 += g * q1; a2 += g * q2;
+        }
       }
     }
   }
-  if (sub == 0) finish_particle<R>(i, last, vi, wi, a0, a1, a2, gx, gy, gz, dt, v, w_out, dv);
+  if (sub == 0) finish_particle<R>(i, last, im, wi, d0, d1, d2, a0, a1, a2, v, w_out, dv);
 }
 
 // Positions from the new velocities (Eq. (5)), x' = x + dt v'; with a cyclic
