@@ -4,14 +4,18 @@ Chooses, for a given workload, the detection work-item node size
 (``tile_node_shift``: Z-order nodes of 2^shift cells), the detection
 workgroup size (``tile_threads``), the LDS budget of a
 detection tile (``tile_max_cells``, ``tile_max_stage``), the interval between
-spatial re-sorts (``reorder_every``) and then the hash-table size n_h (Eq. (6);
-Sec. II-B's heuristic is n_h = 2 n), by timing a few steps of each candidate
+spatial re-sorts (``reorder_every``), the lanes per particle of the sweeps
+(``pja_lanes``), the iteration blocking (one launch per sweep, or the fused
+cooperative step, ``fused``) and then the hash-table size n_h (Eq. (6); Sec.
+II-B's heuristic is n_h = 2 n), by timing a few steps of each candidate
 through the C ABI.  These parameters change only memory layout, bucket
 aliasing and work decomposition: partners are listed by (neighbour cell,
-original index), never by bucket, so every output is bitwise identical across
-them (the GPU tests check this) and the choice is free of numerical side
-effects.  The cell size is left at its default (c = 2 r_max (1 + 2^-10)) because
-it changes which cell, and so which list position, a partner falls in.
+original index), never by bucket, and impulse sums keep list order, so every
+output is bitwise identical across them (the GPU tests check this; the fused
+step agrees to rounding) and the choice is free of numerical side effects.
+The cell size is left at its default (c = 2 r_max (1 + 2^-10)) unless asked
+for, because it changes which cell, and so which list position, a partner
+falls in.
 
 Results are cached in a JSON file keyed by device, particle count, particles
 per cell and body count.
@@ -147,9 +151,16 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             best, best_t = cand, t
     if best is None:
         return {}
-    # then the lanes per particle of the sweeps, and the table size
+    # then the lanes per particle of the sweeps, the iteration blocking (one
+    # launch per sweep, or detection and all sweeps in one cooperative launch
+    # with grid barriers), and the table size
     for lanes in lane_counts():
         cand = dict(best, pja_lanes=lanes)
+        t = timed(cand)
+        if t is not None and t < best_t:
+            best, best_t = cand, t
+    if not sim_kwargs.get("differentiable"):
+        cand = dict(best, fused=True)
         t = timed(cand)
         if t is not None and t < best_t:
             best, best_t = cand, t
