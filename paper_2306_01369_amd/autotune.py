@@ -125,9 +125,11 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             return dict(cache[key]["params"])
 
     def timed(cand):
+        # wall time of `steps` steps after `warmup` (each step call returns
+        # once its steps are done); no phase events, which would distort
+        # launch-bound small beds
         kw = dict(sim_kwargs)
         kw.update(cand)
-        kw["profile"] = True
         try:
             sim = gg.Sim(x, v, radius, bodies, **kw)
             sim.step(warmup)
