@@ -85,6 +85,26 @@ def copy_calibration(mib=512, reps=5):
     log(f"copy calibration: {reps} copies of {mib} MiB")
 
 
+def replay_ready(sim, steps, call):
+    """Make calls of `steps` steps (call(steps)) until the next call starts in a
+    re-sort phase and state-buffer parity already seen, so that it replays a
+    graph captured earlier instead of capturing one inside a timed region.
+    The library keys captures by (steps, re-sort phase, current state buffer);
+    a re-sort at every step index divisible by the interval R swaps the buffers.
+    Returns the number of steps made."""
+    st = sim.stats()
+    R, g0 = int(st["reorder_every"]), int(st["steps_total"])
+
+    def state(g):
+        return (0, 0) if R <= 0 else (g % R, ((g + R - 1) // R) % 2)
+    seen, g = set(), g0
+    while state(g) not in seen:
+        seen.add(state(g))
+        call(steps)
+        g += steps
+    return g - g0
+
+
 def bench_batched(args):
     """256 independent environments of U{8192..65536} spheres stepped in one
     launch sequence, against the same environments stepped one by one."""
@@ -92,24 +112,35 @@ def bench_batched(args):
     import torch
     steps = args.steps if args.steps_given else 100
     log("generating 256 batched environments")
-    sc = scenes.batched_scene(n_steps=max(steps + args.warmup, 8 + args.plain_steps))
+    # the timed call (a multiple of twice the re-sort interval, 16 here, so every
+    # call starts in the same re-sort phase and buffer parity) replays the graph
+    # captured by the call before it; both the batched and the plain loop are
+    # timed from step 128
+    steps = 32 * max(1, steps // 32)
+    sc = scenes.batched_scene(n_steps=128 + steps + max(8, args.plain_steps))
     n = sc.n
     tw = np.ascontiguousarray(sc.twists)
     kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters, env_offsets=sc.env_offsets)
     sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, graph=True, **kw)
-    if args.warmup:
-        sim.step(args.warmup, twists=tw[:args.warmup])
-    # one more call of the timed length captures its launch sequence
+    at = [0]
+
+    def call(k):
+        sim.step(k, twists=tw[at[0]:at[0] + k])
+        at[0] += k
+    while at[0] + steps < 128:
+        call(32)
+    call(steps)   # captures the graph the timed call replays (calls of multiples of
+    warm = at[0]  # 32 steps all start in re-sort phase 0 with the same state buffer)
     prof = gg.Sim(sim.read("pos"), sim.read("vel"), sc.radius, sc.bodies, profile=True, **kw)
     torch.cuda.synchronize()
     log(f"batched: n={n}, timing {steps} steps (one graph launch)")
     t0 = time.perf_counter()
-    sim.step(steps, twists=tw[args.warmup:args.warmup + steps])
+    call(steps)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     sim.close()
     # phase split from a profiled copy (events between phases; not the timed run)
-    prof.step(5, twists=tw[args.warmup:args.warmup + 5])
+    prof.step(5, twists=tw[at[0] - steps:at[0] - steps + 5])
     st = prof.stats()
     prof.close()
     # plain loop: every environment its own simulation, stepped in turn
@@ -122,16 +153,24 @@ def bench_batched(args):
         bodies = [dict(bd, env=0) for bd in sc.bodies[e * nb_env:(e + 1) * nb_env]]
         sims.append((gg.Sim(sc.x[a:b], sc.v[a:b], sc.radius[a:b], bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
                             n_iters=sc.n_iters, graph=True), np.ascontiguousarray(tw[:, e * nb_env:(e + 1) * nb_env])))
-    # one-step calls: eight warm-up calls capture the graph of every re-sort phase
+    # one-step calls: warm-up calls capture the graph of every re-sort phase and
+    # state-buffer parity, so the timed calls replay
+    made = []
     for sm, t in sims:
-        for k in range(8):
-            sm.step(1, twists=t[k:k + 1])
+        pos = [0]
+
+        def one(k, sm=sm, t=t, pos=pos):
+            sm.step(k, twists=t[pos[0]:pos[0] + k])
+            pos[0] += k
+        for _ in range(warm):      # every (re-sort phase, buffer parity) is captured by step 64
+            one(1)
+        made.append(pos[0])
     torch.cuda.synchronize()
     log(f"plain loop: {n_envs} sims, timing {plain_steps} steps")
     t0 = time.perf_counter()
     for k in range(plain_steps):
-        for sm, t in sims:
-            sm.step(1, twists=t[8 + k:8 + k + 1])
+        for (sm, t), m in zip(sims, made):
+            sm.step(1, twists=t[m + k:m + k + 1])
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) * steps / plain_steps
     for sm, _ in sims:
@@ -139,7 +178,7 @@ def bench_batched(args):
     value = n * steps / t_batched
     return {
         "metric": "batched particle-steps/s (256 envs, 20 PJA iters)",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": 1e3 * t_batched / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched: 256 walled beds of U{8192..65536} spheres r=3mm, capsule tools with "
@@ -156,39 +195,56 @@ def bench_batched(args):
 
 
 def bench_drop(args):
-    """4096 spheres dropped into a 0.2 m box (latency-bound): time per step with
-    direct launches and with the captured graph, and launches per step."""
+    """4096 spheres dropped into a 0.2 m box (latency-bound).  value: the
+    workload itself, 100 steps from rest, with direct launches (a first
+    simulation warms the runtime up; a fresh one is timed).  Also: graph replay
+    over 100 steps of the resting pile, once every launch sequence is captured,
+    and launches per step."""
     from paper_2306_01369_amd import gg, scenes
     import torch
     steps = args.steps if args.steps_given else 100
     sc = scenes.drop_scene()
-    out = {}
-    for mode in ("direct", "graph"):
-        sim = gg.scene_sim(sc, graph=(mode == "graph"))
-        # four warm-up calls visit every (re-sort phase, buffer parity) a call of
-        # 100 steps can start in, so the timed call replays a captured graph
-        for _ in range(4):
-            sim.step(steps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step(steps)
-        torch.cuda.synchronize()
-        out[mode] = (time.perf_counter() - t0) / steps
-        sim.close()
+    warm = gg.scene_sim(sc)
+    warm.step(steps)
+    warm.close()
+    sim = gg.scene_sim(sc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t_direct = (time.perf_counter() - t0) / steps
+    st = sim.stats()
+    sim.close()
+    g = gg.scene_sim(sc, graph=True)
+    for _ in range(4):                      # the pile lands
+        g.step(steps)
+    replay_ready(g, steps, g.step)
+    start = g.stats()["steps_total"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    gst = g.stats()
+    g.close()
     I = sc.n_iters
     launches = 6 + I + 1                     # keys, 3 scans, scatter, detect, sweeps, integrate
     resort = 1 + 4 * 5 + 1 + 11              # keys, 4 radix passes x 5, permute, work items
     return {
         "metric": "drop-pile step latency (4096 spheres, 20 PJA iters)",
-        "value": 1e6 * out["graph"], "unit": "us/step", "n_gpus": 1, "steps": steps, "warmup": 4 * steps,
-        "ms_per_step": 1e3 * out["graph"], "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "value": 1e6 * t_direct, "unit": "us/step", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": 1e3 * t_direct, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "drop: 4096 spheres r=5 mm from a 16^3 lattice into a 0.2 m walled box, "
-                               "100 steps from rest", "n": sc.n},
-        "us_per_step_direct_launches": 1e6 * out["direct"],
-        "us_per_step_graph": 1e6 * out["graph"],
+                               "100 steps from rest (direct launches)", "n": sc.n},
+        "contacts_last_step": st["n_pp"] + st["n_pb"],
+        "us_per_step_graph_resting_pile": 1e6 * t_graph,
+        "graph_window_first_step": start,
+        "graph_window_contacts": gst["n_pp"] + gst["n_pb"],
         "launches_per_step": launches,
-        "resort_launches_every_8_steps": resort,
+        "resort_launches": resort,
+        "resort_every": st["reorder_every"],
+        "pja_lanes": st["pja_lanes"],
     }
 
 
@@ -254,7 +310,7 @@ def bench_gears(args):
     4,096 .. 65,536 particles and 0 .. 20 gears (plus the tower wall)."""
     from paper_2306_01369_amd import gg, scenes
     import torch
-    steps = args.steps if args.steps_given else 100
+    steps = args.steps if args.steps_given else 64   # a multiple of twice the re-sort interval
     table = []
     for n in (4096, 16384, 65536):
         for nb in (0, 5, 10, 20):
@@ -262,6 +318,7 @@ def bench_gears(args):
             sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
                          n_iters=sc.n_iters, cyclic_z=cyc, graph=True)
             sim.step(steps)                 # the flow develops; the graph is captured
+            replay_ready(sim, steps, sim.step)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step(steps)
@@ -292,7 +349,7 @@ def bench_hash_sweep(args):
     n/4 .. 16n; speedup over real time = dt / (seconds per step)."""
     from paper_2306_01369_amd import gg, scenes
     import torch
-    steps = args.steps if args.steps_given else 100
+    steps = args.steps if args.steps_given else 64   # a multiple of twice the re-sort interval
     factors = (0.25, 0.5, 1, 2, 4, 8, 16)
     table = []
     for n in (1024, 4096, 16384, 65536):
@@ -301,7 +358,7 @@ def bench_hash_sweep(args):
         for f in factors:
             sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
                          n_iters=sc.n_iters, hash_size=max(1, int(f * n)), graph=True)
-            sim.step(steps)
+            replay_ready(sim, steps, sim.step)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step(steps)
@@ -331,8 +388,6 @@ def bench_passes(args):
     grains) and on the 1M scoop bed; speedup over real time = dt / (s per step)."""
     from paper_2306_01369_amd import gg, scenes
     import torch
-    # step counts are multiples of the re-sort interval (8), so the timed call
-    # replays the graph the warm-up call captured (same re-sort phase)
     steps = 8 * max(1, (args.steps if args.steps_given else 96) // 8)
     modes = (("split", {}), ("split+graph", {"graph": True}), ("fused", {"fused": True}))
     cases = [(f"column-{n}", scenes.column_scene(n=n, r=0.004)) for n in (1024, 4096, 16384, 65536)]
@@ -344,7 +399,7 @@ def bench_passes(args):
             sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, dt=sc.dt, alpha=sc.alpha, mu=sc.mu,
                          n_iters=sc.n_iters, **kw)
             k = steps if sc.n < 500000 else max(8, 8 * (steps // 40))
-            sim.step(k)
+            replay_ready(sim, k, sim.step)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step(k)
@@ -381,6 +436,8 @@ def bench_gym(args):
     log("gym: warm-up (graph capture)")
     for _ in range(5):
         env.step(rng.uniform(-1, 1, (n_envs, 2)))
+    # every re-sort phase and buffer parity an environment step can start in
+    replay_ready(env.sim, env.substeps, lambda k: env.step(rng.uniform(-1, 1, (n_envs, 2))))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):

@@ -102,10 +102,11 @@ typedef struct {
 #define GG_FLAG_TAPE 4u        /* differentiable: keep checkpoints of every gg_step call for
                                   gg_step_backward (one environment only) */
 #define GG_FLAG_GRAPH 8u       /* replay gg_step's launch sequence from a captured HIP graph:
-                                  the first call with a given step count (and re-sort phase)
-                                  captures it, later ones replay it; results are bitwise those
-                                  of direct launches.  Ignored with GG_FLAG_PROFILE or
-                                  GG_FLAG_TAPE. */
+                                  the first call with a given step count, re-sort phase and
+                                  state-buffer parity captures it (the 64 most recently used
+                                  captures are kept), later ones replay it; results are
+                                  bitwise those of direct launches.  Ignored with
+                                  GG_FLAG_PROFILE or GG_FLAG_TAPE. */
 
 #define GG_FLAG_FUSED 16u       /* run each step's detection, projected-Jacobi sweeps and position
                                   update as one cooperative kernel launch with grid-wide
@@ -139,7 +140,7 @@ typedef struct {
   uint32_t flags;    /* GG_FLAG_* */
   int32_t reorder_every;  /* steps between re-sorts of the internal particle order along a
                              Z-order curve (memory locality only; results do not depend on
-                             it); 0 -> 8, < 0 -> never */
+                             it); 0 -> 32 below 2^19 particles, else 16; < 0 -> never */
   int32_t tile_max_cells; /* detection tile limit in cells (item box + halo); 0 -> from the
                              node size (box + one-cell halo + one cell of drift) */
   int32_t tile_max_stage; /* detection tile limit in staged particles; 0 -> from the cells

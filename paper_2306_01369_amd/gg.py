@@ -311,6 +311,11 @@ class Sim:
         self._grids = list(grids)
 
     def step(self, n_steps=1, twists=None):
+        if twists is not None:
+            size = int(twists.numel()) if _is_torch(twists) else int(np.asarray(twists).size)
+            if size != int(n_steps) * self.n_bodies * 6:
+                raise ValueError(f"twists must hold n_steps x n_bodies x 6 = {int(n_steps)} x {self.n_bodies} x 6 "
+                                 f"values, got {size}")
         pt, wt, kt = _arg(twists, np.float32)
         self.last_steps = int(n_steps)
         _check(lib().gg_step(self._h, int(n_steps), pt, wt))
