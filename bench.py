@@ -41,10 +41,15 @@ def pja_algorithmic_bytes(n, contacts):
 
 
 def kernel_source_hash():
+    """Hash of what sets k_pja's memory traffic: the kernel sources and the
+    host function that launches the sweeps (its grid and arguments)."""
     h = hashlib.sha256()
-    for rel in ("paper_2306_01369_amd/csrc/kernels.hip.h", "paper_2306_01369_amd/csrc/gg.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/kernels.hip.h"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/gg.hip"), "rb") as f:
+        host = f.read()
+    a = host.index(b"void launch_sweeps(")
+    h.update(host[a:host.index(b"\n}\n", a)])
     return h.hexdigest()[:16]
 
 
