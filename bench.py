@@ -565,11 +565,6 @@ def bench_large(args):
         "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
                                             "detect_workgroups", "reorder_every", "pja_lanes")},
     }
-    if traffic:
-        # measured HBM bytes per sweep (rocprofv3 counters) over the live sweep duration
-        gbs = traffic / (pja_ms * 1e-3) / 1e9
-        out["hbm_measured"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                               "bytes_per_launch": traffic}
 
 
 def main():
@@ -662,8 +657,13 @@ def main():
         "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
                                "integrate": st["ms_integrate"] / steps},
         "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
-                                            "detect_workgroups", "reorder_every")},
+                                            "detect_workgroups", "reorder_every", "pja_lanes")},
     }
+    if traffic:
+        # measured HBM bytes per sweep (rocprofv3 counters) over the live sweep duration
+        gbs = traffic / (pja_ms * 1e-3) / 1e9
+        out["hbm_measured"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                               "bytes_per_launch": traffic}
     sim.close()
     if not args.skip_cpu_baseline:
         log(f"oracle on the host cores: {args.cpu_steps} steps")
