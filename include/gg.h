@@ -236,7 +236,10 @@ enum {
   GG_FIELD_STATS = 5,      /* one gg_stats */
   GG_FIELD_DV = 6,         /* n x 3 float32: velocity change by impulses in the last
                               step (needs GG_FLAG_DIAGNOSTICS) */
-  GG_FIELD_RADIUS = 7      /* n float32 */
+  GG_FIELD_RADIUS = 7,     /* n float32 */
+  GG_FIELD_BODY_POSES = 8  /* n_bodies x 12 float32: each body's pose at the start of the next
+                              step, row-major [R | t] (body -> world), in gg_set_bodies order,
+                              as the library advanced it (double, rounded once) */
 };
 
 typedef struct {

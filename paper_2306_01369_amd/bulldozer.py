@@ -186,8 +186,10 @@ class BulldozerEnv:
             view = buf.reshape(self.n_envs, per)
         ego = view[:, :self.ego_px].reshape(self.n_envs, self.ego_size[1], self.ego_size[0])
         sky = view[:, self.ego_px:].reshape(self.n_envs, self.sky_size[1], self.sky_size[0])
-        pose = self.state.copy()
-        pose[:, :2] -= self.corners
+        # the blade's planar pose as the library advanced it
+        P = self.sim.read("body_poses")[self.blade_index].astype(np.float64)
+        pose = np.stack([P[:, 0, 3] - self.corners[:, 0], P[:, 1, 3] - self.corners[:, 1],
+                         np.arctan2(P[:, 1, 0], P[:, 0, 0])], axis=1)
         return {"ego": ego, "sky": sky, "pose": pose}
 
     def step(self, actions):

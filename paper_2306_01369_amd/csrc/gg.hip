@@ -1701,6 +1701,7 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
     case GG_FIELD_CONTACTS: need = 8 * C; break;
     case GG_FIELD_IMPULSES: need = 12 * C; break;
     case GG_FIELD_STATS: need = sizeof(gg_stats); break;
+    case GG_FIELD_BODY_POSES: need = 48 * (int64_t)s->bodies.size(); break;
     default: return fail(GG_ERR_INVALID, "unknown field");
   }
   if (field == GG_FIELD_DV && !s->dv) return fail(GG_ERR_INVALID, "GG_FIELD_DV needs GG_FLAG_DIAGNOSTICS at creation");
@@ -1716,6 +1717,19 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
     } else {
       HIPCHK(s, hipMemcpy(dst, &s->stats, sizeof(gg_stats), hipMemcpyHostToDevice));
     }
+    return GG_OK;
+  }
+  if (field == GG_FIELD_BODY_POSES) {
+    std::vector<float> poses(12 * s->bodies.size());
+    for (size_t b = 0; b < s->bodies.size(); ++b)
+      for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) poses[12 * b + 4 * r + c] = (float)s->bodies[b].R[3 * r + c];
+        poses[12 * b + 4 * r + 3] = (float)s->bodies[b].t[r];
+      }
+    if (where == GG_MEM_HOST)
+      std::memcpy(dst, poses.data(), (size_t)need);
+    else
+      HIPCHK(s, hipMemcpy(dst, poses.data(), (size_t)need, hipMemcpyHostToDevice));
     return GG_OK;
   }
   const int blocks = (int)((n + 255) / 256);

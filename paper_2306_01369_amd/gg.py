@@ -21,7 +21,7 @@ GG_OK, GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP, GG_ERR_CAPACITY, GG_ERR_NONFINITE
 GG_MEM_HOST, GG_MEM_DEVICE = 0, 1
 GG_FLAG_PROFILE, GG_FLAG_DIAGNOSTICS, GG_FLAG_TAPE, GG_FLAG_GRAPH, GG_FLAG_FUSED = 1, 2, 4, 8, 16
 FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "stats": 5, "dv": 6,
-         "radius": 7}
+         "radius": 7, "body_poses": 8}
 SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
 
 EXPORTS = ("gg_create", "gg_set_bodies", "gg_set_grids", "gg_step", "gg_step_backward", "gg_read",
@@ -341,7 +341,7 @@ class Sim:
             return s.as_dict()
         dtype, cols = {"pos": (np.float32, 3), "vel": (np.float32, 3), "dv": (np.float32, 3),
                        "radius": (np.float32, 0), "cell_index": (np.int64, 0), "contacts": (np.int32, 2),
-                       "impulses": (np.float32, 3)}[field]
+                       "impulses": (np.float32, 3), "body_poses": (np.float32, 12)}[field]
         item = np.dtype(dtype).itemsize * max(cols, 1)
         rows = nbytes // item
         arr = np.empty((rows, cols) if cols else (rows,), dtype)
@@ -349,6 +349,8 @@ class Sim:
         if nbytes:
             _check(lib().gg_read(self._h, FIELD[field], arr.ctypes.data_as(C.c_void_p), nbytes, C.byref(w),
                                  GG_MEM_HOST))
+        if field == "body_poses":
+            return arr.reshape(-1, 3, 4)
         return arr
 
     def stats(self):

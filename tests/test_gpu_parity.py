@@ -734,3 +734,32 @@ def test_cyclic_boundary_over_steps_follows_the_oracle():
     x = sim.read("pos")
     assert np.abs(x - orc.x).max() <= 2e-8
     assert np.sum(orc.x[:, 2] > s.x[:, 2] + 0.1) > 10      # grains that crossed the bottom re-entered at the top
+
+
+def test_body_poses_follow_the_twists():
+    # the library advances poses in double (t += dt nu, R = Exp(dt [omega]x) R)
+    # and reports them rounded once; the oracle's advance from the same binary32
+    # pose, twists and step is the reference
+    s = scenes.column_scene(n=500, r=0.004)
+    Rm = scenes.random_rotation(np.random.default_rng(3))
+    bodies = s.bodies + [scenes.capsule_tool((0.2, 0.2, 0.3), 0.02, 0.05, R=Rm)]
+    sim = gg.Sim(s.x, s.v, s.radius, bodies)
+    nb = len(bodies)
+    rng = np.random.default_rng(1)
+    tw = np.zeros((25, nb, 6), np.float32)
+    tw[:, -1, :] = rng.uniform(-1, 1, (25, 6)).astype(np.float32)
+    sim.step(25, twists=tw)
+    got = sim.read("body_poses")
+    assert got.shape == (nb, 3, 4)
+    B = O.bodies_to_f32_pose(O.make_bodies(bodies), nb)
+    lib = O.lib()
+    dt = float(np.float32(1e-3))
+    for k in range(25):
+        for q in range(3):
+            B[nb - 1].nu[q] = float(tw[k, -1, q])
+            B[nb - 1].omega[q] = float(tw[k, -1, 3 + q])
+        lib.ggo_advance_bodies(nb, B, dt)
+    want = np.array([[[B[b].R[3 * r + c] for c in range(3)] + [B[b].t[r]] for r in range(3)] for b in range(nb)])
+    say("body poses: max |diff|", float(np.abs(got - want).max()))
+    assert np.abs(got - want).max() <= 1e-6
+    assert np.array_equal(got[:-1], want[:-1].astype(np.float32))   # planes stay put
