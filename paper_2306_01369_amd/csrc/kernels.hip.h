@@ -12,6 +12,7 @@
 //              tests (Sec. II-B, II-C, Eq. (7)); writes each particle's partners
 //   k_pja      one projected-Jacobi sweep (Alg. 1) over all contacts, gathered
 //              per particle; the last sweep also writes the new velocity
+//              (k_pja_lanes: the same with 2 or 4 lanes per particle)
 //   k_integrate  positions from the new velocities (Eq. (5))
 //
 // Precision.  Every state-carrying kernel is a template over the real type R:
@@ -22,8 +23,8 @@
 //
 // Layout.  Particle state is structure-of-arrays float4: x = (x, y, z, r),
 // v = (vx, vy, vz, 1/m), w = (wx, wy, wz, s) with s = n_i/m_i (the split inverse
-// mass), and orig = the caller's index of each (internally reordered)
-// particle.  Every contact is stored once per member ("half contacts") in an
+// mass), orig = the caller's index of each (internally reordered) particle,
+// and 1/m alone for the sweeps.  Every contact is stored once per member ("half contacts") in an
 // ELL table of K slots per particle, laid out slot-major within groups of 64
 // particles: slot(i, k) = (i/64)*64K + 64k + i%64, so the k-th contact of the 64
 // lanes of a wavefront is one contiguous 256-byte row.  Each half contact holds
