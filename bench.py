@@ -40,16 +40,25 @@ def pja_algorithmic_bytes(n, contacts):
     return 64.0 * contacts + 32.0 * n
 
 
+def _code_only(text):
+    """Source text without // comments and without blank space (comment and
+    layout edits do not change the code the counters were taken on)."""
+    import re
+    text = re.sub(r"//[^\n]*", "", text)
+    return re.sub(r"\s+", "", text)
+
+
 def kernel_source_hash():
     """Hash of what sets k_pja's memory traffic: the kernel sources and the
-    host function that launches the sweeps (its grid and arguments)."""
+    host function that launches the sweeps (its grid and arguments), code
+    only."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/kernels.hip.h"), "rb") as f:
-        h.update(f.read())
-    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/gg.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/kernels.hip.h")) as f:
+        h.update(_code_only(f.read()).encode())
+    with open(os.path.join(ROOT, "paper_2306_01369_amd/csrc/gg.hip")) as f:
         host = f.read()
-    a = host.index(b"void launch_sweeps(")
-    h.update(host[a:host.index(b"\n}\n", a)])
+    a = host.index("void launch_sweeps(")
+    h.update(_code_only(host[a:host.index("\n}\n", a)]).encode())
     return h.hexdigest()[:16]
 
 
