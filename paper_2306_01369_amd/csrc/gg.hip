@@ -250,6 +250,7 @@ struct gg_sim {
   int rs_nb = 0, rs_passes = 0;
   int det_grid = 2048;  // detection workgroups: what the device holds at once (occupancy API)
   int fused_grid = 0;   // GG_FLAG_FUSED: workgroups of the cooperative step kernel (all resident)
+  bool small_table = false;  // bucket table built by one workgroup (k_bucket_small)
   void* xs = nullptr;                                  // bucket-ordered positions
   int32_t* os = nullptr;                               // bucket-ordered original indices
   int32_t *it_f = nullptr, *it_e = nullptr, *it_first = nullptr, *it_g = nullptr, *it_h = nullptr;
@@ -579,13 +580,20 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   const int nh1 = s->env_nh[0];
   const int blk1 = s->env_tblk[0];
   hipStream_t S = s->stream;
-  ggk::k_key<R><<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, blk1, et, s->h, s->h6, s->rank, s->counts,
-                                             s->ctl, st);
-  ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
-  ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
-  ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
-  ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
-                                                 s->os);
+  if (s->small_table) {
+    // small bed: keys, scan and scatter in one workgroup (counters in LDS)
+    ggk::k_bucket_small<R><<<1, ggk::kSmallBlock, (size_t)(m + 1) * 4, S>>>(
+        n, m, io.x, s->inv_c, nh1, blk1, et, s->h, s->h6, s->rank, s->bstart, s->orig, s->sidx, (V*)s->xs, s->os,
+        s->ctl, st);
+  } else {
+    ggk::k_key<R><<<grid, ggk::kBlock, 0, S>>>(n, io.x, s->inv_c, nh1, blk1, et, s->h, s->h6, s->rank, s->counts,
+                                               s->ctl, st);
+    ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
+    ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
+    ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
+    ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
+                                                   s->os);
+  }
   if (!with_detect) return;
   switch (s->p.tile_threads) {
     case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et); break;
@@ -1067,6 +1075,12 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (oe == hipSuccess) oe = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->dev);
     if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "occupancy query"));
     s->det_grid = std::max(1, per_cu * n_cu);
+    // small tables: counters of every bucket in one workgroup's LDS
+    int max_lds = 0;
+    oe = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->dev);
+    if (oe != hipSuccess) return bail(hip_fail(nullptr, oe, "LDS size query"));
+    const int64_t need_lds = (s->n_buckets + 1) * 4 + 256;
+    s->small_table = s->n_buckets <= ggk::kSmallBuckets && need_lds <= max_lds;
     if (s->p.flags & GG_FLAG_FUSED) {
       int coop = 0;
       oe = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->dev);
