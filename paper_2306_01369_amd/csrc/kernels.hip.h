@@ -110,6 +110,7 @@ struct Ctl {                    // device control block, one per simulation
   unsigned long long summed;    // contacts summed over the steps of the current call
   int32_t fallback;             // detection work items that took the per-particle path (last detection)
   int32_t items;                // detection work items (set when they are built)
+  int32_t next_item[8];         // detection work queues, one per XCD (zeroed by the key kernels)
 };
 
 struct EnvTables {   // per-environment tables (batched form)
@@ -603,6 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__
   if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->err == 0) {
     ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0; ctl->fallback = 0;
   }
+  if (blockIdx.x == 0 && threadIdx.x < 8) ctl->next_item[threadIdx.x] = 0;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   const float4 p = f32of(x[i]);
@@ -678,6 +680,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_bucket_small(
   if (tid == 0 && ctl->err == 0) {
     ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0; ctl->fallback = 0;
   }
+  if (tid < 8) ctl->next_item[tid] = 0;
   for (int e = tid; e <= m; e += kSmallBlock) cnt[e] = 0;
   __syncthreads();
   // cell keys (as k_key); arrival rank within the bucket from an LDS atomic
@@ -908,7 +911,14 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // inverse mass s_i = n_i / m_i.
 // (five waves per SIMD: the tile's LDS allows five workgroups per CU, and the
 // register budget that fits costs only a few bytes of spill)
-// (the work of workgroup `blk` of `nblk`; k_detect and the fused step call it)
+// Work distribution: with `queue` set, the items are cut into one contiguous
+// range per XCD (workgroup b runs on XCD b mod 8), and the workgroups of an
+// XCD take the items of its range one at a time from a counter
+// (Ctl::next_item, zeroed by the key kernels of the step), so no workgroup
+// idles while another still holds several items; without it, workgroup `blk`
+// of `nblk` takes a fixed contiguous share.  Either way each item's results
+// depend only on its particles.
+// (k_detect and the fused step call it)
 template <typename R, int TB>
 __device__ __forceinline__ void detect_items(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v, const int32_t* __restrict__ orig,
@@ -917,10 +927,11 @@ __device__ __forceinline__ void detect_items(
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step, int blk, int nblk) {
+    int step, int blk, int nblk, bool queue) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[TB / 64][8];
   __shared__ int red[TB / 64];
+  __shared__ int grabbed;
   int* cell_off = (int*)smem;                                  // max_cells + 1
   int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
   V4<R>* st_x = (V4<R>*)(smem + ((((2 * max_cells + 1) * 4) + 31) & ~31));  // max_stage
@@ -928,12 +939,32 @@ __device__ __forceinline__ void detect_items(
   int* st_o = st_j + max_stage;                                // max_stage
 
   const int n_items = *n_items_ptr;
-  const int per = (n_items + nblk - 1) / nblk;
-  const int it0 = min(blk * per, n_items), it1 = min(it0 + per, n_items);
+  int it0, it1, qx = 0;
+  if (queue) {
+    const int nq = min(8, nblk);   // every queue has a workgroup (b = qx)
+    qx = (int)(blockIdx.x % (unsigned)nq);
+    it0 = (int)((int64_t)qx * n_items / nq);
+    it1 = (int)((int64_t)(qx + 1) * n_items / nq);
+  } else {
+    const int per = (n_items + nblk - 1) / nblk;
+    it0 = min(blk * per, n_items);
+    it1 = min(it0 + per, n_items);
+  }
   int cand = 0, npp = 0, npb = 0, mx = 0, fb = 0;
   const int BIG = 0x3fffffff;
+  // (thread 0 takes the next item while the workgroup works on the current one)
+  int ahead = (queue && threadIdx.x == 0) ? atomicAdd(&ctl->next_item[qx], 1) : 0;
 
-  for (int item = it0; item < it1; ++item) {
+  for (int item = it0;; ++item) {
+    if (queue) {
+      // the same item for the whole workgroup; the last barrier of the
+      // previous item orders this write after every read of `grabbed`
+      if (threadIdx.x == 0) grabbed = it0 + ahead;
+      __syncthreads();
+      item = grabbed;
+      if (threadIdx.x == 0 && item < it1) ahead = atomicAdd(&ctl->next_item[qx], 1);
+    }
+    if (item >= it1) break;
     const int i = item_start[item] + threadIdx.x;
     const bool active = i < item_start[item + 1];
     const V4<R> p = active ? x[i] : mk4<R>(R(0), R(0), R(0), R(0));
@@ -1116,11 +1147,16 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step) {
-  if (ctl->err) return;
+    int step, int queue) {
+  // the error word is read once per workgroup: every wave of it takes the
+  // same branch (the work queue needs all of them)
+  __shared__ int err0;
+  if (threadIdx.x == 0) err0 = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (err0) return;
   detect_items<R, TB>(n, K, x, v, orig, inv_c, n_blk, env, start, sidx, xs, os, item_start, n_items_ptr, bodies,
                       n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, imass, ctl,
-                      step, xcd_block(), gridDim.x);
+                      step, xcd_block(), gridDim.x, queue != 0);
 }
 
 // ------------------------------------------------------ projected Jacobi
