@@ -521,7 +521,8 @@ void launch_reorder(gg_sim* s) {
   const int rs_m = 256 * s->rs_nb;
   const int rs_nbs = (rs_m + ggk::kScanTile - 1) / ggk::kScanTile;
   hipStream_t S = s->stream;
-  ggk::k_morton_keys<R><<<grid, ggk::kBlock, 0, S>>>(n, (const V*)s->x, s->inv_c, s->env_of, s->mk[0]);
+  ggk::k_morton_keys<R><<<grid, ggk::kBlock, 0, S>>>(n, (const V*)s->x, s->inv_c, s->env_of, s->ncon,
+                                                     s->p.tile_node_shift, s->mk[0]);
   for (int pass = 0; pass < s->rs_passes; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
@@ -538,7 +539,7 @@ void launch_reorder(gg_sim* s) {
   std::swap(s->orig, s->orig2);
   const unsigned long long* keys = s->mk[s->rs_passes & 1];
   const int it_nbs = (n + ggk::kScanTile - 1) / ggk::kScanTile;
-  ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift, s->it_f);
+  ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift + ggk::kCountBits, s->it_f);
   ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_bsum, 0);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
   ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
@@ -937,8 +938,8 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (s->p.reorder_every == 0) s->p.reorder_every = n < (1 << 19) ? 32 : 16;
   default_tile(n, particles_per_cell(hx, n, inv_c), s->p);
   {
-    int bits = 30;
-    while ((1 << (bits - 30)) < n_envs) ++bits;
+    int bits = 30 + ggk::kCountBits;
+    while ((1 << (bits - 30 - ggk::kCountBits)) < n_envs) ++bits;
     s->rs_passes = (bits + ggk::kRsBits - 1) / ggk::kRsBits;
     s->rs_nb = (int)((n + ggk::kRsItems - 1) / ggk::kRsItems);
   }
@@ -1043,6 +1044,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   }
   if (e == hipSuccess) e = hipMemset(s->counts, 0, (size_t)total_tab * 4);
   if (e == hipSuccess) e = hipMemset(s->ctl, 0, sizeof(ggk::Ctl));
+  if (e == hipSuccess) e = hipMemset(s->ncon, 0, N * 4);   // (the first re-sort's contact counts)
   if (e == hipSuccess && n > 0) {
     ggk::k_iota<<<(int)((n + 255) / 256), 256>>>((int)n, s->orig);
     ggk::k_item_fixed<<<(int)((n + 255) / 256), 256>>>((int)n, s->p.tile_threads, s->item_start, &s->ctl->items);

@@ -459,7 +459,12 @@ __global__ void k_begin(Ctl* ctl) {
 // workgroup's particles occupy a compact block of cells and their neighbours
 // sit nearby in memory.  Keys: environment in the high bits, then the Morton
 // code of the low 10 bits of each cell coordinate (wrap-around only costs
-// locality, never correctness).
+// locality, never correctness), its node part (all but the low `sh` bits)
+// above and its within-node part below 8 bits that order the particles of a
+// node by descending contact count at the last detection.  Within a
+// wavefront, the particles that still have a k-th contact then sit side by
+// side, so row k of the contact table is read and written as one run instead
+// of scattered lanes (bytes move in whole 64-byte segments).
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   v &= 1023u;
@@ -493,18 +498,23 @@ __device__ __forceinline__ int table_bucket(int k0, int k1, int k2, int n_blk) {
   return (int)(blk * 64u + (m & 63u));
 }
 
+constexpr int kCountBits = 8;
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_morton_keys(int n, const V4<R>* __restrict__ x, float inv_c,
                                                         const int32_t* __restrict__ env_of,
+                                                        const int32_t* __restrict__ ncon, int sh,
                                                         unsigned long long* __restrict__ keys) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float4 p = f32of(x[i]);
   bool ok = true;
   const int k0 = cell_coord(p.x, inv_c, ok), k1 = cell_coord(p.y, inv_c, ok), k2 = cell_coord(p.z, inv_c, ok);
-  const uint32_t m = morton_cell(k0, k1, k2);
+  const unsigned long long m = morton_cell(k0, k1, k2);
   const unsigned long long e = env_of ? (unsigned long long)env_of[i] : 0ull;
-  keys[i] = (e << 30) | (unsigned long long)m;
+  const unsigned long long c = (unsigned long long)(255 - min(max(ncon[i], 0), 255));
+  const unsigned long long low = (1ull << sh) - 1;
+  keys[i] = (e << (30 + kCountBits)) | ((m & ~low) << kCountBits) | (c << sh) | (m & low);
 }
 
 // LSD radix sort, 8-bit digits, stable.  Each block owns kRsItems consecutive
