@@ -569,6 +569,31 @@ def test_graph_replay_multi_env():
         assert _bits(graphed) == _bits(direct), f"call {k}"
 
 
+def test_batched_environments_equal_separate_simulations():
+    # each environment of a batch, stepped on its own (one environment, its
+    # own bodies and twists), gives the same bits: the batched form adds no
+    # arithmetic, and its detection (work queues per XCD) and the single
+    # bed's (fixed contiguous shares) only distribute the same work items
+    sc = scenes.batched_scene(n_envs=3, lo=2000, hi=6000, n_steps=12)
+    off = sc.env_offsets
+    kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters)
+    say("batched vs separate", np.diff(off).tolist())
+    batch = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, env_offsets=off, **kw)
+    batch.step(12, twists=sc.twists)
+    xb, vb = batch.read("pos"), batch.read("vel")
+    batch.close()
+    env_of_body = np.array([b.get("env", 0) for b in sc.bodies])
+    for e in range(len(off) - 1):
+        sl = slice(int(off[e]), int(off[e + 1]))
+        idx = np.nonzero(env_of_body == e)[0]
+        bodies = [dict(sc.bodies[b], env=0) for b in idx]
+        one = gg.Sim(sc.x[sl], sc.v[sl], sc.radius[sl], bodies, **kw)
+        one.step(12, twists=np.ascontiguousarray(sc.twists[:, idx]))
+        assert np.array_equal(one.read("pos"), xb[sl]), e
+        assert np.array_equal(one.read("vel"), vb[sl]), e
+        one.close()
+
+
 def test_hash_table_size_changes_no_result():
     # partners are listed by (neighbour cell, original index), never by bucket,
     # so n_h (and with it bucket aliasing) changes only speed: outputs and the
