@@ -1258,6 +1258,7 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
         hipHostMalloc((void**)&s->h_bodies, (size_t)need * sizeof(ggk::DevBody), hipHostMallocDefault) != hipSuccess)
       return fail(GG_ERR_OOM, "body staging allocation failed");
     s->d_bodies_cap = need;
+    ++s->epoch;   // captured launches name the old staging buffer
   }
   s->pose_hist.resize((size_t)(n_steps + 1) * nb);
   std::vector<HostBody> cur = s->bodies;

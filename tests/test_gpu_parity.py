@@ -549,6 +549,26 @@ def test_graph_replay_matches_direct_launches():
     assert float(junk[0]) == len(calls)
 
 
+def test_graph_replay_after_the_pose_staging_grows():
+    # a longer call reallocates the per-step body records; a later short call
+    # must not replay a launch captured before that (it would read the old
+    # records): without re-sorts every call has the same re-sort phase and
+    # buffer parity, so only the allocation epoch tells the captures apart
+    s = scenes.column_scene(n=2000, r=0.004)
+    top = float(s.x[:, 2].max())
+    tool = scenes.box_tool((0.03, 0.03, top + 0.004), (0.01, 0.01, 0.01))
+    bodies = s.bodies + [tool]
+    say("graph replay after staging growth")
+    direct = gg.Sim(s.x, s.v, s.radius, bodies, reorder_every=-1)
+    graphed = gg.Sim(s.x, s.v, s.radius, bodies, reorder_every=-1, graph=True)
+    for k, steps in enumerate((1, 4, 1, 1)):
+        tw = np.zeros((steps, len(bodies), 6), np.float32)
+        tw[:, -1, 2] = -0.3 - 0.1 * k
+        direct.step(steps, twists=tw)
+        graphed.step(steps, twists=tw)
+        assert _bits(graphed) == _bits(direct), f"call {k}"
+
+
 def test_graph_replay_multi_env():
     rng = np.random.default_rng(5)
     counts = [500, 0, 1200, 64]
