@@ -938,8 +938,10 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   if (s->p.reorder_every == 0) s->p.reorder_every = n < (1 << 19) ? 32 : 16;
   default_tile(n, particles_per_cell(hx, n, inv_c), s->p);
   {
+    // (keys are 64 bits: beyond 2^26 environments the environment's high bits
+    // fall off, which only costs locality)
     int bits = 30 + ggk::kCountBits;
-    while ((1 << (bits - 30 - ggk::kCountBits)) < n_envs) ++bits;
+    while (bits < 64 && (int64_t{1} << (bits - 30 - ggk::kCountBits)) < (int64_t)n_envs) ++bits;
     s->rs_passes = (bits + ggk::kRsBits - 1) / ggk::kRsBits;
     s->rs_nb = (int)((n + ggk::kRsItems - 1) / ggk::kRsItems);
   }
