@@ -572,7 +572,8 @@ def bench_large(args):
         "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps},
         "detect_fallback_items": st["detect_fallback"], "detect_items": st["detect_items"],
         "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
-                                            "detect_workgroups", "reorder_every", "pja_lanes")},
+                                            "detect_workgroups", "reorder_every", "pja_lanes",
+                                            "detect_queues")},
     }
 
 
@@ -666,7 +667,8 @@ def main():
         "phases_ms_per_step": {"keys_sort_detect": st["ms_detect"] / steps, "pja": st["ms_pja"] / steps,
                                "integrate": st["ms_integrate"] / steps},
         "launch_shape": {k: st[k] for k in ("tile_threads", "tile_node_shift", "tile_max_cells", "tile_max_stage",
-                                            "detect_workgroups", "reorder_every", "pja_lanes")},
+                                            "detect_workgroups", "reorder_every", "pja_lanes",
+                                            "detect_queues")},
     }
     if traffic:
         # measured HBM bytes per sweep (rocprofv3 counters) over the live sweep duration

@@ -1119,6 +1119,7 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->stats.detect_workgroups = s->det_grid;
   s->stats.reorder_every = s->p.reorder_every;
   s->stats.pja_lanes = s->p.pja_lanes;
+  s->stats.detect_queues = s->det_queue ? 1 : 0;
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
   sample_memory(s);

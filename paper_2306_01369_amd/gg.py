@@ -97,7 +97,7 @@ class Stats(C.Structure):
                 ("detect_items", C.c_int64), ("device_bytes_peak", C.c_int64),
                 ("tile_threads", C.c_int32), ("tile_node_shift", C.c_int32), ("tile_max_cells", C.c_int32),
                 ("tile_max_stage", C.c_int32), ("detect_workgroups", C.c_int32), ("reorder_every", C.c_int32),
-                ("pja_lanes", C.c_int32), ("pad0", C.c_int32)]
+                ("pja_lanes", C.c_int32), ("detect_queues", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

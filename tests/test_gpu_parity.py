@@ -601,6 +601,7 @@ def test_batched_environments_equal_separate_simulations():
     batch = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, env_offsets=off, **kw)
     batch.step(12, twists=sc.twists)
     xb, vb = batch.read("pos"), batch.read("vel")
+    assert batch.stats()["detect_queues"] == 1
     batch.close()
     env_of_body = np.array([b.get("env", 0) for b in sc.bodies])
     for e in range(len(off) - 1):
@@ -609,6 +610,7 @@ def test_batched_environments_equal_separate_simulations():
         bodies = [dict(sc.bodies[b], env=0) for b in idx]
         one = gg.Sim(sc.x[sl], sc.v[sl], sc.radius[sl], bodies, **kw)
         one.step(12, twists=np.ascontiguousarray(sc.twists[:, idx]))
+        assert one.stats()["detect_queues"] == 0
         assert np.array_equal(one.read("pos"), xb[sl]), e
         assert np.array_equal(one.read("vel"), vb[sl]), e
         one.close()
