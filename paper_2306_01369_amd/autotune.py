@@ -7,8 +7,11 @@ detection tile (``tile_max_cells``, ``tile_max_stage``), the interval between
 spatial re-sorts (``reorder_every``), the lanes per particle of the sweeps
 (``pja_lanes``), the iteration blocking (one launch per sweep, or the fused
 cooperative step, ``fused``) and then the hash-table size n_h (Eq. (6); Sec.
-II-B's heuristic is n_h = 2 n), by timing a few steps of each candidate
-through the C ABI.  These parameters change only memory layout, bucket
+II-B's heuristic is n_h = 2 n), by timing each candidate through the C ABI
+over a window that spans at least one re-sort.  The library's own defaults
+are the first candidate, and another replaces the best so far only when it is
+faster by a margin (2% by default), so timing noise does not trade a good
+default for a worse shape.  These parameters change only memory layout, bucket
 aliasing and work decomposition: partners are listed by (neighbour cell,
 original index), never by bucket, and impulse sums keep list order, so every
 output is bitwise identical across them (the GPU tests check this; the fused
@@ -60,7 +63,8 @@ def candidates(ppc):
     """Launch shapes worth timing for ppc particles per occupied cell: for each
     workgroup size (64, 128, 256 threads), nodes holding roughly 0.3 to 1.4
     workgroups of particles, an LDS budget for the node's box plus a one-cell
-    halo and one cell of drift, and three re-sort intervals."""
+    halo and one cell of drift, and three re-sort intervals.  (The library's
+    defaults are timed before these.)"""
     out = []
     for tb in (64, 128, 256):
         for shift in range(2, 10):
@@ -72,7 +76,7 @@ def candidates(ppc):
             stage = int(math.ceil(cells * (ppc + 0.6) * 1.1))
             if stage > 2048 or cells > 4096:
                 continue
-            for reorder in (4, 8, 16):
+            for reorder in (8, 16, 32):
                 out.append({"tile_node_shift": shift, "tile_max_cells": cells, "tile_max_stage": stage,
                             "tile_threads": tb, "reorder_every": reorder})
     return out
@@ -103,8 +107,8 @@ def cell_factors():
     return (1.0, 1.125, 1.25)
 
 
-def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=True, verbose=False,
-         tune_cell=False):
+def tune(x, v, radius, bodies, sim_kwargs=None, steps=32, warmup=8, use_cache=True, verbose=False,
+         tune_cell=False, margin=0.02):
     """Return the fastest launch-shape parameters for this workload (a dict of
     gg.Sim keyword arguments).  With tune_cell the cell size is tuned too:
     a larger cell changes which cell, and so which list position, a partner
@@ -146,31 +150,34 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             print(f"autotune: {cand} -> {1e3 * t:.3f} ms/step, fallback items {st['detect_fallback']}")
         return t
 
-    best, best_t = None, float("inf")
+    best, best_t = {}, timed({})     # the library's defaults
+    if best_t is None:
+        best_t = float("inf")
+
+    def better(t):
+        return t is not None and t < best_t * (1.0 - margin)
     for cand in candidates(ppc):
         t = timed(cand)
-        if t is not None and t < best_t:
+        if better(t):
             best, best_t = cand, t
-    if best is None:
-        return {}
     # then the lanes per particle of the sweeps, the iteration blocking (one
     # launch per sweep, or detection and all sweeps in one cooperative launch
     # with grid barriers), and the table size
     for lanes in lane_counts():
         cand = dict(best, pja_lanes=lanes)
         t = timed(cand)
-        if t is not None and t < best_t:
+        if better(t):
             best, best_t = cand, t
     if not sim_kwargs.get("differentiable"):
         cand = dict(best, fused=True)
         t = timed(cand)
-        if t is not None and t < best_t:
+        if better(t):
             best, best_t = cand, t
     n = len(x)
     for factor in hash_factors():
         cand = dict(best, hash_size=max(1, int(factor * n)))
         t = timed(cand)
-        if t is not None and t < best_t:
+        if better(t):
             best, best_t = cand, t
     if tune_cell:
         c0 = 2.0 * float(np.max(radius)) * (1.0 + 2.0 ** -10)
@@ -179,7 +186,7 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=6, warmup=2, use_cache=Tru
             cand = dict(best, cell_size=c0 * factor,
                         tile_max_stage=min(2048, int(best.get("tile_max_stage", 768) * factor ** 3) + 1))
             t = timed(cand)
-            if t is not None and t < best_t:
+            if better(t):
                 best, best_t = cand, t
     if use_cache:
         cache[key] = {"params": best, "ms_per_step": 1e3 * best_t}

@@ -494,20 +494,22 @@ def test_autotuned_launch_shape_keeps_results_bitwise(tmp_path, monkeypatch):
     s = scenes.column_scene(n=6000, r=0.004)
     say("autotune")
     params = autotune.tune(s.x, s.v, s.radius, s.bodies, steps=2, warmup=1)
-    assert "tile_node_shift" in params
     again = autotune.tune(s.x, s.v, s.radius, s.bodies)      # from the cache
     assert again == params
     say("tuned", params)
     ref, _ = _run_bits(s, 15)
-    got, st = _run_bits(s, 15, **params)
-    if params.get("fused"):            # the fused step agrees to rounding
-        pos_r = np.frombuffer(ref[0], np.float32)
-        pos_g = np.frombuffer(got[0], np.float32)
-        assert np.abs(pos_r - pos_g).max() <= 1e-6
-        return
-    assert got[:4] == ref[:4]          # the bucket ids differ when n_h was tuned
-    if "hash_size" not in params:
-        assert got == ref
+    # the tuned shape (the defaults when none beat them) and a candidate shape
+    cand = autotune.candidates(autotune.particles_per_cell(s.x, s.radius))[0]
+    for shape in (params, cand):
+        got, st = _run_bits(s, 15, **shape)
+        if shape.get("fused"):             # the fused step agrees to rounding
+            pos_r = np.frombuffer(ref[0], np.float32)
+            pos_g = np.frombuffer(got[0], np.float32)
+            assert np.abs(pos_r - pos_g).max() <= 1e-6
+            continue
+        assert got[:4] == ref[:4], shape   # the bucket ids differ when n_h was tuned
+        if "hash_size" not in shape:
+            assert got == ref, shape
 
 
 # ------------------------------------------------- graph replay, hash size
