@@ -141,7 +141,8 @@ typedef struct {
   int32_t reorder_every;  /* steps between re-sorts of the internal particle order along a
                              Z-order curve, each node's particles by descending contact
                              count (memory locality only; results do not depend on it);
-                             0 -> 32 below 2^19 particles, else 16; < 0 -> never */
+                             0 -> 32 below 2^19 particles, else 16 (4 when the
+                             largest radius exceeds 1.25x the smallest); < 0 -> never */
   int32_t tile_max_cells; /* detection tile limit in cells (item box + halo); 0 -> from the
                              node size (box + one-cell halo + one cell of drift) */
   int32_t tile_max_stage; /* detection tile limit in staged particles; 0 -> from the cells
