@@ -8,8 +8,10 @@
 // contact geometry (normals, gaps, body point velocities) differentiated with
 // respect to positions, body poses and twists (SDF gradients and Hessians).
 //
-// Recorded impulses and the adjoint's per-contact state are indexed compactly,
-// pofs[i] + k with pofs the prefix sum of the contact counts.
+// Recorded impulses are indexed compactly, pofs[i] + k with pofs the prefix
+// sum of the contact counts; the adjoint's per-contact state, read and written
+// in every reverse sweep, like the contact table (slot-major per 64
+// particles), so that a wavefront's loads of it are whole rows.
 // Per half contact the adjoint keeps a carry (the adjoint of the impulse of the
 // previous sweep, identical bits in both halves of a pair, as the forward's
 // impulse copies) and accumulators of the adjoints of the normal, the gap and
@@ -22,7 +24,7 @@
 namespace ggk {
 
 template <typename R>
-struct AdjSlots {         // per half-contact adjoint state (SoA)
+struct AdjSlots {         // per half-contact adjoint state (SoA), indexed like the contact table
   R *cx, *cy, *cz;    // carry: adjoint of the impulse of the previous sweep
   R *nx, *ny, *nz;    // accumulated adjoint of the contact normal (lower-index orientation)
   R *ps;              // accumulated adjoint of the gap psi
@@ -76,8 +78,9 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
 }
 
 // One half contact of a reverse sweep: recomputes y of sweep l for contact
-// `code` of particle i from the recorded impulse P^(l-1) and iterate w^(l-1),
-// updates the contact's adjoint state (index q) and returns ub (the adjoint of
+// `code` of particle i from the recorded impulse P^(l-1) (compact index q) and
+// iterate w^(l-1), updates the contact's adjoint state (at its contact-table
+// slot, so that a wavefront's k-th contacts are one row) and returns ub (the adjoint of
 // its velocity residual) with the sign sg it takes in i's sum.  Multiply-adds
 // are fused only within an expression (fp contract on), so every kernel that
 // calls it computes the same bits.
@@ -98,7 +101,7 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
     P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
   }
   R nrm[3], u[3], mt, Pb[3];
-  const R carry[3] = {A.cx[q], A.cy[q], A.cz[q]};
+  const R carry[3] = {A.cx[slot], A.cy[slot], A.cz[slot]};
   bool lo = true, body = code < 0;
   if (!body) {
     const int j = code & (kHiFlag - 1);
@@ -140,17 +143,17 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
   R yb[3], nb[3] = {R(0), R(0), R(0)};
   proj_adjoint(y, nrm, mu, Qb, yb, nb);
   const R keep = R(1) - relax;
-  A.cx[q] = yb[0] + keep * Pb[0];
-  A.cy[q] = yb[1] + keep * Pb[1];
-  A.cz[q] = yb[2] + keep * Pb[2];
+  A.cx[slot] = yb[0] + keep * Pb[0];
+  A.cy[slot] = yb[1] + keep * Pb[1];
+  A.cz[slot] = yb[2] + keep * Pb[2];
   ub[0] = -mt * yb[0]; ub[1] = -mt * yb[1]; ub[2] = -mt * yb[2];
   const R bb = -mt * dot3f(yb, nrm);
-  A.nx[q] += nb[0] - mt * bias * yb[0];
-  A.ny[q] += nb[1] - mt * bias * yb[1];
-  A.nz[q] += nb[2] - mt * bias * yb[2];
-  A.ps[q] += alpha_dt * bb;
+  A.nx[slot] += nb[0] - mt * bias * yb[0];
+  A.ny[slot] += nb[1] - mt * bias * yb[1];
+  A.nz[slot] += nb[2] - mt * bias * yb[2];
+  A.ps[slot] += alpha_dt * bb;
   if (body) {
-    A.vx[q] -= ub[0]; A.vy[q] -= ub[1]; A.vz[q] -= ub[2];
+    A.vx[slot] -= ub[0]; A.vy[slot] -= ub[1]; A.vz[slot] -= ub[2];
   }
   sg = lo ? R(1) : R(-1);
 }
@@ -254,8 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_begin(int n, const V4<R>* __rest
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_zero_f(size_t m, R* __restrict__ a) {
-  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e < m) a[e] = R(0);
+  // grid-stride: arrays beyond 2^32 elements do not fit one grid's work-item count
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < m; e += (size_t)gridDim.x * kBlock) a[e] = R(0);
 }
 
 // vbar^k = adjoint of w0 (w0 = v + dt g), including the last reverse sweep's output.
@@ -412,9 +415,8 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
       const R L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       if (!(L > R(0))) continue;
       const R nr[3] = {d[0] / L, d[1] / L, d[2] / L};
-      const int q = pofs[i] + k;
-      const R nb[3] = {A.nx[q], A.ny[q], A.nz[q]};
-      const R psb = A.ps[q];
+      const R nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
+      const R psb = A.ps[slot];
       const R nn = dot3f(nr, nb);
       const R sg = lo ? R(1) : R(-1);
       for (int a = 0; a < 3; ++a) xb[a] += sg * ((nb[a] - nn * nr[a]) / L + psb * nr[a]);
@@ -459,10 +461,9 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
         const R psi = Psi[slot];
         const R f = psi + xi.w;
         const R a[3] = {xi.x - f * nr[0] - Bt[0], xi.y - f * nr[1] - Bt[1], xi.z - f * nr[2] - Bt[2]};
-        const int qq = pofs[i] + k;
-        const R Vb[3] = {A.vx[qq], A.vy[qq], A.vz[qq]};
-        const R nb[3] = {A.nx[qq], A.ny[qq], A.nz[qq]};
-        const R psb = A.ps[qq];
+        const R Vb[3] = {A.vx[slot], A.vy[slot], A.vz[slot]};
+        const R nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
+        const R psb = A.ps[slot];
         // V = nu + om x a
         acc[0] += Vb[0]; acc[1] += Vb[1]; acc[2] += Vb[2];
         acc[3] += a[1] * Vb[2] - a[2] * Vb[1];

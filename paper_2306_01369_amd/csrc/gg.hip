@@ -1516,7 +1516,8 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
   V* wba = (V*)alloc(n4);
   V* wbb = (V*)alloc(n4);
   V* w0b = (V*)alloc(n4);
-  R* adj = (R*)alloc(hc_max * sizeof(R) * 10);
+  const size_t aslots = (size_t)s->n_pad * (size_t)K;   // adjoint state: one per contact-table slot
+  R* adj = (R*)alloc(aslots * sizeof(R) * 10);
   R* part = (R*)alloc((size_t)grid * std::max(nb, 1) * 18 * sizeof(R));
   R* bgrad = (R*)alloc((size_t)std::max(nb, 1) * 18 * sizeof(R) * N);
   float* io3 = (float*)alloc((size_t)n * 12 * 2);
@@ -1531,10 +1532,10 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
   }
   sample_memory(s);
   ggk::AdjSlots<R> A;
-  A.cx = adj; A.cy = adj + hc_max; A.cz = adj + 2 * hc_max;
-  A.nx = adj + 3 * hc_max; A.ny = adj + 4 * hc_max; A.nz = adj + 5 * hc_max;
-  A.ps = adj + 6 * hc_max;
-  A.vx = adj + 7 * hc_max; A.vy = adj + 8 * hc_max; A.vz = adj + 9 * hc_max;
+  A.cx = adj; A.cy = adj + aslots; A.cz = adj + 2 * aslots;
+  A.nx = adj + 3 * aslots; A.ny = adj + 4 * aslots; A.nz = adj + 5 * aslots;
+  A.ps = adj + 6 * aslots;
+  A.vx = adj + 7 * aslots; A.vy = adj + 8 * aslots; A.vz = adj + 9 * aslots;
 
   // ---- final-state adjoints into the internal order
   const hipMemcpyKind kin = where == GG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -1611,7 +1612,8 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       const R* ps = tpsi + slots * r;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
       ggk::k_adj_begin<R><<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
-      ggk::k_zero_f<R><<<(int)((hc_max * 10 + ggk::kBlock - 1) / ggk::kBlock), ggk::kBlock, 0, S>>>(hc_max * 10, adj);
+      ggk::k_zero_f<R><<<(int)std::min<size_t>((aslots * 10 + ggk::kBlock - 1) / ggk::kBlock, 65536), ggk::kBlock,
+                         0, S>>>(aslots * 10, adj);
       V* win = wba;
       V* wout = wbb;
       const int32_t* po = tpofs + (size_t)r * (n + 1);
