@@ -85,7 +85,8 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
 // are fused only within an expression (fp contract on), so every kernel that
 // calls it computes the same bits.
 template <typename R>
-__device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool first_sweep, const V4<R>& xi,
+__device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool first_sweep, bool fresh,
+                                                 const V4<R>& xi,
                                                  const V4<R>& vi, const V4<R>& wi, const V4<R>& bi,
                                                  const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
                                                  const V4<R>* __restrict__ w_prev,
@@ -101,7 +102,8 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
     P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
   }
   R nrm[3], u[3], mt, Pb[3];
-  const R carry[3] = {A.cx[slot], A.cy[slot], A.cz[slot]};
+  // (fresh: the first reverse sweep of a step, whose state starts at zero)
+  const R carry[3] = {fresh ? R(0) : A.cx[slot], fresh ? R(0) : A.cy[slot], fresh ? R(0) : A.cz[slot]};
   bool lo = true, body = code < 0;
   if (!body) {
     const int j = code & (kHiFlag - 1);
@@ -148,12 +150,14 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
   A.cz[slot] = yb[2] + keep * Pb[2];
   ub[0] = -mt * yb[0]; ub[1] = -mt * yb[1]; ub[2] = -mt * yb[2];
   const R bb = -mt * dot3f(yb, nrm);
-  A.nx[slot] += nb[0] - mt * bias * yb[0];
-  A.ny[slot] += nb[1] - mt * bias * yb[1];
-  A.nz[slot] += nb[2] - mt * bias * yb[2];
-  A.ps[slot] += alpha_dt * bb;
+  A.nx[slot] = (fresh ? R(0) : A.nx[slot]) + (nb[0] - mt * bias * yb[0]);
+  A.ny[slot] = (fresh ? R(0) : A.ny[slot]) + (nb[1] - mt * bias * yb[1]);
+  A.nz[slot] = (fresh ? R(0) : A.nz[slot]) + (nb[2] - mt * bias * yb[2]);
+  A.ps[slot] = (fresh ? R(0) : A.ps[slot]) + alpha_dt * bb;
   if (body) {
-    A.vx[slot] -= ub[0]; A.vy[slot] -= ub[1]; A.vz[slot] -= ub[2];
+    A.vx[slot] = (fresh ? R(0) : A.vx[slot]) - ub[0];
+    A.vy[slot] = (fresh ? R(0) : A.vy[slot]) - ub[1];
+    A.vz[slot] = (fresh ? R(0) : A.vz[slot]) - ub[2];
   }
   sg = lo ? R(1) : R(-1);
 }
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
     const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
     const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
-    R relax, int first_sweep, const int32_t* __restrict__ pofs) {
+    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs) {
 #pragma clang fp contract(on)
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
     R ub[3], sg;
-    half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, xi, vi, wi, bi, x, v, w_prev, wbar_in,
+    half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x, v, w_prev, wbar_in,
                         Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
     acc[0] += sg * ub[0]; acc[1] += sg * ub[1]; acc[2] += sg * ub[2];
   }
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj_lanes(
     V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
     const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
     const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
-    R relax, int first_sweep, const int32_t* __restrict__ pofs) {
+    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs) {
 #pragma clang fp contract(on)
   static_assert(L == 2 || L == 4, "lanes per particle");
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj_lanes(
     R ub[3] = {R(0), R(0), R(0)}, sg = R(0);
     if (k < c) {
       const int slot = ell_slot(i, k, K);
-      half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, xi, vi, wi, bi, x, v, w_prev,
+      half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x, v, w_prev,
                           wbar_in, Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
     }
 #pragma unroll
@@ -255,11 +259,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_begin(int n, const V4<R>* __rest
   w0bar[i] = mk4<R>(R(0), R(0), R(0), R(0));
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_zero_f(size_t m, R* __restrict__ a) {
-  // grid-stride: arrays beyond 2^32 elements do not fit one grid's work-item count
-  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < m; e += (size_t)gridDim.x * kBlock) a[e] = R(0);
-}
 
 // vbar^k = adjoint of w0 (w0 = v + dt g), including the last reverse sweep's output.
 template <typename R>

@@ -1612,8 +1612,8 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       const R* ps = tpsi + slots * r;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
       ggk::k_adj_begin<R><<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
-      ggk::k_zero_f<R><<<(int)std::min<size_t>((aslots * 10 + ggk::kBlock - 1) / ggk::kBlock, 65536), ggk::kBlock,
-                         0, S>>>(aslots * 10, adj);
+      // (no zeroing of the adjoint state: the first reverse sweep, l = I >= 1,
+      // writes every slot in use before anything reads it)
       V* win = wba;
       V* wout = wbb;
       const int32_t* po = tpofs + (size_t)r * (n + 1);
@@ -1626,15 +1626,17 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
           ggk::k_pja_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
                                                       Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr,
                                                       A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
-                                                      po);
+                                                      l == I ? 1 : 0, po);
         else if (Ln == 2)
           ggk::k_pja_adj_lanes<R, 2><<<lg, ggk::kBlock, 0, S>>>(
               n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
-              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
+              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
+              l == I ? 1 : 0, po);
         else
           ggk::k_pja_adj_lanes<R, 4><<<lg, ggk::kBlock, 0, S>>>(
               n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
-              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0, po);
+              Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
+              l == I ? 1 : 0, po);
         std::swap(win, wout);
       }
       ggk::k_adj_vbar<R><<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);
