@@ -166,20 +166,33 @@ typedef struct {
 } gg_params;
 
 /* Create a simulation of n particles split into n_envs independent
- * environments: particles env_offsets[e] .. env_offsets[e+1]-1 form
+ * environments.  The state is the problem statement of Sec. II: positions and
+ * velocities of n spheres (3 x n each, no rotational degrees of freedom) with
+ * radii; the environments are the independent simulations run side by side
+ * in Sec. III.  Particles env_offsets[e] .. env_offsets[e+1]-1 form
  * environment e (env_offsets: n_envs+1 host int64 values, first 0, last n,
  * non-decreasing; NULL means one environment).  Particles of different
  * environments never touch.  x, v: n x 3; radius: n (> 0).  where applies to
  * x, v and radius.  n may be 0.  On success *out owns a new handle.
  * Errors: GG_ERR_INVALID (bad params, offsets, radius <= 0, cell smaller than
- * 2 r_max, |x / c| >= 2^30), GG_ERR_NONFINITE (non-finite x or v),
- * GG_ERR_OOM, GG_ERR_HIP. */
+ * 2 r_max, |x / c| >= 2^30, a contact table of more than 2^31 - 1 slots:
+ * n rounded up to a multiple of 64, times the contact capacity -- the
+ * capacity is max_contacts_per_particle or the packing bound of the radius
+ * ratio, 19 for equal spheres, plus the bodies of the largest environment),
+ * GG_ERR_NONFINITE (non-finite x or v), GG_ERR_OOM, GG_ERR_HIP. */
 gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_offsets, int64_t n,
                     const float* x, const float* v, const float* radius, gg_mem where, gg_sim** out);
 
-/* Replace all bodies (n_bodies >= 0).  Each body's env must be < n_envs.
+/* Replace all bodies (n_bodies >= 0): the kinematic bodies of Sec. II, whose
+ * pose in SE(3) and twist in se(3) the caller prescribes and which receive no
+ * reaction; they enter the step through their SDFs (Eq. (7), Sec. II-C).
+ * Each body's env must be < n_envs.  The contact capacity grows by the bodies
+ * of the largest environment (see gg_create).  A successful call discards the
+ * record of the last differentiable gg_step (gg_step_backward then returns
+ * GG_ERR_NO_TAPE until the next gg_step).
  * Errors: GG_ERR_INVALID (unknown shape, bad env, non-positive extents,
- * non-finite pose or twist). */
+ * non-finite pose or twist, a contact table beyond 2^31 - 1 slots; nothing is
+ * changed), GG_ERR_OOM, GG_ERR_HIP. */
 gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg_mem where);
 
 /* Register the grids that GG_GRID bodies refer to by index, replacing any
@@ -187,11 +200,17 @@ gg_status gg_set_bodies(gg_sim* sim, int32_t n_bodies, const gg_body* bodies, gg
  * n_values floats in host or device memory (where), copied.  Each grid must
  * lie inside the values array and every value must be finite; otherwise
  * GG_ERR_INVALID and nothing changes.  gg_set_bodies checks grid indices
- * against the grids registered at that time. */
+ * against the grids registered at that time.  A successful call discards the
+ * record of the last differentiable gg_step, like gg_set_bodies. */
 gg_status gg_set_grids(gg_sim* sim, int32_t n_grids, const gg_grid* grids, int64_t n_values,
                        const float* values, gg_mem where);
 
-/* Advance n_steps timesteps (>= 0).  twists: NULL keeps every body's current
+/* Advance n_steps timesteps (>= 0), each the step of Sec. II: cell keys and
+ * the bucket table (Eq. (6), Alg. 2's role), particle-particle and
+ * particle-body contact detection (Sec. II-B, II-C, Eq. (7)), n_iters
+ * projected-Jacobi sweeps (Alg. 1, Eqs. (1)-(3)) and the symplectic-Euler
+ * update (Eqs. (4)-(5)); then the bodies' poses advance by their twists.
+ * twists: NULL keeps every body's current
  * twist, else n_steps x n_bodies x 6 floats, the twist of each body during
  * each step (where applies to twists).
  * Capacity: if a particle has more contacts than its capacity (see
@@ -210,7 +229,9 @@ gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem wher
  * set being piecewise constant in the inputs.  The forward kept (x, v) every
  * params.checkpoint_every steps; each segment is recomputed from its
  * checkpoint before its steps are reversed, so device memory grows with
- * n_steps / checkpoint_every plus one segment's contacts.
+ * n_steps / checkpoint_every, one segment's recorded sweeps and a per-call
+ * workspace of 40 bytes per contact-table slot (n rounded up to 64 times the
+ * contact capacity), allocated and freed by each call.
  * dL_dx, dL_dv: n x 3 float32 gradients of the loss with respect to the final
  * positions and velocities, caller's particle order; NULL means zero.
  * Outputs (any may be NULL): dL_dx0, dL_dv0 (n x 3) with respect to the
@@ -220,8 +241,9 @@ gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem wher
  * Errors: GG_ERR_NO_TAPE if the simulation has no tape or the last gg_step
  * failed; GG_ERR_UNSUPPORTED for more than one environment; GG_ERR_OOM if the
  * workspace cannot be allocated; GG_ERR_HIP if the recomputed contact counts
- * differ from the recorded forward.  The tape stays valid, so the call may be
- * repeated with other loss gradients. */
+ * differ from the recorded forward.  The tape stays valid until the next
+ * gg_step, gg_set_bodies or gg_set_grids call, so the call may be repeated
+ * with other loss gradients. */
 gg_status gg_step_backward(gg_sim* sim, const float* dL_dx, const float* dL_dv, float* dL_dx0,
                            float* dL_dv0, float* dL_dtwists, gg_mem where);
 

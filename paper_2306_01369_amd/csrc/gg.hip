@@ -383,9 +383,21 @@ gg_status ensure_tmp(gg_sim* s, size_t bytes) {
   return GG_OK;
 }
 
+// Contact-table slots are indexed in 32-bit arithmetic on the device
+// (ell_slot): n_pad * K must stay below 2^31.
+constexpr int64_t kMaxSlots = ((int64_t)1 << 31) - 1;
+
+bool slots_fit(int64_t n_pad, int K) { return n_pad * (int64_t)K <= kMaxSlots; }
+
+gg_status slots_error(int64_t n_pad, int K) {
+  return fail(GG_ERR_INVALID, "contact table of " + std::to_string(n_pad) + " x " + std::to_string(K) +
+                                  " slots exceeds 2^31 - 1 (fewer particles or a smaller contact capacity)");
+}
+
 // (Re)allocate the contact table for capacity K per particle.
 gg_status ensure_ell(gg_sim* s, int K) {
   if (K == s->K && s->partner) return GG_OK;
+  if (!slots_fit(s->n_pad, K)) return slots_error(s->n_pad, K);
   (void)hipFree(s->partner); (void)hipFree(s->Px); (void)hipFree(s->Py); (void)hipFree(s->Pz);
   (void)hipFree(s->Psi);
   s->partner = nullptr; s->Px = s->Py = s->Pz = s->Psi = nullptr;
@@ -402,13 +414,19 @@ gg_status ensure_ell(gg_sim* s, int K) {
   return GG_OK;
 }
 
-int compute_K(const gg_sim* s) {
-  if (s->p.max_contacts_per_particle > 0) return s->p.max_contacts_per_particle;
-  int nb_env = 0;
-  for (int e = 0; e < s->n_envs; ++e) nb_env = std::max(nb_env, s->body_hi[e] - s->body_lo[e]);
-  int K = s->K_pp + nb_env;
+// Contact capacity per particle: the explicit one, else the packing bound of
+// the radius ratio plus the largest number of bodies of one environment.
+int capacity_for(const gg_params& p, int K_pp, int nb_env) {
+  if (p.max_contacts_per_particle > 0) return p.max_contacts_per_particle;
+  int K = K_pp + nb_env;
   K = (K + 1) & ~1;
   return std::min(K, 256);
+}
+
+int compute_K(const gg_sim* s) {
+  int nb_env = 0;
+  for (int e = 0; e < s->n_envs; ++e) nb_env = std::max(nb_env, s->body_hi[e] - s->body_lo[e]);
+  return capacity_for(s->p, s->K_pp, nb_env);
 }
 
 ggk::EnvTables env_tables(const gg_sim* s) {
@@ -926,6 +944,12 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     if (total_tab > ((int64_t)1 << 31) - 2) return fail(GG_ERR_INVALID, "total hash buckets exceed 2^31 - 2");
   }
 
+  {
+    const int64_t n_pad = (n + 63) / 64 * 64;
+    const int K0 = capacity_for(*params, contact_bound(rmin, rmax), 0);
+    if (!slots_fit(n_pad, K0)) return slots_error(n_pad, K0);
+  }
+
   gg_sim* s = new (std::nothrow) gg_sim();
   if (!s) return fail(GG_ERR_OOM, "host allocation failed");
   s->p = *params;
@@ -1180,7 +1204,19 @@ gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_m
       H.om[q] = B.twist[3 + q];
     }
   }
+  {
+    int nb_env = 0;
+    for (int b = 0; b < n_bodies;) {
+      int e = nb[b].env, c = 0;
+      while (b < n_bodies && nb[b].env == e) ++b, ++c;
+      nb_env = std::max(nb_env, c);
+    }
+    const int K1 = capacity_for(s->p, s->K_pp, nb_env);
+    if (!slots_fit(s->n_pad, K1)) return slots_error(s->n_pad, K1);
+  }
   DeviceGuard g(s->dev);
+  // the recorded forward names the old bodies (count, poses, grid values)
+  s->tape_ok = false;
   s->bodies = nb;
   gg_status st = upload_env_bodies(s);
   if (st != GG_OK) return st;
@@ -1222,6 +1258,8 @@ gg_status gg_set_grids(gg_sim* s, int32_t n_grids, const gg_grid* grids, int64_t
     }
   }
   if (s->stream) HIPCHK(s, hipStreamSynchronize(s->stream));  // no step still reads the old values
+  // the recorded forward's body records point into the old values
+  s->tape_ok = false;
   if (s->d_grid_values) HIPCHK(s, hipFree(s->d_grid_values));
   s->d_grid_values = d;
   s->grids = G;

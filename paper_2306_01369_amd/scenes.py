@@ -397,6 +397,20 @@ def large_scene(seed=0, n=1 << 22, side=2.0):
     one below, so the start has no contacts and compacts by grains sinking
     into the hollows of the layer beneath (falls of at most a few mm)."""
     rng = np.random.default_rng(seed)
+    pos, rad, top = layered_polydisperse_bed(n, side, rng)
+    box = box_tool((0.6, 1.0, top + 0.11), (0.025, 0.15, 0.1), nu=(0.2, 0.0, -0.3))
+    cap = capsule_tool((1.4, 1.0, top + 0.03), 0.02, 0.075, nu=(-0.2, 0.0, -0.3), omega=(0.0, 1.0, 0.0),
+                       R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
+    bodies = walled_box(0.0, side, 0.0, side) + [box, cap]
+    return Scene(f"large-{n}", _f32(pos), np.zeros((n, 3), np.float32), _f32(rad), bodies, dt=1e-3,
+                 n_iters=64, mu=0.5, alpha=0.2, n_steps=100)
+
+
+def layered_polydisperse_bed(n, side, rng):
+    """The large bed's start (see large_scene): lognormal radii sorted and cut
+    into square-lattice layers over a side x side footprint, stacked in random
+    order 2% of the radius sum apart, index order shuffled.  Returns
+    (positions, radii, top of the highest layer)."""
     rad = np.sort(polydisperse_radii(n, rng))
     pos = np.zeros((n, 3))
     layers = []
@@ -431,13 +445,7 @@ def large_scene(seed=0, n=1 << 22, side=2.0):
         prev_r = rl
     perm = rng.permutation(n)
     pos, rad = pos[perm], rad[perm]
-    top = z + prev_r
-    box = box_tool((0.6, 1.0, top + 0.11), (0.025, 0.15, 0.1), nu=(0.2, 0.0, -0.3))
-    cap = capsule_tool((1.4, 1.0, top + 0.03), 0.02, 0.075, nu=(-0.2, 0.0, -0.3), omega=(0.0, 1.0, 0.0),
-                       R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
-    bodies = walled_box(0.0, side, 0.0, side) + [box, cap]
-    return Scene(f"large-{n}", _f32(pos), np.zeros((n, 3), np.float32), _f32(rad), bodies, dt=1e-3,
-                 n_iters=64, mu=0.5, alpha=0.2, n_steps=100)
+    return pos, rad, z + prev_r
 
 
 def random_spheres(n, box, r, rng, r_jitter=0.0):

@@ -143,3 +143,17 @@ def test_body_layout_from_scene_dict():
     assert b.env == 2 and b.shape == 1
     assert list(b.pose) == [1, 0, 0, 1, 0, 1, 0, 2, 0, 0, 1, 3]
     assert list(b.twist) == [4, 5, 6, 7, 8, 9]
+
+
+def test_contact_table_beyond_32_bit_slots_is_rejected_on_host():
+    # The contact table holds (n rounded up to 64) x capacity slots indexed in
+    # 32-bit arithmetic on the device; 2^23 particles at the largest capacity
+    # (256) make 2^31 slots, one too many.  The check runs before any device
+    # work, so it needs no GPU.
+    n = 1 << 23
+    x = np.zeros((n, 3), np.float32)
+    r = np.full(n, 0.001, np.float32)
+    with pytest.raises(gg.GGError) as e:
+        gg.Sim(x, x, r, max_contacts=256)
+    assert e.value.status == gg.GG_ERR_INVALID
+    assert "2^31" in str(e.value)

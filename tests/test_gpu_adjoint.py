@@ -351,3 +351,112 @@ def test_adjoint_with_a_grid_tool_matches_dual_numbers():
             err = abs(an - ref) / max(abs(ref), 1e-12)
             say(kind, "precision", prec, "adjoint", an, "dual", ref, "rel err", err)
             assert err <= REL_TOL, (kind, prec, err)
+
+
+def test_setting_bodies_or_grids_discards_the_tape():
+    # the recorded forward names the bodies (count, per-step poses, grid
+    # values) it ran with; replacing them drops the record before any launch
+    x, v, r, bodies, tw, loss = _setup(n=300, steps=2)
+    say("tape dropped by gg_set_bodies / gg_set_grids")
+    gx = np.zeros((len(x), 3))
+    sim = gg.Sim(x, v, r, bodies, differentiable=True)
+    sim.step(2, twists=tw.astype(np.float32))
+    sim.backward(gx, None)                       # the record is there
+    sim.set_bodies(bodies[:-1])                  # one body fewer
+    with pytest.raises(gg.GGError) as e:
+        sim.backward(gx, None, n_steps=2)
+    assert e.value.status == gg.GG_ERR_NO_TAPE
+    sim.step(2)
+    sim.backward(gx, None)
+    sim.set_grids([{"values": np.ones((2, 2, 2), np.float32), "origin": (0, 0, 0), "inv_spacing": 1.0}])
+    with pytest.raises(gg.GGError) as e:
+        sim.backward(gx, None, n_steps=2)
+    assert e.value.status == gg.GG_ERR_NO_TAPE
+    sim.close()
+
+
+def _poly_setup(n=2400, steps=8, seed=31, side=0.05, gravity=True, settle=40):
+    """Polydisperse grains (the large bed's recipe at small size: lognormal
+    radii, median 2 mm, sigma 0.25, clipped to [1, 4] mm, so masses differ by
+    up to 64x) with a box and a capsule tool driven into them, 64 sweeps."""
+    rng = np.random.default_rng(seed)
+    pos, rad, top = scenes.layered_polydisperse_bed(n, side, rng)
+    x = pos.astype(np.float32)
+    r = rad.astype(np.float32)
+    box = scenes.box_tool((0.3 * side, 0.5 * side, top + 0.001 + 0.01), (0.004, 0.3 * side, 0.01),
+                          nu=(0.1, 0.0, -0.3))
+    cap = scenes.capsule_tool((0.7 * side, 0.5 * side, top + 0.001 + 0.006), 0.006, 0.015,
+                              nu=(-0.1, 0.0, -0.3), omega=(0.0, 2.0, 0.0),
+                              R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
+    bodies = scenes.walled_box(0.0, side, 0.0, side) + [box, cap]
+    nb = len(bodies)
+    tw = np.zeros((steps, nb, 6))
+    for b in (nb - 2, nb - 1):
+        tw[:, b, :3] = np.float32(bodies[b]["nu"])
+        tw[:, b, 3:] = np.float32(bodies[b]["omega"])
+    v = np.zeros((n, 3), np.float32)
+    if gravity:
+        # let the layers fall into each other first (tools still), by the oracle
+        orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, bodies, dt=_f32(1e-3), alpha=_f32(0.2),
+                       gravity=EXACT_G, n_iters=64)
+        orc.set_twists(np.zeros((nb, 6)))
+        for _ in range(settle):
+            orc.step(advance_bodies=False)
+        x, v = orc.x.astype(np.float32), orc.v.astype(np.float32)
+    else:
+        v = (0.3 * rng.normal(size=(n, 3))).astype(np.float32)
+    loss = TargetLoss((0.5 * side, 0.5 * side, top - 0.004), (0.25 * side, 0.2 * side, 0.004), width=1e-3,
+                      vel_weight=(0.02, -0.01, 0.03))
+    return x, v, r, bodies, tw, loss
+
+
+def _dual_check(x, v, r, bodies, tw, loss, grads, kw, tol, tag):
+    from gradcheck import jvp_directional
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    rng = np.random.default_rng(77)
+    errs = []
+    for kind in ("x0", "v0", "twist", "all", "x0", "twist"):
+        dx = rng.normal(size=x.shape) if kind in ("x0", "all") else np.zeros(x.shape)
+        dv = rng.normal(size=v.shape) if kind in ("v0", "all") else np.zeros(v.shape)
+        dt_ = np.zeros_like(tw)
+        if kind in ("twist", "all"):
+            dt_[:, -2:, :] = rng.normal(size=(tw.shape[0], 2, 6))
+        ref = jvp_directional(loss, x64, v64, r, bodies, tw, (dx, dv, dt_), **kw)
+        gx0, gv0, gtw = grads
+        an = np.sum(gx0 * dx) + np.sum(gv0 * dv) + np.sum(gtw * dt_)
+        err = abs(an - ref) / max(abs(ref), 1e-12)
+        say(tag, kind, "adjoint", an, "dual", ref, "rel err", err)
+        errs.append(err)
+        assert abs(ref) > 0
+        assert err <= tol, (tag, kind, an, ref, err)
+    return errs
+
+
+def test_polydisperse_adjoint_fp64_build_matches_dual_numbers():
+    # unequal masses in every pair (a swapped lower/higher-mass term in the
+    # pair adjoint would show), 64 sweeps, two tools, a checkpoint every 3 of 8
+    # steps so segments are recomputed; gravity on, grains settling into the
+    # layer beneath while the tools push in
+    x, v, r, bodies, tw, loss = _poly_setup()
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=EXACT_G, n_iters=64)
+    say("polydisperse adjoint, double build: n", len(x), "radii", float(r.min()), float(r.max()))
+    diffs = _contact_list_differences(x, v, r, bodies, tw, precision=1, **kw)
+    say("contact list differences per step (gpu-only, oracle-only):", diffs)
+    assert all(a == 0 and b == 0 for a, b in diffs)
+    grads, st = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3, precision=1, **kw)
+    assert st["n_pp"] > 1000 and st["n_pb"] > 10
+    _dual_check(x, v, r, bodies, tw, loss, grads, kw, REL_TOL, "fp64")
+
+
+def test_polydisperse_adjoint_fp32_build_matches_dual_numbers_on_colliding_grains():
+    # the production (binary32) build on the same recipe without gravity and
+    # with random velocities: contacts open and close far from the touching
+    # threshold, so the binary32 run keeps the oracle's contact sets
+    x, v, r, bodies, tw, loss = _poly_setup(seed=32, gravity=False)
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=(0.0, 0.0, 0.0), n_iters=64)
+    say("polydisperse adjoint, binary32 build: n", len(x))
+    diffs = _contact_list_differences(x, v, r, bodies, tw, **kw)
+    say("contact list differences per step (gpu-only, oracle-only):", diffs)
+    grads, st = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3, **kw)
+    assert st["n_pp"] > 500 and st["n_pb"] > 10
+    _dual_check(x, v, r, bodies, tw, loss, grads, kw, REL_TOL, "fp32")

@@ -312,3 +312,98 @@ def test_cyclic_vertical_boundary_closed_form():
     np.testing.assert_allclose(orc.x[:, 2], z, rtol=0, atol=1e-11)
     np.testing.assert_array_equal(orc.v, v)
     assert np.all(steps * dt * v[:, 2] < -(hi - lo) * 0.8)    # every grain wrapped at least once
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def test_turntable_carries_a_sticking_sphere_at_the_rigid_velocity():
+    # A plane spinning about the vertical axis through (a, b, 0) (an se(3)
+    # twist with nu = 0, omega = Omega z, Sec. II) under a sphere resting on it
+    # at (rho, 0, r).  The contact point is (rho, 0, 0), so the body point
+    # velocity is omega x (p_c - t) = Omega (b, rho - a, 0).  With gravity
+    # pressing the sphere down, one step makes it move with that point as long
+    # as Omega |arm| <= mu g dt (sticking); beyond, the tangential impulse is
+    # capped at mu m g dt and the sphere slides along the point velocity at
+    # speed mu g dt (disk projection of Alg. 1).
+    g, dt, mu = 9.81, 1e-3, 0.5
+    r = float(np.float32(0.01))
+    a, b, rho = 0.25, -0.125, 0.5
+    arm = math.hypot(rho - a, b)
+    for Omega, sticking in ((0.5 * mu * g * dt / arm, True), (0.9 * mu * g * dt / arm, True),
+                            (4.0 * mu * g * dt / arm, False), (-3.0 * mu * g * dt / arm, False)):
+        Om = float(np.float32(Omega))
+        pl = scenes.plane((a, b, 0.0), (0, 0, 1))
+        pl["omega"] = np.array([0.0, 0.0, Om])
+        o = O.Oracle(np.array([[rho, 0.0, r]]), np.zeros((1, 3)), np.array([r], np.float32), [pl],
+                     dt=dt, mu=mu, n_iters=20, alpha=0.0)
+        d = o.step(detail=True)
+        assert d["n_pb"] == 1
+        V = Om * np.array([b, rho - a, 0.0])
+        if sticking:
+            np.testing.assert_allclose(o.v[0], V, rtol=0, atol=1e-15)
+        else:
+            expect = mu * g * dt * V / np.linalg.norm(V)
+            np.testing.assert_allclose(o.v[0], expect, rtol=0, atol=1e-15)
+        # the normal impulse carries the weight exactly: no vertical motion
+        assert abs(o.v[0, 2]) < 1e-15
+
+
+def test_pushing_body_imparts_its_rigid_point_velocity():
+    # A body pushing a free sphere (no gravity, no Baumgarte bias) within the
+    # friction cone: after one sweep the sphere moves with the body's rigid
+    # velocity at the contact point, V = nu + omega x (p_c - t), where
+    # p_c = x - f n is the point of the surface under the sphere centre (the
+    # body contact geometry of Eq. (7)), and later sweeps keep that fixed
+    # point.  The rotation is generic, so omega is not parallel to the normal
+    # and using the sphere centre x instead of p_c, or the opposite sign of the
+    # cross product, would change V.
+    rng = np.random.default_rng(21)
+    r = float(np.float32(0.01))
+    mu = 0.5
+    checked = 0
+    for trial in range(12):
+        R = scenes.random_rotation(rng)
+        t = rng.uniform(-0.2, 0.2, 3)
+        Rf, tf = _f32(R), _f32(t)
+        n = Rf[:, 2] / np.linalg.norm(Rf[:, 2])
+        om = _f32(rng.uniform(-1.0, 1.0, 3))
+        nu = _f32(1.0 * n + rng.uniform(-0.05, 0.05, 3))
+        pb = np.array([rng.uniform(-0.1, 0.1), rng.uniform(-0.1, 0.1), r * (1 - 1e-3)])
+        x = tf + Rf @ pb
+        body = {"shape": "plane", "params": [0.0] * 4, "R": R, "t": t, "nu": nu, "omega": om, "env": 0}
+        for iters in (1, 3):
+            o = O.Oracle(x[None, :], np.zeros((1, 3)), np.array([r], np.float32), [body],
+                         gravity=(0.0, 0.0, 0.0), alpha=0.0, mu=mu, n_iters=iters)
+            d = o.step(detail=True)
+            assert d["n_pb"] == 1
+            f = float(np.dot(Rf.T @ (x - tf), [0, 0, 1.0]))
+            pc = x - f * n
+            V = nu + np.cross(om, pc - tf)
+            Vn = float(V @ n)
+            Vt = V - Vn * n
+            assert Vn > 0 and np.linalg.norm(Vt) <= mu * Vn      # the sticking regime
+            np.testing.assert_allclose(o.v[0], V, rtol=0, atol=1e-12)
+            # x instead of p_c shifts the arm by f n: a different velocity
+            assert np.linalg.norm(np.cross(om, f * n)) > 1e-4
+            checked += 1
+    assert checked == 24
+
+
+@pytest.mark.parametrize("relax", [0.3, 0.7, 1.3])
+def test_relaxed_sweeps_decay_the_relative_velocity_geometrically(relax):
+    # Two equal spheres touching head on (no gravity), approaching with a
+    # relative velocity u0 inside the friction cone.  Every sweep's projected
+    # value is the full inelastic impulse y = -mt u0 (mt = m/2), so the blend
+    # lam_l = (1 - w) lam_{l-1} + w y leaves lam* - lam_l = (1 - w)^l lam*, and
+    # the relative velocity after I sweeps is (1 - w)^I u0, both along the
+    # normal and (sticking) along the tangent.  Momentum is unchanged.
+    m = mass(0.5)
+    v0 = np.array([[1.0, 0.2, -0.1], [-1.0, 0.0, 0.1]])
+    for iters in (1, 2, 5, 9):
+        o = _two([0, 0, 0], [1, 0, 0], v0[0], v0[1], n_iters=iters, mu=0.5, relax=relax)
+        o.step()
+        u0 = v0[0] - v0[1]
+        np.testing.assert_allclose(o.v[0] - o.v[1], (1.0 - relax) ** iters * u0, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(m * (o.v[0] + o.v[1]), m * (v0[0] + v0[1]), rtol=1e-13, atol=1e-13)
