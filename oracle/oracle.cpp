@@ -46,6 +46,12 @@
 
 namespace {
 
+// Loops over fewer items than this run on one thread.  Every item of a loop is
+// computed on its own (no shared accumulation), so the thread count never
+// changes a result; tiny systems iterated thousands of times skip the
+// fork-join cost.
+const int64_t kOmpMin = 4096;
+
 // ---------------------------------------------------------------- Eq. (6)
 const int64_t kP1 = 73856093, kP2 = 19349663, kP3 = 83492791, kQ = 100;
 
@@ -315,7 +321,7 @@ void pp_contacts_grid(int64_t n, const float* x, const float* r, const int32_t* 
   hm.build(n, x, inv_c, n_h);
   std::vector<std::vector<int32_t>> partners(n);
   int64_t cand_total = 0;
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : cand_total)
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : cand_total) if (n > kOmpMin)
   for (int64_t i = 0; i < n; ++i) {
     const int64_t* ki = &hm.kappa[3 * i];
     for (int dx = -1; dx <= 1; ++dx)
@@ -576,7 +582,7 @@ int64_t ggo_step(const Params* P, int64_t n, double* x, double* v, const float* 
   }
   const double mu = P->mu, om = P->relax;
   for (int32_t l = 1; l <= P->n_iters; ++l) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C > kOmpMin)
     for (int64_t c = 0; c < C; ++c) {
       const Contact& K = cs[c];
       double u[3];
@@ -600,7 +606,7 @@ int64_t ggo_step(const Params* P, int64_t n, double* x, double* v, const float* 
       }
     }
     lam.swap(lam_new);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > kOmpMin)
     for (int64_t i = 0; i < n; ++i) {
       double acc[3] = {0, 0, 0};
       for (int64_t q = start[i]; q < start[i + 1]; ++q) {
@@ -957,7 +963,7 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
   }
   const double mu = P->mu, om = P->relax;
   for (int32_t l = 1; l <= P->n_iters; ++l) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (C > kOmpMin)
     for (int64_t c = 0; c < C; ++c) {
       const DContact& K = cs[c];
       Dual u[3];
@@ -980,7 +986,7 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
       }
     }
     lam.swap(lam_new);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > kOmpMin)
     for (int64_t i = 0; i < n; ++i) {
       Dual acc[3] = {mkd(0), mkd(0), mkd(0)};
       for (int64_t q = start[i]; q < start[i + 1]; ++q) {
@@ -1165,7 +1171,7 @@ void ggo_render_depth(int64_t n, const float* x, const float* r, int32_t n_envs,
   std::vector<int64_t> base(n_cams + 1, 0);
   for (int k = 0; k < n_cams; ++k) base[k + 1] = base[k] + (int64_t)cams[k].width * cams[k].height;
   const int64_t total = pixels ? n_pix : base[n_cams];
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (total > kOmpMin)
   for (int64_t q = 0; q < total; ++q) {
     const int64_t p = pixels ? pixels[q] : q;
     const int k = (int)(std::upper_bound(base.begin(), base.end(), p) - base.begin()) - 1;

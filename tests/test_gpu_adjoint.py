@@ -375,37 +375,47 @@ def test_setting_bodies_or_grids_discards_the_tape():
     sim.close()
 
 
-def _poly_setup(n=2400, steps=8, seed=31, side=0.05, gravity=True, settle=40):
+def _poly_setup(n=2400, steps=8, seed=31, side=0.05, gravity=True, settle=150):
     """Polydisperse grains (the large bed's recipe at small size: lognormal
     radii, median 2 mm, sigma 0.25, clipped to [1, 4] mm, so masses differ by
-    up to 64x) with a box and a capsule tool driven into them, 64 sweeps."""
+    up to 64x) with a box and a capsule tool driven into them, 64 sweeps.
+    With gravity the layers first fall into each other for `settle` steps (by
+    the oracle, walls only); the tools are then placed with their lowest
+    points 0.4 mm below the highest grain surface under them, so they touch
+    grains from the first step."""
     rng = np.random.default_rng(seed)
     pos, rad, top = scenes.layered_polydisperse_bed(n, side, rng)
     x = pos.astype(np.float32)
     r = rad.astype(np.float32)
-    box = scenes.box_tool((0.3 * side, 0.5 * side, top + 0.001 + 0.01), (0.004, 0.3 * side, 0.01),
-                          nu=(0.1, 0.0, -0.3))
-    cap = scenes.capsule_tool((0.7 * side, 0.5 * side, top + 0.001 + 0.006), 0.006, 0.015,
+    walls = scenes.walled_box(0.0, side, 0.0, side)
+    v = np.zeros((n, 3), np.float32)
+    if gravity:
+        orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, walls, dt=_f32(1e-3), alpha=_f32(0.2),
+                       gravity=EXACT_G, n_iters=64)
+        for _ in range(settle):
+            orc.step()
+        x, v = orc.x.astype(np.float32), orc.v.astype(np.float32)
+    else:
+        v = (0.3 * rng.normal(size=(n, 3))).astype(np.float32)
+
+    def surface(xc, half_x):
+        m = (np.abs(x[:, 0] - xc) <= half_x) & (np.abs(x[:, 1] - 0.5 * side) <= 0.3 * side)
+        return float((x[m, 2] + r[m]).max())
+
+    zb = surface(0.3 * side, 0.004) - 4e-4
+    zc = surface(0.7 * side, 0.006) - 4e-4
+    box = scenes.box_tool((0.3 * side, 0.5 * side, zb + 0.01), (0.004, 0.3 * side, 0.01), nu=(0.1, 0.0, -0.3))
+    cap = scenes.capsule_tool((0.7 * side, 0.5 * side, zc + 0.006), 0.006, 0.015,
                               nu=(-0.1, 0.0, -0.3), omega=(0.0, 2.0, 0.0),
                               R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
-    bodies = scenes.walled_box(0.0, side, 0.0, side) + [box, cap]
+    bodies = walls + [box, cap]
     nb = len(bodies)
     tw = np.zeros((steps, nb, 6))
     for b in (nb - 2, nb - 1):
         tw[:, b, :3] = np.float32(bodies[b]["nu"])
         tw[:, b, 3:] = np.float32(bodies[b]["omega"])
-    v = np.zeros((n, 3), np.float32)
-    if gravity:
-        # let the layers fall into each other first (tools still), by the oracle
-        orc = O.Oracle(x.astype(np.float64), v.astype(np.float64), r, bodies, dt=_f32(1e-3), alpha=_f32(0.2),
-                       gravity=EXACT_G, n_iters=64)
-        orc.set_twists(np.zeros((nb, 6)))
-        for _ in range(settle):
-            orc.step(advance_bodies=False)
-        x, v = orc.x.astype(np.float32), orc.v.astype(np.float32)
-    else:
-        v = (0.3 * rng.normal(size=(n, 3))).astype(np.float32)
-    loss = TargetLoss((0.5 * side, 0.5 * side, top - 0.004), (0.25 * side, 0.2 * side, 0.004), width=1e-3,
+    top_s = float(np.percentile(x[:, 2] + r, 99.0))
+    loss = TargetLoss((0.5 * side, 0.5 * side, top_s - 0.004), (0.25 * side, 0.2 * side, 0.004), width=1e-3,
                       vel_weight=(0.02, -0.01, 0.03))
     return x, v, r, bodies, tw, loss
 
