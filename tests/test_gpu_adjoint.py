@@ -467,6 +467,13 @@ def test_polydisperse_adjoint_fp32_build_matches_dual_numbers_on_colliding_grain
     say("polydisperse adjoint, binary32 build: n", len(x))
     diffs = _contact_list_differences(x, v, r, bodies, tw, **kw)
     say("contact list differences per step (gpu-only, oracle-only):", diffs)
+    # the gradient is that of the branch the run took: compare over the steps
+    # whose binary32 contact lists equal the oracle's (a grazing contact can
+    # open a step earlier or later once rounding has moved the grains)
+    horizon = next((k for k, d in enumerate(diffs) if d != (0, 0)), len(diffs))
+    say("horizon with identical contact lists:", horizon)
+    assert horizon >= 4
+    tw = tw[:horizon]
     grads, st = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=3, **kw)
     assert st["n_pp"] > 500 and st["n_pb"] > 10
     _dual_check(x, v, r, bodies, tw, loss, grads, kw, REL_TOL, "fp32")
