@@ -980,6 +980,14 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
         y1 = y1 * f;
         y2 = y2 * f;
       }
+      if (!(yn.v > 0)) {
+        // A non-positive normal part projects the whole impulse to zero, and
+        // so it does on a neighbourhood: the tangent is zero.  The tangential
+        // test alone would keep the tangents of y_t where y_t is exactly zero
+        // (0 > 0 is false), which is not the derivative of the projection.
+        y1.d = 0.0;
+        y2.d = 0.0;
+      }
       for (int a = 0; a < 3; ++a) {
         Dual yw = yn * K.n[a] + y1 * K.t1[a] + y2 * K.t2[a];
         lam_new[3 * c + a] = (1.0 - om) * L[a] + om * yw;

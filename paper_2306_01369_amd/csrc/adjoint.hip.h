@@ -47,16 +47,10 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
   const R ts = sqrt(dot3f(t, t));
   const bool scaled = ts > mu * ynp;
   if (yn <= R(0)) {
-    if (scaled) {  // Q = 0 identically
-      yb[0] = yb[1] = yb[2] = R(0);
-      return;
-    }
-    // Q = y - (n.y) n
-    const R qn = dot3f(Qb, n);
-    for (int a = 0; a < 3; ++a) {
-      yb[a] = Qb[a] - qn * n[a];
-      nb[a] += -qn * y[a] - yn * Qb[a];
-    }
+    // Q = 0, and so on a neighbourhood (the normal part stays clamped): also
+    // where the tangential part is exactly zero and the strict test does not
+    // scale it, the derivative is zero
+    yb[0] = yb[1] = yb[2] = R(0);
     return;
   }
   if (!scaled) {  // Q = y

@@ -141,3 +141,30 @@ def test_dual_numbers_with_a_grid_body():
     fd, same = fd_directional(loss, x, v, r, bodies, tw, (dx, dv, dtw), h, **kw)
     assert same
     assert abs(jv - fd) <= 1e-5 * abs(fd), (jv, fd)
+
+
+def test_separating_contact_with_zero_tangential_velocity_has_zero_derivative():
+    # A sphere touching a ground plane that slides along x at 0.1 m/s; the
+    # sphere moves with the plane along x (relative tangential velocity exactly
+    # zero) and leaves it upward.  The normal part of y is negative, so the
+    # projection maps y to zero on a whole neighbourhood: the step does not
+    # depend on the plane's velocity, and central differences give zero.  The
+    # tangential test alone (0 > 0 is false) would keep the tangent of y_t and
+    # make the sphere follow a perturbed plane.
+    r = 0.004
+    ground = scenes.plane((0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    ground["nu"] = np.array([0.1, 0.0, 0.0])
+    x = np.array([[0.0, 0.0, r - 1e-6]])
+    v = np.array([[0.1, 0.0, 0.5]])
+    kw = dict(dt=1e-3, alpha=0.2, mu=0.5, gravity=(0.0, 0.0, 0.0))
+    tw = np.array([[[0.1, 0.0, 0.0, 0.0, 0.0, 0.0]]])
+    for comp in range(3):
+        dtw = np.zeros_like(tw)
+        dtw[0, 0, comp] = 1.0
+        loss = TargetLoss((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), width=1e-3, vel_weight=(1.0, 1.0, 1.0))
+        z = np.zeros((1, 3))
+        ref = jvp_directional(loss, x, v, np.full(1, r, np.float32), [ground], tw, (z, z, dtw), **kw)
+        fd, same = fd_directional(loss, x, v, np.full(1, r, np.float32), [ground], tw, (z, z, dtw), 1e-7, **kw)
+        assert same
+        assert abs(fd) < 1e-9, (comp, fd)
+        assert ref == 0.0, (comp, ref)
