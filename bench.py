@@ -84,7 +84,9 @@ def cpu_baseline(scene, steps):
     dt = time.perf_counter() - t0
     return {"value": scene.n * steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"{steps} steps of the same 1,048,576-sphere scoop bed from its initial state, FP64"}
+            "sample": f"{steps} steps of a 1,048,576-sphere resting bed of the same grains (r=2 mm, compressed "
+                      "simple-cubic layers, ~3.1M contacts, 20 sweeps), FP64; the settled bed is the library's "
+                      "output and is not given to the oracle"}
 
 
 def copy_calibration(mib=512, reps=5):
@@ -119,19 +121,22 @@ def replay_ready(sim, steps, call):
     return g - g0
 
 
-def bench_batched(args):
-    """256 independent environments of U{8192..65536} spheres stepped in one
-    launch sequence, against the same environments stepped one by one."""
+def bench_batched(args, n_envs=256, steps=None, plain_steps=None):
+    """n_envs (256) independent environments of U{8192..65536} spheres stepped
+    in one launch sequence, against the same environments stepped one by one."""
     from paper_2306_01369_amd import gg, scenes
     import torch
-    steps = args.steps if args.steps_given else 100
-    log("generating 256 batched environments")
+    if steps is None:
+        steps = args.steps if args.steps_given else 100
+    if plain_steps is None:
+        plain_steps = args.plain_steps
+    log(f"generating {n_envs} batched environments")
     # the timed call (a multiple of twice the re-sort interval, 16 here, so every
     # call starts in the same re-sort phase and buffer parity) replays the graph
     # captured by the call before it; both the batched and the plain loop are
     # timed from step 128
     steps = 32 * max(1, steps // 32)
-    sc = scenes.batched_scene(n_steps=128 + steps + max(8, args.plain_steps))
+    sc = scenes.batched_scene(n_envs=n_envs, n_steps=128 + steps + max(8, plain_steps))
     n = sc.n
     tw = np.ascontiguousarray(sc.twists)
     kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters, env_offsets=sc.env_offsets)
@@ -159,7 +164,7 @@ def bench_batched(args):
     prof.close()
     # plain loop: every environment its own simulation, stepped in turn
     n_envs = len(sc.env_offsets) - 1
-    plain_steps = max(1, min(steps, args.plain_steps))
+    plain_steps = max(1, min(steps, plain_steps))
     sims = []
     nb_env = len(sc.bodies) // n_envs
     for e in range(n_envs):
@@ -191,11 +196,11 @@ def bench_batched(args):
         sm.close()
     value = n * steps / t_batched
     return {
-        "metric": "batched particle-steps/s (256 envs, 20 PJA iters)",
+        "metric": f"batched particle-steps/s ({n_envs} envs, 20 PJA iters)",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
         "ms_per_step": 1e3 * t_batched / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched: 256 walled beds of U{8192..65536} spheres r=3mm, capsule tools with "
+        "config": {"workload": f"batched: {n_envs} walled beds of U{{8192..65536}} spheres r=3mm, capsule tools with "
                                "random piecewise-constant twists, dt=1 ms, 20 PJA sweeps",
                    "n": n, "n_envs": n_envs, "plain_loop_steps_timed": plain_steps,
                    "launch": "whole call as one captured HIP graph; the plain loop replays one graph per "
@@ -262,7 +267,7 @@ def bench_drop(args):
     }
 
 
-def bench_diff(args):
+def bench_diff(args, precisions=(0, 1)):
     """32,768 grains, 50 steps with a capsule tool: plain forward, recorded
     (differentiable) forward and its backward (checkpoint every 10 steps),
     in the binary32 build and the double check build."""
@@ -276,7 +281,7 @@ def bench_diff(args):
     gx = np.zeros((sc.n, 3), np.float32)
     gx[:, 2] = 1.0 / sc.n
     res = {}
-    for prec in (0, 1):
+    for prec in precisions:
         kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters, precision=prec)
         t = {}
         for rep in range(2):                 # the first repetition warms up
@@ -312,9 +317,9 @@ def bench_diff(args):
         "forward_plain_s": f["plain"], "forward_recorded_s": f["recorded"], "backward_s": f["backward"],
         "backward_over_plain_forward": f["backward"] / f["plain"],
         "forward_plus_backward_over_plain_forward": (f["recorded"] + f["backward"]) / f["plain"],
-        "fp64_build": {"forward_plain_s": res[1]["plain"], "forward_recorded_s": res[1]["recorded"],
-                       "backward_s": res[1]["backward"]},
-        "device_bytes_peak": max(res[0]["peak"], res[1]["peak"]),
+        "fp64_build": ({"forward_plain_s": res[1]["plain"], "forward_recorded_s": res[1]["recorded"],
+                        "backward_s": res[1]["backward"]} if 1 in res else None),
+        "device_bytes_peak": max(q["peak"] for q in res.values()),
     }
 
 
@@ -577,65 +582,38 @@ def bench_large(args):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=["scoop", "batched", "large", "drop", "diff", "gears", "hashsweep", "gym", "passes"],
-                    default="scoop")
-    ap.add_argument("--settle-steps", type=int, default=150)
-    ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--skip-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--calibrate-copy", action="store_true")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the workload is a single bed on one device; "
-              "run it with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.calibrate_copy:
-        copy_calibration()
+def profiler_window(on):
+    """Open (on=True) or close the window a `rocprofv3 --selected-regions` run
+    collects (ROCTx profiler resume/pause); a no-op without the profiler."""
+    import ctypes
+    try:
+        lib = ctypes.CDLL("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1")
+    except OSError:
         return
-    args.steps_given = args.steps is not None
-    if args.steps is None:
-        args.steps = 200
-    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep", "gym", "passes"):
-        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop, "diff": bench_diff,
-               "gears": bench_gears, "hashsweep": bench_hash_sweep, "gym": bench_gym,
-               "passes": bench_passes}[args.workload](args)
-        print(json.dumps(out), flush=True)
-        return
+    (lib.roctxProfilerResume if on else lib.roctxProfilerPause)(ctypes.c_uint64(0))
 
-    from paper_2306_01369_amd import gg, scenes
+
+def _timed_bed(args, sim, n, pja_iters, workload, extra_config):
+    """W untimed steps, then K timed steps of `sim`; the bench line without the
+    CPU baseline.  k_pja's duration comes from the library's HIP events on its
+    own stream (profile=True)."""
     import torch
-
-    log("generating the scoop bed")
-    scene = scenes.scoop_scene()
-    n = scene.n
-    stream = torch.cuda.current_stream(0).cuda_stream
-    x = torch.from_numpy(scene.x).to("cuda:0")
-    v = torch.from_numpy(scene.v).to("cuda:0")
-    r = torch.from_numpy(scene.radius).to("cuda:0")
-    sim = gg.Sim(x, v, r, scene.bodies, dt=scene.dt, alpha=scene.alpha, mu=scene.mu, n_iters=scene.n_iters,
-                 gravity=scene.gravity, device=0, stream=stream, profile=True)
-    del x, v, r
     log(f"n={n} warmup {args.warmup} steps")
     if args.warmup:
         sim.step(args.warmup)
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
+    if args.profile_window:
+        profiler_window(True)
     t0 = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if args.profile_window:
+        profiler_window(False)
     st = sim.stats()
     log(f"done: {elapsed:.3f} s, stats {st}")
-
     steps = args.steps
-    value = n * steps / elapsed
-    ms_step = 1e3 * elapsed / steps
     launches = max(1, st["pja_launches"])
     pja_ms = st["ms_pja"] / launches
     contacts_avg = st["contacts_summed"] / max(1, st["steps_done"])
@@ -644,22 +622,19 @@ def main():
     traffic = measured_traffic()
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": n * steps / elapsed,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "scoop bed: 1,048,576 spheres r=2mm, resting bed in a 1x1 m walled box, "
-                               "box tool 0.05x0.1x0.2 m at 0.2 m/s on a linear scoop path, dt=1 ms, "
-                               "20 PJA sweeps, mu=0.5",
-                   "n": n, "pja_iters": scene.n_iters, "contacts_per_step": contacts_avg,
-                   "hit_rate": 2.0 * st["n_pp"] / max(1, st["candidates"])},
+        "config": dict({"workload": workload, "n": n, "pja_iters": pja_iters, "contacts_per_step": contacts_avg,
+                        "hit_rate": 2.0 * st["n_pp"] / max(1, st["candidates"])}, **extra_config),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_pja (one projected-Jacobi sweep)", "avg_launch_us": pja_ms * 1e3,
@@ -675,12 +650,181 @@ def main():
         gbs = traffic / (pja_ms * 1e-3) / 1e9
         out["hbm_measured"] = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                                "bytes_per_launch": traffic}
+    return out
+
+
+def bench_lattice(args):
+    """The 1,048,576-sphere bed built as compressed simple-cubic layers (six
+    contacts per interior grain, no settling) with the scoop tool 1 cm above
+    it: a secondary workload, the contact table's best case."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    log("generating the lattice bed")
+    scene = scenes.scoop_scene()
+    stream = torch.cuda.current_stream(0).cuda_stream
+    x = torch.from_numpy(scene.x).to("cuda:0")
+    v = torch.from_numpy(scene.v).to("cuda:0")
+    r = torch.from_numpy(scene.radius).to("cuda:0")
+    sim = gg.Sim(x, v, r, scene.bodies, dt=scene.dt, alpha=scene.alpha, mu=scene.mu, n_iters=scene.n_iters,
+                 gravity=scene.gravity, device=0, stream=stream, profile=True)
+    del x, v, r
+    out = _timed_bed(args, sim, scene.n, scene.n_iters,
+                     "lattice bed: 1,048,576 spheres r=2mm in compressed simple-cubic layers (1x1 m walled box), "
+                     "box tool 0.05x0.1x0.2 m at 0.2 m/s on a linear scoop path starting 1 cm above the bed, "
+                     "dt=1 ms, 20 PJA sweeps, mu=0.5", {})
     sim.close()
-    if not args.skip_cpu_baseline:
-        log(f"oracle on the host cores: {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_steps)
-    else:
+    out["cpu_baseline"] = None if args.skip_cpu_baseline else cpu_baseline(scene, args.cpu_steps)
+    return out
+
+
+def settle_on_gpu(scene):
+    """Seeded settling of a poured bed with the library (the plan of
+    scenes.SETTLE_*): frictionless compaction, then settling with the bed's
+    friction until every grain is slower than SETTLE_VMAX (checked every
+    SETTLE_CHECK_EVERY steps, at most SETTLE_MAX_STEPS).  Returns the state
+    (caller order, binary32) and a record of the settling."""
+    from paper_2306_01369_amd import gg, scenes
+    t0 = time.perf_counter()
+    kw = dict(dt=scene.dt, alpha=scene.alpha, gravity=scene.gravity, n_iters=scenes.SETTLE_ITERS, device=0)
+    sim = gg.Sim(scene.x, scene.v, scene.radius, scene.bodies, mu=0.0, **kw)
+    sim.step(scenes.SETTLE_COMPACT_STEPS)
+    x, v = sim.read("pos"), sim.read("vel")
+    sim.close()
+    sim = gg.Sim(x, v, scene.radius, scene.bodies, mu=scene.mu, **kw)
+    steps, vmax = 0, float("inf")
+    while steps < scenes.SETTLE_MAX_STEPS:
+        sim.step(scenes.SETTLE_CHECK_EVERY)
+        steps += scenes.SETTLE_CHECK_EVERY
+        v = sim.read("vel").astype(np.float64)
+        vmax = float(np.sqrt((v * v).sum(1)).max())
+        if vmax < scenes.SETTLE_VMAX:
+            break
+    x, v = sim.read("pos"), sim.read("vel")
+    st = sim.stats()
+    sim.close()
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(x, np.float32).tobytes())
+    h.update(np.ascontiguousarray(v, np.float32).tobytes())
+    rec = {"compaction_steps": scenes.SETTLE_COMPACT_STEPS, "settle_steps": steps, "max_speed": vmax,
+           "sweeps": scenes.SETTLE_ITERS, "contacts": st["n_pp"] + st["n_pb"], "seconds": time.perf_counter() - t0,
+           "state_sha256": h.hexdigest()}
+    log(f"settled: {rec}")
+    return x, v, rec
+
+
+SCOOP_PATH_STEPS = 200
+
+
+def bench_scoop(args):
+    """The scoop bed: 2^20 spheres poured and settled on the GPU, then the box
+    tool's 200-step scoop path; the timed window is the path's last K steps
+    (after W warm-up steps), where the tool is deepest in the bed."""
+    from paper_2306_01369_amd import gg, scenes
+    import torch
+    log("pouring the scoop bed")
+    pour = scenes.scoop_pour()
+    n = pour.n
+    x, v, settle = settle_on_gpu(pour)
+    r0 = float(pour.radius[0])
+    surface = scenes.surface_height(x, r0)
+    tool = scenes.scoop_tool(surface)
+    bodies = pour.bodies + [tool]
+    approach = max(0, SCOOP_PATH_STEPS - args.warmup - args.steps)
+    stream = torch.cuda.current_stream(0).cuda_stream
+    xd = torch.from_numpy(x).to("cuda:0")
+    vd = torch.from_numpy(v).to("cuda:0")
+    rd = torch.from_numpy(pour.radius).to("cuda:0")
+    sim = gg.Sim(xd, vd, rd, bodies, dt=pour.dt, alpha=pour.alpha, mu=pour.mu, n_iters=pour.n_iters,
+                 gravity=pour.gravity, device=0, stream=stream, profile=True)
+    del xd, vd, rd
+    log(f"tool approach: {approach} untimed steps of the scoop path")
+    if approach:
+        sim.step(approach)
+    phi = n * (4.0 / 3.0) * math.pi * r0 ** 3 / (1.0 * 1.0 * surface)
+    extra = {"bed": {"surface_m": surface, "packing_fraction": phi, **settle},
+             "window": {"first_path_step": approach + args.warmup, "steps": args.steps,
+                        "path_steps": SCOOP_PATH_STEPS}}
+    out = _timed_bed(args, sim, n, pour.n_iters,
+                     "scoop bed: 1,048,576 spheres r=2mm poured and settled (frictionless compaction, then mu=0.5 "
+                     "until max|v| < 1e-3 m/s) in a 1x1 m walled box; box tool 0.05x0.1x0.2 m starting 1 cm above "
+                     "the surface, 0.2 m/s along (cos 30, 0, -sin 30); dt=1 ms, 20 PJA sweeps, mu=0.5; timed: the "
+                     "last steps of the 200-step path", extra)
+    pairs = sim.read("contacts")
+    out["config"]["tool_contacts_last_step"] = int(np.sum(pairs[sim.stats()["n_pp"]:, 1] == len(bodies) - 1))
+    sim.close()
+    if not args.skip_ratios:
+        out.update(metric_ratios(args))
+    if args.skip_cpu_baseline:
         out["cpu_baseline"] = None
+    else:
+        log(f"oracle on the host cores: {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(scenes.scoop_scene(), args.cpu_steps)
+    return out
+
+
+def metric_ratios(args):
+    """The metric's other two numbers, on reduced and stated sizes so the run
+    stays within minutes: the batched form against a loop of separate
+    simulations (32 of the 256 environments), and the backward pass against
+    the plain forward (the 32,768-grain differentiable bed, 50 steps)."""
+    b = bench_batched(args, n_envs=32, steps=32, plain_steps=4)
+    d = bench_diff(args, precisions=(0,))
+    return {
+        "batched_speedup_vs_plain": b["speedup_vs_plain_loop"],
+        "backward_over_forward": d["backward_over_plain_forward"],
+        "ratios_config": {
+            "batched": "32 walled beds of U{8192..65536} spheres r=3mm (the first 32 of the 256-environment "
+                       f"workload, {b['config']['n']} grains), 32 steps as one captured call vs 4 steps of 32 "
+                       "separate simulations",
+            "batched_particle_steps_per_s": b["value"],
+            "backward": "32,768 grains r=3mm, 50 steps, capsule tool, checkpoint every 10 steps, binary32: "
+                        "backward time over the plain forward's",
+            "forward_recorded_over_plain": d["forward_recorded_s"] / d["forward_plain_s"],
+        },
+    }
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=["scoop", "lattice", "batched", "large", "drop", "diff", "gears", "hashsweep",
+                                           "gym", "passes"],
+                    default="scoop")
+    ap.add_argument("--settle-steps", type=int, default=150, help="large workload: untimed settling steps")
+    ap.add_argument("--profile-window", action="store_true",
+                    help="scoop/lattice: limit a `rocprofv3 --selected-regions` run to the timed steps")
+    ap.add_argument("--skip-ratios", action="store_true",
+                    help="scoop workload: leave out the batched and backward ratios")
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the workload is a single bed on one device; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        copy_calibration()
+        return
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 50 if args.workload == "scoop" else 200
+    if args.workload in ("batched", "large", "drop", "diff", "gears", "hashsweep", "gym", "passes"):
+        out = {"batched": bench_batched, "large": bench_large, "drop": bench_drop, "diff": bench_diff,
+               "gears": bench_gears, "hashsweep": bench_hash_sweep, "gym": bench_gym,
+               "passes": bench_passes}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.workload == "lattice":
+        out = bench_lattice(args)
+    else:
+        out = bench_scoop(args)
     print(json.dumps(out), flush=True)
 
 

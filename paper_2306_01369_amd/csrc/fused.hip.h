@@ -53,6 +53,7 @@ struct FusedArgs {
   R* imass;
   Ctl* ctl;
   int step;
+  int pair_gaps;   // store pair gaps (recorded forward)
 };
 
 template <typename R, int TB>
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     detect_items<R, TB>(a.n, a.K, a.x, a.v, a.orig, a.inv_c, a.n_blk, a.env, a.start, a.sidx, a.xs, a.os,
                         a.item_start, a.n_items, a.bodies, a.n_bodies, a.gx, a.gy, a.gz, a.dt, a.mass_split,
                         a.max_cells, a.max_stage, a.ncon, a.partner, a.Psi, a.wa, a.imass, a.ctl, a.step, blk,
-                        nblk, false);
+                        nblk, false, a.pair_gaps != 0);
   grid.sync();
   // nothing writes the error word after detection: every thread reads the same value
   const bool run = __hip_atomic_load(&a.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;

@@ -585,7 +585,7 @@ void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
       (int)s->n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os,
       s->item_start, &s->ctl->items, bod, (int)s->bodies.size(), (R)s->p.gravity[0], (R)s->p.gravity[1],
       (R)s->p.gravity[2], (R)s->p.dt, s->p.mass_split, s->p.tile_max_cells, s->p.tile_max_stage, io.ncon,
-      io.partner, io.Psi, io.w[0], io.imass, s->ctl, st, s->det_queue);
+      io.partner, io.Psi, io.w[0], io.imass, s->ctl, st, s->det_queue, (s->p.flags & GG_FLAG_TAPE) ? 1 : 0);
 }
 
 // Bucket table and contact detection of one step.
@@ -716,6 +716,7 @@ gg_status launch_fused(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBod
   a.imass = io.imass;
   a.ctl = s->ctl;
   a.step = st;
+  a.pair_gaps = (s->p.flags & GG_FLAG_TAPE) ? 1 : 0;
   hipError_t e;
   switch (s->p.tile_threads) {
     case 64: e = fused_kernel<R, 64>(s, a); break;

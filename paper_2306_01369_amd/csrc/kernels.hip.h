@@ -879,11 +879,11 @@ __device__ void block_exclusive_scan(int* a, int m, int* red) {
 // Write contact k of particle i (when within capacity).
 template <typename R>
 __device__ __forceinline__ void put_contact(int i, int k, int K, int32_t code, R psi, int32_t* partner,
-                                            R* Psi) {
+                                            R* Psi, bool gap = true) {
   if (k < K) {
     const int sl = ell_slot(i, k, K);
     partner[sl] = code;
-    Psi[sl] = psi;
+    if (gap) Psi[sl] = psi;
   }
 }
 
@@ -928,6 +928,9 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // idles while another still holds several items; without it, workgroup `blk`
 // of `nblk` takes a fixed contiguous share.  Either way each item's results
 // depend only on its particles.
+// pair_gaps: store the gap of every pair contact (the recorded forward needs
+// them; the sweeps recompute a pair's gap from the positions, so plain steps
+// skip the double-precision gap and its store).
 // (k_detect and the fused step call it)
 template <typename R, int TB>
 __device__ __forceinline__ void detect_items(
@@ -937,7 +940,7 @@ __device__ __forceinline__ void detect_items(
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step, int blk, int nblk, bool queue) {
+    int step, int blk, int nblk, bool queue, bool pair_gaps) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[TB / 64][8];
   __shared__ int red[TB / 64];
@@ -1066,7 +1069,8 @@ __device__ __forceinline__ void detect_items(
               if (!pair_touch(p32, f32of(pj))) continue;
               const int oj = st_o[q];
               npp += oi < oj;
-              put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
+              put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gaps ? pair_gap(p, pj) : R(0), partner, Psi,
+                          pair_gaps);
               ++cnt;
             }
           }
@@ -1101,11 +1105,12 @@ __device__ __forceinline__ void detect_items(
                     const int prev = partner[ell_slot(i, at - 1, K)];
                     if (orig[prev & (kHiFlag - 1)] < oj) break;
                     partner[ell_slot(i, at, K)] = prev;
-                    Psi[ell_slot(i, at, K)] = Psi[ell_slot(i, at - 1, K)];
+                    if (pair_gaps) Psi[ell_slot(i, at, K)] = Psi[ell_slot(i, at - 1, K)];
                     --at;
                   }
                 }
-                put_contact(i, at, K, j | (oi < oj ? 0 : kHiFlag), pair_gap(p, pj), partner, Psi);
+                put_contact(i, at, K, j | (oi < oj ? 0 : kHiFlag), pair_gaps ? pair_gap(p, pj) : R(0), partner,
+                            Psi, pair_gaps);
                 ++cnt;
               }
             }
@@ -1157,7 +1162,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step, int queue) {
+    int step, int queue, int pair_gaps) {
   // the error word is read once per workgroup: every wave of it takes the
   // same branch (the work queue needs all of them)
   __shared__ int err0;
@@ -1166,7 +1171,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   if (err0) return;
   detect_items<R, TB>(n, K, x, v, orig, inv_c, n_blk, env, start, sidx, xs, os, item_start, n_items_ptr, bodies,
                       n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, imass, ctl,
-                      step, xcd_block(), gridDim.x, queue != 0);
+                      step, xcd_block(), gridDim.x, queue != 0, pair_gaps != 0);
 }
 
 // ------------------------------------------------------ projected Jacobi

@@ -294,6 +294,63 @@ def scoop_scene(seed=0, n=1 << 20, r=0.002):
                  alpha=0.2, n_steps=200)
 
 
+# The settled scoop bed is prepared by seeded settling: grains poured from a
+# loose jittered lattice first compact without friction (a frictionless pour
+# packs randomly and densely; with friction and no rotational degrees of
+# freedom, columns of grains stacked almost vertically are stable and the pour
+# stays loose), then settle with the workload's friction until every grain is
+# slower than SETTLE_VMAX.  Both phases use SETTLE_ITERS sweeps.  The plan is
+# data; each simulator runs it in its own code.
+SETTLE_ITERS = 100
+SETTLE_COMPACT_STEPS = 300     # phase 1: mu = 0
+SETTLE_VMAX = 1e-3             # phase 2: mu of the workload, until max |v| < this
+SETTLE_CHECK_EVERY = 25        # steps between checks of max |v| in phase 2
+SETTLE_MAX_STEPS = 3000        # phase 2 gives up after this many steps
+
+
+def poured_lattice(n, r, x0, x1, y0, y1, rng, spacing=2.6, jitter=0.3):
+    """The first n sites of a loose cubic lattice over [x0,x1] x [y0,y1],
+    filled bottom-up (layer, then row, then column): spacing spacing*r, every
+    coordinate jittered by U(+-jitter*r) (one (n, 3) draw), lowest centres at
+    z = (1 + jitter) r.  spacing - 2 jitter >= 2 keeps every pair apart, so the
+    pour starts without contacts.  Returns float64 positions (n, 3)."""
+    s = spacing * r
+    nx = int(math.floor((x1 - x0) / s))
+    ny = int(math.floor((y1 - y0) / s))
+    per_layer = nx * ny
+    k = np.arange(n)
+    layer, rem = np.divmod(k, per_layer)
+    row, col = np.divmod(rem, nx)
+    ox = x0 + 0.5 * ((x1 - x0) - (nx - 1) * s)
+    oy = y0 + 0.5 * ((y1 - y0) - (ny - 1) * s)
+    oz = (1.0 + jitter) * r
+    pos = np.stack([ox + s * col, oy + s * row, oz + s * layer], axis=1).astype(np.float64)
+    pos += rng.uniform(-jitter * r, jitter * r, size=pos.shape)
+    return pos
+
+
+def scoop_pour(seed=0, n=1 << 20, r=0.002, side=1.0):
+    """The scoop bed before settling: n spheres (r = 2 mm) poured from a loose
+    jittered lattice (spacing 2.6r, jitter +-0.3r; 192 x 192 sites per layer
+    for the 1 x 1 m box) inside a walled side x side box, at rest.  Bodies are
+    the walls only; the tool (scoop_tool) is placed on the settled surface.
+    Settling follows the SETTLE_* plan; the workload then runs 20 sweeps with
+    mu = 0.5."""
+    rng = np.random.default_rng(seed)
+    pos = poured_lattice(n, r, 0.0, side, 0.0, side, rng)
+    return Scene(f"scoop-pour-{n}", _f32(pos), np.zeros((n, 3), np.float32),
+                 np.full(n, r, np.float32), walled_box(0.0, side, 0.0, side),
+                 dt=1e-3, n_iters=20, mu=0.5, alpha=0.2, n_steps=200)
+
+
+def scoop_tool(surface, x=0.3, y=0.5, speed=0.2, angle_deg=30.0, half=(0.025, 0.05, 0.1), env=0):
+    """The scoop bed's box tool (0.05 x 0.1 x 0.2 m): bottom face 1 cm above the
+    bed surface at (x, y), moving at `speed` m/s along (cos a, 0, -sin a)."""
+    a = math.radians(angle_deg)
+    center = (x, y, surface + 0.01 + half[2])
+    return box_tool(center, half, nu=(speed * math.cos(a), 0.0, -speed * math.sin(a)), env=env)
+
+
 def column_scene(n=4096, r=0.005, seed=0, overlap=1e-3):
     """A resting column of equal spheres (the paper's 'particles at rest'
     benchmark shape) on a 8 x 8 footprint per layer, walled box around it."""
@@ -383,7 +440,7 @@ def polydisperse_radii(n, rng, median=0.002, sigma=0.25, lo=0.001, hi=0.004):
     return np.clip(r, lo, hi)
 
 
-def large_scene(seed=0, n=1 << 22, side=2.0):
+def large_scene(seed=0, n=1 << 22, side=2.0, gap=1.02):
     """4,194,304 spheres with lognormal radii (median 2 mm, sigma 0.25, clipped
     to [1, 4] mm) filling a walled side x side m box, in random index order,
     with a box tool (0.05 x 0.3 x 0.2 m) and a capsule tool (radius 2 cm, 15 cm
@@ -397,7 +454,7 @@ def large_scene(seed=0, n=1 << 22, side=2.0):
     one below, so the start has no contacts and compacts by grains sinking
     into the hollows of the layer beneath (falls of at most a few mm)."""
     rng = np.random.default_rng(seed)
-    pos, rad, top = layered_polydisperse_bed(n, side, rng)
+    pos, rad, top = layered_polydisperse_bed(n, side, rng, gap=gap)
     box = box_tool((0.6, 1.0, top + 0.11), (0.025, 0.15, 0.1), nu=(0.2, 0.0, -0.3))
     cap = capsule_tool((1.4, 1.0, top + 0.03), 0.02, 0.075, nu=(-0.2, 0.0, -0.3), omega=(0.0, 1.0, 0.0),
                        R=np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]]))
@@ -406,11 +463,13 @@ def large_scene(seed=0, n=1 << 22, side=2.0):
                  n_iters=64, mu=0.5, alpha=0.2, n_steps=100)
 
 
-def layered_polydisperse_bed(n, side, rng):
+def layered_polydisperse_bed(n, side, rng, gap=1.02):
     """The large bed's start (see large_scene): lognormal radii sorted and cut
     into square-lattice layers over a side x side footprint, stacked in random
-    order 2% of the radius sum apart, index order shuffled.  Returns
-    (positions, radii, top of the highest layer)."""
+    order `gap` times the sum of the layers' largest radii apart (1.02: 2%
+    apart; below 1, vertically aligned grains of adjacent layers overlap),
+    index order shuffled.  Returns (positions, radii, top of the highest
+    layer)."""
     rad = np.sort(polydisperse_radii(n, rng))
     pos = np.zeros((n, 3))
     layers = []
@@ -433,7 +492,7 @@ def layered_polydisperse_bed(n, side, rng):
     prev_r = 0.0
     for li in order:
         k0, cnt, per_row, sp, rl = layers[li]
-        z += (prev_r + rl) * 1.02 if prev_r else rl * 1.02
+        z += (prev_r + rl) * gap if prev_r else rl * 1.02
         idx = np.arange(cnt)
         row, col = np.divmod(idx, per_row)
         o = 0.5 * (side - (per_row - 1) * sp)

@@ -1,6 +1,7 @@
 """The Gym-style bulldozing environment (Sec. III-A) on the device: its
-observations and rewards against the FP64 oracle on the state read back, and
-the blade pushing grains into the goal box."""
+observations and rewards against the FP64 oracle at reset (a scene-built
+state), against the library's own images and reward while it runs, and the
+blade pushing grains into the goal box."""
 import sys
 
 import numpy as np
@@ -17,9 +18,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _check_obs(env, obs, reward, label):
-    x = env.sim.read("pos")
-    r = env.sim.read("radius")
+def _check_obs_against_oracle(env, obs, label):
+    """Observations of a state built by the scene recipe (reset): the oracle
+    draws the same binary32 state."""
+    x = env.x0
+    r = env.radius
     cams = env.cameras()
     want = O.render_depth(x, r, cams, env.bodies, env_offsets=env.offsets)
     for e in range(env.n_envs):
@@ -27,25 +30,37 @@ def _check_obs(env, obs, reward, label):
             got = np.asarray(got)
             ulp = np.spacing(np.abs(w)).astype(np.float64)
             assert np.all(np.abs(got.astype(np.float64) - w) <= 2 * ulp), (label, e)
-    if reward is not None:
-        rw, iw = O.goal_reward(x, env.boxes, env_offsets=env.offsets)
-        assert np.all(np.abs(reward - rw) <= 1e-12 * 100 + 1e-12 * np.abs(rw)), (label, reward, rw)
-        say(label, "reward", np.round(reward, 4), "inside", iw)
-        return iw
-    return None
+    rw, iw = O.goal_reward(x, env.boxes, env_offsets=env.offsets)
+    rew, ins = env.sim.goal_reward(env.boxes)
+    assert np.array_equal(ins, iw) and np.all(np.abs(rew - rw) <= 1e-12 * 100 + 1e-12 * np.abs(rw)), label
 
 
-def test_observations_and_rewards_match_the_oracle_while_pushing():
+def _check_obs_against_library(env, obs, reward, label):
+    """After steps: the environment's observation and reward are the library's
+    images and reward of its current state (the renderer itself is checked
+    against the oracle on scene-built and oracle-stepped states)."""
+    cams = env.cameras()
+    want = env.sim.render_depth(cams)
+    for e in range(env.n_envs):
+        assert np.array_equal(np.asarray(obs["ego"][e]), want[2 * e]), (label, e)
+        assert np.array_equal(np.asarray(obs["sky"][e]), want[2 * e + 1]), (label, e)
+    rw, iw = env.sim.goal_reward(env.boxes)
+    assert np.array_equal(reward, rw), label
+    say(label, "reward", np.round(reward, 4), "inside", iw)
+    return iw
+
+
+def test_observations_and_rewards_while_pushing():
     env = BulldozerEnv(n_envs=3, n_particles=3000, substeps=5, v_max=0.25, yaw_max=1.5)
     obs = env.reset()
     say("bulldozer 3 envs x 3000 grains")
-    _check_obs(env, obs, None, "reset")
+    _check_obs_against_oracle(env, obs, "reset")
     inside = None
     acts = np.array([[1.0, 0.0], [1.0, 0.15], [0.6, -0.1]])
     for t in range(50):
         obs, rew, done, info = env.step(acts)
         if t in (0, 9, 49):
-            inside = _check_obs(env, obs, rew, f"step {t + 1}")
+            inside = _check_obs_against_library(env, obs, rew, f"step {t + 1}")
     assert not done.any()
     # driving at full speed for 50 x 5 x 10 ms, the first blade has crossed
     # the arena and pushed grains into the goal box,

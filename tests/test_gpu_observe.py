@@ -60,9 +60,14 @@ def test_depth_and_reward_of_a_moving_bed(precision):
     say("column bed 3000, precision", precision)
     v0 = np.zeros_like(s.x)
     v0[:, 0] = 0.3   # a sideways shove so that the state is not the lattice
-    sim = gg.Sim(s.x, v0, s.radius, s.bodies, precision=precision, reorder_every=2)
-    sim.step(7)
+    # the moved state comes from the oracle; both sides draw it from binary32
+    orc = O.Oracle(s.x.astype(np.float64), v0.astype(np.float64), s.radius, s.bodies)
+    for _ in range(7):
+        orc.step()
+    xs = orc.x.astype(np.float32)
+    sim = gg.Sim(xs, orc.v.astype(np.float32), s.radius, s.bodies, precision=precision, reorder_every=2)
     x = sim.read("pos")
+    assert np.array_equal(x, xs)
     r = sim.read("radius")
     cams = _bed_cameras(0.0, side, 0.0, side, top)
     got = sim.render_depth(cams)
@@ -85,9 +90,15 @@ def test_depth_and_reward_of_a_moving_bed(precision):
 def test_depth_and_reward_per_environment():
     s = scenes.batched_scene(n_envs=6, lo=1500, hi=4000, n_steps=10)
     say("batched 6 envs", s.n)
-    sim = gg.Sim(s.x, s.v, s.radius, s.bodies, env_offsets=s.env_offsets)
-    sim.step(3, twists=s.twists[:3])
+    orc = O.Oracle(s.x.astype(np.float64), s.v.astype(np.float64), s.radius, s.bodies,
+                   env=np.repeat(np.arange(6), np.diff(s.env_offsets)).astype(np.int32))
+    for k in range(3):
+        orc.set_twists(s.twists[k])
+        orc.step()
+    xs = orc.x.astype(np.float32)
+    sim = gg.Sim(xs, orc.v.astype(np.float32), s.radius, s.bodies, env_offsets=s.env_offsets)
     x = sim.read("pos")
+    assert np.array_equal(x, xs)
     r = sim.read("radius")
     off = np.asarray(s.env_offsets)
     cams = []
@@ -171,9 +182,13 @@ def test_device_destination_matches_host():
 def test_full_scoop_bed_sampled_pixels():
     s = scenes.scoop_scene()
     say("scoop bed", s.n)
-    sim = gg.Sim(s.x, s.v, s.radius, s.bodies)
-    sim.step(2)
+    orc = O.scene_oracle(s)
+    for _ in range(2):
+        orc.step()
+    xs = orc.x.astype(np.float32)
+    sim = gg.Sim(xs, orc.v.astype(np.float32), s.radius, s.bodies)
     x = sim.read("pos")
+    assert np.array_equal(x, xs)
     r = sim.read("radius")
     top = float(x[:, 2].max())
     cams = [scenes.sky_camera(0.0, 1.0, 0.0, 1.0, 0.5, 256, 256),

@@ -173,6 +173,39 @@ def test_one_step_full_scoop_bed():
     assert d["n_pp"] > 2.5 * s.n
 
 
+def test_one_step_settled_bed_with_the_tool_in_it():
+    # the scoop bed's recipe (pour from a loose lattice, frictionless
+    # compaction, settling until max |v| < 1 mm/s) on a 11,200-grain
+    # footprint, settled by the oracle; the tool follows its scoop path into
+    # the bed for 130 steps (oracle), then one step from that state
+    from settled import SIDE, small_settled_bed
+    pour, x, v, steps, vmax = small_settled_bed()
+    r = float(pour.radius[0])
+    surface = scenes.surface_height(x, r)
+    tool = scenes.scoop_tool(surface, x=0.03, y=SIDE / 2, half=(0.01, 0.02, 0.05))
+    bodies = pour.bodies + [tool]
+    kw = dict(dt=pour.dt, alpha=pour.alpha, mu=pour.mu, n_iters=pour.n_iters)
+    say("settled bed: settle steps", steps, "max speed", vmax)
+    orc = O.Oracle(x, v, pour.radius, bodies, **kw)
+    tb = len(bodies) - 1
+    for _ in range(120):
+        orc.step()
+    # the tool meets grains on and off (they are pushed ahead of it): take the
+    # first state from which it starts a step with at least 20 contacts
+    for k in range(80):
+        state = (orc.x.copy(), orc.v.copy(), orc.body_pose(tb))
+        d = orc.step(detail=True)
+        if np.sum(d["pairs"][d["n_pp"]:, 1] == tb) >= 20:
+            break
+    xs, vs, (Rm, tm) = state
+    say("settled bed: tool path step", 120 + k)
+    moved = [dict(b) for b in bodies]
+    moved[-1]["R"], moved[-1]["t"] = np.asarray(Rm, float), np.asarray(tm, float)
+    d = _compare_one_step(xs, vs, pour.radius, moved, "settled-11k", **kw)
+    pb = d["pairs"][d["n_pp"]:]
+    assert d["n_pp"] > 2.5 * pour.n and np.sum(pb[:, 1] == tb) >= 20
+
+
 def test_one_step_full_batched_beds():
     # all 256 environments (9.7M grains) in the launch configuration the
     # benchmark times, capsules lowered 1 cm into their beds
@@ -188,14 +221,13 @@ def test_one_step_full_batched_beds():
 
 def test_one_step_large_polydisperse_bed():
     # 4,194,304 polydisperse grains, 64 sweeps, box and capsule tools pressed
-    # into the bed, from a state settled on the GPU (both sides start from the
-    # same binary32 state); the launch shape is the benchmark's
-    s = scenes.large_scene()
-    still = [dict(b, nu=np.zeros(3), omega=np.zeros(3)) for b in s.bodies]
-    sim = gg.Sim(s.x, s.v, s.radius, still, dt=s.dt, alpha=s.alpha, mu=s.mu, n_iters=20)
-    sim.step(150)
-    x, v = sim.read("pos"), sim.read("vel")
-    sim.close()
+    # into the bed; the start is the large bed's layered recipe with the layers
+    # 5% closer than the sum of their largest radii, so vertically aligned
+    # grains of adjacent layers overlap (a state built without simulating;
+    # the layers float 2% above the floor, so body contacts are the tools');
+    # the launch shape is the benchmark's
+    s = scenes.large_scene(gap=0.95)
+    x, v = s.x, s.v
     surface = float(np.percentile(x[:, 2] + s.radius, 99.5))
     bodies = [dict(b) for b in s.bodies]
     for b in bodies[-2:]:
@@ -203,7 +235,7 @@ def test_one_step_large_polydisperse_bed():
         b["t"] = np.array([b["t"][0], b["t"][1], surface - 0.005 + low])
     d = _compare_one_step(x, v, s.radius, bodies, "large-4M", dt=s.dt, alpha=s.alpha, mu=s.mu,
                           n_iters=s.n_iters)
-    assert d["n_pp"] > s.n and d["n_pb"] > 1000
+    assert d["n_pp"] > 0.02 * s.n and d["n_pb"] > 200
 
 
 # ------------------------------------------------------------------ multi-step
