@@ -361,6 +361,24 @@ gg_status gg_render_depth(gg_sim* sim, int32_t n_cams, const gg_camera* cams, fl
  * Errors: GG_ERR_INVALID, GG_ERR_OOM, GG_ERR_HIP. */
 gg_status gg_goal_reward(gg_sim* sim, const float* boxes, double* reward, int64_t* inside, gg_mem where);
 
+/* gg_goal_reward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, checks, kernels and results (bit for bit) as
+ * gg_goal_reward, with no hipMalloc, hipFree or other allocation.  The
+ * per-call workspace (a partial sum per chunk of at most 4096 particles of one
+ * environment, the staged boxes and, for host outputs, the staged results)
+ * lives in a 2 MiB device array of the library, one copy per GPU, held until
+ * the process ends.  It needs 12 bytes per chunk and 40 bytes per environment,
+ * each of its five regions rounded up to 256 bytes; a simulation beyond that
+ * (about 170,000 chunks, or 50,000 environments) is rejected with
+ * GG_ERR_INVALID before any device work.  Every call on a GPU shares that
+ * array: calls that overlap on one GPU (from several host threads, or on
+ * streams not ordered with each other) race.  Returns after the results are
+ * written.  Errors: as gg_goal_reward, GG_ERR_INVALID also for a simulation
+ * beyond the workspace. */
+gg_status gg_goal_reward_noalloc(gg_sim* sim, const float* boxes, double* reward, int64_t* inside,
+                                 gg_mem where);
+
 /* Release every resource of the handle (NULL is ignored). */
 void gg_destroy(gg_sim* sim);
 

@@ -13,6 +13,13 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
+
+// Workspace of gg_goal_reward_noalloc: one copy per GPU, held until the process
+// ends; every call on a GPU shares it.
+constexpr size_t kNoAllocScratchBytes = (size_t)2 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -470,6 +477,34 @@ gg_status copy_in(const void* src, size_t bytes, gg_mem where, void* host_dst) {
   }
   hipError_t e = hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(GG_ERR_HIP, std::string("copy of device input: ") + hipGetErrorString(e));
+  return GG_OK;
+}
+
+// Goal-reward chunk tables, fixed for a simulation: chunks of at most
+// kRewardChunk particles, none spanning two environments (env, begin, end),
+// each environment's first chunk, and its particle count.
+gg_status build_reward_tables(gg_sim* s) {
+  const int ne = s->n_envs;
+  std::vector<int32_t> ch, ec(ne + 1, 0), cnt(ne);
+  for (int e = 0; e < ne; ++e) {
+    ec[e] = (int32_t)(ch.size() / 3);
+    cnt[e] = (int32_t)(s->env_off[e + 1] - s->env_off[e]);
+    for (int64_t b = s->env_off[e]; b < s->env_off[e + 1]; b += ggk::kRewardChunk) {
+      ch.push_back(e);
+      ch.push_back((int32_t)b);
+      ch.push_back((int32_t)std::min<int64_t>(b + ggk::kRewardChunk, s->env_off[e + 1]));
+    }
+  }
+  ec[ne] = (int32_t)(ch.size() / 3);
+  const int nc = ec[ne];
+  bool ok = dev_alloc(&s->d_chunks, (size_t)std::max(1, nc) * 3) == hipSuccess &&
+            dev_alloc(&s->d_env_chunk, (size_t)ne + 1) == hipSuccess &&
+            dev_alloc(&s->d_env_count, (size_t)std::max(1, ne)) == hipSuccess;
+  if (!ok) return fail(GG_ERR_OOM, "reward table allocation failed");
+  if (nc > 0) HIPCHK(s, hipMemcpy(s->d_chunks, ch.data(), ch.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(s, hipMemcpy(s->d_env_chunk, ec.data(), ec.size() * 4, hipMemcpyHostToDevice));
+  if (ne > 0) HIPCHK(s, hipMemcpy(s->d_env_count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
+  s->n_chunks = nc;
   return GG_OK;
 }
 
@@ -1150,6 +1185,8 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->stats.detect_queues = s->det_queue ? 1 : 0;
   st = ensure_ell(s, compute_K(s));
   if (st != GG_OK) return bail(st);
+  st = build_reward_tables(s);
+  if (st != GG_OK) return bail(st);
   sample_memory(s);
   *out = s;
   return GG_OK;
@@ -1753,6 +1790,80 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
 }
 
 
+// Per-call workspace of the goal reward: partial sums per chunk, the staged
+// boxes, and the staged results for host outputs.
+struct RewardWork {
+  double* part_d;
+  int32_t* part_n;
+  float* boxes;
+  double* reward;
+  int64_t* inside;
+};
+
+gg_status reward_check(gg_sim* s, const float* boxes, const double* reward, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  if (!boxes || !reward) return fail(GG_ERR_INVALID, "boxes and reward are required");
+  for (int e = 0; e < s->n_envs; ++e)
+    for (int q = 0; q < 3; ++q) {
+      const float lo = boxes[6 * e + q], hi = boxes[6 * e + 3 + q];
+      if (!std::isfinite(lo) || !std::isfinite(hi) || lo > hi)
+        return fail(GG_ERR_INVALID, "goal boxes must be finite with lo <= hi");
+    }
+  return GG_OK;
+}
+
+// Stage the boxes, sum each chunk, combine the chunks of each environment in
+// order, copy host results out; returns after the results are written.
+gg_status reward_run(gg_sim* s, const float* boxes, double* reward, int64_t* inside, gg_mem where,
+                     const RewardWork& W) {
+  const int ne = s->n_envs;
+  HIPCHK(s, hipMemcpyAsync(W.boxes, boxes, (size_t)ne * 24, hipMemcpyHostToDevice, s->stream));
+  if (s->n_chunks > 0) {
+    if (s->fp64)
+      ggk::k_reward_chunks<double><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const double4*)s->x, s->d_chunks,
+                                                                            W.boxes, W.part_d, W.part_n);
+    else
+      ggk::k_reward_chunks<float><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const float4*)s->x, s->d_chunks,
+                                                                           W.boxes, W.part_d, W.part_n);
+    HIPCHK(s, hipGetLastError());
+  }
+  double* rw = where == GG_MEM_DEVICE ? reward : W.reward;
+  int64_t* in = where == GG_MEM_DEVICE ? inside : (inside ? W.inside : nullptr);
+  if (ne > 0) {
+    ggk::k_reward_envs<<<(ne + 255) / 256, 256, 0, s->stream>>>(ne, s->d_env_chunk, s->d_env_count, W.part_d,
+                                                                 W.part_n, rw, in);
+    HIPCHK(s, hipGetLastError());
+  }
+  if (where == GG_MEM_HOST && ne > 0) {
+    HIPCHK(s, hipMemcpyAsync(reward, W.reward, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
+    if (inside) HIPCHK(s, hipMemcpyAsync(inside, W.inside, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return GG_OK;
+}
+
+// Address of this device's copy of the no-allocation workspace, taken once per
+// device with that device current (the array's name in host code is not a
+// device address).
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+gg_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GG_ERR_INVALID, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(GG_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1993,69 +2104,45 @@ gg_status gg_render_depth(gg_sim* s, int32_t n_cams, const gg_camera* cams, floa
 }
 
 gg_status gg_goal_reward(gg_sim* s, const float* boxes, double* reward, int64_t* inside, gg_mem where) {
-  g_detail.clear();
-  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
-  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
-  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
-  if (!boxes || !reward) return fail(GG_ERR_INVALID, "boxes and reward are required");
+  gg_status st = reward_check(s, boxes, reward, where);
+  if (st != GG_OK) return st;
   const int ne = s->n_envs;
-  for (int e = 0; e < ne; ++e)
-    for (int q = 0; q < 3; ++q) {
-      const float lo = boxes[6 * e + q], hi = boxes[6 * e + 3 + q];
-      if (!std::isfinite(lo) || !std::isfinite(hi) || lo > hi)
-        return fail(GG_ERR_INVALID, "goal boxes must be finite with lo <= hi");
-    }
   DeviceGuard g(s->dev);
-  if (!s->d_chunks) {
-    // chunks of at most kRewardChunk particles, none spanning two environments
-    std::vector<int32_t> ch, ec(ne + 1, 0), cnt(ne);
-    for (int e = 0; e < ne; ++e) {
-      ec[e] = (int32_t)(ch.size() / 3);
-      cnt[e] = (int32_t)(s->env_off[e + 1] - s->env_off[e]);
-      for (int64_t b = s->env_off[e]; b < s->env_off[e + 1]; b += ggk::kRewardChunk) {
-        ch.push_back(e);
-        ch.push_back((int32_t)b);
-        ch.push_back((int32_t)std::min<int64_t>(b + ggk::kRewardChunk, s->env_off[e + 1]));
-      }
-    }
-    ec[ne] = (int32_t)(ch.size() / 3);
-    const int nc = ec[ne];
-    bool ok = dev_alloc(&s->d_chunks, (size_t)std::max(1, nc) * 3) == hipSuccess &&
-              dev_alloc(&s->d_env_chunk, (size_t)ne + 1) == hipSuccess &&
-              dev_alloc(&s->d_env_count, (size_t)ne) == hipSuccess &&
-              dev_alloc(&s->d_part_n, (size_t)std::max(1, nc)) == hipSuccess &&
-              dev_alloc(&s->d_part_d, (size_t)std::max(1, nc)) == hipSuccess &&
-              dev_alloc(&s->d_boxes, (size_t)ne * 6) == hipSuccess && dev_alloc(&s->d_reward, (size_t)ne) == hipSuccess &&
-              dev_alloc(&s->d_inside, (size_t)ne) == hipSuccess;
+  if (!s->d_part_d) {
+    const size_t nc = (size_t)std::max(1, s->n_chunks);
+    bool ok = dev_alloc(&s->d_part_n, nc) == hipSuccess && dev_alloc(&s->d_part_d, nc) == hipSuccess &&
+              dev_alloc(&s->d_boxes, (size_t)std::max(1, ne) * 6) == hipSuccess &&
+              dev_alloc(&s->d_reward, (size_t)std::max(1, ne)) == hipSuccess &&
+              dev_alloc(&s->d_inside, (size_t)std::max(1, ne)) == hipSuccess;
     if (!ok) return fail(GG_ERR_OOM, "reward buffer allocation failed");
-    if (nc > 0) HIPCHK(s, hipMemcpy(s->d_chunks, ch.data(), ch.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(s->d_env_chunk, ec.data(), ec.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(s->d_env_count, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice));
-    s->n_chunks = nc;
   }
-  HIPCHK(s, hipMemcpyAsync(s->d_boxes, boxes, (size_t)ne * 24, hipMemcpyHostToDevice, s->stream));
-  if (s->n_chunks > 0) {
-    if (s->fp64)
-      ggk::k_reward_chunks<double><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const double4*)s->x, s->d_chunks,
-                                                                            s->d_boxes, s->d_part_d, s->d_part_n);
-    else
-      ggk::k_reward_chunks<float><<<s->n_chunks, ggk::kBlock, 0, s->stream>>>((const float4*)s->x, s->d_chunks,
-                                                                           s->d_boxes, s->d_part_d, s->d_part_n);
-    HIPCHK(s, hipGetLastError());
-  }
-  double* rw = where == GG_MEM_DEVICE ? reward : s->d_reward;
-  int64_t* in = where == GG_MEM_DEVICE ? inside : (inside ? s->d_inside : nullptr);
-  ggk::k_reward_envs<<<(ne + 255) / 256, 256, 0, s->stream>>>(ne, s->d_env_chunk, s->d_env_count, s->d_part_d,
-                                                               s->d_part_n, rw, in);
-  HIPCHK(s, hipGetLastError());
-  if (where == GG_MEM_HOST) {
-    HIPCHK(s, hipMemcpyAsync(reward, s->d_reward, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
-    if (inside) HIPCHK(s, hipMemcpyAsync(inside, s->d_inside, (size_t)ne * 8, hipMemcpyDeviceToHost, s->stream));
-  }
-  HIPCHK(s, hipStreamSynchronize(s->stream));
-  return GG_OK;
+  return reward_run(s, boxes, reward, inside, where,
+                    RewardWork{s->d_part_d, s->d_part_n, s->d_boxes, s->d_reward, s->d_inside});
 }
 
+gg_status gg_goal_reward_noalloc(gg_sim* s, const float* boxes, double* reward, int64_t* inside, gg_mem where) {
+  gg_status st = reward_check(s, boxes, reward, where);
+  if (st != GG_OK) return st;
+  // the workspace carved from the device array: partial sums per chunk,
+  // staged boxes, staged results (host outputs only)
+  const size_t nc = (size_t)std::max(1, s->n_chunks), ne = (size_t)std::max(1, s->n_envs);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_n = up(nc * 8), o_b = o_n + up(nc * 4), o_r = o_b + up(ne * 24), o_i = o_r + up(ne * 8);
+  const size_t need = o_i + up(ne * 8);
+  if (need > kNoAllocScratchBytes)
+    return fail(GG_ERR_INVALID, "goal reward of " + std::to_string(s->n_chunks) + " chunks and " +
+                                    std::to_string(s->n_envs) + " environments needs " + std::to_string(need) +
+                                    " bytes of workspace; the no-allocation call has " +
+                                    std::to_string(kNoAllocScratchBytes));
+  DeviceGuard g(s->dev);
+  if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+  unsigned char* w = nullptr;
+  st = scratch_address(s->dev, &w);
+  if (st != GG_OK) return st;
+  return reward_run(s, boxes, reward, inside, where,
+                    RewardWork{(double*)w, (int32_t*)(w + o_n), (float*)(w + o_b), (double*)(w + o_r),
+                               (int64_t*)(w + o_i)});
+}
 void gg_destroy(gg_sim* s) {
   if (!s) return;
   {

@@ -25,7 +25,7 @@ FIELD = {"pos": 0, "vel": 1, "cell_index": 2, "contacts": 3, "impulses": 4, "sta
 SHAPES = {"plane": 0, "box": 1, "capsule": 2, "grid": 3}
 
 EXPORTS = ("gg_create", "gg_set_bodies", "gg_set_grids", "gg_step", "gg_step_backward", "gg_read",
-           "gg_render_depth", "gg_goal_reward", "gg_destroy",
+           "gg_render_depth", "gg_goal_reward", "gg_goal_reward_noalloc", "gg_destroy",
            "gg_status_string", "gg_error_detail")
 
 
@@ -138,6 +138,8 @@ def lib():
         L.gg_render_depth.argtypes = [vp, i32, vp, vp, i64, i32]
         L.gg_goal_reward.restype = i32
         L.gg_goal_reward.argtypes = [vp, vp, vp, vp, i32]
+        L.gg_goal_reward_noalloc.restype = i32
+        L.gg_goal_reward_noalloc.argtypes = [vp, vp, vp, vp, i32]
         L.gg_destroy.restype = None
         L.gg_destroy.argtypes = [vp]
         L.gg_status_string.restype = C.c_char_p
@@ -390,16 +392,18 @@ class Sim:
         _check(lib().gg_render_depth(self._h, int(n_cams), C.byref(cam_array), ptr, nbytes, where))
         return out
 
-    def goal_reward(self, boxes):
-        """(reward, inside) per environment for goal boxes n_envs x (lo, hi)."""
+    def goal_reward(self, boxes, noalloc=False):
+        """(reward, inside) per environment for goal boxes n_envs x (lo, hi);
+        noalloc: through gg_goal_reward_noalloc (no device allocation)."""
         bx = np.ascontiguousarray(boxes, np.float32).reshape(-1, 6)
         ne = bx.shape[0]
         if ne != self.n_envs:
             raise ValueError(f"need one goal box per environment ({self.n_envs}), got {ne}")
         rew = np.zeros(ne, np.float64)
         ins = np.zeros(ne, np.int64)
-        _check(lib().gg_goal_reward(self._h, bx.ctypes.data_as(C.c_void_p), rew.ctypes.data_as(C.c_void_p),
-                                    ins.ctypes.data_as(C.c_void_p), GG_MEM_HOST))
+        call = lib().gg_goal_reward_noalloc if noalloc else lib().gg_goal_reward
+        _check(call(self._h, bx.ctypes.data_as(C.c_void_p), rew.ctypes.data_as(C.c_void_p),
+                    ins.ctypes.data_as(C.c_void_p), GG_MEM_HOST))
         return rew, ins
 
     def backward(self, dL_dx=None, dL_dv=None, n_steps=None):
