@@ -680,9 +680,10 @@ def bench_lattice(args):
 def settle_on_gpu(scene):
     """Seeded settling of a poured bed with the library (the plan of
     scenes.SETTLE_*): frictionless compaction, then settling with the bed's
-    friction until every grain is slower than SETTLE_VMAX (checked every
-    SETTLE_CHECK_EVERY steps, at most SETTLE_MAX_STEPS).  Returns the state
-    (caller order, binary32) and a record of the settling."""
+    friction until all but scenes.settle_fast_allowed(n) grains are slower
+    than SETTLE_VMAX (checked every SETTLE_CHECK_EVERY steps, at most
+    SETTLE_MAX_STEPS).  Returns the state (caller order, binary32) and a record
+    of the settling."""
     from paper_2306_01369_amd import gg, scenes
     t0 = time.perf_counter()
     kw = dict(dt=scene.dt, alpha=scene.alpha, gravity=scene.gravity, n_iters=scenes.SETTLE_ITERS, device=0)
@@ -691,13 +692,16 @@ def settle_on_gpu(scene):
     x, v = sim.read("pos"), sim.read("vel")
     sim.close()
     sim = gg.Sim(x, v, scene.radius, scene.bodies, mu=scene.mu, **kw)
-    steps, vmax = 0, float("inf")
+    steps, vmax, fast = 0, float("inf"), scene.n
+    allowed = scenes.settle_fast_allowed(scene.n)
     while steps < scenes.SETTLE_MAX_STEPS:
         sim.step(scenes.SETTLE_CHECK_EVERY)
         steps += scenes.SETTLE_CHECK_EVERY
         v = sim.read("vel").astype(np.float64)
-        vmax = float(np.sqrt((v * v).sum(1)).max())
-        if vmax < scenes.SETTLE_VMAX:
+        speed = np.sqrt((v * v).sum(1))
+        vmax = float(speed.max())
+        fast = int((speed >= scenes.SETTLE_VMAX).sum())
+        if fast <= allowed:
             break
     x, v = sim.read("pos"), sim.read("vel")
     st = sim.stats()
@@ -706,6 +710,7 @@ def settle_on_gpu(scene):
     h.update(np.ascontiguousarray(x, np.float32).tobytes())
     h.update(np.ascontiguousarray(v, np.float32).tobytes())
     rec = {"compaction_steps": scenes.SETTLE_COMPACT_STEPS, "settle_steps": steps, "max_speed": vmax,
+           "grains_at_or_above_1mm_s": fast, "p999_speed": float(np.percentile(speed, 99.9)),
            "sweeps": scenes.SETTLE_ITERS, "contacts": st["n_pp"] + st["n_pb"], "seconds": time.perf_counter() - t0,
            "state_sha256": h.hexdigest()}
     log(f"settled: {rec}")
@@ -746,7 +751,8 @@ def bench_scoop(args):
                         "path_steps": SCOOP_PATH_STEPS}}
     out = _timed_bed(args, sim, n, pour.n_iters,
                      "scoop bed: 1,048,576 spheres r=2mm poured and settled (frictionless compaction, then mu=0.5 "
-                     "until max|v| < 1e-3 m/s) in a 1x1 m walled box; box tool 0.05x0.1x0.2 m starting 1 cm above "
+                     "until at most 10 grains move at 1 mm/s or more) in a 1x1 m walled box; box tool 0.05x0.1x0.2 m "
+                     "starting 1 cm above "
                      "the surface, 0.2 m/s along (cos 30, 0, -sin 30); dt=1 ms, 20 PJA sweeps, mu=0.5; timed: the "
                      "last steps of the 200-step path", extra)
     pairs = sim.read("contacts")
