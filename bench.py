@@ -583,14 +583,13 @@ def bench_large(args):
 
 
 def profiler_window(on):
-    """Open (on=True) or close the window a `rocprofv3 --selected-regions` run
-    collects (ROCTx profiler resume/pause); a no-op without the profiler."""
-    import ctypes
-    try:
-        lib = ctypes.CDLL("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1")
-    except OSError:
-        return
-    (lib.roctxProfilerResume if on else lib.roctxProfilerPause)(ctypes.c_uint64(0))
+    """Mark the start (on=True) or end of the timed steps in a profiler's
+    kernel list: one short spin kernel (torch's `_sleep`, one thread) on the
+    current stream, so a summary can keep only the dispatches between the two
+    marks."""
+    import torch
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
 
 
 def _timed_bed(args, sim, n, pja_iters, workload, extra_config):
@@ -801,7 +800,7 @@ def main():
                     default="scoop")
     ap.add_argument("--settle-steps", type=int, default=150, help="large workload: untimed settling steps")
     ap.add_argument("--profile-window", action="store_true",
-                    help="scoop/lattice: limit a `rocprofv3 --selected-regions` run to the timed steps")
+                    help="scoop/lattice: bracket the timed steps with marker kernels for a profiler summary")
     ap.add_argument("--skip-ratios", action="store_true",
                     help="scoop workload: leave out the batched and backward ratios")
     ap.add_argument("--plain-steps", type=int, default=5)

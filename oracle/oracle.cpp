@@ -980,11 +980,12 @@ int64_t ggo_step_jvp(const Params* P, int64_t n, double* x, double* v, double* d
         y1 = y1 * f;
         y2 = y2 * f;
       }
-      if (!(yn.v > 0)) {
-        // A non-positive normal part projects the whole impulse to zero, and
-        // so it does on a neighbourhood: the tangent is zero.  The tangential
-        // test alone would keep the tangents of y_t where y_t is exactly zero
-        // (0 > 0 is false), which is not the derivative of the projection.
+      if (!(mu * yn.v > 0)) {
+        // A friction disk of radius zero (a non-positive normal part, or no
+        // friction) maps the tangential part to zero, and so it does on a
+        // neighbourhood: its tangent is zero.  The tangential test alone
+        // would keep the tangents of y_t where y_t is exactly zero (0 > 0 is
+        // false), which is not the derivative of the projection.
         y1.d = 0.0;
         y2.d = 0.0;
       }

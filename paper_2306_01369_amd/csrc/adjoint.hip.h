@@ -53,8 +53,18 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
     yb[0] = yb[1] = yb[2] = R(0);
     return;
   }
-  if (!scaled) {  // Q = y
-    for (int a = 0; a < 3; ++a) yb[a] = Qb[a];
+  if (!scaled) {
+    if (mu * ynp > R(0)) {  // Q = y (inside the friction disk)
+      for (int a = 0; a < 3; ++a) yb[a] = Qb[a];
+      return;
+    }
+    // no friction and y_t exactly zero: Q = (n.y) n, the tangential part is
+    // dropped on a neighbourhood too, so only the normal part has a derivative
+    const R qn = dot3f(Qb, n);
+    for (int a = 0; a < 3; ++a) {
+      yb[a] = qn * n[a];
+      nb[a] += qn * y[a] + yn * Qb[a];
+    }
     return;
   }
   // Q = yn n + mu yn t/|t|

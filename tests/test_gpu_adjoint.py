@@ -319,6 +319,76 @@ def test_differentiable_bed_gradients_along_16_directions():
     assert max(errs[1]) <= REL_TOL
 
 
+def _diff_bed(steps):
+    from paper_2306_01369_amd import scenes as S
+    sc = S.diff_scene()
+    nb = len(sc.bodies)
+    tw = np.zeros((steps, nb, 6))
+    tw[:, -1, :3] = np.float32(sc.bodies[-1]["nu"])
+    top = S.surface_height(sc.x, float(sc.radius[0]))
+    loss = TargetLoss((0.15, 0.15, top), (0.05, 0.05, 0.025), width=1e-3)
+    return sc.x, sc.v, sc.radius, sc.bodies, tw, loss
+
+
+def test_differentiable_bed_binary32_gradient_over_ten_steps():
+    """The production (binary32) build on the 32,768-grain bed over 10 steps
+    (its contact lists equal the oracle's for the first 16): its gradient
+    along 6 unit directions in x0 is within 1e-3 of the oracle's dual numbers.
+    Over longer horizons the binary32 trajectory itself moves away from the
+    FP64 one (the next test shows the binary32 adjoint is exact for its own
+    trajectory), and the two gradients are those of different trajectories."""
+    from gradcheck import jvp_directional
+    x, v, r, bodies, tw, loss = _diff_bed(10)
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=EXACT_G)
+    diffs = _contact_list_differences(x, v, r, bodies, tw, **kw)
+    assert all(d == (0, 0) for d in diffs)
+    (gx0, _, _), st = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=10, **kw)
+    rng = np.random.default_rng(2024)
+    errs = []
+    for k in range(6):
+        dx = rng.normal(size=x.shape)
+        dx /= np.linalg.norm(dx)
+        ref = jvp_directional(loss, x.astype(np.float64), v.astype(np.float64), r, bodies, tw,
+                              (dx, np.zeros(x.shape), np.zeros_like(tw)), **kw)
+        errs.append(abs(np.sum(gx0 * dx) - ref) / abs(ref))
+    say("binary32 rel err over 10 steps:", ["%.2e" % e for e in errs])
+    assert max(errs) <= REL_TOL
+
+
+def test_binary32_adjoint_is_the_double_adjoint_of_its_own_trajectory():
+    """Rounding of the binary32 adjoint, apart from trajectory decorrelation:
+    along the binary32 trajectory of the 32,768-grain bed (16 steps, states
+    and body poses read back after every step), the double build's one-step
+    adjoints chained backwards from the same loss gradient give dL/dx0 and
+    dL/dv0 within 1e-4 of the binary32 build's own 16-step backward pass."""
+    x, v, r, bodies, tw, loss = _diff_bed(16)
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=EXACT_G)
+    H, nb = tw.shape[0], tw.shape[1]
+    sim = gg.Sim(x, v, r, bodies, **kw)
+    xs, vs, poses = [x.copy()], [v.copy()], [sim.read("body_poses")]
+    for k in range(H):
+        sim.step(1, twists=tw[k:k + 1].astype(np.float32))
+        xs.append(sim.read("pos"))
+        vs.append(sim.read("vel"))
+        poses.append(sim.read("body_poses"))
+    sim.close()
+    gx, gv = loss.grads(xs[-1].astype(np.float64), vs[-1].astype(np.float64))
+    (g32x, g32v, _), _ = _gpu_grads(x, v, r, bodies, tw, loss, checkpoint_every=10, **kw)
+    for k in range(H - 1, -1, -1):
+        bk = [dict(b) for b in bodies]
+        for q in range(nb):
+            bk[q]["R"] = poses[k][q][:, :3].astype(np.float64)
+            bk[q]["t"] = poses[k][q][:, 3].astype(np.float64)
+        one = gg.Sim(xs[k], vs[k], r, bk, differentiable=True, checkpoint_every=1, precision=1, **kw)
+        one.step(1, twists=tw[k:k + 1].astype(np.float32))
+        gx, gv, _ = one.backward(np.asarray(gx, np.float32), np.asarray(gv, np.float32))
+        one.close()
+    ex = np.linalg.norm(g32x - gx) / np.linalg.norm(gx)
+    ev = np.linalg.norm(g32v - gv) / np.linalg.norm(gv)
+    say("binary32 adjoint vs chained double adjoints on its trajectory: x0", ex, "v0", ev)
+    assert ex <= 1e-4 and ev <= 1e-4
+
+
 def test_adjoint_with_a_grid_tool_matches_dual_numbers():
     # colliding grains around a spinning bowl sampled on a grid: the adjoint
     # through the trilinear interpolant, its normalised gradient and its

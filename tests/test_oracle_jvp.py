@@ -168,3 +168,31 @@ def test_separating_contact_with_zero_tangential_velocity_has_zero_derivative():
         assert same
         assert abs(fd) < 1e-9, (comp, fd)
         assert ref == 0.0, (comp, ref)
+
+
+def test_frictionless_contact_with_zero_tangential_velocity_ignores_the_body_sliding():
+    # A sphere pressed onto a frictionless ground plane that slides along x,
+    # moving with it (relative tangential velocity exactly zero).  Without
+    # friction the plane's tangential velocity cannot act on the sphere: the
+    # disk of radius mu y_n = 0 drops the tangential part on a neighbourhood,
+    # so the derivative with respect to nu_x and nu_y is zero (central
+    # differences agree), while nu_z (normal) acts.
+    r = 0.004
+    ground = scenes.plane((0.0, 0.0, 0.0), (0.0, 0.0, 1.0))
+    ground["nu"] = np.array([0.1, 0.0, 0.0])
+    x = np.array([[0.0, 0.0, r - 1e-5]])
+    v = np.array([[0.1, 0.0, -0.05]])
+    kw = dict(dt=1e-3, alpha=0.2, mu=0.0, gravity=(0.0, 0.0, -9.81))
+    tw = np.array([[[0.1, 0.0, 0.0, 0.0, 0.0, 0.0]]])
+    loss = TargetLoss((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), width=1e-3, vel_weight=(1.0, 1.0, 1.0))
+    z = np.zeros((1, 3))
+    for comp in range(3):
+        dtw = np.zeros_like(tw)
+        dtw[0, 0, comp] = 1.0
+        ref = jvp_directional(loss, x, v, np.full(1, r, np.float32), [ground], tw, (z, z, dtw), **kw)
+        fd, same = fd_directional(loss, x, v, np.full(1, r, np.float32), [ground], tw, (z, z, dtw), 1e-7, **kw)
+        assert same
+        if comp < 2:
+            assert abs(fd) < 1e-9 and ref == 0.0, (comp, fd, ref)
+        else:
+            assert abs(ref - fd) <= 1e-6 * abs(fd) and abs(fd) > 0.1, (fd, ref)
