@@ -738,14 +738,31 @@ def bench_scoop(args):
     xd = torch.from_numpy(x).to("cuda:0")
     vd = torch.from_numpy(v).to("cuda:0")
     rd = torch.from_numpy(pour.radius).to("cuda:0")
-    sim = gg.Sim(xd, vd, rd, bodies, dt=pour.dt, alpha=pour.alpha, mu=pour.mu, n_iters=pour.n_iters,
-                 gravity=pour.gravity, device=0, stream=stream, profile=True)
+    kw = dict(dt=pour.dt, alpha=pour.alpha, mu=pour.mu, n_iters=pour.n_iters, gravity=pour.gravity)
+    sim = gg.Sim(xd, vd, rd, bodies, device=0, stream=stream, profile=True, **kw)
     del xd, vd, rd
     log(f"tool approach: {approach} untimed steps of the scoop path")
     if approach:
         sim.step(approach)
+    tuned = None
+    if not args.no_tune:
+        # the launch shape for this bed, timed by the autotuner from the state
+        # the window starts in (every candidate gives the same bits)
+        from paper_2306_01369_amd import autotune
+        x1, v1, poses = sim.read("pos"), sim.read("vel"), sim.read("body_poses")
+        sim.close()
+        for q, b in enumerate(bodies):
+            b["R"], b["t"] = poses[q][:, :3].astype(np.float64), poses[q][:, 3].astype(np.float64)
+        t0 = time.perf_counter()
+        table = []
+        params = autotune.tune(x1, v1, pour.radius, bodies, sim_kwargs=kw, use_cache=False, record=table)
+        tuned = {"params": params, "seconds": time.perf_counter() - t0,
+                 "default_ms_per_step": table[0][1] if table and table[0][1] else None,
+                 "tuned_ms_per_step": min(t for _, t in table if t) if table else None}
+        log(f"autotune: {tuned}")
+        sim = gg.Sim(x1, v1, pour.radius, bodies, device=0, stream=stream, profile=True, **kw, **params)
     phi = n * (4.0 / 3.0) * math.pi * r0 ** 3 / (1.0 * 1.0 * surface)
-    extra = {"bed": {"surface_m": surface, "packing_fraction": phi, **settle},
+    extra = {"bed": {"surface_m": surface, "packing_fraction": phi, **settle}, "autotune": tuned,
              "window": {"first_path_step": approach + args.warmup, "steps": args.steps,
                         "path_steps": SCOOP_PATH_STEPS}}
     out = _timed_bed(args, sim, n, pour.n_iters,
@@ -801,6 +818,8 @@ def main():
     ap.add_argument("--settle-steps", type=int, default=150, help="large workload: untimed settling steps")
     ap.add_argument("--profile-window", action="store_true",
                     help="scoop/lattice: bracket the timed steps with marker kernels for a profiler summary")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="scoop: time the library's default launch shape instead of the autotuned one")
     ap.add_argument("--skip-ratios", action="store_true",
                     help="scoop workload: leave out the batched and backward ratios")
     ap.add_argument("--plain-steps", type=int, default=5)

@@ -127,8 +127,10 @@ typedef struct {
   float gravity[3];  /* external acceleration (F_ext / m) */
   int32_t n_iters;   /* projected-Jacobi sweeps per step, Alg. 1 (>= 1) */
   float cell_size;   /* hash cell edge c; 0 -> 2 r_max (1 + 2^-10); must be >= 2 r_max */
-  int64_t hash_size; /* buckets n_h per environment; 0 -> 2 x (particles of the env),
-                        the heuristic of Sec. II-B */
+  int64_t hash_size; /* buckets n_h per environment of Eq. (6) (the reported cell index);
+                        0 -> 2 x (particles of the env), the heuristic of Sec. II-B.  The
+                        internal table follows it, with at least 4 buckets per particle in
+                        a single environment of 2^18 or more particles */
   float relax;       /* over-relaxation of the impulse update, 0 -> 1 */
   int32_t mass_split;/* 1: per-contact mass m/n_i (mass splitting); 0: plain masses */
   int32_t checkpoint_every;          /* backward pass: steps per checkpoint (0 -> 10) */
@@ -277,7 +279,9 @@ typedef struct {
   int64_t last_status;    /* gg_status of the last gg_step call */
   int64_t n;              /* particles */
   int64_t n_buckets;      /* buckets of the internal cell table over all environments (per
-                             environment hash_size rounded up to a multiple of 64) */
+                             environment hash_size, or 4 per particle in a single environment
+                             of 2^18 or more particles if that is larger, rounded up to a
+                             multiple of 64) */
   double ms_detect;       /* profiled: cell keys + sort + detection, summed over the last call */
   double ms_pja;          /* profiled: projected-Jacobi sweeps, summed */
   double ms_integrate;    /* profiled: position update, summed */

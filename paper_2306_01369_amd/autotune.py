@@ -108,12 +108,14 @@ def cell_factors():
 
 
 def tune(x, v, radius, bodies, sim_kwargs=None, steps=32, warmup=8, use_cache=True, verbose=False,
-         tune_cell=False, margin=0.02):
+         tune_cell=False, margin=0.02, record=None):
     """Return the fastest launch-shape parameters for this workload (a dict of
     gg.Sim keyword arguments).  With tune_cell the cell size is tuned too:
     a larger cell changes which cell, and so which list position, a partner
     falls in, hence the summation order and the rounding of the impulses
-    (never the contact set); by default it stays at the smallest cell."""
+    (never the contact set); by default it stays at the smallest cell.
+    record: a list that receives (candidate, ms per step or None) for every
+    candidate timed, the library's defaults first."""
     sim_kwargs = dict(sim_kwargs or {})
     ppc = particles_per_cell(x, radius)
     key = key_of(len(x), ppc, len(bodies)) + ("|cell" if tune_cell else "")
@@ -148,6 +150,8 @@ def tune(x, v, radius, bodies, sim_kwargs=None, steps=32, warmup=8, use_cache=Tr
             return None
         if verbose:
             print(f"autotune: {cand} -> {1e3 * t:.3f} ms/step, fallback items {st['detect_fallback']}")
+        if record is not None:
+            record.append((dict(cand), 1e3 * t))
         return t
 
     best, best_t = {}, timed({})     # the library's defaults

@@ -973,7 +973,15 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
     env_nh[e] = (int32_t)nh;
     env_boff[e] = (int32_t)total;
     total += nh;
-    const int64_t blk = (nh + 63) / 64;
+    // The internal table (the counting sort's buckets) follows n_h, but a
+    // large single bed gets at least four buckets per particle: Z-order nodes
+    // that share a block of buckets stage each other's particles, and at two
+    // per particle about a third of the nodes share one (1M-grain settled
+    // bed: 9-12 items per step exceed the detection tile and take the
+    // per-particle path; none at four).  Eq. (6)'s index still uses n_h.
+    int64_t tab = nh;
+    if (n_envs == 1 && ne >= ((int64_t)1 << 18)) tab = std::max<int64_t>(tab, 4 * ne);
+    const int64_t blk = (tab + 63) / 64;
     env_tblk[e] = (int32_t)blk;
     env_toff[e] = (int32_t)total_tab;
     total_tab += 64 * blk;
