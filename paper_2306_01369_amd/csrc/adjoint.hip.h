@@ -8,25 +8,32 @@
 // contact geometry (normals, gaps, body point velocities) differentiated with
 // respect to positions, body poses and twists (SDF gradients and Hessians).
 //
-// Recorded impulses are indexed compactly, pofs[i] + k with pofs the prefix
-// sum of the contact counts; the adjoint's per-contact state, read and written
-// in every reverse sweep, like the contact table (slot-major per 64
-// particles), so that a wavefront's loads of it are whole rows.
-// Per half contact the adjoint keeps a carry (the adjoint of the impulse of the
-// previous sweep, identical bits in both halves of a pair, as the forward's
-// impulse copies) and accumulators of the adjoints of the normal, the gap and
-// the body point velocity over all sweeps; per particle it keeps the adjoint
-// of the iterate.  Like the forward, every particle gathers its own half
-// contacts: no atomics, deterministic results.
+// Recorded impulses are indexed compactly from pofs, the prefix sum of the
+// contact counts, as the forward sweep of the same lane count wrote them
+// (jagged rows per wavefront with one lane per particle, rec_row; pofs[i] + k
+// with several).  Per half contact the adjoint keeps a carry (the
+// adjoint of the impulse of the previous sweep, identical bits in both halves
+// of a pair, as the forward's impulse copies), read and written in every
+// reverse sweep and indexed like the contact table (slot-major per 64
+// particles), so that a wavefront's loads of it are whole rows.  The geometry
+// of a pair (normal and gap, functions of the two positions) enters linearly
+// in the adjoints of its normal and gap, so every reverse sweep adds its share
+// of a pair's position adjoint straight into the particle's xbar; only body
+// contacts accumulate the adjoints of their normal, gap and body point
+// velocity over the sweeps (compact index), for the body pose and twist
+// adjoints.  Per particle the adjoint keeps the adjoint of the iterate, whose
+// w component carries the particle's inverse mass.  Like the forward, every
+// particle gathers its own half contacts: no atomics, deterministic results.
 #pragma once
 #include "kernels.hip.h"
 
 namespace ggk {
 
 template <typename R>
-struct AdjSlots {         // per half-contact adjoint state (SoA), indexed like the contact table
-  R *cx, *cy, *cz;    // carry: adjoint of the impulse of the previous sweep
-  R *nx, *ny, *nz;    // accumulated adjoint of the contact normal (lower-index orientation)
+struct AdjSlots {     // per half-contact adjoint state (SoA)
+  R *cx, *cy, *cz;    // carry: adjoint of the impulse of the previous sweep (contact-table slot)
+  // body contacts only, compact index pofs[i] + k:
+  R *nx, *ny, *nz;    // accumulated adjoint of the contact normal
   R *ps;              // accumulated adjoint of the gap psi
   R *vx, *vy, *vz;    // accumulated adjoint of the body point velocity V
 };
@@ -83,13 +90,17 @@ __device__ __forceinline__ void proj_adjoint(const R y[3], const R n[3], R mu, c
 
 // One half contact of a reverse sweep: recomputes y of sweep l for contact
 // `code` of particle i from the recorded impulse P^(l-1) (compact index q) and
-// iterate w^(l-1), updates the contact's adjoint state (at its contact-table
-// slot, so that a wavefront's k-th contacts are one row) and returns ub (the adjoint of
-// its velocity residual) with the sign sg it takes in i's sum.  Multiply-adds
-// are fused only within an expression (fp contract on), so every kernel that
-// calls it computes the same bits.
+// iterate w^(l-1) (recorded impulse at index qp, body accumulators at the
+// per-particle compact index q), updates the contact's carry (at its contact-table slot, so
+// that a wavefront's k-th contacts are one row) and returns ub (the adjoint of
+// its velocity residual) with the sign sg it takes in i's sum, and xg, this
+// sweep's share of a pair's adjoint of x_i through its normal n = d / |d| and
+// gap psi = |d| - r_i - r_j (d = x_lo - x_hi): sg ((nbar - (nbar.n) n) / |d| +
+// psibar n).  A body contact instead adds its shares to the accumulators at q.
+// Multiply-adds are fused only within an expression (fp contract on), so every
+// kernel that calls it computes the same bits.
 template <typename R>
-__device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool first_sweep, bool fresh,
+__device__ __forceinline__ void half_contact_adj(int code, int slot, int qp, int q, bool first_sweep, bool fresh,
                                                  const V4<R>& xi,
                                                  const V4<R>& vi, const V4<R>& wi, const V4<R>& bi,
                                                  const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
@@ -98,14 +109,14 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
                                                  const R* __restrict__ Ppx, const R* __restrict__ Ppy,
                                                  const R* __restrict__ Ppz, AdjSlots<R>& A,
                                                  const DevBody* __restrict__ bodies, R alpha_dt, R mu, R relax,
-                                                 R ub[3], R& sg) {
+                                                 R ub[3], R& sg, R xg[3]) {
 #pragma clang fp contract(on)
   const R psi = Psi[slot];
   R P[3] = {R(0), R(0), R(0)};
   if (!first_sweep) {
-    P[0] = Ppx[q]; P[1] = Ppy[q]; P[2] = Ppz[q];
+    P[0] = Ppx[qp]; P[1] = Ppy[qp]; P[2] = Ppz[qp];
   }
-  R nrm[3], u[3], mt, Pb[3];
+  R nrm[3], u[3], mt, Pb[3], il = R(0);
   // (fresh: the first reverse sweep of a step, whose state starts at zero)
   const R carry[3] = {fresh ? R(0) : A.cx[slot], fresh ? R(0) : A.cy[slot], fresh ? R(0) : A.cz[slot]};
   bool lo = true, body = code < 0;
@@ -115,7 +126,7 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
     const V4<R> xj = x[j];
     const V4<R> wj = w_prev[j];
     const V4<R> bj = wbar_in[j];
-    const R imj = v[j].w;
+    const R imj = bj.w;
     const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
     const V4<R> wl = lo ? wi : wj, wh = lo ? wj : wi;
     const V4<R> bl = lo ? bi : bj, bh = lo ? bj : bi;
@@ -123,7 +134,7 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
     const R d0 = xl.x - xh.x, d1 = xl.y - xh.y, d2 = xl.z - xh.z;
     const R L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     if (L > R(0)) {
-      const R il = R(1) / L;
+      il = R(1) / L;
       nrm[0] = d0 * il; nrm[1] = d1 * il; nrm[2] = d2 * il;
     } else {
       nrm[0] = R(0); nrm[1] = R(0); nrm[2] = R(1);
@@ -154,21 +165,28 @@ __device__ __forceinline__ void half_contact_adj(int code, int slot, int q, bool
   A.cz[slot] = yb[2] + keep * Pb[2];
   ub[0] = -mt * yb[0]; ub[1] = -mt * yb[1]; ub[2] = -mt * yb[2];
   const R bb = -mt * dot3f(yb, nrm);
-  A.nx[slot] = (fresh ? R(0) : A.nx[slot]) + (nb[0] - mt * bias * yb[0]);
-  A.ny[slot] = (fresh ? R(0) : A.ny[slot]) + (nb[1] - mt * bias * yb[1]);
-  A.nz[slot] = (fresh ? R(0) : A.nz[slot]) + (nb[2] - mt * bias * yb[2]);
-  A.ps[slot] = (fresh ? R(0) : A.ps[slot]) + alpha_dt * bb;
-  if (body) {
-    A.vx[slot] = (fresh ? R(0) : A.vx[slot]) - ub[0];
-    A.vy[slot] = (fresh ? R(0) : A.vy[slot]) - ub[1];
-    A.vz[slot] = (fresh ? R(0) : A.vz[slot]) - ub[2];
-  }
+  const R ns[3] = {nb[0] - mt * bias * yb[0], nb[1] - mt * bias * yb[1], nb[2] - mt * bias * yb[2]};
+  const R pss = alpha_dt * bb;
   sg = lo ? R(1) : R(-1);
+  xg[0] = xg[1] = xg[2] = R(0);
+  if (body) {
+    A.nx[q] = (fresh ? R(0) : A.nx[q]) + ns[0];
+    A.ny[q] = (fresh ? R(0) : A.ny[q]) + ns[1];
+    A.nz[q] = (fresh ? R(0) : A.nz[q]) + ns[2];
+    A.ps[q] = (fresh ? R(0) : A.ps[q]) + pss;
+    A.vx[q] = (fresh ? R(0) : A.vx[q]) - ub[0];
+    A.vy[q] = (fresh ? R(0) : A.vy[q]) - ub[1];
+    A.vz[q] = (fresh ? R(0) : A.vz[q]) - ub[2];
+  } else if (il > R(0)) {
+    const R nn = dot3f(nrm, ns);
+    for (int a = 0; a < 3; ++a) xg[a] = sg * ((ns[a] - nn * nrm[a]) * il + pss * nrm[a]);
+  }
 }
 
 // One reverse sweep: from wbar_in (adjoint of iterate l) to wbar_out (adjoint of
 // iterate l-1).  Recomputes y of sweep l from the recorded impulses P^(l-1) and
-// iterate w^(l-1).  Also accumulates wbar_in into the adjoint of w0.
+// iterate w^(l-1).  Also accumulates wbar_in into the adjoint of w0 and the
+// sweep's pair geometry shares into xbar.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pja_adj(
     int n, int K, const V4<R>* __restrict__ x, const V4<R>* __restrict__ v,
@@ -176,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
     V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
     const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
     const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
-    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs) {
+    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs, V4<R>* __restrict__ xbar) {
 #pragma clang fp contract(on)
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -185,19 +203,25 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj(
   const V4<R> vi = v[i];
   const V4<R> wi = w_prev[i];
   const V4<R> bi = wbar_in[i];
-  R acc[3] = {R(0), R(0), R(0)};
+  R acc[3] = {R(0), R(0), R(0)}, gx[3] = {R(0), R(0), R(0)};
   const int c = ncon[i];
+  int rbase = pofs[i & ~63];
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
-    R ub[3], sg;
-    half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x, v, w_prev, wbar_in,
-                        Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
+    R ub[3], sg, xg[3];
+    const int qp = rec_row(rbase);
+    half_contact_adj<R>(partner[slot], slot, qp, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x, v, w_prev, wbar_in,
+                        Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg, xg);
     acc[0] += sg * ub[0]; acc[1] += sg * ub[1]; acc[2] += sg * ub[2];
+    gx[0] += xg[0]; gx[1] += xg[1]; gx[2] += xg[2];
   }
-  wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], R(0));
+  wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], vi.w);
   V4<R> z = w0bar[i];
   z.x += bi.x; z.y += bi.y; z.z += bi.z;
   w0bar[i] = z;
+  V4<R> g = xbar[i];
+  g.x += gx[0]; g.y += gx[1]; g.z += gx[2];
+  xbar[i] = g;
 }
 
 // The same reverse sweep with L lanes per particle (L = 2 or 4): lane s takes
@@ -210,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj_lanes(
     V4<R>* __restrict__ w0bar, const int32_t* __restrict__ ncon, const int32_t* __restrict__ partner,
     const R* __restrict__ Psi, const R* __restrict__ Ppx, const R* __restrict__ Ppy,
     const R* __restrict__ Ppz, AdjSlots<R> A, const DevBody* __restrict__ bodies, R alpha_dt, R mu,
-    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs) {
+    R relax, int first_sweep, int fresh, const int32_t* __restrict__ pofs, V4<R>* __restrict__ xbar) {
 #pragma clang fp contract(on)
   static_assert(L == 2 || L == 4, "lanes per particle");
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -221,45 +245,52 @@ __global__ __launch_bounds__(kBlock) void k_pja_adj_lanes(
   const V4<R> vi = v[i];
   const V4<R> wi = w_prev[i];
   const V4<R> bi = wbar_in[i];
-  R acc[3] = {R(0), R(0), R(0)};
+  R acc[3] = {R(0), R(0), R(0)}, gx[3] = {R(0), R(0), R(0)};
   const int c = ncon[i];
   for (int m = 0; m * L < c; ++m) {
     const int k = m * L + sub;
-    R ub[3] = {R(0), R(0), R(0)}, sg = R(0);
+    R ub[3] = {R(0), R(0), R(0)}, sg = R(0), xg[3] = {R(0), R(0), R(0)};
     if (k < c) {
       const int slot = ell_slot(i, k, K);
-      half_contact_adj<R>(partner[slot], slot, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x, v, w_prev,
-                          wbar_in, Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg);
+      half_contact_adj<R>(partner[slot], slot, pbase + k, pbase + k, first_sweep != 0, fresh != 0, xi, vi, wi, bi, x,
+                          v, w_prev, wbar_in, Psi, Ppx, Ppy, Ppz, A, bodies, alpha_dt, mu, relax, ub, sg, xg);
     }
 #pragma unroll
     for (int qq = 0; qq < L; ++qq) {
       const R g = __shfl(sg, qq, L), u0 = __shfl(ub[0], qq, L), u1 = __shfl(ub[1], qq, L),
               u2 = __shfl(ub[2], qq, L);
+      const R e0 = __shfl(xg[0], qq, L), e1 = __shfl(xg[1], qq, L), e2 = __shfl(xg[2], qq, L);
       if (m * L + qq < c) {
         acc[0] += g * u0; acc[1] += g * u1; acc[2] += g * u2;
+        gx[0] += e0; gx[1] += e1; gx[2] += e2;
       }
     }
   }
   if (sub == 0) {
-    wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], R(0));
+    wbar_out[i] = mk4<R>(acc[0], acc[1], acc[2], vi.w);
     V4<R> z = w0bar[i];
     z.x += bi.x; z.y += bi.y; z.z += bi.z;
     w0bar[i] = z;
+    V4<R> g = xbar[i];
+    g.x += gx[0]; g.y += gx[1]; g.z += gx[2];
+    xbar[i] = g;
   }
 }
 
 // Start of the reverse of one step: xbar^k = xbar^{k+1} (positions pass through),
-// wbar^(I) = vbar^{k+1} + dt xbar^{k+1}; clears the per-particle w0 adjoint.
+// wbar^(I) = vbar^{k+1} + dt xbar^{k+1} (w: the inverse mass, v.w); clears the
+// per-particle w0 adjoint.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_adj_begin(int n, const V4<R>* __restrict__ xbar_next,
-                                                      const V4<R>* __restrict__ vbar_next, R dt,
+                                                      const V4<R>* __restrict__ vbar_next,
+                                                      const V4<R>* __restrict__ v, R dt,
                                                       V4<R>* __restrict__ xbar, V4<R>* __restrict__ wbar,
                                                       V4<R>* __restrict__ w0bar) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const V4<R> a = xbar_next[i], b = vbar_next[i];
   xbar[i] = a;
-  wbar[i] = mk4<R>(b.x + dt * a.x, b.y + dt * a.y, b.z + dt * a.z, R(0));
+  wbar[i] = mk4<R>(b.x + dt * a.x, b.y + dt * a.y, b.z + dt * a.z, v[i].w);
   w0bar[i] = mk4<R>(R(0), R(0), R(0), R(0));
 }
 
@@ -385,9 +416,10 @@ __device__ __forceinline__ R sdf_grad(const DevBody& B, const R p[3], R g[3]) {
   return L - B.params[0];
 }
 
-// Geometry adjoint of one step: positions from the accumulated normal / gap /
-// body-velocity adjoints of every half contact; body pose and twist adjoints
-// reduced per workgroup and body (LDS tree, fixed order) into
+// Geometry adjoint of the body contacts of one step (the reverse sweeps have
+// added the pairs' shares to xbar): positions from the accumulated normal /
+// gap / body-velocity adjoints of every body contact; body pose and twist
+// adjoints reduced per workgroup and body (LDS tree, fixed order) into
 // part[block][body][18] = (nu, omega, R row-major, t).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* __restrict__ x,
@@ -401,29 +433,12 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
   V4<R> xi = mk4<R>(R(0), R(0), R(0), R(0));
-  int c = 0;
+  int c = 0, pbase = 0;
   R xb[3] = {R(0), R(0), R(0)};
   if (active) {
     xi = x[i];
     c = ncon[i];
-    for (int k = 0; k < c; ++k) {
-      const int slot = ell_slot(i, k, K);
-      const int code = partner[slot];
-      if (code < 0) continue;
-      const int j = code & (kHiFlag - 1);
-      const bool lo = (code & kHiFlag) == 0;
-      const V4<R> xj = x[j];
-      const V4<R> xl = lo ? xi : xj, xh = lo ? xj : xi;
-      const R d[3] = {xl.x - xh.x, xl.y - xh.y, xl.z - xh.z};
-      const R L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (!(L > R(0))) continue;
-      const R nr[3] = {d[0] / L, d[1] / L, d[2] / L};
-      const R nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
-      const R psb = A.ps[slot];
-      const R nn = dot3f(nr, nb);
-      const R sg = lo ? R(1) : R(-1);
-      for (int a = 0; a < 3; ++a) xb[a] += sg * ((nb[a] - nn * nr[a]) / L + psb * nr[a]);
-    }
+    pbase = pofs[i];
   }
   // body contacts: one pass per body so the block reduction has a fixed order
   for (int b = 0; b < n_bodies; ++b) {
@@ -464,9 +479,10 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
         const R psi = Psi[slot];
         const R f = psi + xi.w;
         const R a[3] = {xi.x - f * nr[0] - Bt[0], xi.y - f * nr[1] - Bt[1], xi.z - f * nr[2] - Bt[2]};
-        const R Vb[3] = {A.vx[slot], A.vy[slot], A.vz[slot]};
-        const R nb[3] = {A.nx[slot], A.ny[slot], A.nz[slot]};
-        const R psb = A.ps[slot];
+        const int q = pbase + k;
+        const R Vb[3] = {A.vx[q], A.vy[q], A.vz[q]};
+        const R nb[3] = {A.nx[q], A.ny[q], A.nz[q]};
+        const R psb = A.ps[q];
         // V = nu + om x a
         acc[0] += Vb[0]; acc[1] += Vb[1]; acc[2] += Vb[2];
         acc[3] += a[1] * Vb[2] - a[2] * Vb[1];

@@ -1600,8 +1600,10 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
   V* wba = (V*)alloc(n4);
   V* wbb = (V*)alloc(n4);
   V* w0b = (V*)alloc(n4);
-  const size_t aslots = (size_t)s->n_pad * (size_t)K;   // adjoint state: one per contact-table slot
-  R* adj = (R*)alloc(aslots * sizeof(R) * 10);
+  // adjoint state: the carry per contact-table slot, the body-contact
+  // accumulators per contact (compact index)
+  const size_t aslots = (size_t)s->n_pad * (size_t)K;
+  R* adj = (R*)alloc((aslots * 3 + hc_max * 7) * sizeof(R));
   R* part = (R*)alloc((size_t)grid * std::max(nb, 1) * 18 * sizeof(R));
   R* bgrad = (R*)alloc((size_t)std::max(nb, 1) * 18 * sizeof(R) * N);
   float* io3 = (float*)alloc((size_t)n * 12 * 2);
@@ -1617,9 +1619,10 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
   sample_memory(s);
   ggk::AdjSlots<R> A;
   A.cx = adj; A.cy = adj + aslots; A.cz = adj + 2 * aslots;
-  A.nx = adj + 3 * aslots; A.ny = adj + 4 * aslots; A.nz = adj + 5 * aslots;
-  A.ps = adj + 6 * aslots;
-  A.vx = adj + 7 * aslots; A.vy = adj + 8 * aslots; A.vz = adj + 9 * aslots;
+  R* const abody = adj + 3 * aslots;
+  A.nx = abody; A.ny = abody + hc_max; A.nz = abody + 2 * hc_max;
+  A.ps = abody + 3 * hc_max;
+  A.vx = abody + 4 * hc_max; A.vy = abody + 5 * hc_max; A.vz = abody + 6 * hc_max;
 
   // ---- final-state adjoints into the internal order
   const hipMemcpyKind kin = where == GG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -1695,7 +1698,7 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       const int32_t* pt = tpart + slots * r;
       const R* ps = tpsi + slots * r;
       const ggk::DevBody* bod = s->d_bodies + (size_t)st * nb;
-      ggk::k_adj_begin<R><<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, dt, xb, wba, w0b);
+      ggk::k_adj_begin<R><<<grid, ggk::kBlock, 0, S>>>(n, xbn, vbn, vk, dt, xb, wba, w0b);
       // (no zeroing of the adjoint state: the first reverse sweep, l = I >= 1,
       // writes every slot in use before anything reads it)
       V* win = wba;
@@ -1710,17 +1713,17 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
           ggk::k_pja_adj<R><<<grid, ggk::kBlock, 0, S>>>(n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp,
                                                       Pp ? Pp + hc[st] : nullptr, Pp ? Pp + 2 * hc[st] : nullptr,
                                                       A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
-                                                      l == I ? 1 : 0, po);
+                                                      l == I ? 1 : 0, po, xb);
         else if (Ln == 2)
           ggk::k_pja_adj_lanes<R, 2><<<lg, ggk::kBlock, 0, S>>>(
               n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
               Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
-              l == I ? 1 : 0, po);
+              l == I ? 1 : 0, po, xb);
         else
           ggk::k_pja_adj_lanes<R, 4><<<lg, ggk::kBlock, 0, S>>>(
               n, K, xk, vk, wprev, win, wout, w0b, nc, pt, ps, Pp, Pp ? Pp + hc[st] : nullptr,
               Pp ? Pp + 2 * hc[st] : nullptr, A, bod, alpha_dt, (R)s->p.mu, (R)s->p.relax, l == 1 ? 1 : 0,
-              l == I ? 1 : 0, po);
+              l == I ? 1 : 0, po, xb);
         std::swap(win, wout);
       }
       ggk::k_adj_vbar<R><<<grid, ggk::kBlock, 0, S>>>(n, w0b, win, vb);

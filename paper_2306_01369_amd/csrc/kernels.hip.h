@@ -1190,7 +1190,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
 // (the same arrays, or per-sweep arrays when the sweeps are recorded, then
-// indexed compactly: pofs[i] + k, pofs = prefix sum of the contact counts).
+// indexed compactly from pofs, the prefix sum of the contact counts: see
+// rec_row for one lane per particle; pofs[i] + k with several lanes).
 // One half contact of a sweep: the impulse Q of contact `code` (slot `slot`,
 // impulse index `ps`) of particle i from the previous impulse P and iterate,
 // stored to P*, P itself, and the sign sg with which it enters i's sum.  Multiply-adds
@@ -1280,6 +1281,23 @@ __device__ __forceinline__ void finish_particle(int i, bool last, R im, const V4
   }
 }
 
+// Recorded impulses with one lane per particle: the 64 particles of a
+// wavefront (an aligned group) keep theirs in jagged rows -- row k holds, in
+// lane order, the particles that have a contact k, and the rows follow each
+// other from the group's first compact offset pofs[64 g].  The total is the
+// same as one run per particle, but each row is a single contiguous run, so a
+// wavefront's loads and stores of recorded impulses are coalesced.  Called by
+// the lanes that have contact k, once per k in increasing order; `rbase`
+// starts at pofs[64 g] and is advanced past the row.  (The forward sweep and
+// its reverse both call it, so they agree on every index.)
+__device__ __forceinline__ int rec_row(int& rbase) {
+  const unsigned long long row = __ballot(1);
+  const unsigned long long below = (1ull << (threadIdx.x & 63)) - 1ull;
+  const int q = rbase + __popcll(row & below);
+  rbase += __popcll(row);
+  return q;
+}
+
 // (one particle's part of a sweep; k_pja and the fused step call it)
 template <typename R>
 __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restrict__ x,
@@ -1294,15 +1312,15 @@ __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restri
                                              const R* __restrict__ imass) {
 #pragma clang fp contract(on)
   const bool first = mode & 1, last = mode & 2;
-  const int pbase = pofs ? pofs[i] : 0;
   const V4<R> xi = x[i];
   const V4<R> wi = w_in[i];
   const R im = imass[i];
   R d0 = R(0), d1 = R(0), d2 = R(0), a0 = R(0), a1 = R(0), a2 = R(0);
   const int c = ncon[i];
+  int rbase = pofs ? pofs[i & ~63] : 0;
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
-    const int ps = pofs ? pbase + k : slot;   // impulse index (compact when recorded)
+    const int ps = pofs ? rec_row(rbase) : slot;   // impulse index (jagged rows when recorded)
     R Q0, Q1, Q2, P0, P1, P2, sg;
     half_contact<R>(partner[slot], slot, ps, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies,
                     alpha_dt, mu, relax, Q0, Q1, Q2, P0, P1, P2, sg);
