@@ -134,7 +134,11 @@ typedef struct {
   float relax;       /* over-relaxation of the impulse update, 0 -> 1 */
   int32_t mass_split;/* 1: per-contact mass m/n_i (mass splitting); 0: plain masses */
   int32_t checkpoint_every;          /* backward pass: steps per checkpoint (0 -> 10) */
-  int32_t max_contacts_per_particle; /* 0 -> bound from the radius ratio + bodies */
+  int32_t max_contacts_per_particle; /* contact capacity per particle (<= 256); 0 ->
+                        automatic: min(packing bound, 24 + bodies of the largest
+                        environment) at first, grown on demand up to the packing
+                        bound of the radius ratio (19 for equal spheres) + those
+                        bodies; see gg_step */
   int32_t precision; /* 0: binary32 state and arithmetic; 1: binary64 state and arithmetic
                         (a check build: contact decisions stay the binary32 predicates on
                         the state rounded to binary32; inputs and outputs stay float) */
@@ -179,8 +183,8 @@ typedef struct {
  * Errors: GG_ERR_INVALID (bad params, offsets, radius <= 0, cell smaller than
  * 2 r_max, |x / c| >= 2^30, a contact table of more than 2^31 - 1 slots:
  * n rounded up to a multiple of 64, times the contact capacity -- the
- * capacity is max_contacts_per_particle or the packing bound of the radius
- * ratio, 19 for equal spheres, plus the bodies of the largest environment),
+ * explicit max_contacts_per_particle, or the automatic capacity's starting
+ * value),
  * GG_ERR_NONFINITE (non-finite x or v), GG_ERR_OOM, GG_ERR_HIP. */
 gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_offsets, int64_t n,
                     const float* x, const float* v, const float* radius, gg_mem where, gg_sim** out);
@@ -216,10 +220,15 @@ gg_status gg_set_grids(gg_sim* sim, int32_t n_grids, const gg_grid* grids, int64
  * twist, else n_steps x n_bodies x 6 floats, the twist of each body during
  * each step (where applies to twists).
  * Capacity: if a particle has more contacts than its capacity (see
- * GG_FIELD_STATS), the step is abandoned before any impulse is applied, the
- * state stays that of the start of that step, later steps of the call are not
- * run, and GG_ERR_CAPACITY is returned; GG_FIELD_STATS reports the steps
- * completed.  GG_ERR_NONFINITE likewise if a position leaves the hashable
+ * GG_FIELD_STATS), the step is abandoned before any impulse is applied.  With
+ * the automatic capacity (max_contacts_per_particle 0) the capacity then grows
+ * -- to twice its value or the count found, at most the packing bound -- and
+ * the call goes on from that step (a differentiable call starts again from its
+ * first step, restored from its first checkpoint); contact lists do not depend
+ * on the capacity, so neither does any result.  With an explicit capacity, or
+ * past the bound, the state stays that of the start of that step, later steps
+ * of the call are not run, and GG_ERR_CAPACITY is returned; GG_FIELD_STATS
+ * reports the steps completed.  GG_ERR_NONFINITE likewise if a position leaves the hashable
  * range or becomes non-finite. */
 gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem where);
 

@@ -268,6 +268,7 @@ struct gg_sim {
   int64_t steps_global = 0;
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
+  int K_floor = 0;   // automatic capacity: the largest a step has needed
   void* imass = nullptr;  // 1/m_i in the internal order (written by detection, R)
   void *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
   int32_t* h6 = nullptr;  // Eq. (6) cell index of each particle at the last detection
@@ -430,10 +431,27 @@ int capacity_for(const gg_params& p, int K_pp, int nb_env) {
   return std::min(K, 256);
 }
 
-int compute_K(const gg_sim* s) {
+// The capacity limit: the explicit capacity, else the packing bound.
+int bound_K(const gg_sim* s) {
   int nb_env = 0;
   for (int e = 0; e < s->n_envs; ++e) nb_env = std::max(nb_env, s->body_hi[e] - s->body_lo[e]);
   return capacity_for(s->p, s->K_pp, nb_env);
+}
+
+// Particles of a bed seldom come near the packing bound (a polydisperse bed
+// of radii 1-4 mm: 22 contacts at most against a bound of 132), so the
+// automatic capacity starts here, plus the bodies, and grows when a step
+// needs more (gg_step); it never shrinks below what a step has needed.
+constexpr int kAutoCapacity = 24;
+
+// The capacity to allocate: the explicit one, else the automatic one.
+int compute_K(const gg_sim* s) {
+  const int bound = bound_K(s);
+  if (s->p.max_contacts_per_particle > 0) return bound;
+  int nb_env = 0;
+  for (int e = 0; e < s->n_envs; ++e) nb_env = std::max(nb_env, s->body_hi[e] - s->body_lo[e]);
+  const int start = (kAutoCapacity + nb_env + 1) & ~1;
+  return std::min(bound, std::max(start, s->K_floor));
 }
 
 ggk::EnvTables env_tables(const gg_sim* s) {
@@ -990,7 +1008,8 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
 
   {
     const int64_t n_pad = (n + 63) / 64 * 64;
-    const int K0 = capacity_for(*params, contact_bound(rmin, rmax), 0);
+    int K0 = capacity_for(*params, contact_bound(rmin, rmax), 0);
+    if (params->max_contacts_per_particle == 0) K0 = std::min(K0, kAutoCapacity);
     if (!slots_fit(n_pad, K0)) return slots_error(n_pad, K0);
   }
 
@@ -1257,7 +1276,8 @@ gg_status gg_set_bodies(gg_sim* s, int32_t n_bodies, const gg_body* bodies, gg_m
       while (b < n_bodies && nb[b].env == e) ++b, ++c;
       nb_env = std::max(nb_env, c);
     }
-    const int K1 = capacity_for(s->p, s->K_pp, nb_env);
+    int K1 = capacity_for(s->p, s->K_pp, nb_env);
+    if (s->p.max_contacts_per_particle == 0) K1 = std::min(K1, std::max((kAutoCapacity + nb_env + 1) & ~1, s->K_floor));
     if (!slots_fit(s->n_pad, K1)) return slots_error(s->n_pad, K1);
   }
   DeviceGuard g(s->dev);
@@ -1312,26 +1332,10 @@ gg_status gg_set_grids(gg_sim* s, int32_t n_grids, const gg_grid* grids, int64_t
   return GG_OK;
 }
 
-gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where) {
-  g_detail.clear();
-  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
-  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
-  if (n_steps < 0) return fail(GG_ERR_INVALID, "n_steps must be >= 0");
-  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+// One attempt at n_steps steps with the current contact capacity (gg_step's
+// work; tw: n_steps x bodies x 6 twists, or empty to keep the bodies' own).
+gg_status run_steps(gg_sim* s, int32_t n_steps, const std::vector<float>& tw) {
   const int nb = (int)s->bodies.size();
-  DeviceGuard g(s->dev);
-  if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
-  std::vector<float> tw;
-  if (twists && nb > 0 && n_steps > 0) {
-    tw.resize((size_t)n_steps * nb * 6);
-    gg_status st = copy_in(twists, tw.size() * 4, where, tw.data());
-    if (st != GG_OK) return st;
-    for (float f : tw)
-      if (!std::isfinite(f)) return fail(GG_ERR_INVALID, "non-finite twist");
-  }
-  for (const HostBody& b : s->bodies)
-    if (b.shape == GG_GRID && (b.grid < 0 || b.grid >= (int32_t)s->grids.size()))
-      return fail(GG_ERR_INVALID, "a grid body refers to a grid that is no longer registered");
   s->stats.steps_done = 0;
   s->stats.last_status = GG_OK;
   if (n_steps == 0) return GG_OK;
@@ -1490,6 +1494,67 @@ gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where)
                         hipMemcpyDeviceToHost));
   }
   return GG_OK;
+}
+
+
+gg_status gg_step(gg_sim* s, int32_t n_steps, const float* twists, gg_mem where) {
+  g_detail.clear();
+  if (!s) return fail(GG_ERR_INVALID, "sim is NULL");
+  if (s->failed) return fail(GG_ERR_HIP, "simulation is in a failed state");
+  if (n_steps < 0) return fail(GG_ERR_INVALID, "n_steps must be >= 0");
+  if (where != GG_MEM_HOST && where != GG_MEM_DEVICE) return fail(GG_ERR_INVALID, "bad gg_mem");
+  const int nb = (int)s->bodies.size();
+  DeviceGuard g(s->dev);
+  if (!g.ok) return fail(GG_ERR_HIP, "hipSetDevice failed");
+  std::vector<float> tw;
+  if (twists && nb > 0 && n_steps > 0) {
+    tw.resize((size_t)n_steps * nb * 6);
+    gg_status st = copy_in(twists, tw.size() * 4, where, tw.data());
+    if (st != GG_OK) return st;
+    for (float f : tw)
+      if (!std::isfinite(f)) return fail(GG_ERR_INVALID, "non-finite twist");
+  }
+  for (const HostBody& b : s->bodies)
+    if (b.shape == GG_GRID && (b.grid < 0 || b.grid >= (int32_t)s->grids.size()))
+      return fail(GG_ERR_INVALID, "a grid body refers to a grid that is no longer registered");
+  // Automatic capacity (max_contacts_per_particle 0): a step that would exceed
+  // the current capacity is abandoned before any impulse, as always; the
+  // capacity then grows (at most to the packing bound) and the call goes on
+  // from that step -- a differentiable call from its start, restored from its
+  // first checkpoint, so that its record is one pass.  Contact lists do not
+  // depend on the capacity, so neither do the results.
+  const bool taped = (s->p.flags & GG_FLAG_TAPE) != 0;
+  const std::vector<HostBody> bodies0 = s->bodies;
+  int first = 0;
+  for (;;) {
+    std::vector<float> rest;
+    if (!tw.empty()) rest.assign(tw.begin() + (size_t)first * nb * 6, tw.end());
+    const gg_status r = run_steps(s, n_steps - first, rest);
+    const int done = (int)s->stats.steps_done;
+    const int bound = bound_K(s);
+    if (r != GG_ERR_CAPACITY || s->p.max_contacts_per_particle != 0 || s->K >= bound ||
+        !slots_fit(s->n_pad, std::min(bound, std::max(2 * s->K, (int)s->stats.max_contacts)))) {
+      s->stats.steps_done += first;
+      return r;
+    }
+    const int K = std::min(bound, (std::max(2 * s->K, (int)s->stats.max_contacts) + 1) & ~1);
+    s->K_floor = std::max(s->K_floor, K);
+    gg_status e = ensure_ell(s, K);
+    if (e != GG_OK) return e;
+    if (taped) {
+      // back to the call's start: the first checkpoint and the first poses
+      const size_t n4 = (size_t)s->n * s->es4;
+      HIPCHK(s, hipMemcpyAsync(s->x, s->ck, n4, hipMemcpyDeviceToDevice, s->stream));
+      HIPCHK(s, hipMemcpyAsync(s->v, (char*)s->ck + n4, n4, hipMemcpyDeviceToDevice, s->stream));
+      HIPCHK(s, hipStreamSynchronize(s->stream));
+      s->bodies = bodies0;
+      s->stats.steps_total -= done;
+      first = 0;
+    } else {
+      first += done;
+    }
+    g_detail.clear();
+  }
 }
 
 // Left Jacobian of SO(3): Exp(phi + d) ~= Exp([J_l(phi) d]x) Exp(phi).

@@ -1,0 +1,99 @@
+"""Automatic contact capacity (max_contacts_per_particle 0).
+
+The capacity starts below the packing bound and grows when a step would
+exceed it; the abandoned step is then recomputed (a differentiable call from
+its start), so every result equals that of a simulation created with the
+bound itself.  The scene: sixty 1 mm spheres on a shell around a 4 mm sphere,
+moving inward without gravity, so that the first eight steps have no
+contacts and then most small spheres touch the large one within a step or
+two -- 40 to 60 contacts on one particle, past the starting capacity of 24, in
+the middle of a call.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_01369_amd import gg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def crowded_sphere(m=60, R=0.004, r=0.001, gap=0.0008, speed=0.1):
+    # Fibonacci points on the shell |p| = R + r + gap, velocities toward the centre
+    k = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * k / m
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    u = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+    x = np.vstack([np.zeros((1, 3)), (R + r + gap) * u]).astype(np.float32)
+    v = np.vstack([np.zeros((1, 3)), -speed * u]).astype(np.float32)
+    rad = np.concatenate([[R], np.full(m, r)]).astype(np.float32)
+    return x, v, rad
+
+
+KW = dict(gravity=(0.0, 0.0, 0.0), dt=1e-3, n_iters=20)
+
+
+def test_automatic_capacity_grows_in_the_middle_of_a_call_and_changes_no_result():
+    x, v, r = crowded_sphere()
+    say("crowded sphere: automatic capacity, 12 steps (contact at step 8)")
+    auto = gg.Sim(x, v, r, **KW)
+    k0 = auto.stats()["capacity"]
+    assert k0 == 24
+    auto.step(12)
+    st = auto.stats()
+    say("capacity", k0, "->", st["capacity"])
+    assert st["steps_done"] == 12 and st["capacity"] > 24
+    ref = gg.Sim(x, v, r, max_contacts=132, **KW)
+    ref.step(12)
+    assert auto.read("pos").tobytes() == ref.read("pos").tobytes()
+    assert auto.read("vel").tobytes() == ref.read("vel").tobytes()
+    np.testing.assert_array_equal(auto.read("contacts"), ref.read("contacts"))
+    # the grown capacity stays for the next call
+    auto.step(2)
+    assert auto.stats()["capacity"] == st["capacity"]
+
+
+def test_automatic_capacity_step_of_first_contact_against_the_oracle():
+    x, v, r = crowded_sphere()
+    sim = gg.Sim(x, v, r, **KW)
+    sim.step(8)
+    x8, v8 = sim.read("pos"), sim.read("vel")
+    say("crowded sphere: the step of first contact, capacity", sim.stats()["capacity"])
+    sim.step(1)
+    st = sim.stats()
+    say("capacity", st["capacity"], "max contacts", st["max_contacts"])
+    assert st["max_contacts"] > 24 and st["capacity"] >= st["max_contacts"]
+    orc = O.Oracle(x8.astype(np.float64), v8.astype(np.float64), r, [], **KW)
+    d = orc.step(detail=True)
+    pairs = sim.read("contacts")
+    np.testing.assert_array_equal(pairs, d["pairs"])
+    P = sim.read("impulses").astype(np.float64)
+    assert np.abs(P - d["impulses"]).max() <= 1e-5 * np.abs(d["impulses"]).max()
+
+
+def test_automatic_capacity_in_a_differentiable_call_gives_the_same_gradients():
+    x, v, r = crowded_sphere()
+    say("crowded sphere: differentiable call with automatic capacity")
+    g = np.zeros((len(x), 3), np.float32)
+    g[:, 0] = 1.0
+    g[1:, 2] = np.linspace(-1.0, 1.0, len(x) - 1, dtype=np.float32)
+    out = []
+    for cap in (0, 132):
+        sim = gg.Sim(x, v, r, max_contacts=cap, differentiable=True, checkpoint_every=4, **KW)
+        sim.step(16)
+        st = sim.stats()
+        assert st["steps_done"] == 16
+        dx, dv, _ = sim.backward(g, None)
+        out.append((sim.read("pos").tobytes(), dx.tobytes(), dv.tobytes(), st["capacity"]))
+        sim.close()
+    say("capacities", out[0][3], out[1][3])
+    assert out[0][3] < out[1][3]
+    assert out[0][:3] == out[1][:3]
