@@ -269,6 +269,7 @@ struct gg_sim {
   int32_t *h = nullptr, *rank = nullptr, *counts = nullptr, *bstart = nullptr, *bsum = nullptr;
   int32_t *sidx = nullptr, *ncon = nullptr, *partner = nullptr;
   int K_floor = 0;   // automatic capacity: the largest a step has needed
+  bool imp_rows = false;   // the last step's impulses lie in jagged rows (one lane per particle)
   void* imass = nullptr;  // 1/m_i in the internal order (written by detection, R)
   void *Px = nullptr, *Py = nullptr, *Pz = nullptr, *Psi = nullptr;
   int32_t* h6 = nullptr;  // Eq. (6) cell index of each particle at the last detection
@@ -1412,6 +1413,7 @@ gg_status run_steps(gg_sim* s, int32_t n_steps, const std::vector<float>& tw) {
       s->d_counts_cap = (size_t)n_steps * 2;
     }
   }
+  s->imp_rows = (s->p.flags & GG_FLAG_FUSED) || s->p.pja_lanes == 1;   // (launch_sweeps, the fused step)
   const bool graphed = (s->p.flags & GG_FLAG_GRAPH) && !(s->p.flags & GG_FLAG_FUSED) && !prof && !taped && n > 0;
   if (graphed) {
     gg_status gs = launch_graphed(s, n_steps, nb);
@@ -2049,14 +2051,24 @@ gg_status gg_read(gg_sim* s, int32_t field, void* dst, int64_t capacity_bytes, i
   std::vector<Rec> pp, pb;
   pp.reserve((size_t)s->stats.n_pp);
   const int K = s->K;
+  // impulse index of contact k of particle i: its table slot, or with one lane
+  // per particle the jagged rows of its 64-group's block (rec_row)
+  std::vector<size_t> rows((size_t)64 * K);
   for (int64_t i = 0; i < n; ++i) {
+    if (s->imp_rows && (i & 63) == 0) {
+      size_t at = (size_t)(i >> 6) * ((size_t)K << 6);
+      for (int k = 0; k < K; ++k)
+        for (int64_t l = i; l < std::min<int64_t>(i + 64, n); ++l)
+          if (cnt[l] > k) rows[(size_t)(l - i) * K + k] = at++;
+    }
     for (int k = 0; k < cnt[i]; ++k) {
       const size_t sl = (size_t)(i >> 6) * ((size_t)K << 6) + ((size_t)k << 6) + (size_t)(i & 63);
+      const size_t q = s->imp_rows ? rows[(size_t)(i & 63) * K + k] : sl;
       const int32_t code = part[sl];
       if (code >= 0) {
-        if ((code & ggk::kHiFlag) == 0) pp.push_back({org[i], org[code & (ggk::kHiFlag - 1)], sl});
+        if ((code & ggk::kHiFlag) == 0) pp.push_back({org[i], org[code & (ggk::kHiFlag - 1)], q});
       } else {
-        pb.push_back({org[i], -1 - code, sl});
+        pb.push_back({org[i], -1 - code, q});
       }
     }
   }

@@ -1189,9 +1189,11 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // bits detection stored), which saves streaming it; a body contact's is read.
 // mode bit 0: first sweep (impulses start at 0); bit 1: last sweep (write v and
 // optionally dv instead of w_out).  Impulses are read from Pi* and written to P*
-// (the same arrays, or per-sweep arrays when the sweeps are recorded, then
-// indexed compactly from pofs, the prefix sum of the contact counts: see
-// rec_row for one lane per particle; pofs[i] + k with several lanes).
+// (the same arrays, or per-sweep arrays when the sweeps are recorded).  With
+// one lane per particle they lie in jagged rows (rec_row): in each group's
+// block of the contact table, or, recorded, from the group's compact offset
+// pofs[64 g] (pofs: the prefix sum of the contact counts).  With several
+// lanes: at the contact's table slot, or, recorded, at pofs[i] + k.
 // One half contact of a sweep: the impulse Q of contact `code` (slot `slot`,
 // impulse index `ps`) of particle i from the previous impulse P and iterate,
 // stored to P*, P itself, and the sign sg with which it enters i's sum.  Multiply-adds
@@ -1281,15 +1283,17 @@ __device__ __forceinline__ void finish_particle(int i, bool last, R im, const V4
   }
 }
 
-// Recorded impulses with one lane per particle: the 64 particles of a
-// wavefront (an aligned group) keep theirs in jagged rows -- row k holds, in
-// lane order, the particles that have a contact k, and the rows follow each
-// other from the group's first compact offset pofs[64 g].  The total is the
-// same as one run per particle, but each row is a single contiguous run, so a
-// wavefront's loads and stores of recorded impulses are coalesced.  Called by
-// the lanes that have contact k, once per k in increasing order; `rbase`
-// starts at pofs[64 g] and is advanced past the row.  (The forward sweep and
-// its reverse both call it, so they agree on every index.)
+// Impulses with one lane per particle: the 64 particles of a wavefront (an
+// aligned group) keep theirs in jagged rows -- row k holds, in lane order, the
+// particles that have a contact k, and the rows follow each other without
+// gaps from the group's base: its block of the contact table, 64 K g, or,
+// recorded, its first compact offset pofs[64 g].  A group's impulses are then
+// one contiguous run of its contact count, and each row is a contiguous part
+// of it, so a wavefront's loads and stores touch no cache line that holds
+// none of its impulses.  Called by the lanes that have contact k, once per k
+// in increasing order; `rbase` starts at the group's base and is advanced past
+// the row.  (The forward sweep and its reverse both call it, so they agree on
+// every index; the host's reader of impulses follows the same rule.)
 __device__ __forceinline__ int rec_row(int& rbase) {
   const unsigned long long row = __ballot(1);
   const unsigned long long below = (1ull << (threadIdx.x & 63)) - 1ull;
@@ -1317,10 +1321,10 @@ __device__ __forceinline__ void pja_particle(int i, int K, const V4<R>* __restri
   const R im = imass[i];
   R d0 = R(0), d1 = R(0), d2 = R(0), a0 = R(0), a1 = R(0), a2 = R(0);
   const int c = ncon[i];
-  int rbase = pofs ? pofs[i & ~63] : 0;
+  int rbase = pofs ? pofs[i & ~63] : (i >> 6) * (K << 6);
   for (int k = 0; k < c; ++k) {
     const int slot = ell_slot(i, k, K);
-    const int ps = pofs ? rec_row(rbase) : slot;   // impulse index (jagged rows when recorded)
+    const int ps = rec_row(rbase);   // impulse index (jagged rows)
     R Q0, Q1, Q2, P0, P1, P2, sg;
     half_contact<R>(partner[slot], slot, ps, first, xi, wi, x, w_in, Psi, Pix, Piy, Piz, Px, Py, Pz, bodies,
                     alpha_dt, mu, relax, Q0, Q1, Q2, P0, P1, P2, sg);
