@@ -355,6 +355,46 @@ def test_differentiable_bed_binary32_gradient_over_ten_steps():
     assert max(errs) <= REL_TOL
 
 
+def test_two_step_double_adjoint_with_the_loss_gradient_at_the_oracle_state():
+    """diff-32k, mu = 0.5, two steps.  A grain of the target box ends the second
+    step 5.5e-9 m past the box SDF's edge ridge (q_x = q_y inside the box), where
+    the loss gradient jumps from x to y; read back through the binary32 API its
+    position lies on the ridge, so a loss gradient evaluated at the read state
+    takes the other branch (a 0.9% error in the directional derivative, from
+    that one grain).  Evaluated at the oracle's double-precision final state, as
+    the dual numbers do, the double build's adjoint agrees with them as at every
+    other horizon."""
+    from paper_2306_01369_amd import scenes as S
+    from gradcheck import jvp_rollout
+    sc = S.diff_scene()
+    x, v, r, bodies = sc.x, sc.v, sc.radius, sc.bodies
+    nb = len(bodies)
+    H = 2
+    tw = np.zeros((H, nb, 6))
+    tw[:, -1, :3] = np.float32(sc.bodies[-1]["nu"])
+    top = S.surface_height(x, float(r[0]))
+    loss = TargetLoss((0.15, 0.15, top), (0.05, 0.05, 0.025), width=1e-3)
+    kw = dict(dt=_f32(1e-3), alpha=_f32(0.2), gravity=EXACT_G, mu=0.5)
+    say("two-step double adjoint, loss gradient at the oracle state")
+    x64, v64 = x.astype(np.float64), v.astype(np.float64)
+    rng = np.random.default_rng(2024)
+    dirs = [rng.normal(size=x.shape) for _ in range(3)]
+    duals = []
+    for d in dirs:
+        d /= np.linalg.norm(d)
+        xN, vN, dxN, dvN = jvp_rollout(x64, v64, r, bodies, tw, d, np.zeros(x.shape), np.zeros_like(tw), **kw)
+        gx, gv = loss.grads(xN, vN)
+        duals.append(float(np.sum(gx * dxN) + np.sum(gv * dvN)))
+    sim = gg.Sim(x, v, r, bodies, differentiable=True, checkpoint_every=10, precision=1, **kw)
+    sim.step(H, twists=tw.astype(np.float32))
+    gX, _, _ = sim.backward(gx, gv)
+    sim.close()
+    for d, ref in zip(dirs, duals):
+        err = abs(float(np.sum(gX * d)) - ref) / abs(ref)
+        say("rel err", err)
+        assert err < 1e-4
+
+
 def test_binary32_adjoint_is_the_double_adjoint_of_its_own_trajectory():
     """Rounding of the binary32 adjoint, apart from trajectory decorrelation:
     along the binary32 trajectory of the 32,768-grain bed (16 steps, states
