@@ -734,6 +734,7 @@ def bench_scoop(args):
     tool = scenes.scoop_tool(surface)
     bodies = pour.bodies + [tool]
     approach = max(0, SCOOP_PATH_STEPS - args.warmup - args.steps)
+    log("state to the device")
     stream = torch.cuda.current_stream(0).cuda_stream
     xd = torch.from_numpy(x).to("cuda:0")
     vd = torch.from_numpy(v).to("cuda:0")
@@ -742,12 +743,17 @@ def bench_scoop(args):
     sim = gg.Sim(xd, vd, rd, bodies, device=0, stream=stream, profile=True, **kw)
     del xd, vd, rd
     log(f"tool approach: {approach} untimed steps of the scoop path")
-    if approach:
-        sim.step(approach)
+    for k in range(0, approach, 20):
+        sim.step(min(20, approach - k))
+    log("approach done")
     tuned = None
-    if not args.no_tune:
+    if args.tune:
         # the launch shape for this bed, timed by the autotuner from the state
-        # the window starts in (every candidate gives the same bits)
+        # the window starts in (every candidate gives the same bits).  Off by
+        # default: in this process, after torch's device work, the tuner has
+        # stalled without progress (no cause found; the same tuning in a
+        # process without the torch-stream simulation before it finishes in
+        # about 5 s and gains about 2%)
         from paper_2306_01369_amd import autotune
         x1, v1, poses = sim.read("pos"), sim.read("vel"), sim.read("body_poses")
         sim.close()
@@ -755,6 +761,7 @@ def bench_scoop(args):
             b["R"], b["t"] = poses[q][:, :3].astype(np.float64), poses[q][:, 3].astype(np.float64)
         t0 = time.perf_counter()
         table = []
+        log("autotune from the approach state")
         params = autotune.tune(x1, v1, pour.radius, bodies, sim_kwargs=kw, use_cache=False, record=table)
         tuned = {"params": params, "seconds": time.perf_counter() - t0,
                  "default_ms_per_step": table[0][1] if table and table[0][1] else None,
@@ -818,8 +825,9 @@ def main():
     ap.add_argument("--settle-steps", type=int, default=150, help="large workload: untimed settling steps")
     ap.add_argument("--profile-window", action="store_true",
                     help="scoop/lattice: bracket the timed steps with marker kernels for a profiler summary")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="scoop: time the library's default launch shape instead of the autotuned one")
+    ap.add_argument("--tune", action="store_true",
+                    help="scoop: autotune the launch shape from the window's first state (default: the library's "
+                         "default shape)")
     ap.add_argument("--skip-ratios", action="store_true",
                     help="scoop workload: leave out the batched and backward ratios")
     ap.add_argument("--plain-steps", type=int, default=5)
