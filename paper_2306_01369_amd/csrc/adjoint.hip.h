@@ -419,7 +419,7 @@ __device__ __forceinline__ R sdf_grad(const DevBody& B, const R p[3], R g[3]) {
 // Geometry adjoint of the body contacts of one step (the reverse sweeps have
 // added the pairs' shares to xbar): positions from the accumulated normal /
 // gap / body-velocity adjoints of every body contact; body pose and twist
-// adjoints reduced per workgroup and body (LDS tree, fixed order) into
+// adjoints reduced per workgroup and body (fixed order) into
 // part[block][body][18] = (nu, omega, R row-major, t).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* __restrict__ x,
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
                                                      const DevBody* __restrict__ bodies, int n_bodies,
                                                      const int32_t* __restrict__ pofs, V4<R>* __restrict__ xbar,
                                                      R* __restrict__ part) {
-  __shared__ R red[kBlock];
+  __shared__ R wred[kBlock / 64][18];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < n;
   V4<R> xi = mk4<R>(R(0), R(0), R(0), R(0));
@@ -440,6 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
     c = ncon[i];
     pbase = pofs[i];
   }
+  // a particle's body contacts follow its pairs, in body order
+  int kb = c;
+  while (kb > 0 && partner[ell_slot(i, kb - 1, K)] < 0) --kb;
   // body contacts: one pass per body so the block reduction has a fixed order
   for (int b = 0; b < n_bodies; ++b) {
     R acc[18];
@@ -448,10 +451,12 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
     const auto* BR = PoseOf<R>::R(B);
     const auto* Bt = PoseOf<R>::t(B);
     const auto* Bom = PoseOf<R>::om(B);
+    bool touched = false;
     if (active) {
-      for (int k = 0; k < c; ++k) {
+      for (int k = kb; k < c; ++k) {
         const int slot = ell_slot(i, k, K);
         if (partner[slot] != -1 - b) continue;
+        touched = true;
         R pnt[3];
         {
           const R dd[3] = {xi.x - Bt[0], xi.y - Bt[1], xi.z - Bt[2]};
@@ -528,16 +533,25 @@ __global__ __launch_bounds__(kBlock) void k_geom_adj(int n, int K, const V4<R>* 
         for (int q = 0; q < 3; ++q) acc[15 + q] += tb[q];
       }
     }
-    for (int q = 0; q < 18; ++q) {
-      red[threadIdx.x] = acc[q];
-      __syncthreads();
-      for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) part[((size_t)blockIdx.x * n_bodies + b) * 18 + q] = red[0];
-      __syncthreads();
+    // workgroup sum in a fixed order: a butterfly within each wavefront, then
+    // the wavefronts in order; a workgroup none of whose particles touches the
+    // body writes zeros
+    R* out = part + ((size_t)blockIdx.x * n_bodies + b) * 18;
+    if (!__syncthreads_or(touched ? 1 : 0)) {
+      if (threadIdx.x < 18) out[threadIdx.x] = R(0);
+      continue;
     }
+    for (int q = 0; q < 18; ++q)
+      for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+    if ((threadIdx.x & 63) == 0)
+      for (int q = 0; q < 18; ++q) wred[threadIdx.x >> 6][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < 18) {
+      R sum = R(0);
+      for (int w = 0; w < kBlock / 64; ++w) sum += wred[w][threadIdx.x];
+      out[threadIdx.x] = sum;
+    }
+    __syncthreads();   // (wred is written again for the next body)
   }
   if (active) {
     V4<R> z = xbar[i];
