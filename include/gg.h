@@ -240,9 +240,11 @@ gg_status gg_step(gg_sim* sim, int32_t n_steps, const float* twists, gg_mem wher
  * set being piecewise constant in the inputs.  The forward kept (x, v) every
  * params.checkpoint_every steps; each segment is recomputed from its
  * checkpoint before its steps are reversed, so device memory grows with
- * n_steps / checkpoint_every, one segment's recorded sweeps and a per-call
- * workspace of 40 bytes per contact-table slot (n rounded up to 64 times the
- * contact capacity), allocated and freed by each call.
+ * n_steps / checkpoint_every and one segment's recorded sweeps (12 bytes per
+ * half contact per sweep, and the segment's contact tables), plus a per-call
+ * workspace of 12 bytes per contact-table slot (n rounded up to 64 times the
+ * contact capacity) and 28 bytes per half contact, allocated and freed by
+ * each call.
  * dL_dx, dL_dv: n x 3 float32 gradients of the loss with respect to the final
  * positions and velocities, caller's particle order; NULL means zero.
  * Outputs (any may be NULL): dL_dx0, dL_dv0 (n x 3) with respect to the
