@@ -97,3 +97,36 @@ def test_automatic_capacity_in_a_differentiable_call_gives_the_same_gradients():
     say("capacities", out[0][3], out[1][3])
     assert out[0][3] < out[1][3]
     assert out[0][:3] == out[1][:3]
+
+
+@pytest.mark.parametrize("mode", ["graph", "fused", "fp64", "two-envs"])
+def test_automatic_capacity_in_every_launch_mode_changes_no_result(mode):
+    # the growth happens in the middle of a 12-step call (contact at step 8);
+    # with graphs the call is re-captured at the new capacity
+    x, v, r = crowded_sphere()
+    kw = dict(KW)
+    env = None
+    if mode == "graph":
+        kw["graph"] = True
+    elif mode == "fused":
+        kw["fused"] = True
+    elif mode == "fp64":
+        kw["precision"] = 1
+    else:
+        # the same crowd twice, the second far away in its own environment
+        x = np.vstack([x, x + np.float32(0.05)])
+        v = np.vstack([v, v])
+        r = np.concatenate([r, r])
+        env = np.array([0, len(x) // 2, len(x)], np.int64)
+    say("crowded sphere, automatic capacity:", mode)
+    out = []
+    for cap in (0, 132):
+        sim = gg.Sim(x, v, r, max_contacts=cap, env_offsets=env, **kw)
+        sim.step(12)
+        st = sim.stats()
+        assert st["steps_done"] == 12
+        out.append((sim.read("pos").tobytes(), sim.read("vel").tobytes(), st["capacity"]))
+        sim.close()
+    say("capacities", out[0][2], out[1][2])
+    assert 24 < out[0][2] < out[1][2]
+    assert out[0][:2] == out[1][:2]
