@@ -311,9 +311,9 @@ typedef struct {
   int32_t detect_workgroups; /* detection grid: workgroups resident at once on the device */
   int32_t reorder_every;
   int32_t pja_lanes;      /* lanes per particle of the sweeps (default resolved) */
-  int32_t detect_queues;  /* 1: detection work items are taken from per-XCD work queues
-                             (several environments or radii spread beyond 1.25x);
-                             0: each detection workgroup takes a fixed contiguous share */
+  int32_t detect_queues;  /* 1: detection work items are taken from per-XCD work queues;
+                             0 (GG_FLAG_FUSED): each detection workgroup takes a fixed
+                             contiguous share */
 } gg_stats;
 
 /* Copy a field into dst (where says where dst lives).  If dst is NULL only

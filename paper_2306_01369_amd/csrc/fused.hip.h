@@ -52,6 +52,7 @@ struct FusedArgs {
   V4<R>* dv;
   R* imass;
   Ctl* ctl;
+  DetPart* part;   // per-workgroup detection counts (summed by k_detect_stats)
   int step;
   int pair_gaps;   // store pair gaps (recorded forward)
 };
@@ -73,8 +74,8 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   if (err0 == 0)
     detect_items<R, TB>(a.n, a.K, a.x, a.v, a.orig, a.inv_c, a.n_blk, a.env, a.start, a.sidx, a.xs, a.os,
                         a.item_start, a.n_items, a.bodies, a.n_bodies, a.gx, a.gy, a.gz, a.dt, a.mass_split,
-                        a.max_cells, a.max_stage, a.ncon, a.partner, a.Psi, a.wa, a.imass, a.ctl, a.step, blk,
-                        nblk, false, a.pair_gaps != 0);
+                        a.max_cells, a.max_stage, a.ncon, a.partner, a.Psi, a.wa, a.imass, a.ctl, a.part, a.step,
+                        blk, nblk, false, a.pair_gaps != 0);
   grid.sync();
   // nothing writes the error word after detection: every thread reads the same value
   const bool run = __hip_atomic_load(&a.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;

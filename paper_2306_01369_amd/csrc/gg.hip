@@ -258,8 +258,8 @@ struct gg_sim {
   int det_grid = 2048;  // detection workgroups: what the device holds at once (occupancy API)
   int fused_grid = 0;   // GG_FLAG_FUSED: workgroups of the cooperative step kernel (all resident)
   bool small_table = false;  // bucket table built by one workgroup (k_bucket_small)
-  // detection items taken from per-XCD work queues (uneven beds: several
-  // environments or spread radii) rather than in fixed contiguous shares
+  // detection items taken from per-XCD work queues rather than in fixed
+  // contiguous shares (the fused step kernel keeps fixed shares)
   bool det_queue = false;
   void* xs = nullptr;                                  // bucket-ordered positions
   int32_t* os = nullptr;                               // bucket-ordered original indices
@@ -282,6 +282,7 @@ struct gg_sim {
   int64_t h_bodies_cap = 0;
   ggk::Ctl* ctl = nullptr;
   ggk::Ctl* h_ctl = nullptr;  // pinned
+  ggk::DetPart* det_part = nullptr;  // per-workgroup detection counts (max of both detection grids)
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   std::vector<hipEvent_t> events;
@@ -472,7 +473,7 @@ void free_all(gg_sim* s) {
                   s->mv[0], s->mv[1], s->rs_hist, s->rs_bsum, s->xs, s->os, s->it_f, s->it_e, s->it_first,
                   s->it_g, s->it_h, s->item_start, s->it_bsum, s->ck, s->d_counts, s->h, s->rank, s->counts, s->bstart, s->bsum,
                   s->sidx, s->ncon, s->imass, s->partner, s->Px, s->Py, s->Pz, s->Psi, s->env_of, s->d_env_nh,
-                  s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->tmp, s->h6,
+                  s->d_env_boff, s->d_body_lo, s->d_body_hi, s->d_bodies, s->ctl, s->det_part, s->tmp, s->h6,
                   s->d_env_tblk, s->d_env_toff, s->d_grid_values, s->d_cams, s->d_planes, s->obs_img,
                   s->d_chunks, s->d_env_chunk, s->d_env_count, s->d_part_n, s->d_part_d, s->d_boxes,
                   s->d_reward, s->d_inside};
@@ -633,18 +634,21 @@ size_t detect_lds_bytes(const gg_sim* s) {
 // The detection kernel for a workgroup size of TB threads.
 template <typename R, int TB>
 void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, int dgrid, size_t dlds,
-                   int blk1, const ggk::EnvTables& et) {
+                   int blk1, const ggk::EnvTables& et, unsigned long long* rec) {
   using V = ggk::V4<R>;
   ggk::k_detect<R, TB><<<dgrid, TB, dlds, s->stream>>>(
       (int)s->n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os,
       s->item_start, &s->ctl->items, bod, (int)s->bodies.size(), (R)s->p.gravity[0], (R)s->p.gravity[1],
       (R)s->p.gravity[2], (R)s->p.dt, s->p.mass_split, s->p.tile_max_cells, s->p.tile_max_stage, io.ncon,
-      io.partner, io.Psi, io.w[0], io.imass, s->ctl, st, s->det_queue, (s->p.flags & GG_FLAG_TAPE) ? 1 : 0);
+      io.partner, io.Psi, io.w[0], io.imass, s->ctl, s->det_part, st, s->det_queue,
+      (s->p.flags & GG_FLAG_TAPE) ? 1 : 0);
+  ggk::k_detect_stats<<<1, ggk::kBlock, 0, s->stream>>>(dgrid, s->det_part, s->ctl, rec);
 }
 
-// Bucket table and contact detection of one step.
+// Bucket table and contact detection of one step (rec: see k_detect_stats).
 template <typename R>
-void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, bool with_detect = true) {
+void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, bool with_detect = true,
+                   unsigned long long* rec = nullptr) {
   using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
@@ -672,9 +676,9 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   }
   if (!with_detect) return;
   switch (s->p.tile_threads) {
-    case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et); break;
-    case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et); break;
-    default: detect_kernel<R, 128>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+    case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
+    case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
+    default: detect_kernel<R, 128>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
   }
 }
 
@@ -769,6 +773,7 @@ gg_status launch_fused(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBod
   a.dv = io.dv;
   a.imass = io.imass;
   a.ctl = s->ctl;
+  a.part = s->det_part;
   a.step = st;
   a.pair_gaps = (s->p.flags & GG_FLAG_TAPE) ? 1 : 0;
   hipError_t e;
@@ -778,6 +783,7 @@ gg_status launch_fused(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBod
     default: e = fused_kernel<R, 128>(s, a); break;
   }
   HIPCHK(s, e);
+  ggk::k_detect_stats<<<1, ggk::kBlock, 0, s->stream>>>(s->fused_grid, s->det_part, s->ctl, nullptr);
   return GG_OK;
 }
 
@@ -820,8 +826,7 @@ gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof)
       if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
       continue;
     }
-    launch_detect<R>(s, io, st, bod);
-    if (taped) ggk::k_record_counts<<<1, 64, 0, S>>>(s->ctl, s->d_counts + 2 * (size_t)st);
+    launch_detect<R>(s, io, st, bod, true, taped ? s->d_counts + 2 * (size_t)st : nullptr);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
     launch_sweeps<R>(s, io, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
@@ -1053,10 +1058,11 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
   s->r_max = rmax;
   s->r_min = rmin;
   s->K_pp = contact_bound(rmin, rmax);
-  // measured: the queues take 16% off detection in a polydisperse 4M bed and
-  // help 256 uneven environments, but cost 7% in a uniform 1M bed, where
-  // each workgroup's consecutive items share cached cells
-  s->det_queue = n_envs > 1 || (double)rmax > 1.25 * (double)rmin;
+  // measured with keys and sort: the queues take 16% off detection in a
+  // polydisperse 4M bed, 17% in a settled uniform 1M bed and 11% in a
+  // uniform lattice, against fixed contiguous shares (the fused step kernel
+  // keeps those)
+  s->det_queue = (s->p.flags & GG_FLAG_FUSED) == 0;
   s->n_pad = (n + 63) / 64 * 64;
   s->body_lo.assign(n_envs, 0);
   s->body_hi.assign(n_envs, 0);
@@ -1202,6 +1208,10 @@ gg_status gg_create(const gg_params* params, int32_t n_envs, const int64_t* env_
       // resident at once, and no more workgroups than particles call for
       s->fused_grid = std::max(1, std::min(fpc * n_cu, (int)((s->n + tb - 1) / tb)));
     }
+    const size_t parts = (size_t)std::max(s->det_grid, s->fused_grid);
+    oe = dev_alloc(&s->det_part, parts);
+    if (oe == hipSuccess) oe = hipMemset(s->det_part, 0, parts * sizeof(ggk::DetPart));
+    if (oe != hipSuccess) return bail(fail(GG_ERR_OOM, "device allocation failed"));
   }
   s->stats.tile_threads = s->p.tile_threads;
   s->stats.tile_node_shift = s->p.tile_node_shift;

@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstddef>
+
 namespace ggk {
 
 constexpr int kBlock = 256;
@@ -46,6 +48,7 @@ constexpr int kRsBits = 8;
 constexpr int kDetBlock = 128;  // default detection workgroup (and work item) size
 constexpr int kScanTile = 1024;  // elements per block of the bucket scan
 constexpr int kQ = 100;
+constexpr int kQueueStride = 32;  // int32 slots between two work-queue counters
 
 struct DevBody {  // one body at one step; 312 bytes
   int32_t shape, env;
@@ -110,7 +113,22 @@ struct Ctl {                    // device control block, one per simulation
   unsigned long long summed;    // contacts summed over the steps of the current call
   int32_t fallback;             // detection work items that took the per-particle path (last detection)
   int32_t items;                // detection work items (set when they are built)
-  int32_t next_item[8];         // detection work queues, one per XCD (zeroed by the key kernels)
+  int32_t pad_[18];
+  // detection work queues, one per XCD, each on a 128-byte line of its own
+  // (zeroed by the key kernels): next_item[q * kQueueStride]
+  int32_t next_item[8 * kQueueStride];
+};
+static_assert(offsetof(Ctl, next_item) == 128, "work-queue counters start a cache line");
+
+// Counts of one detection workgroup, stored once when it ends and summed by
+// k_detect_stats: device-scope atomics from every workgroup on the control
+// block cost more time than the rest of the statistics by far (they queue on
+// one address, and loads and stores of the workgroups still running wait
+// behind them).
+struct DetPart {
+  unsigned long long n_pp, n_pb, cand;
+  int32_t max_cnt;
+  int32_t fb_ran;  // (fallback items << 1) | 1; 0: the workgroup stopped at an earlier failure
 };
 
 struct EnvTables {   // per-environment tables (batched form)
@@ -614,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__
   if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->err == 0) {
     ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0; ctl->fallback = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x < 8) ctl->next_item[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8) ctl->next_item[threadIdx.x * kQueueStride] = 0;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= n) return;
   const float4 p = f32of(x[i]);
@@ -690,7 +708,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_bucket_small(
   if (tid == 0 && ctl->err == 0) {
     ctl->n_pp = 0; ctl->n_pb = 0; ctl->cand = 0; ctl->max_cnt = 0; ctl->fallback = 0;
   }
-  if (tid < 8) ctl->next_item[tid] = 0;
+  if (tid < 8) ctl->next_item[tid * kQueueStride] = 0;
   for (int e = tid; e <= m; e += kSmallBlock) cnt[e] = 0;
   __syncthreads();
   // cell keys (as k_key); arrival rank within the bucket from an LDS atomic
@@ -921,13 +939,14 @@ __device__ __forceinline__ void block_min8(int v[8], int (*red)[8]) {
 // inverse mass s_i = n_i / m_i.
 // (five waves per SIMD: the tile's LDS allows five workgroups per CU, and the
 // register budget that fits costs only a few bytes of spill)
-// Work distribution: with `queue` set, the items are cut into one contiguous
-// range per XCD (workgroup b runs on XCD b mod 8), and the workgroups of an
-// XCD take the items of its range one at a time from a counter
-// (Ctl::next_item, zeroed by the key kernels of the step), so no workgroup
-// idles while another still holds several items; without it, workgroup `blk`
-// of `nblk` takes a fixed contiguous share.  Either way each item's results
-// depend only on its particles.
+// Work distribution: with `queue` set (k_detect), the items are cut into one
+// contiguous range per XCD (workgroup b runs on XCD b mod 8), and the
+// workgroups of an XCD take the items of its range one at a time from a
+// counter (Ctl::next_item, zeroed by the key kernels of the step), so no
+// workgroup idles while another still holds several items (item times vary
+// several-fold); without it (the fused step kernel), workgroup `blk` of `nblk`
+// takes a fixed contiguous share.  Either way each item's results depend only
+// on its particles.
 // pair_gaps: store the gap of every pair contact (the recorded forward needs
 // them; the sweeps recompute a pair's gap from the positions, so plain steps
 // skip the double-precision gap and its store).
@@ -940,7 +959,7 @@ __device__ __forceinline__ void detect_items(
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step, int blk, int nblk, bool queue, bool pair_gaps) {
+    DetPart* __restrict__ part, int step, int blk, int nblk, bool queue, bool pair_gaps) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int red8[TB / 64][8];
   __shared__ int red[TB / 64];
@@ -966,7 +985,7 @@ __device__ __forceinline__ void detect_items(
   int cand = 0, npp = 0, npb = 0, mx = 0, fb = 0;
   const int BIG = 0x3fffffff;
   // (thread 0 takes the next item while the workgroup works on the current one)
-  int ahead = (queue && threadIdx.x == 0) ? atomicAdd(&ctl->next_item[qx], 1) : 0;
+  int ahead = (queue && threadIdx.x == 0) ? atomicAdd(&ctl->next_item[qx * kQueueStride], 1) : 0;
 
   for (int item = it0;; ++item) {
     if (queue) {
@@ -975,7 +994,7 @@ __device__ __forceinline__ void detect_items(
       if (threadIdx.x == 0) grabbed = it0 + ahead;
       __syncthreads();
       item = grabbed;
-      if (threadIdx.x == 0 && item < it1) ahead = atomicAdd(&ctl->next_item[qx], 1);
+      if (threadIdx.x == 0 && item < it1) ahead = atomicAdd(&ctl->next_item[qx * kQueueStride], 1);
     }
     if (item >= it1) break;
     const int i = item_start[item] + threadIdx.x;
@@ -1139,18 +1158,30 @@ __device__ __forceinline__ void detect_items(
     }
     __syncthreads();  // LDS is reused by the next item
   }
-  // statistics: one atomic per wavefront
-  unsigned long long a = wave_sum_u64((unsigned long long)npp);
-  unsigned long long b2 = wave_sum_u64((unsigned long long)npb);
-  unsigned long long c = wave_sum_u64((unsigned long long)cand);
+  // statistics: summed over the wavefronts, then the workgroup's counts in its
+  // own slot (every thread has passed the loop's last barrier)
+  __shared__ unsigned long long st_sum[TB / 64][3];
+  __shared__ int st_max[TB / 64];
+  const unsigned long long a = wave_sum_u64((unsigned long long)npp);
+  const unsigned long long b2 = wave_sum_u64((unsigned long long)npb);
+  const unsigned long long c = wave_sum_u64((unsigned long long)cand);
   mx = wave_max_i32(mx);
   if ((threadIdx.x & 63) == 0) {
-    if (a) atomicAdd(&ctl->n_pp, a);
-    if (b2) atomicAdd(&ctl->n_pb, b2);
-    if (a + b2) atomicAdd(&ctl->summed, a + b2);
-    if (c) atomicAdd(&ctl->cand, c);
-    if (mx) atomicMax(&ctl->max_cnt, mx);
-    if (fb) atomicAdd(&ctl->fallback, fb);
+    st_sum[threadIdx.x >> 6][0] = a;
+    st_sum[threadIdx.x >> 6][1] = b2;
+    st_sum[threadIdx.x >> 6][2] = c;
+    st_max[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DetPart d{0ull, 0ull, 0ull, 0, (fb << 1) | 1};
+    for (int q = 0; q < TB / 64; ++q) {
+      d.n_pp += st_sum[q][0];
+      d.n_pb += st_sum[q][1];
+      d.cand += st_sum[q][2];
+      d.max_cnt = max(d.max_cnt, st_max[q]);
+    }
+    part[blk] = d;
   }
 }
 
@@ -1162,7 +1193,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
     const int32_t* __restrict__ n_items_ptr, const DevBody* __restrict__ bodies, int n_bodies, R gx,
     R gy, R gz, R dt, int mass_split, int max_cells, int max_stage, int32_t* __restrict__ ncon,
     int32_t* __restrict__ partner, R* __restrict__ Psi, V4<R>* __restrict__ w, R* __restrict__ imass, Ctl* ctl,
-    int step, int queue, int pair_gaps) {
+    DetPart* __restrict__ part, int step, int queue, int pair_gaps) {
   // the error word is read once per workgroup: every wave of it takes the
   // same branch (the work queue needs all of them)
   __shared__ int err0;
@@ -1171,7 +1202,59 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
   if (err0) return;
   detect_items<R, TB>(n, K, x, v, orig, inv_c, n_blk, env, start, sidx, xs, os, item_start, n_items_ptr, bodies,
                       n_bodies, gx, gy, gz, dt, mass_split, max_cells, max_stage, ncon, partner, Psi, w, imass, ctl,
-                      step, xcd_block(), gridDim.x, queue != 0, pair_gaps != 0);
+                      part, step, xcd_block(), gridDim.x, queue != 0, pair_gaps != 0);
+}
+
+// Totals of one detection from its workgroups' counts, which are cleared for
+// the next detection.  A detection whose workgroups all stopped at an earlier
+// failure of the call leaves the control block as it was.  rec (differentiable
+// calls, else null): the step's pair and body contact counts.
+__global__ __launch_bounds__(kBlock) void k_detect_stats(int nblk, DetPart* __restrict__ part, Ctl* ctl,
+                                                         unsigned long long* __restrict__ rec) {
+  __shared__ unsigned long long ws[kBlock / 64][5];
+  __shared__ int wm[kBlock / 64];
+  unsigned long long pp = 0, pb = 0, cd = 0, fb = 0, ran = 0;
+  int mx = 0;
+  for (int q = threadIdx.x; q < nblk; q += kBlock) {
+    const DetPart d = part[q];
+    pp += d.n_pp;
+    pb += d.n_pb;
+    cd += d.cand;
+    mx = max(mx, d.max_cnt);
+    fb += (unsigned)d.fb_ran >> 1;
+    ran += d.fb_ran & 1;
+    part[q] = DetPart{0ull, 0ull, 0ull, 0, 0};
+  }
+  pp = wave_sum_u64(pp);
+  pb = wave_sum_u64(pb);
+  cd = wave_sum_u64(cd);
+  fb = wave_sum_u64(fb);
+  ran = wave_sum_u64(ran);
+  mx = wave_max_i32(mx);
+  if ((threadIdx.x & 63) == 0) {
+    const int w = threadIdx.x >> 6;
+    ws[w][0] = pp; ws[w][1] = pb; ws[w][2] = cd; ws[w][3] = fb; ws[w][4] = ran;
+    wm[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      pp += ws[w][0]; pb += ws[w][1]; cd += ws[w][2]; fb += ws[w][3]; ran += ws[w][4];
+      mx = max(mx, wm[w]);
+    }
+    if (ran) {
+      ctl->n_pp = pp;
+      ctl->n_pb = pb;
+      ctl->cand = cd;
+      ctl->max_cnt = mx;
+      ctl->fallback = (int32_t)fb;
+      ctl->summed += pp + pb;
+    }
+    if (rec) {
+      rec[0] = ctl->n_pp;
+      rec[1] = ctl->n_pb;
+    }
+  }
 }
 
 // ------------------------------------------------------ projected Jacobi
@@ -1458,14 +1541,6 @@ __global__ void k_unpermute_i64(int n, const int32_t* __restrict__ orig, const i
                                 int64_t* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) out[orig[k]] = a[k];
-}
-
-// Contact counts of the last detection into per-step slots (differentiable calls).
-__global__ void k_record_counts(const Ctl* __restrict__ ctl, unsigned long long* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    out[0] = ctl->n_pp;
-    out[1] = ctl->n_pb;
-  }
 }
 
 __global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {

@@ -53,6 +53,8 @@ def test_fused_step_is_bitwise_the_split_step(case):
     xf, vf, cf, sf = _run(sc, steps, True, **kw)
     say(case, "contacts", len(cs), "max |dx|", float(np.abs(xf - xs).max()), "max |dv|", float(np.abs(vf - vs).max()))
     assert sf["steps_done"] == ss["steps_done"] == steps
+    # the split step's detection takes work items from queues, the fused one in fixed shares
+    assert ss["detect_queues"] == 1 and sf["detect_queues"] == 0
     if case == "fp64":
         assert np.array_equal(xs, xf) and np.array_equal(vs, vf) and np.array_equal(cs, cf)
         assert sf["contacts_summed"] == ss["contacts_summed"]

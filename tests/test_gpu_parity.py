@@ -626,8 +626,8 @@ def test_graph_replay_multi_env():
 def test_batched_environments_equal_separate_simulations():
     # each environment of a batch, stepped on its own (one environment, its
     # own bodies and twists), gives the same bits: the batched form adds no
-    # arithmetic, and its detection (work queues per XCD) and the single
-    # bed's (fixed contiguous shares) only distribute the same work items
+    # arithmetic, and the work queues of detection only distribute the work
+    # items (which workgroup takes an item changes no result)
     sc = scenes.batched_scene(n_envs=3, lo=2000, hi=6000, n_steps=12)
     off = sc.env_offsets
     kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters)
@@ -644,10 +644,36 @@ def test_batched_environments_equal_separate_simulations():
         bodies = [dict(sc.bodies[b], env=0) for b in idx]
         one = gg.Sim(sc.x[sl], sc.v[sl], sc.radius[sl], bodies, **kw)
         one.step(12, twists=np.ascontiguousarray(sc.twists[:, idx]))
-        assert one.stats()["detect_queues"] == 0
         assert np.array_equal(one.read("pos"), xb[sl]), e
         assert np.array_equal(one.read("vel"), vb[sl]), e
         one.close()
+
+
+def test_detection_statistics_sum_over_workgroups_and_steps():
+    # each detection workgroup stores its own counts and one small kernel sums
+    # them: a call of several steps reports the last step's counts and the sum
+    # over its steps, equal to the same steps taken one call at a time
+    sc = scenes.column_scene(n=6000, r=0.004)
+    side = float(sc.x[:, 0].max())
+    bodies = sc.bodies + [scenes.box_tool((side / 2, side / 2, float(sc.x[:, 2].max()) + 0.01),
+                                          (0.01, 0.02, 0.03), nu=(0.0, 0.0, -0.5))]
+    kw = dict(dt=sc.dt, alpha=sc.alpha, mu=sc.mu, n_iters=sc.n_iters)
+    say("statistics", sc.n)
+    one = gg.Sim(sc.x, sc.v, sc.radius, bodies, **kw)
+    per_step = []
+    for _ in range(8):
+        one.step(1)
+        st = one.stats()
+        assert st["contacts_summed"] == st["n_pp"] + st["n_pb"]
+        per_step.append((st["n_pp"], st["n_pb"], st["candidates"], st["max_contacts"]))
+    one.close()
+    assert per_step[-1][0] > 1000 and per_step[-1][1] > 0
+    many = gg.Sim(sc.x, sc.v, sc.radius, bodies, **kw)
+    many.step(8)
+    st = many.stats()
+    many.close()
+    assert (st["n_pp"], st["n_pb"], st["candidates"], st["max_contacts"]) == per_step[-1]
+    assert st["contacts_summed"] == sum(a + b for a, b, _, _ in per_step)
 
 
 def test_hash_table_size_changes_no_result():
