@@ -601,7 +601,7 @@ void launch_reorder(gg_sim* s) {
     ggk::k_rs_hist<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
     ggk::k_scan_a<<<rs_nbs, ggk::kBlock, 0, S>>>(rs_m, s->rs_hist, s->rs_hist, s->rs_bsum, 0);
     ggk::k_scan_b<<<1, 1024, 0, S>>>(rs_nbs, s->rs_bsum, rs_m, s->rs_hist);
-    ggk::k_scan_c<<<(rs_m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(rs_m, s->rs_bsum, s->rs_hist);
+    ggk::k_scan_c<<<rs_nbs, ggk::kBlock, 0, S>>>(rs_m, s->rs_bsum, s->rs_hist);
     ggk::k_rs_scatter<<<s->rs_nb, ggk::kBlock, 0, S>>>(n, s->mk[src], pass == 0 ? nullptr : s->mv[src], s->mk[dst],
                                                          s->mv[dst], pass * ggk::kRsBits, s->rs_nb, s->rs_hist);
   }
@@ -615,12 +615,12 @@ void launch_reorder(gg_sim* s) {
   ggk::k_node_flags<<<grid, ggk::kBlock, 0, S>>>(n, keys, s->p.tile_node_shift + ggk::kCountBits, s->it_f);
   ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_bsum, 0);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_e);
-  ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
+  ggk::k_scan_c<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_e);
   ggk::k_node_first<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first);
   ggk::k_item_flags<<<grid, ggk::kBlock, 0, S>>>(n, s->it_f, s->it_e, s->it_first, s->p.tile_threads, s->it_g);
   ggk::k_scan_a<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->it_bsum, 0);
   ggk::k_scan_b<<<1, 1024, 0, S>>>(it_nbs, s->it_bsum, n, s->it_h);
-  ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
+  ggk::k_scan_c<<<it_nbs, ggk::kBlock, 0, S>>>(n, s->it_bsum, s->it_h);
   ggk::k_item_starts<<<grid, ggk::kBlock, 0, S>>>(n, s->it_g, s->it_h, s->item_start);
   ggk::k_copy_i32<<<1, 64, 0, S>>>(s->it_h + n, &s->ctl->items);
 }
@@ -670,7 +670,7 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
                                                s->ctl, st);
     ggk::k_scan_a<<<nbs, ggk::kBlock, 0, S>>>(m, s->counts, s->bstart, s->bsum, 1);
     ggk::k_scan_b<<<1, 1024, 0, S>>>(nbs, s->bsum, m, s->bstart);
-    ggk::k_scan_c<<<(m + ggk::kBlock - 1) / ggk::kBlock, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
+    ggk::k_scan_c<<<nbs, ggk::kBlock, 0, S>>>(m, s->bsum, s->bstart);
     ggk::k_scatter<R><<<grid, ggk::kBlock, 0, S>>>(n, s->h, s->rank, s->bstart, io.x, s->orig, s->sidx, (V*)s->xs,
                                                    s->os);
   }
@@ -1755,7 +1755,7 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
       const int pnb = (n + ggk::kScanTile - 1) / ggk::kScanTile;
       ggk::k_scan_a<<<pnb, ggk::kBlock, 0, S>>>(n, io.ncon, io.pofs, pbsum, 0);
       ggk::k_scan_b<<<1, 1024, 0, S>>>(pnb, pbsum, n, io.pofs);
-      ggk::k_scan_c<<<grid, ggk::kBlock, 0, S>>>(n, pbsum, io.pofs);
+      ggk::k_scan_c<<<pnb, ggk::kBlock, 0, S>>>(n, pbsum, io.pofs);
       int32_t total = -1;
       BWCHK(hipMemcpyAsync(&total, io.pofs + n, 4, hipMemcpyDeviceToHost, S));
       BWCHK(hipStreamSynchronize(S));

@@ -657,17 +657,27 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__
 
 // Block-local exclusive scan of kScanTile counters; zeroes the counters when
 // asked (the bucket counters are reused next step) and writes the block total.
+// Each thread takes four consecutive counters, with 16-byte loads and stores
+// where both arrays are 16-byte aligned and the four lie inside [0, m).
 __global__ __launch_bounds__(kBlock) void k_scan_a(int m, int32_t* __restrict__ counts,
                                                    int32_t* __restrict__ start, int32_t* __restrict__ bsum,
                                                    int zero) {
   __shared__ int wsum[kBlock / 64];
   const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(counts) | reinterpret_cast<uintptr_t>(start)) & 15) == 0 &&
+                   base + 3 < m;
   int v[4];
+  if (vec) {
+    const int4 c4 = *reinterpret_cast<const int4*>(counts + base);
+    v[0] = c4.x; v[1] = c4.y; v[2] = c4.z; v[3] = c4.w;
+    if (zero) *reinterpret_cast<int4*>(counts + base) = make_int4(0, 0, 0, 0);
+  } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = base + q;
-    v[q] = e < m ? counts[e] : 0;
-    if (zero && e < m) counts[e] = 0;
+    for (int q = 0; q < 4; ++q) {
+      int e = base + q;
+      v[q] = e < m ? counts[e] : 0;
+      if (zero && e < m) counts[e] = 0;
+    }
   }
   const int t = v[0] + v[1] + v[2] + v[3];
   const int s = wave_incl_scan(t);
@@ -677,11 +687,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_a(int m, int32_t* __restrict__ 
   int off = 0;
   for (int w = 0; w < wid; ++w) off += wsum[w];
   int run = off + s - t;
+  if (vec) {
+    const int r1 = run + v[0], r2 = r1 + v[1], r3 = r2 + v[2];
+    *reinterpret_cast<int4*>(start + base) = make_int4(run, r1, r2, r3);
+    run = r3 + v[3];
+  } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = base + q;
-    if (e < m) start[e] = run;
-    run += v[q];
+    for (int q = 0; q < 4; ++q) {
+      int e = base + q;
+      if (e < m) start[e] = run;
+      run += v[q];
+    }
   }
   if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = run;
 }
@@ -784,10 +800,21 @@ __global__ __launch_bounds__(1024) void k_scan_b(int nb, int32_t* __restrict__ b
   if (threadIdx.x == 0) start[m] = carry;
 }
 
+// Adds the scanned block totals: one workgroup per scan tile (grid
+// ceil(m / kScanTile)), four counters per thread as in k_scan_a.
 __global__ __launch_bounds__(kBlock) void k_scan_c(int m, const int32_t* __restrict__ bsum,
                                                    int32_t* __restrict__ start) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e < m) start[e] += bsum[e / kScanTile];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * 4;
+  const int add = bsum[blockIdx.x];
+  if ((reinterpret_cast<uintptr_t>(start) & 15) == 0 && base + 3 < m) {
+    int4 s4 = *reinterpret_cast<const int4*>(start + base);
+    s4.x += add; s4.y += add; s4.z += add; s4.w += add;
+    *reinterpret_cast<int4*>(start + base) = s4;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (base + q < m) start[base + q] += add;
+  }
 }
 
 // Particles into bucket order: index, position and original index, so that a
@@ -967,8 +994,7 @@ __device__ __forceinline__ void detect_items(
   int* cell_off = (int*)smem;                                  // max_cells + 1
   int* cell_s = cell_off + (max_cells + 1);                    // max_cells: first bucket entry
   V4<R>* st_x = (V4<R>*)(smem + ((((2 * max_cells + 1) * 4) + 31) & ~31));  // max_stage
-  int* st_j = (int*)(st_x + max_stage);                        // max_stage (-1: other cell)
-  int* st_o = st_j + max_stage;                                // max_stage
+  int2* st_jo = (int2*)(st_x + max_stage);                     // max_stage: (index (-1: other cell), original index)
 
   const int n_items = *n_items_ptr;
   int it0, it1, qx = 0;
@@ -1052,22 +1078,19 @@ __device__ __forceinline__ void detect_items(
           const bool mine = cell_coord(pj32.x, inv_c, okj) == cx && cell_coord(pj32.y, inv_c, okj) == cy &&
                             cell_coord(pj32.z, inv_c, okj) == cz;
           st_x[first + u] = pj;
-          st_j[first + u] = mine ? sidx[s0 + u] : -1;
-          st_o[first + u] = mine ? os[s0 + u] : 0x7fffffff;
+          st_jo[first + u] = mine ? make_int2(sidx[s0 + u], os[s0 + u]) : make_int2(-1, 0x7fffffff);
         }
         for (int u = 1; u < m; ++u) {
           const V4<R> kx = st_x[first + u];
-          const int kj = st_j[first + u], ko = st_o[first + u];
+          const int2 kjo = st_jo[first + u];
           int at = first + u;
-          while (at > first && st_o[at - 1] > ko) {
+          while (at > first && st_jo[at - 1].y > kjo.y) {
             st_x[at] = st_x[at - 1];
-            st_j[at] = st_j[at - 1];
-            st_o[at] = st_o[at - 1];
+            st_jo[at] = st_jo[at - 1];
             --at;
           }
           st_x[at] = kx;
-          st_j[at] = kj;
-          st_o[at] = ko;
+          st_jo[at] = kjo;
         }
       }
       __syncthreads();
@@ -1075,22 +1098,35 @@ __device__ __forceinline__ void detect_items(
         // the three cells dx = -1, 0, 1 of a row are consecutive in the tile,
         // and so are their staged members: one scan per row, skipping the
         // other cells' members (sorted last within each cell), visits the
-        // partners in the same order as 27 cell scans
+        // partners in the same order as 27 cell scans.  The scan reads four
+        // members at a time (their loads in flight together; past the row's
+        // end the last member is read again and skipped) and tests them in
+        // order.
         for (int dz = -1; dz <= 1; ++dz)
           for (int dy = -1; dy <= 1; ++dy) {
             const int c = ((k2 + dz - ez) * Dy + (k1 + dy - ey)) * Dx + (k0 - 1 - ex);
             const int s0 = cell_off[c], s1 = cell_off[c + 3];
-            for (int q = s0; q < s1; ++q) {
-              const int j = st_j[q];
-              if (j < 0 || j == i) continue;
-              ++cand;
-              const V4<R> pj = st_x[q];
-              if (!pair_touch(p32, f32of(pj))) continue;
-              const int oj = st_o[q];
-              npp += oi < oj;
-              put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gaps ? pair_gap(p, pj) : R(0), partner, Psi,
-                          pair_gaps);
-              ++cnt;
+            for (int q0 = s0; q0 < s1; q0 += 4) {
+              int2 jo[4];
+              V4<R> px[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int q = min(q0 + u, s1 - 1);
+                jo[u] = st_jo[q];
+                px[u] = st_x[q];
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int j = jo[u].x;
+                if (q0 + u >= s1 || j < 0 || j == i) continue;
+                ++cand;
+                if (!pair_touch(p32, f32of(px[u]))) continue;
+                const int oj = jo[u].y;
+                npp += oi < oj;
+                put_contact(i, cnt, K, j | (oi < oj ? 0 : kHiFlag), pair_gaps ? pair_gap(p, px[u]) : R(0), partner,
+                            Psi, pair_gaps);
+                ++cnt;
+              }
             }
           }
       }
