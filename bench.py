@@ -592,7 +592,7 @@ def profiler_window(on):
     torch.cuda.synchronize()
 
 
-def _timed_bed(args, sim, n, pja_iters, workload, extra_config):
+def _timed_bed(args, sim, n, pja_iters, workload, extra_config, traffic_measured=False):
     """W untimed steps, then K timed steps of `sim`; the bench line without the
     CPU baseline.  k_pja's duration comes from the library's HIP events on its
     own stream (profile=True)."""
@@ -618,7 +618,8 @@ def _timed_bed(args, sim, n, pja_iters, workload, extra_config):
     contacts_avg = st["contacts_summed"] / max(1, st["steps_done"])
     algo = pja_algorithmic_bytes(n, contacts_avg)
     achieved = algo / (pja_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    # the counters were taken on the settled scoop bed only: another bed reports none
+    traffic = measured_traffic() if traffic_measured else None
     out = {
         "metric": METRIC,
         "value": n * steps / elapsed,
@@ -777,7 +778,7 @@ def bench_scoop(args):
                      "until at most 10 grains move at 1 mm/s or more) in a 1x1 m walled box; box tool 0.05x0.1x0.2 m "
                      "starting 1 cm above "
                      "the surface, 0.2 m/s along (cos 30, 0, -sin 30); dt=1 ms, 20 PJA sweeps, mu=0.5; timed: the "
-                     "last steps of the 200-step path", extra)
+                     "last steps of the 200-step path", extra, traffic_measured=True)
     pairs = sim.read("contacts")
     out["config"]["tool_contacts_last_step"] = int(np.sum(pairs[sim.stats()["n_pp"]:, 1] == len(bodies) - 1))
     sim.close()
