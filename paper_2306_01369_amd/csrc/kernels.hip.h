@@ -652,7 +652,25 @@ __global__ __launch_bounds__(kBlock) void k_key(int n, const V4<R>* __restrict__
   if (!ok) set_error(ctl, 5 /* GG_ERR_NONFINITE */, step);
   h[i] = bucket;
   h6[i] = cell;
-  rank[i] = atomicAdd(&counts[bucket], 1);
+  // a cell's particles are mostly consecutive (Z order), so each run of lanes
+  // with the same bucket takes one atomic: the run's first lane adds its
+  // length, and a lane's rank is the old count plus its place in the run
+  // (lanes with i >= n have left, so the active lanes are a prefix).  The
+  // shuffle and both ballots run on every active lane, outside any branch: a
+  // ballot in a divergent branch sees only that branch's lanes.
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(bucket, 1, 64);
+  const unsigned long long live = __ballot(1);
+  const unsigned long long heads = __ballot(lane == 0 || prev != bucket);
+  const bool head = (heads >> lane) & 1ull;
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane
+  const int first = 63 - __clzll(heads & upto);
+  const unsigned long long later = heads & ~upto;
+  const int end = later ? __ffsll((unsigned long long)later) - 1 : __popcll(live);
+  int base = 0;
+  if (head) base = atomicAdd(&counts[bucket], end - first);
+  base = __shfl(base, first, 64);
+  rank[i] = base + (lane - first);
 }
 
 // Block-local exclusive scan of kScanTile counters; zeroes the counters when

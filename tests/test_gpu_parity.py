@@ -508,6 +508,21 @@ def test_larger_cell_keeps_contacts_and_parity():
     _compare_one_step(s.x, s.v, s.radius, s.bodies, "cell-x1.25", cell_size=float(np.float32(1.25 * c)))
 
 
+def test_crowded_cells_one_step():
+    # cells four times the default hold about 90 grains each: in the key
+    # kernel runs of equal buckets span whole wavefronts (one atomic per run
+    # of lanes), and detection takes the per-particle path; contacts exact,
+    # impulses within the one-step bar of the oracle
+    rng = np.random.default_rng(5)
+    x, r = scenes.random_spheres(20000, ((0, 0.12), (0, 0.12), (0, 0.12)), 0.002, rng, r_jitter=0.25)
+    v = (rng.normal(size=(20000, 3)) * 0.1).astype(np.float32)
+    c, _ = O.default_cell(r)
+    say("crowded cells: cell x4")
+    d = _compare_one_step(x, v, r, [], "crowded-cells", gravity=(0, 0, 0), n_iters=5, mu=0.3,
+                          cell_size=float(np.float32(4 * c)))
+    assert d["n_pp"] > 10000
+
+
 @pytest.mark.parametrize("threads,shift", [(64, 5), (64, 6), (256, 7)])
 def test_detection_workgroup_size_keeps_results_bitwise(threads, shift):
     s = scenes.column_scene(n=5000, r=0.004)
