@@ -634,7 +634,7 @@ size_t detect_lds_bytes(const gg_sim* s) {
 // The detection kernel for a workgroup size of TB threads.
 template <typename R, int TB>
 void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, int dgrid, size_t dlds,
-                   int blk1, const ggk::EnvTables& et, unsigned long long* rec) {
+                   int blk1, const ggk::EnvTables& et) {
   using V = ggk::V4<R>;
   ggk::k_detect<R, TB><<<dgrid, TB, dlds, s->stream>>>(
       (int)s->n, s->K, io.x, io.v, s->orig, s->inv_c, blk1, et, s->bstart, s->sidx, (const V*)s->xs, s->os,
@@ -642,19 +642,22 @@ void detect_kernel(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
       (R)s->p.gravity[2], (R)s->p.dt, s->p.mass_split, s->p.tile_max_cells, s->p.tile_max_stage, io.ncon,
       io.partner, io.Psi, io.w[0], io.imass, s->ctl, s->det_part, st, s->det_queue,
       (s->p.flags & GG_FLAG_TAPE) ? 1 : 0);
-  ggk::k_detect_stats<<<1, ggk::kBlock, 0, s->stream>>>(dgrid, s->det_part, s->ctl, rec);
 }
 
-// Bucket table and contact detection of one step (rec: see k_detect_stats).
+// Detection workgroups of a split step (their counts are summed by k_integrate).
+int detect_grid(const gg_sim* s) {
+  return std::max(1, std::min((int)((s->n + 31) / 32), s->det_grid));
+}
+
+// Bucket table and contact detection of one step.
 template <typename R>
-void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, bool with_detect = true,
-                   unsigned long long* rec = nullptr) {
+void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* bod, bool with_detect = true) {
   using V = ggk::V4<R>;
   const int n = (int)s->n;
   const int grid = (n + ggk::kBlock - 1) / ggk::kBlock;
   const int m = (int)s->n_buckets;
   const int nbs = (m + ggk::kScanTile - 1) / ggk::kScanTile;
-  const int dgrid = std::max(1, std::min((n + 31) / 32, s->det_grid));
+  const int dgrid = detect_grid(s);
   const size_t dlds = detect_lds_bytes(s);
   const ggk::EnvTables et = env_tables(s);
   const int nh1 = s->env_nh[0];
@@ -676,9 +679,9 @@ void launch_detect(gg_sim* s, const StepIO<R>& io, int st, const ggk::DevBody* b
   }
   if (!with_detect) return;
   switch (s->p.tile_threads) {
-    case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
-    case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
-    default: detect_kernel<R, 128>(s, io, st, bod, dgrid, dlds, blk1, et, rec); break;
+    case 64: detect_kernel<R, 64>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+    case 256: detect_kernel<R, 256>(s, io, st, bod, dgrid, dlds, blk1, et); break;
+    default: detect_kernel<R, 128>(s, io, st, bod, dgrid, dlds, blk1, et); break;
   }
 }
 
@@ -826,12 +829,13 @@ gg_status enqueue_steps_t(gg_sim* s, int n_steps, int nb, bool taped, bool prof)
       if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
       continue;
     }
-    launch_detect<R>(s, io, st, bod, true, taped ? s->d_counts + 2 * (size_t)st : nullptr);
+    launch_detect<R>(s, io, st, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 1], S));
     launch_sweeps<R>(s, io, bod);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 2], S));
     ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, (V*)s->x, (const V*)s->v, dt, cyc_lo<R>(s), cyc_span<R>(s),
-                                                     s->ctl);
+                                                     s->ctl, s->det_part, detect_grid(s),
+                                                     taped ? s->d_counts + 2 * (size_t)st : nullptr);
     if (prof) HIPCHK(s, hipEventRecord(s->events[4 * st + 3], S));
   }
   return GG_OK;
@@ -1764,7 +1768,8 @@ gg_status backward_t(gg_sim* s, const float* dL_dx, const float* dL_dv, float* d
         return fail(GG_ERR_HIP, "recomputed contacts differ from the recorded forward");
       }
       launch_sweeps<R>(s, io, bod);
-      ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, cyc_lo<R>(s), cyc_span<R>(s), s->ctl);
+      ggk::k_integrate<R><<<grid, ggk::kBlock, 0, S>>>(n, xw, vw, dt, cyc_lo<R>(s), cyc_span<R>(s), s->ctl,
+                                                       s->det_part, detect_grid(s), nullptr);
     }
     // reverse the segment
     for (int st = s1 - 1; st >= s0; --st) {

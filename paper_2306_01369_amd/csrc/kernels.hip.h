@@ -121,7 +121,8 @@ struct Ctl {                    // device control block, one per simulation
 static_assert(offsetof(Ctl, next_item) == 128, "work-queue counters start a cache line");
 
 // Counts of one detection workgroup, stored once when it ends and summed by
-// k_detect_stats: device-scope atomics from every workgroup on the control
+// detect_stats_block (workgroup 0 of the step's k_integrate, or k_detect_stats
+// after the fused step): device-scope atomics from every workgroup on the control
 // block cost more time than the rest of the statistics by far (they queue on
 // one address, and loads and stores of the workgroups still running wait
 // behind them).
@@ -1260,11 +1261,12 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(5))) void k_
 }
 
 // Totals of one detection from its workgroups' counts, which are cleared for
-// the next detection.  A detection whose workgroups all stopped at an earlier
-// failure of the call leaves the control block as it was.  rec (differentiable
-// calls, else null): the step's pair and body contact counts.
-__global__ __launch_bounds__(kBlock) void k_detect_stats(int nblk, DetPart* __restrict__ part, Ctl* ctl,
-                                                         unsigned long long* __restrict__ rec) {
+// the next detection; run by one whole workgroup of kBlock threads.  A
+// detection whose workgroups all stopped at an earlier failure of the call
+// leaves the control block as it was.  rec (differentiable calls, else null):
+// the step's pair and body contact counts.
+__device__ void detect_stats_block(int nblk, DetPart* __restrict__ part, Ctl* ctl,
+                                   unsigned long long* __restrict__ rec) {
   __shared__ unsigned long long ws[kBlock / 64][5];
   __shared__ int wm[kBlock / 64];
   unsigned long long pp = 0, pb = 0, cd = 0, fb = 0, ran = 0;
@@ -1309,6 +1311,13 @@ __global__ __launch_bounds__(kBlock) void k_detect_stats(int nblk, DetPart* __re
       rec[1] = ctl->n_pb;
     }
   }
+}
+
+// The statistics of the fused step's detection (the split step sums them in
+// k_integrate).
+__global__ __launch_bounds__(kBlock) void k_detect_stats(int nblk, DetPart* __restrict__ part, Ctl* ctl,
+                                                         unsigned long long* __restrict__ rec) {
+  detect_stats_block(nblk, part, ctl, rec);
 }
 
 // ------------------------------------------------------ projected Jacobi
@@ -1560,10 +1569,15 @@ __device__ __forceinline__ void integrate_particle(int i, V4<R>* __restrict__ x,
   x[i] = p;
 }
 
+// Positions of one step; workgroup 0 first sums the step's detection
+// statistics (detect_stats_block over nblk slots; part null: none), also
+// after a failure, which needs the largest contact count.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_integrate(int n, V4<R>* __restrict__ x,
                                                       const V4<R>* __restrict__ v, R dt, R zlo, R zspan,
-                                                      Ctl* ctl) {
+                                                      Ctl* ctl, DetPart* __restrict__ part, int nblk,
+                                                      unsigned long long* __restrict__ rec) {
+  if (blockIdx.x == 0 && part) detect_stats_block(nblk, part, ctl, rec);
   if (ctl->err) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->steps_done, 1);
