@@ -79,14 +79,20 @@ def test_fused_step_is_bitwise_the_split_step(case):
 
 
 def test_fused_step_reports_capacity_errors_like_the_split_step():
+    # the failed step still reports the largest contact count its detection
+    # saw (what a caller sizes the capacity from), the same in both forms
     sc = scenes.column_scene(n=3000, r=0.004)
+    largest = []
     for fused in (False, True):
         sim = gg.Sim(sc.x, sc.v, sc.radius, sc.bodies, fused=fused, max_contacts=4)
         x0 = sim.read("pos")
         with pytest.raises(gg.CapacityError):
             sim.step(3)
         st = sim.stats()
-        say("fused" if fused else "split", "steps done before the capacity error", st["steps_done"])
+        say("fused" if fused else "split", "steps done before the capacity error", st["steps_done"],
+            "largest count", st["max_contacts"])
         assert st["steps_done"] == 0
         assert np.array_equal(sim.read("pos"), x0)   # the step was abandoned before integration
+        largest.append(st["max_contacts"])
         sim.close()
+    assert largest[0] == largest[1] > 4
