@@ -285,7 +285,8 @@ typedef struct {
   int64_t n_pp;           /* particle-particle contacts at the last detection */
   int64_t n_pb;           /* particle-body contacts at the last detection */
   int64_t candidates;     /* ordered candidate pairs tested at the last detection */
-  int64_t max_contacts;   /* largest contact count of one particle at the last detection */
+  int64_t max_contacts;   /* largest contact count of one particle at the last detection
+                             (also when that detection overflowed the capacity) */
   int64_t capacity;       /* contact capacity per particle */
   int64_t last_status;    /* gg_status of the last gg_step call */
   int64_t n;              /* particles */
@@ -295,7 +296,8 @@ typedef struct {
                              multiple of 64) */
   double ms_detect;       /* profiled: cell keys + sort + detection, summed over the last call */
   double ms_pja;          /* profiled: projected-Jacobi sweeps, summed */
-  double ms_integrate;    /* profiled: position update, summed */
+  double ms_integrate;    /* profiled: position update (with the summing of the step's
+                             detection statistics), summed */
   int64_t pja_launches;   /* profiled: projected-Jacobi launches timed */
   int64_t contacts_summed;/* contacts (pairs + body) summed over the steps of the last call */
   int64_t detect_fallback;/* detection work items (up to tile_threads particles each) that queried
